@@ -1,0 +1,191 @@
+"""CPU oracle for batched ranged random integer generation.
+
+TEST INFRASTRUCTURE. Only the tests, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may import this package. The product
+(``paper_2408_06213_amd``) never imports it, and the two share no code: the
+only common dependency is the seeded input generator module, which holds none
+of the method's arithmetic.
+
+``liboracle.so`` is built from ``brr_oracle.c`` (plain C, gcc) by
+:func:`build`; the wrappers below only marshal numpy arrays into it.
+``ref`` holds the width-generic big-integer forms used for exhaustive checks.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "brr_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OK, EINVAL, EOVERFLOW = 0, 1, 2
+
+
+def build() -> str:
+    """Compile liboracle.so with gcc (plain C, -O2)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", LIB, SRC]
+    subprocess.run(cmd, check=True)
+    return LIB
+
+
+class Schedule(ctypes.Structure):
+    """A batch-size schedule: while more than thr[g] elements remain, roll
+    batches of k[g] dice with upper bound u[g] (0 = exact product); then, if
+    ``tail``, one last batch of i-1 dice bounded by ``u_tail``."""
+
+    _fields_ = [
+        ("nseg", ctypes.c_uint32),
+        ("tail", ctypes.c_uint32),
+        ("thr", ctypes.c_uint64 * 16),
+        ("k", ctypes.c_uint32 * 16),
+        ("u", ctypes.c_uint64 * 16),
+        ("u_tail", ctypes.c_uint64),
+    ]
+
+    def segments(self):
+        return [(int(self.thr[g]), int(self.k[g]), int(self.u[g])) for g in range(self.nseg)]
+
+    @classmethod
+    def from_segments(cls, segs, tail=True, u_tail=720):
+        s = cls()
+        s.nseg = len(segs)
+        for g, (thr, k, u) in enumerate(segs):
+            s.thr[g], s.k[g], s.u[g] = thr, k, u
+        s.tail = 1 if tail else 0
+        s.u_tail = u_tail
+        return s
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        u64, u32, p = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
+        L.orc_philox4x32_10.argtypes = [p, p, p]
+        L.orc_philox4x32_10.restype = None
+        L.orc_word.argtypes = [u64, u64, u64]
+        L.orc_word.restype = u64
+        L.orc_chain.argtypes = [ctypes.c_uint, p, ctypes.c_uint, u64, p]
+        L.orc_chain.restype = u64
+        L.orc_threshold.argtypes = [ctypes.c_uint, p, ctypes.c_uint, p]
+        L.orc_threshold.restype = ctypes.c_int
+        L.orc_dice.argtypes = [p, p, u64, ctypes.c_uint, u64, u64]
+        L.orc_dice.restype = ctypes.c_int
+        L.orc_dice_const.argtypes = [u32, p, u64, ctypes.c_uint, u64, u64]
+        L.orc_dice_const.restype = ctypes.c_int
+        L.orc_schedule_paper.argtypes = [ctypes.c_int, ctypes.POINTER(Schedule)]
+        L.orc_schedule_paper.restype = ctypes.c_int
+        L.orc_count_batches.argtypes = [u64, u64, ctypes.POINTER(Schedule)]
+        L.orc_count_batches.restype = u64
+        L.orc_shuffle.argtypes = [p, u64, ctypes.c_uint, ctypes.POINTER(Schedule), u64, u64]
+        L.orc_shuffle.restype = ctypes.c_int
+        L.orc_shuffle_words.argtypes = [p, u64, ctypes.c_uint, ctypes.POINTER(Schedule), p, u64]
+        L.orc_shuffle_words.restype = ctypes.c_int
+        L.orc_shuffle_batched.argtypes = [p, p, u64, ctypes.c_uint, ctypes.POINTER(Schedule), u64, u64]
+        L.orc_shuffle_batched.restype = ctypes.c_int
+        L.orc_partial_shuffle.argtypes = [p, u64, u64, ctypes.c_uint, ctypes.POINTER(Schedule), u64, u64]
+        L.orc_partial_shuffle.restype = ctypes.c_int
+        L.orc_sample.argtypes = [p, u64, u64, ctypes.c_uint, p, ctypes.POINTER(Schedule), u64, u64]
+        L.orc_sample.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ----------------------------------------------------------------------------
+# thin wrappers
+# ----------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return [int(x) for x in out]
+
+
+def word(seed: int, inst: int, c: int) -> int:
+    return int(lib().orc_word(seed, inst, c))
+
+
+def chain(L: int, bounds, r0: int):
+    b = np.asarray(bounds, dtype=np.uint64).copy()
+    a = np.zeros(max(1, len(b)), dtype=np.uint64)
+    r = lib().orc_chain(L, _ptr(b), len(b), r0, _ptr(a))
+    return [int(x) for x in a[: len(b)]], int(r)
+
+
+def threshold(L: int, bounds):
+    b = np.asarray(bounds, dtype=np.uint64).copy()
+    t = np.zeros(1, dtype=np.uint64)
+    err = lib().orc_threshold(L, _ptr(b), len(b), _ptr(t))
+    return err, int(t[0])
+
+
+def dice(bounds: np.ndarray, k: int, seed: int, inst: int = 0):
+    bounds = np.ascontiguousarray(bounds, dtype=np.uint32)
+    out = np.zeros(bounds.size, dtype=np.uint32)
+    err = lib().orc_dice(_ptr(bounds), _ptr(out), bounds.size, k, seed, inst)
+    return err, out
+
+
+def dice_const(bound: int, count: int, k: int, seed: int, inst: int = 0):
+    out = np.zeros(count, dtype=np.uint32)
+    err = lib().orc_dice_const(bound, _ptr(out), count, k, seed, inst)
+    return err, out
+
+
+def schedule_paper(max_k: int) -> Schedule:
+    s = Schedule()
+    err = lib().orc_schedule_paper(max_k, ctypes.byref(s))
+    if err:
+        raise ValueError(f"no paper schedule for max_k={max_k}")
+    return s
+
+
+def count_batches(n: int, steps: int, sched: Schedule) -> int:
+    return int(lib().orc_count_batches(n, steps, ctypes.byref(sched)))
+
+
+def shuffle(data: np.ndarray, sched: Schedule, seed: int, inst: int = 0):
+    """In-place scheduled batched Fisher-Yates shuffle of a u32/u64 array."""
+    assert data.dtype in (np.uint32, np.uint64)
+    return lib().orc_shuffle(_ptr(data), data.size, data.itemsize, ctypes.byref(sched), seed, inst)
+
+
+def shuffle_words(data: np.ndarray, sched: Schedule, words):
+    w = np.asarray(words, dtype=np.uint64).copy()
+    return lib().orc_shuffle_words(_ptr(data), data.size, data.itemsize, ctypes.byref(sched),
+                                   _ptr(w), w.size)
+
+
+def shuffle_batched(data: np.ndarray, offsets: np.ndarray, sched: Schedule, seed: int,
+                    inst_base: int = 0):
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    return lib().orc_shuffle_batched(_ptr(data), _ptr(offsets), offsets.size - 1, data.itemsize,
+                                     ctypes.byref(sched), seed, inst_base)
+
+
+def partial_shuffle(data: np.ndarray, m: int, sched: Schedule, seed: int, inst: int = 0):
+    return lib().orc_partial_shuffle(_ptr(data), data.size, m, data.itemsize, ctypes.byref(sched),
+                                     seed, inst)
+
+
+def sample(data: np.ndarray, m: int, sched: Schedule, seed: int, inst: int = 0):
+    out = np.zeros(m, dtype=data.dtype)
+    err = lib().orc_sample(_ptr(data), data.size, m, data.itemsize, _ptr(out), ctypes.byref(sched),
+                           seed, inst)
+    return err, out

@@ -1,0 +1,482 @@
+/*
+ * Plain CPU oracle for batched ranged random integer generation
+ * (Brackett-Rozinsky and Lemire, "Batched Ranged Random Integer Generation").
+ *
+ * TEST INFRASTRUCTURE ONLY. The tests, the smoke check and the benchmark's
+ * CPU-baseline leg are the only callers. The product library shares no
+ * source, header or helper with this file and never loads it.
+ *
+ * Everything here is the slow, direct form of a definition in the paper,
+ * written with unsigned __int128 so that every full-width product is exact:
+ *   - full-width multiply b (x) r = (x, y), 2^L x + y = b r      (Sec. 1.1)
+ *   - Theorem 1 chain + Lemire's criterion on the leftover       (Sec. 4)
+ *   - Algorithm 2 (known threshold) and Algorithm 3 (unknown)    (Sec. 5)
+ *   - Algorithm 4 (batched partial shuffle with carried bound u) (Sec. 6)
+ *   - the full-shuffle procedure with batch sizes growing as the
+ *     array shrinks, and one last batch at the end              (Sec. 6, 6.1)
+ *
+ * Where the paper is silent these readings apply (also listed in the design
+ * notes of the repository):
+ *   - Word source: the paper draws L-bit words from a sequential generator.
+ *     Here word c of instance `inst` under `seed` is one 64-bit half of
+ *     Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
+ *     key = (lo32 seed, hi32 seed) and counter = (lo32 c/2, hi32 c/2,
+ *     lo32 inst, hi32 inst); even c takes x0 | x1<<32, odd c x2 | x3<<32.
+ *   - Word addressing: attempt a (0 = first) of batch/group s of an
+ *     instance that has S batches/groups uses word c = a*S + s. Without
+ *     rejections this is the paper's sequential consumption of words 0..S-1.
+ *   - Digit order: b_1 is applied first and a_1 is the most significant
+ *     digit; in a shuffle batch at size n the bounds are n, n-1, ..., n-k+1
+ *     and the swaps run z[n-1] first.
+ *
+ * Error codes: 0 ok, 1 invalid argument (e.g. a zero bound),
+ * 2 overflow (a bound product above 2^L).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+#define ORC_OK 0
+#define ORC_EINVAL 1
+#define ORC_EOVERFLOW 2
+
+/* ------------------------------------------------------------------ */
+/* Word source: Philox4x32-10, from its published description.         */
+/* ------------------------------------------------------------------ */
+
+/* One Philox4x32 round: two 32x32->64 products with the round multipliers,
+ * the high halves mixed with the other two counter words and the key. */
+static void philox_round(uint32_t x[4], const uint32_t key[2])
+{
+    const uint64_t prod_a = (uint64_t)0xD2511F53u * (uint64_t)x[0];
+    const uint64_t prod_b = (uint64_t)0xCD9E8D57u * (uint64_t)x[2];
+    uint32_t y[4];
+    y[0] = (uint32_t)(prod_b >> 32) ^ x[1] ^ key[0];
+    y[1] = (uint32_t)prod_b;
+    y[2] = (uint32_t)(prod_a >> 32) ^ x[3] ^ key[1];
+    y[3] = (uint32_t)prod_a;
+    memcpy(x, y, sizeof y);
+}
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t x[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t key[2] = {key_in[0], key_in[1]};
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { /* Weyl key schedule between rounds */
+            key[0] += 0x9E3779B9u;
+            key[1] += 0xBB67AE85u;
+        }
+        philox_round(x, key);
+    }
+    memcpy(out, x, sizeof x);
+}
+
+uint64_t orc_word(uint64_t seed, uint64_t inst, uint64_t c)
+{
+    const uint64_t block = c / 2;
+    const uint32_t ctr[4] = {(uint32_t)block, (uint32_t)(block >> 32), (uint32_t)inst,
+                             (uint32_t)(inst >> 32)};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    if (c % 2 == 0) return (uint64_t)x[0] | ((uint64_t)x[1] << 32);
+    return (uint64_t)x[2] | ((uint64_t)x[3] << 32);
+}
+
+/* ------------------------------------------------------------------ */
+/* Theorem 1 at word width L (1..64)                                   */
+/* ------------------------------------------------------------------ */
+
+/* (a_i, r_i) <- b_i (x) r_{i-1}, i = 1..k: a_i takes the high L bits and
+ * r_i the low L bits of the 2L-bit product. Returns r_k. */
+uint64_t orc_chain(unsigned L, const uint64_t *b, unsigned k, uint64_t r0, uint64_t *a)
+{
+    const u128 two_L = (u128)1 << L;
+    u128 r = r0;
+    for (unsigned i = 0; i < k; ++i) {
+        const u128 product = (u128)b[i] * r; /* b < 2^64, r < 2^64: exact */
+        a[i] = (uint64_t)(product / two_L);
+        r = product % two_L;
+    }
+    return (uint64_t)r;
+}
+
+/* The bound product prod b_i as an exact integer, or an error if a bound is
+ * zero or the product exceeds 2^L (Theorem 1 requires prod b_i <= 2^L). */
+static int bound_product(unsigned L, const uint64_t *b, unsigned k, u128 *prod)
+{
+    const u128 two_L = (u128)1 << L;
+    u128 p = 1;
+    for (unsigned i = 0; i < k; ++i) {
+        if (b[i] == 0) return ORC_EINVAL;
+        if ((u128)b[i] > two_L) return ORC_EOVERFLOW;
+        p *= b[i]; /* both factors <= 2^64 here, so no 128-bit wrap */
+        if (p > two_L) return ORC_EOVERFLOW;
+    }
+    *prod = p;
+    return ORC_OK;
+}
+
+/* t = 2^L mod prod b_i (Lemire's criterion threshold of the whole batch). */
+int orc_threshold(unsigned L, const uint64_t *b, unsigned k, uint64_t *t)
+{
+    u128 prod;
+    const int err = bound_product(L, b, k, &prod);
+    if (err) return err;
+    *t = (uint64_t)((((u128)1) << L) % prod);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Dice streams: Algorithm 3 per group, groups of k consecutive bounds */
+/* ------------------------------------------------------------------ */
+
+static uint64_t ceil_div(uint64_t x, uint64_t y) { return x / y + (x % y != 0); }
+
+/* One group of dice by Algorithm 3: roll, form the exact product, and only
+ * when the leftover is below it compute the threshold and reroll. */
+static int roll_group_alg3(const uint64_t *b, unsigned k, uint64_t seed, uint64_t inst,
+                           uint64_t S, uint64_t s, uint64_t *a)
+{
+    u128 prod;
+    const int err = bound_product(64, b, k, &prod);
+    if (err) return err;
+    uint64_t attempt = 0;
+    uint64_t r = orc_chain(64, b, k, orc_word(seed, inst, attempt * S + s), a);
+    if ((u128)r < prod) {
+        const uint64_t t = (uint64_t)((((u128)1) << 64) % prod);
+        while (r < t) {
+            ++attempt;
+            r = orc_chain(64, b, k, orc_word(seed, inst, attempt * S + s), a);
+        }
+    }
+    return ORC_OK;
+}
+
+/* Group g holds bounds[g*k .. g*k+k-1]; the last group keeps count mod k
+ * bounds when that is non-zero. out[j] is the die rolled against bounds[j]. */
+int orc_dice(const uint32_t *bounds, uint32_t *out, uint64_t count, unsigned k, uint64_t seed,
+             uint64_t inst)
+{
+    if (k == 0 || k > 64) return ORC_EINVAL;
+    const uint64_t S = ceil_div(count, k);
+    int status = ORC_OK;
+    for (uint64_t s = 0; s < S; ++s) {
+        const uint64_t first = s * k;
+        const unsigned kk = (unsigned)((count - first < k) ? count - first : k);
+        uint64_t b[64], a[64];
+        for (unsigned i = 0; i < kk; ++i) b[i] = bounds[first + i];
+        const int err = roll_group_alg3(b, kk, seed, inst, S, s, a);
+        if (err) {
+            if (!status) status = err;
+            continue;
+        }
+        for (unsigned i = 0; i < kk; ++i) out[first + i] = (uint32_t)a[i];
+    }
+    return status;
+}
+
+/* Sampling with replacement from [0, bound): Algorithm 2, with the threshold
+ * of a full group and of the last short group computed once up front. */
+int orc_dice_const(uint32_t bound, uint32_t *out, uint64_t count, unsigned k, uint64_t seed,
+                   uint64_t inst)
+{
+    if (k == 0 || k > 64) return ORC_EINVAL;
+    if (bound == 0) return count ? ORC_EINVAL : ORC_OK;
+    const uint64_t S = ceil_div(count, k);
+    uint64_t b[64], a[64];
+    for (unsigned i = 0; i < k; ++i) b[i] = bound;
+    uint64_t t_full = 0, t_last = 0;
+    int err = orc_threshold(64, b, k, &t_full);
+    if (err && count >= k) return err;
+    const unsigned k_last = (unsigned)(count - (S ? (S - 1) * k : 0));
+    if (S) {
+        err = orc_threshold(64, b, k_last, &t_last);
+        if (err) return err;
+    }
+    for (uint64_t s = 0; s < S; ++s) {
+        const unsigned kk = (s + 1 == S) ? k_last : k;
+        const uint64_t t = (s + 1 == S) ? t_last : t_full;
+        uint64_t attempt = 0, r;
+        do {
+            r = orc_chain(64, b, kk, orc_word(seed, inst, attempt * S + s), a);
+            ++attempt;
+        } while (r < t);
+        for (unsigned i = 0; i < kk; ++i) out[s * k + i] = (uint32_t)a[i];
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Shuffles: Algorithm 4 batches under a batch-size schedule           */
+/* ------------------------------------------------------------------ */
+
+/* A schedule lists segments in order: while the number i of elements still
+ * to shuffle exceeds thr[s], roll batches of k[s] dice with the upper bound
+ * starting at u[s] (u[s] = 0: the exact falling factorial is the bound).
+ * If `tail` is set and i > 1 afterwards, one last batch of i-1 dice with
+ * bound u_tail finishes the shuffle. */
+typedef struct {
+    uint32_t nseg;
+    uint32_t tail;
+    uint64_t thr[16];
+    uint32_t k[16];
+    uint64_t u[16];
+    uint64_t u_tail;
+} orc_schedule;
+
+/* The paper's schedules: max_k = 6 is shuffle_6 (one die above 2^30
+ * elements, then 2/3/4/5/6 dice at or below 2^30/2^19/2^14/2^11/2^9, with
+ * bounds 2^60/2^57/2^56/2^55/2^54 and a last batch bounded by 720);
+ * max_k = 2 is "at most two dice" with the same tail rule; max_k = 1 is the
+ * unbatched shuffle. */
+int orc_schedule_paper(int max_k, orc_schedule *out)
+{
+    memset(out, 0, sizeof *out);
+    if (max_k == 1) {
+        out->nseg = 1;
+        out->thr[0] = 1;
+        out->k[0] = 1;
+        out->u[0] = 0;
+        return ORC_OK;
+    }
+    if (max_k == 2) {
+        out->nseg = 2;
+        out->thr[0] = (uint64_t)1 << 30; out->k[0] = 1; out->u[0] = 0;
+        out->thr[1] = 2;                 out->k[1] = 2; out->u[1] = (uint64_t)1 << 60;
+        out->tail = 1;
+        out->u_tail = 720;
+        return ORC_OK;
+    }
+    if (max_k == 6) {
+        const uint64_t thr[6] = {(uint64_t)1 << 30, (uint64_t)1 << 19, (uint64_t)1 << 14,
+                                 (uint64_t)1 << 11, (uint64_t)1 << 9, 6};
+        const uint64_t u[6] = {0, (uint64_t)1 << 60, (uint64_t)1 << 57, (uint64_t)1 << 56,
+                               (uint64_t)1 << 55, (uint64_t)1 << 54};
+        out->nseg = 6;
+        for (int s = 0; s < 6; ++s) {
+            out->thr[s] = thr[s];
+            out->k[s] = (uint32_t)(s + 1);
+            out->u[s] = u[s];
+        }
+        out->tail = 1;
+        out->u_tail = 720;
+        return ORC_OK;
+    }
+    return ORC_EINVAL;
+}
+
+/* n^(falling k) = n (n-1) ... (n-k+1), exact; any value above 2^64 is
+ * reported as 2^64 + 1 so that the product never wraps. */
+static u128 falling(uint64_t n, unsigned k)
+{
+    const u128 cap = ((u128)1 << 64) + 1;
+    u128 p = 1;
+    for (unsigned i = 0; i < k; ++i) {
+        p *= (u128)(n - i);
+        if (p > cap) return cap;
+    }
+    return p;
+}
+
+typedef struct {
+    /* word source: Philox (words == NULL) or an explicit attempt-major list */
+    uint64_t seed, inst;
+    const uint64_t *words;
+    uint64_t nwords;
+    uint64_t S; /* batches in this instance */
+    int exhausted;
+} word_src;
+
+static uint64_t next_word(word_src *w, uint64_t attempt, uint64_t s)
+{
+    const uint64_t c = attempt * w->S + s;
+    if (w->words) {
+        if (c >= w->nwords) {
+            w->exhausted = 1;
+            return ~(uint64_t)0;
+        }
+        return w->words[c];
+    }
+    return orc_word(w->seed, w->inst, c);
+}
+
+static void swap_elems(uint8_t *z, uint64_t p, uint64_t q, unsigned eb)
+{
+    uint8_t tmp[8];
+    memcpy(tmp, z + p * eb, eb);
+    memcpy(z + p * eb, z + q * eb, eb);
+    memcpy(z + q * eb, tmp, eb);
+}
+
+/* Algorithm 4 on the first n elements of z with k dice and upper bound u
+ * (u = 0: no bound known, use the exact product), as batch s of the
+ * instance. Returns the bound for the next batch. */
+static u128 partial_shuffle(uint8_t *z, uint64_t n, unsigned k, u128 u, unsigned eb, word_src *w,
+                            uint64_t s)
+{
+    uint64_t bounds[64], a[64];
+    for (unsigned i = 1; i <= k; ++i) bounds[i - 1] = n + 1 - i;
+    uint64_t attempt = 0;
+    uint64_t r = orc_chain(64, bounds, k, next_word(w, attempt, s), a);
+    if (u == 0 || (u128)r < u) {
+        u = falling(n, k);
+        const uint64_t t = (uint64_t)((((u128)1) << 64) % u);
+        while (r < t && !w->exhausted) {
+            ++attempt;
+            r = orc_chain(64, bounds, k, next_word(w, attempt, s), a);
+        }
+    }
+    for (unsigned i = 1; i <= k; ++i) swap_elems(z, a[i - 1], n - i, eb);
+    return u;
+}
+
+enum { RUN_COUNT = 0, RUN_CHECK = 1, RUN_EXEC = 2 };
+
+/* Walks the batches of an n-element shuffle that performs `steps`
+ * Fisher-Yates steps (steps = n-1 for a full shuffle): counts them,
+ * checks each against the requirements of Algorithm 4 (bound product at
+ * most 2^64, a non-zero upper bound at least the product it guards), or
+ * executes them on z. A batch cut short by `steps` rolls only the dice it
+ * needs. Returns the number of batches, or ~0 when a check fails (the
+ * reason in *err). */
+static uint64_t run_schedule(int mode, uint8_t *z, uint64_t n, uint64_t steps, unsigned eb,
+                             const orc_schedule *sch, word_src *w, int *err)
+{
+    const u128 two64 = (u128)1 << 64;
+    uint64_t i = n, s = 0, done = 0;
+    for (uint32_t g = 0; g < sch->nseg && done < steps; ++g) {
+        const u128 u0 = sch->u[g];
+        u128 u = u0;
+        while (i > sch->thr[g] && done < steps) {
+            unsigned k = sch->k[g];
+            if (steps - done < k) k = (unsigned)(steps - done);
+            if (mode == RUN_CHECK) {
+                const u128 p = falling(i, k);
+                if (p > two64) { *err = ORC_EOVERFLOW; return ~(uint64_t)0; }
+                if (u0 && u < p) { *err = ORC_EINVAL; return ~(uint64_t)0; }
+            }
+            if (mode == RUN_EXEC) {
+                const u128 next_u = partial_shuffle(z, i, k, u, eb, w, s);
+                if (u0) u = next_u; /* carry the bound only when one was given */
+            }
+            ++s;
+            i -= k;
+            done += k;
+        }
+    }
+    if (sch->tail && i > 1 && done < steps) {
+        unsigned k = (unsigned)(i - 1);
+        if (steps - done < k) k = (unsigned)(steps - done);
+        if (mode == RUN_CHECK) {
+            const u128 p = falling(i, k);
+            if (p > two64) { *err = ORC_EOVERFLOW; return ~(uint64_t)0; }
+            if (sch->u_tail && (u128)sch->u_tail < p) { *err = ORC_EINVAL; return ~(uint64_t)0; }
+        }
+        if (mode == RUN_EXEC) partial_shuffle(z, i, k, sch->u_tail, eb, w, s);
+        ++s;
+        done += k;
+    }
+    if (mode == RUN_CHECK && done < steps) { *err = ORC_EINVAL; return ~(uint64_t)0; }
+    return s;
+}
+
+/* Structural requirements on a schedule: 1..16 segments, non-increasing
+ * thresholds, 1 <= k <= 64, and thr >= k - 1 so that no bound reaches 0. */
+static int check_segments(const orc_schedule *sch)
+{
+    if (sch->nseg == 0 || sch->nseg > 16) return ORC_EINVAL;
+    for (uint32_t g = 0; g < sch->nseg; ++g) {
+        if (sch->k[g] == 0 || sch->k[g] > 64) return ORC_EINVAL;
+        if (sch->thr[g] + 1 < sch->k[g]) return ORC_EINVAL;
+        if (g > 0 && sch->thr[g] > sch->thr[g - 1]) return ORC_EINVAL;
+    }
+    return ORC_OK;
+}
+
+uint64_t orc_count_batches(uint64_t n, uint64_t steps, const orc_schedule *sch)
+{
+    word_src w = {0};
+    int err = 0;
+    return run_schedule(RUN_COUNT, NULL, n, steps, 8, sch, &w, &err);
+}
+
+static int shuffle_impl(void *data, uint64_t n, uint64_t steps, unsigned eb,
+                        const orc_schedule *sch, word_src *w)
+{
+    if (eb != 4 && eb != 8) return ORC_EINVAL;
+    if (n <= 1) return ORC_OK;
+    if (n > 0xFFFFFFFFull) return ORC_EINVAL;
+    int err = check_segments(sch);
+    if (err) return err;
+    if (run_schedule(RUN_CHECK, NULL, n, steps, eb, sch, w, &err) == ~(uint64_t)0) return err;
+    w->S = run_schedule(RUN_COUNT, NULL, n, steps, eb, sch, w, &err);
+    run_schedule(RUN_EXEC, (uint8_t *)data, n, steps, eb, sch, w, &err);
+    return w->exhausted ? ORC_EINVAL : ORC_OK;
+}
+
+int orc_shuffle(void *data, uint64_t n, unsigned eb, const orc_schedule *sch, uint64_t seed,
+                uint64_t inst)
+{
+    word_src w = {seed, inst, NULL, 0, 0, 0};
+    return shuffle_impl(data, n, n ? n - 1 : 0, eb, sch, &w);
+}
+
+/* The same shuffle fed from an explicit attempt-major word list
+ * (word c = words[c]); used to pin the method to hand-worked cases. */
+int orc_shuffle_words(void *data, uint64_t n, unsigned eb, const orc_schedule *sch,
+                      const uint64_t *words, uint64_t nwords)
+{
+    word_src w = {0, 0, words, nwords, 0, 0};
+    return shuffle_impl(data, n, n ? n - 1 : 0, eb, sch, &w);
+}
+
+/* Shuffle q of a CSR batch covers elements offsets[q] .. offsets[q+1]-1
+ * and uses instance inst_base + q. */
+int orc_shuffle_batched(void *data, const uint64_t *offsets, uint64_t count, unsigned eb,
+                        const orc_schedule *sch, uint64_t seed, uint64_t inst_base)
+{
+    int status = ORC_OK;
+    for (uint64_t q = 0; q < count; ++q) {
+        if (offsets[q + 1] < offsets[q]) return ORC_EINVAL;
+        const int err = orc_shuffle((uint8_t *)data + offsets[q] * eb, offsets[q + 1] - offsets[q],
+                                    eb, sch, seed, inst_base + q);
+        if (err && !status) status = err;
+    }
+    return status;
+}
+
+/* The first m steps of the scheduled shuffle, in place. */
+int orc_partial_shuffle(void *data, uint64_t n, uint64_t m, unsigned eb, const orc_schedule *sch,
+                        uint64_t seed, uint64_t inst)
+{
+    if (m > n) return ORC_EINVAL;
+    word_src w = {seed, inst, NULL, 0, 0, 0};
+    const uint64_t steps = (m < n) ? m : n - 1;
+    return shuffle_impl(data, n, steps, eb, sch, &w);
+}
+
+/* Sample m of n without replacement: out[t] = z[n-1-t] after the first m
+ * steps of the scheduled shuffle of a copy of the input. */
+int orc_sample(const void *data, uint64_t n, uint64_t m, unsigned eb, void *out,
+               const orc_schedule *sch, uint64_t seed, uint64_t inst)
+{
+    if (eb != 4 && eb != 8) return ORC_EINVAL;
+    if (m > n) return ORC_EINVAL;
+    if (m == 0) return ORC_OK;
+    uint8_t *z = (uint8_t *)malloc(n * eb);
+    if (!z) return ORC_EINVAL;
+    memcpy(z, data, n * eb);
+    const int err = orc_partial_shuffle(z, n, m, eb, sch, seed, inst);
+    if (!err)
+        for (uint64_t t = 0; t < m; ++t) memcpy((uint8_t *)out + t * eb, z + (n - 1 - t) * eb, eb);
+    free(z);
+    return err;
+}
+
+/* Number of words (Philox halves) that the first attempts of a dice stream
+ * or a shuffle consume: S. Exposed so tests can check word accounting. */
+uint64_t orc_dice_groups(uint64_t count, unsigned k) { return k ? ceil_div(count, k) : 0; }

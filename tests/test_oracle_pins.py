@@ -1,0 +1,419 @@
+"""Pins of the CPU oracle to what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (Table 1), published known answers (Philox), closed forms
+(Theorem 1's equal counts, the one-shot product), special cases that reduce
+to another routine of the paper (k = 1 is Lemire's method; Algorithms 2 and 3
+agree), invariants (permutations) and chi-square uniformity.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.stats import chi2
+
+from conftest import golden_rows
+from oracle import ref
+
+TWO64 = 1 << 64
+
+
+# ---------------------------------------------------------------------------
+# Word source
+# ---------------------------------------------------------------------------
+
+def test_philox_known_answers(orc):
+    rows = golden_rows("philox_kat.txt")
+    assert len(rows) == 3
+    for row in rows:
+        v = [int(x, 16) for x in row.split()]
+        assert orc.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_word_halves(orc):
+    # word c is half (c mod 2) of Philox block c // 2 of counter (c//2, inst)
+    seed, inst = 0x0123456789ABCDEF, 0xFEDCBA9876543210
+    for c in (0, 1, 2, 3, 1 << 33, (1 << 33) + 1):
+        blk = c // 2
+        x = orc.philox4x32_10([blk & 0xFFFFFFFF, blk >> 32, inst & 0xFFFFFFFF, inst >> 32],
+                              [seed & 0xFFFFFFFF, seed >> 32])
+        want = (x[0] | x[1] << 32) if c % 2 == 0 else (x[2] | x[3] << 32)
+        assert orc.word(seed, inst, c) == want
+
+
+# ---------------------------------------------------------------------------
+# Theorem 1
+# ---------------------------------------------------------------------------
+
+def test_table1_worked_example(orc):
+    rows = golden_rows("table1.txt")
+    assert len(rows) == 16
+    accepted = set()
+    for row in rows:
+        r0, two_r0, a1, r1, six_r1, a2, r2, rej = map(int, row.split())
+        assert two_r0 == 2 * r0 and six_r1 == 6 * r1
+        for impl in (orc.chain, ref.chain):
+            a, rk = impl(4, [2, 6], r0)
+            assert (a, rk) == ([a1, a2], r2)
+        _, r_1 = orc.chain(4, [2], r0)
+        assert r_1 == r1
+        err, t = orc.threshold(4, [2, 6])
+        assert err == 0 and t == 4
+        assert (r2 < t) == bool(rej)
+        if not rej:
+            accepted.add((a1, a2))
+    # every (coin, die) pair appears exactly once among the 12 accepted rows
+    assert accepted == {(x, y) for x in range(2) for y in range(6)}
+
+
+TUPLES = [
+    (3,), (7,), (2, 6), (3, 5, 7), (2, 3, 4, 5), (5, 5), (1, 9), (9, 1, 1), (1,),
+    (16, 16),            # product = 2^8  (t = 0 at L = 8)
+    (4, 4, 16),          # product = 2^8
+    (255,), (17, 15),    # product just below 2^8
+    (11, 13, 17), (64, 64, 16), (6, 10, 15, 21),
+]
+
+
+@pytest.mark.parametrize("L", [8, 12, 16])
+def test_theorem1_exhaustive(orc, L):
+    """Every L-bit word: each accepted digit tuple occurs floor(2^L/b) times
+    and exactly 2^L mod b words are rejected (Theorem 1 with Lemma 1)."""
+    for bounds in TUPLES:
+        b = math.prod(bounds)
+        if b > (1 << L):
+            continue
+        err, t = orc.threshold(L, bounds)
+        assert err == 0 and t == (1 << L) % b
+        counts = {}
+        rejects = 0
+        for r0 in range(1 << L):
+            a, rk = orc.chain(L, bounds, r0)
+            assert all(0 <= ai < bi for ai, bi in zip(a, bounds))
+            if rk >= t:
+                counts[tuple(a)] = counts.get(tuple(a), 0) + 1
+            else:
+                rejects += 1
+        assert rejects == (1 << L) % b
+        assert len(counts) == b
+        assert set(counts.values()) == {(1 << L) // b}
+        if L <= 12:  # the big-integer reference agrees word for word
+            rc, rr = ref.enumerate_all(L, list(bounds))
+            assert rr == rejects and dict(rc) == counts
+
+
+def test_chain_equals_one_shot_product_L64(orc):
+    """(prod b) (x) r0 = (a, r_k) with a the mixed-radix value of the digits
+    (the claim inside the proof of Theorem 1), at L = 64."""
+    rng = np.random.default_rng(2408)
+    for _ in range(400):
+        k = int(rng.integers(1, 9))
+        bounds = [int(x) for x in rng.integers(1, 1 << int(rng.integers(1, 33)), size=k)]
+        if math.prod(bounds) > TWO64:
+            continue
+        r0 = int(rng.integers(0, TWO64, dtype=np.uint64))
+        a, rk = orc.chain(64, bounds, r0)
+        value, low = divmod(math.prod(bounds) * r0, TWO64)
+        assert rk == low
+        assert ref.mixed_radix(a, bounds) == value
+        assert ref.digits(value, bounds) == a
+    # a 64-bit bound (one die covering most of the word)
+    a, rk = orc.chain(64, [TWO64 - 59], TWO64 - 1)
+    assert (a[0], rk) == divmod((TWO64 - 59) * (TWO64 - 1), TWO64)
+
+
+def test_threshold_L64(orc):
+    for bounds in ([1], [2], [3], [6], [2**32 - 1, 2**32 - 1], [2**31, 2**31, 4], [TWO64 - 1],
+                   [10**9, 10**9, 18]):
+        err, t = orc.threshold(64, bounds)
+        assert err == 0 and t == TWO64 % math.prod(bounds)
+    assert orc.threshold(64, [2**32, 2**32, 2])[0] == 2   # product 2^65
+    assert orc.threshold(64, [3, 0])[0] == 1              # zero bound
+
+
+# ---------------------------------------------------------------------------
+# Dice streams (Algorithms 2 and 3)
+# ---------------------------------------------------------------------------
+
+def _stream_words(orc, seed, inst, S, g):
+    a = 0
+    while True:
+        yield orc.word(seed, inst, a * S + g)
+        a += 1
+
+
+def test_k1_dice_is_lemire(orc):
+    """With one die per word the batched stream is Lemire's method (Sec. 2)."""
+    rng = np.random.default_rng(5)
+    bounds = np.concatenate([
+        rng.integers(1, 1 << 32, size=300, dtype=np.uint64),
+        rng.integers(1, 7, size=100, dtype=np.uint64),
+        np.array([1, 2, 2**31, 2**31 + 1, 2**32 - 1], dtype=np.uint64)]).astype(np.uint32)
+    err, out = orc.dice(bounds, 1, seed=99, inst=3)
+    assert err == 0
+    S = bounds.size
+    for g, b in enumerate(bounds):
+        x, _ = ref.lemire(64, int(b), _stream_words(orc, 99, 3, S, g))
+        assert out[g] == x
+
+
+def test_rejection_heavy_groups(orc):
+    """Pairs (2^31+1, 2^32-1) have product 2^63 + 2^31 - 1, so about half of
+    all words are rejected; every group must still follow Theorem 1 with the
+    rerolls reading words a*S + g."""
+    count = 400
+    bounds = np.tile(np.array([2**31 + 1, 2**32 - 1], dtype=np.uint32), count // 2)
+    err, out = orc.dice(bounds, 2, seed=1, inst=0)
+    assert err == 0
+    S = count // 2
+    rerolled = 0
+    for g in range(S):
+        b = [2**31 + 1, 2**32 - 1]
+        for att, r0 in enumerate(_stream_words(orc, 1, 0, S, g)):
+            a, rk = ref.chain(64, b, r0)
+            if rk >= TWO64 % (b[0] * b[1]):
+                break
+        rerolled += att > 0
+        assert list(out[2 * g:2 * g + 2]) == a
+    assert rerolled > S // 4
+
+
+@pytest.mark.parametrize("k,bits", [(2, 32), (3, 21), (4, 16), (7, 9)])
+def test_dice_groups_follow_theorem1(orc, k, bits):
+    rng = np.random.default_rng(k)
+    count = 1000 + k - 1  # last group short when k does not divide the count
+    bounds = rng.integers(1, 1 << bits, size=count, dtype=np.uint64).astype(np.uint32)
+    err, out = orc.dice(bounds, k, seed=7, inst=11)
+    assert err == 0
+    S = -(-count // k)
+    for g in range(S):
+        b = [int(x) for x in bounds[g * k:(g + 1) * k]]
+        for r0 in _stream_words(orc, 7, 11, S, g):
+            a, rk = ref.chain(64, b, r0)
+            if ref.accept(64, b, rk):
+                break
+        assert list(out[g * k:g * k + len(b)]) == a
+    assert np.all(out < bounds)
+
+
+@pytest.mark.parametrize("bound,k,count", [(6, 4, 1001), (2**16 - 1, 4, 999), (2**31 + 1, 2, 500),
+                                           (1, 3, 10), (2**32 - 1, 1, 300)])
+def test_alg2_equals_alg3(orc, bound, k, count):
+    """Known threshold (Algorithm 2) and unknown threshold (Algorithm 3)
+    produce the same dice from the same words."""
+    e1, a = orc.dice_const(bound, count, k, seed=5, inst=2)
+    e2, b = orc.dice(np.full(count, bound, dtype=np.uint32), k, seed=5, inst=2)
+    assert e1 == e2 == 0
+    assert np.array_equal(a, b)
+
+
+def test_dice_edge_cases(orc):
+    # bound product exactly 2^64: threshold 0, every word accepted first time
+    bounds = np.array([2**31, 2**31, 4], dtype=np.uint32)
+    err, out = orc.dice(bounds, 3, seed=3, inst=0)
+    assert err == 0
+    a, _ = ref.chain(64, [2**31, 2**31, 4], orc.word(3, 0, 0))
+    assert list(out) == a
+    # product above 2^64
+    assert orc.dice(np.array([2**32 - 1] * 3, dtype=np.uint32), 3, 1, 0)[0] == 2
+    # zero bound
+    assert orc.dice(np.array([5, 0, 7, 9], dtype=np.uint32), 2, 1, 0)[0] == 1
+    # empty stream
+    err, out = orc.dice(np.zeros(0, dtype=np.uint32), 4, 1, 0)
+    assert err == 0 and out.size == 0
+
+
+def test_dice_uniform_chi2(orc):
+    """Digits of a k = 4 stream of 6-sided dice are uniform (chi-square)."""
+    count = 400_000
+    err, out = orc.dice_const(6, count, 4, seed=13, inst=0)
+    assert err == 0
+    hist = np.bincount(out, minlength=6)
+    stat = float(((hist - count / 6) ** 2 / (count / 6)).sum())
+    assert stat < chi2.ppf(1 - 1e-3, 5)
+
+
+# ---------------------------------------------------------------------------
+# Shuffles (Algorithm 4 under the paper's schedules)
+# ---------------------------------------------------------------------------
+
+def test_s6_batch_counts(orc):
+    s6 = orc.schedule_paper(6)
+    for row in golden_rows("s6_batches.txt"):
+        n, batches = map(int, row.split()[:2])
+        assert orc.count_batches(n, n - 1, s6) == batches
+
+
+def test_paper_schedules(orc):
+    s6 = orc.schedule_paper(6)
+    assert s6.segments() == [(2**30, 1, 0), (2**19, 2, 2**60), (2**14, 3, 2**57), (2**11, 4, 2**56),
+                             (2**9, 5, 2**55), (6, 6, 2**54)]
+    assert s6.tail == 1 and s6.u_tail == 720
+    s1 = orc.schedule_paper(1)
+    assert orc.count_batches(1000, 999, s1) == 999
+
+
+def test_worked_shuffles(orc):
+    for row in golden_rows("worked_shuffles.txt"):
+        head, words, result = [p.split() for p in row.split("|")]
+        sched = orc.schedule_paper(6 if head[0] == "s6" else 1)
+        n = int(head[1])
+        z = np.arange(n, dtype=np.uint64)
+        assert orc.shuffle_words(z, sched, [int(w, 16) for w in words]) == 0
+        assert list(z) == [int(x) for x in result], row
+
+
+@pytest.mark.parametrize("max_k", [1, 2, 6])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_shuffle_is_permutation(orc, max_k, dtype):
+    sched = orc.schedule_paper(max_k)
+    for n in (0, 1, 2, 3, 5, 6, 7, 13, 256, 1000, 10000):
+        z = np.arange(n, dtype=dtype)
+        assert orc.shuffle(z, sched, seed=42, inst=n) == 0
+        assert np.array_equal(np.sort(z), np.arange(n, dtype=dtype))
+        if n >= 13:
+            assert not np.array_equal(z, np.arange(n, dtype=dtype))
+
+
+def _dice_for_shuffle(orc, n, sched, seed, inst):
+    """Dice of the scheduled shuffle by the big-integer chain: returns the
+    sequence j_{n-1}, ..., j_1 that Algorithm 1 consumes."""
+    segs = sched.segments()
+    batches = []
+    i = n
+    for thr, k, _ in segs:
+        while i > thr:
+            batches.append((i, k))
+            i -= k
+    if sched.tail and i > 1:
+        batches.append((i, i - 1))
+    S = len(batches)
+    js = []
+    for s, (i, k) in enumerate(batches):
+        bounds = [i - l for l in range(k)]
+        att = 0
+        while True:
+            a, rk = ref.chain(64, bounds, orc.word(seed, inst, att * S + s))
+            if ref.accept(64, bounds, rk):
+                break
+            att += 1
+        js.extend(a)
+    return js
+
+
+@pytest.mark.parametrize("max_k,n", [(1, 50), (2, 77), (6, 300), (6, 10000)])
+def test_shuffle_is_fisher_yates(orc, max_k, n):
+    """The batched shuffle is Algorithm 1 driven by the batch digits: digit
+    a_i of the batch at size i serves step i-1, a_2 step i-2, and so on."""
+    sched = orc.schedule_paper(max_k)
+    z = np.arange(n, dtype=np.uint32)
+    assert orc.shuffle(z, sched, seed=17, inst=4) == 0
+    js = _dice_for_shuffle(orc, n, sched, 17, 4)
+    assert list(z) == ref.fisher_yates(range(n), js)
+
+
+def test_k1_shuffle_is_lemire_fisher_yates(orc):
+    """Unbatched: step i rolls Lemire's method with bound i+1 (Sec. 2)."""
+    n = 200
+    sched = orc.schedule_paper(1)
+    z = np.arange(n, dtype=np.uint64)
+    assert orc.shuffle(z, sched, seed=8, inst=1) == 0
+    S = n - 1
+    js = [ref.lemire(64, i + 1, _stream_words(orc, 8, 1, S, s))[0]
+          for s, i in enumerate(range(n - 1, 0, -1))]
+    assert list(z) == ref.fisher_yates(range(n), js)
+
+
+def test_upper_bound_never_changes_output(orc):
+    """The bound u of Algorithm 4 only saves work: with every guard replaced
+    by the exact product the output is identical."""
+    s6 = orc.schedule_paper(6)
+    exact = orc.Schedule.from_segments([(t, k, 0) for t, k, _ in s6.segments()], tail=True, u_tail=0)
+    for n in (7, 100, 3000, 40000):
+        a = np.arange(n, dtype=np.uint32)
+        b = a.copy()
+        assert orc.shuffle(a, s6, 9, n) == 0
+        assert orc.shuffle(b, exact, 9, n) == 0
+        assert np.array_equal(a, b)
+
+
+def test_bad_schedules_rejected(orc):
+    z = np.arange(100, dtype=np.uint32)
+    # product of 20 dice at n = 100 exceeds 2^64
+    bad = orc.Schedule.from_segments([(19, 20, 0)], tail=True, u_tail=0)
+    assert orc.shuffle(z, bad, 1, 0) == 2
+    # an upper bound smaller than the product it guards
+    bad = orc.Schedule.from_segments([(6, 6, 1000)], tail=True, u_tail=720)
+    assert orc.shuffle(z, bad, 1, 0) == 1
+    # no tail and a last threshold above 1 leaves elements unshuffled
+    bad = orc.Schedule.from_segments([(6, 6, 2**54)], tail=False)
+    assert orc.shuffle(z, bad, 1, 0) == 1
+
+
+def _perm_index4(rows):
+    # lexicographic rank of each length-4 permutation row
+    idx = np.zeros(rows.shape[0], dtype=np.int64)
+    fact = [6, 2, 1, 1]
+    for p in range(4):
+        smaller = (rows[:, p + 1:] < rows[:, p:p + 1]).sum(axis=1)
+        idx += smaller * fact[p]
+    return idx
+
+
+@pytest.mark.parametrize("max_k", [6, 1])
+def test_chi2_all_24_permutations(orc, max_k):
+    """10^7 shuffles of n = 4 (instances 0..10^7-1, seed 42): all 24
+    permutations appear, chi-square with 23 dof at alpha = 1e-3."""
+    trials = 10_000_000
+    data = np.tile(np.arange(4, dtype=np.uint32), trials)
+    offsets = np.arange(0, 4 * trials + 1, 4, dtype=np.uint64)
+    assert orc.shuffle_batched(data, offsets, orc.schedule_paper(max_k), seed=42) == 0
+    hist = np.bincount(_perm_index4(data.reshape(trials, 4)), minlength=24)
+    assert hist.size == 24 and hist.min() > 0
+    expected = trials / 24
+    stat = float(((hist - expected) ** 2 / expected).sum())
+    assert stat < chi2.ppf(1 - 1e-3, 23), stat
+
+
+# ---------------------------------------------------------------------------
+# Sampling without replacement (partial Fisher-Yates)
+# ---------------------------------------------------------------------------
+
+def test_sample_is_partial_shuffle_tail(orc):
+    s6 = orc.schedule_paper(6)
+    rng = np.random.default_rng(1)
+    for n, m in ((10, 3), (1000, 100), (5000, 1), (70000, 7000), (12, 12), (12, 11), (9, 0)):
+        data = rng.integers(0, 2**63, size=n, dtype=np.uint64)
+        err, out = orc.sample(data, m, s6, seed=4, inst=n)
+        assert err == 0
+        z = data.copy()
+        assert orc.partial_shuffle(z, m, s6, seed=4, inst=n) == 0
+        assert np.array_equal(out, z[::-1][:m])
+        assert len(set(out.tolist())) == m
+
+
+def test_sample_of_n_minus_1_is_full_shuffle(orc):
+    s6 = orc.schedule_paper(6)
+    for n in (5, 64, 999):
+        data = np.arange(n, dtype=np.uint32)
+        err, out = orc.sample(data, n - 1, s6, seed=6, inst=0)
+        full = data.copy()
+        assert orc.shuffle(full, s6, seed=6, inst=0) == 0
+        assert err == 0 and np.array_equal(out, full[::-1][:n - 1])
+
+
+def test_sample_chi2_ordered_pairs(orc):
+    """Ordered 2-samples of n = 5: all 20 outcomes equally likely."""
+    s6 = orc.schedule_paper(6)
+    data = np.arange(5, dtype=np.uint32)
+    trials = 200_000
+    hist = np.zeros(25, dtype=np.int64)
+    for inst in range(trials):
+        err, out = orc.sample(data, 2, s6, seed=77, inst=inst)
+        hist[int(out[0]) * 5 + int(out[1])] += 1
+    diag = hist.reshape(5, 5).diagonal()
+    assert diag.sum() == 0
+    cells = hist[hist > 0]
+    assert cells.size == 20
+    stat = float(((cells - trials / 20) ** 2 / (trials / 20)).sum())
+    assert stat < chi2.ppf(1 - 1e-3, 19)
