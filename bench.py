@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched dice-roll hot path on one MI355X.
+
+The timed step is one pass of the flat dice stream: 2^28 u32 bounds uniform
+in [1, 2^16) (seed 7) rolled k = 4 per 64-bit word (brr_dice, Theorem 1 chain
++ Algorithm 3 acceptance), inputs resident in HBM. The same stream at k = 1
+(the single-roll multiply-and-reject form) is timed beside it. Secondary
+workloads report shuffled elements per second: 65,536 shuffles of 256
+elements, 20,000 ragged shuffles, one 10,000-element shuffle and one
+2^26-element shuffle, each batched (shuffle_6) and unbatched (k = 1).
+
+Prints one JSON line. Timing: HIP events recorded on the stream the kernels
+are launched on (torch's current stream), K steps after W warmup steps.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+COUNT = 1 << 28
+BYTES_PER_ROLL = 8  # 4 B bound read + 4 B die written
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("dice.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2408_06213_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(k):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current dice kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "dice_stream_2p28_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    ent = rec.get("per_k", {}).get(str(k))
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def time_launches(fn, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per step
+
+
+def secondary(brr, workloads, up, steps):
+    import numpy as np
+
+    out = {}
+    s6 = brr.brr_schedule_paper(6)
+    s1 = brr.brr_schedule_paper(1)
+
+    def batched(sizes, tag):
+        off = workloads.csr_offsets(sizes)
+        data = workloads.iota_segments(sizes)
+        d, d_off = up(data), up(off)
+        res = {}
+        for name, sched in (("k6", s6), ("k1", s1)):
+            plan = brr.Plan(off, 4, sched)
+            f = lambda: brr.check(brr.brr_shuffle_batched(d, d_off, sizes.size, 4, plan, 1, 0))
+            ms = time_launches(f, steps, 2)
+            res[name] = {"ms": ms, "elems_per_s": data.size / (ms * 1e-3)}
+            plan.close()
+        res["speedup_k6_vs_k1"] = res["k1"]["ms"] / res["k6"]["ms"]
+        res["hbm_frac_k6"] = 2 * 4 * data.size / (res["k6"]["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS
+        out[tag] = res
+
+    batched(np.full(65536, 256, dtype=np.uint64), "equal_65536x256_u32")
+    batched(workloads.ragged_sizes(20000, seed=3), "ragged_20000_u32")
+
+    for n, tag in ((10000, "single_10000_u32"), (1 << 26, "single_2p26_u32")):
+        a = up(np.arange(n, dtype=np.uint32))
+        res = {}
+        for name, sched in (("k6", s6), ("k1", s1)):
+            f = lambda: brr.check(brr.brr_shuffle(a, n, 4, sched, 42, 0))
+            ms = time_launches(f, max(3, steps // 2), 1)
+            res[name] = {"ms": ms, "elems_per_s": n / (ms * 1e-3)}
+        res["speedup_k6_vs_k1"] = res["k1"]["ms"] / res["k6"]["ms"]
+        out[tag] = res
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--k", type=int, default=4, help="dice per word of the timed stream")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the batched dice and shuffle kernels have no multi-GPU path in this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2408_06213_amd import brr, workloads
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    def up(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    bounds_np = workloads.dice_bounds(COUNT, seed=7)
+    bounds = up(bounds_np)
+    out = torch.empty(COUNT, dtype=torch.uint32, device=dev)
+
+    def step(k):
+        return lambda: brr.check(brr.brr_dice(bounds, out, COUNT, k, 7, 0), "brr_dice")
+
+    ms = time_launches(step(args.k), args.steps, args.warmup)
+    brr.check(brr.brr_sync_status(), "device status")
+    ms_k = {}
+    for k in (1, 2, 3, 4):
+        ms_k[k] = ms if k == args.k else time_launches(step(k), max(5, args.steps // 2), 2)
+    value = COUNT / (ms * 1e-3)
+    achieved = BYTES_PER_ROLL * COUNT / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.k)
+
+    rec = {
+        "metric": "dice rolls/s and shuffled elems/s, batched vs k=1 on GPU, bit-exact; % roofline",
+        "value": value,
+        "unit": "rolls/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"flat dice stream: 2^28 u32 bounds uniform in [1,2^16) (seed 7), "
+                        f"k={args.k} dice per 64-bit Philox4x32-10 word",
+            "count": COUNT,
+            "k": args.k,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": traffic,
+        },
+        "k_sweep": {str(k): {"ms": v, "rolls_per_s": COUNT / (v * 1e-3),
+                             "hbm_frac": BYTES_PER_ROLL * COUNT / (v * 1e-3) / 1e9 / PEAK_HBM_GBS}
+                    for k, v in ms_k.items()},
+        "speedup_vs_k1": ms_k[1] / ms,
+    }
+    del out, bounds
+    torch.cuda.empty_cache()
+
+    if not args.no_secondary:
+        rec["secondary"] = secondary(brr, workloads, up, max(5, args.steps // 2))
+
+    if not args.no_cpu_baseline:
+        import oracle
+
+        t0 = time.perf_counter()
+        err, _ = oracle.dice(bounds_np, args.k, 7, 0)
+        dt = time.perf_counter() - t0
+        assert err == 0
+        rec["cpu_baseline"] = {
+            "value": COUNT / dt,
+            "unit": "rolls/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"the whole 2^28-roll stream at k={args.k}, plain C oracle, one thread "
+                      f"({dt:.1f} s)",
+        }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

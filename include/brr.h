@@ -1,0 +1,198 @@
+/*
+ * brr.h -- C ABI of libbrr, batched ranged random integers on MI355X (gfx950).
+ *
+ * The operations follow Brackett-Rozinsky and Lemire, "Batched Ranged Random
+ * Integer Generation": several bounded integers a_i in [0, b_i) are taken
+ * from one 64-bit random word r by the multiply chain of Theorem 1,
+ * (a_i, r) <- b_i (x) r for i = 1..k, and the batch is accepted when the
+ * leftover satisfies r >= 2^64 mod (b_1 ... b_k) (Lemire's criterion on the
+ * bound product; Algorithms 2 and 3, Sec. 5); otherwise it is rolled again.
+ * Shuffles apply Algorithm 4 (Sec. 6) batch by batch.
+ *
+ * Word source and addressing (not fixed by the paper; identical in every
+ * entry point): word c of instance `inst` under `seed` is one 64-bit half of
+ * Philox4x32-10 with key (lo32 seed, hi32 seed) and counter
+ * (lo32 c/2, hi32 c/2, lo32 inst, hi32 inst); even c is x0 | x1 << 32, odd c
+ * is x2 | x3 << 32. Attempt a (0 = first) of group/batch s of an instance
+ * with S groups/batches reads word c = a*S + s. Results are therefore a pure
+ * function of (inputs, seed, inst, schedule), independent of launch shape.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are device pointers (HIP device memory, 16-byte
+ *    aligned for full speed; other alignments take a slower path). Pointers
+ *    named h_* and struct pointers are host pointers read during the call.
+ *  - The caller owns every buffer. The library keeps no pointer after a call
+ *    returns, except that a brr_plan remembers the last buffers it was bound
+ *    to (it is re-bound on each call).
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *    null stream). Host-checkable errors return at once with nothing
+ *    enqueued. Errors only the device can see (a zero bound, a bound product
+ *    above 2^64 in a dice stream) are recorded in a per-device status word
+ *    that brr_sync_status() returns; the affected outputs are unspecified.
+ *  - Thread safety: calls may come from several host threads; work on one
+ *    stream is ordered, work on different streams may overlap.
+ */
+#ifndef BRR_H
+#define BRR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BRR_OK = 0,
+    BRR_EINVAL = 1,    /* bad argument: null pointer, k = 0, zero bound, m > n, bad schedule */
+    BRR_EOVERFLOW = 2, /* a bound product above 2^64 (Theorem 1 needs prod b_i <= 2^64) */
+    BRR_ENOMEM = 3,    /* the library could not allocate device scratch memory */
+    BRR_EHIP = 4,      /* a HIP runtime call failed */
+    BRR_EDEVICE = 5    /* no usable gfx950 device */
+} brr_status;
+
+/* ------------------------------------------------------------------------ */
+/* Batch-size schedules (Sec. 6 full-shuffle procedure, Sec. 6.1 batch sizes) */
+/* ------------------------------------------------------------------------ */
+
+#define BRR_MAX_STEPS 16
+#define BRR_MAX_K 20 /* 21 dice never fit: 21! > 2^64 */
+
+/* While more than n_above elements remain to be shuffled, roll batches of k
+ * dice; u0 is the initial upper bound on the batch's bound product (Algorithm
+ * 4's u; 0 = none known, compare against the exact product). A schedule's
+ * upper bounds only decide how often the exact product is formed; they never
+ * change an output. */
+typedef struct {
+    uint64_t n_above;
+    uint32_t k;
+    uint32_t reserved;
+    uint64_t u0;
+} brr_step;
+
+/* Steps run in order with non-increasing n_above. With tail = 1, when more
+ * than one element remains after the last step, one batch of (i - 1) dice
+ * bounded by u_tail finishes the shuffle (the last batch of Sec. 6). */
+typedef struct {
+    uint32_t nsteps;
+    uint32_t tail;
+    uint64_t u_tail;
+    brr_step step[BRR_MAX_STEPS];
+} brr_schedule;
+
+/* Fills *out with one of the paper's schedules (Sec. 7, Appendix A):
+ * max_k = 6: shuffle_6 -- one die above 2^30 elements, then batches of 2, 3,
+ *            4, 5, 6 dice at or below 2^30, 2^19, 2^14, 2^11, 2^9 elements
+ *            with bounds 2^60, 2^57, 2^56, 2^55, 2^54, and a last batch of at
+ *            most 5 dice bounded by 720;
+ * max_k = 2: at most two dice (one die above 2^30, pairs bounded by 2^60,
+ *            the same last-batch rule);
+ * max_k = 1: the unbatched shuffle, one die per word.
+ * Returns BRR_EINVAL for any other max_k or a null out. */
+brr_status brr_schedule_paper(int max_k, brr_schedule *out);
+
+/* Number of batches (= words on first attempts) of an n-element shuffle that
+ * performs `steps` Fisher-Yates steps (steps = n - 1 for a full shuffle).
+ * Returns 0 for an invalid schedule. */
+uint64_t brr_schedule_batches(const brr_schedule *sched, uint64_t n, uint64_t steps);
+
+/* Checks a schedule for an n-element shuffle: every batch's bound product at
+ * most 2^64, every non-zero upper bound at least the product it guards, no
+ * element left unshuffled. BRR_OK, BRR_EINVAL or BRR_EOVERFLOW. */
+brr_status brr_schedule_check(const brr_schedule *sched, uint64_t n);
+
+/* ------------------------------------------------------------------------ */
+/* Dice streams (Theorem 1; Algorithm 3 per group, Algorithm 2 for a constant) */
+/* ------------------------------------------------------------------------ */
+
+/* out[j] is uniform in [0, bounds[j]), j < count. Bounds are grouped k at a
+ * time (group s = bounds[s*k .. s*k+k-1]; the last group keeps count mod k
+ * bounds when non-zero) and each group is rolled from one word, b_1 applied
+ * first (a_1 most significant digit). 1 <= k <= 8.
+ * d_bounds: u32[count], read only. d_out: u32[count], written; must not
+ * overlap d_bounds. A zero bound or a group product above 2^64 is reported
+ * by brr_sync_status (BRR_EINVAL / BRR_EOVERFLOW). */
+brr_status brr_dice(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
+                    uint64_t seed, uint64_t inst, void *stream);
+
+/* Sampling with replacement: out[j] uniform in [0, bound), k dice per word,
+ * the threshold 2^64 mod bound^k computed once (Algorithm 2). Produces
+ * exactly what brr_dice produces for a constant bounds array. bound >= 1,
+ * 1 <= k <= 8, bound^k <= 2^64 (else BRR_EOVERFLOW). */
+brr_status brr_dice_const(uint32_t bound, uint32_t *d_out, uint64_t count, uint32_t k,
+                          uint64_t seed, uint64_t inst, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Shuffles (Algorithm 1 driven by Algorithm 4 batches)                     */
+/* ------------------------------------------------------------------------ */
+
+/* Shuffles d_data[0..n-1] in place. elem_bytes is 4 or 8. sched = NULL uses
+ * shuffle_6. The result is the permutation that the sequential batched
+ * Fisher-Yates shuffle produces: batch at size i rolls bounds i, i-1, ...,
+ * i-k+1 and swaps z[i-1] with z[a_1] first. n <= 1 is a no-op;
+ * n < 2^32. Large n allocates device scratch (about 24 bytes per element)
+ * on first use; it is cached per device and reused. */
+brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_schedule *sched,
+                       uint64_t seed, uint64_t inst, void *stream);
+
+/* A plan for a batch of shuffles given in CSR form: shuffle q covers
+ * elements offsets[q] .. offsets[q+1]-1 of one array and uses instance
+ * inst_base + q. The plan sorts the shuffles into size classes (one lane,
+ * one wavefront, one workgroup, or device-wide per shuffle), owns the device
+ * copies of that classification, any scratch it needs, and a hip graph of
+ * the launch sequence. h_offsets: host u64[count + 1], non-decreasing,
+ * offsets[0] = 0. sched = NULL uses shuffle_6; it is copied. */
+typedef struct brr_plan brr_plan;
+brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t count,
+                           uint32_t elem_bytes, const brr_schedule *sched);
+void brr_plan_destroy(brr_plan *plan);
+
+/* Plan knobs for the size-class mapping; brr_plan_create uses defaults that
+ * brr_plan_set_mapping may replace before the first run. lane_max: shuffles
+ * with n <= lane_max run one per lane; wave_max: n <= wave_max one per
+ * wavefront; larger shuffles one per workgroup of wg_threads threads while
+ * they fit in LDS, else with device scratch. use_graph: 1 = capture the
+ * launch sequence once and replay it as a hip graph. */
+typedef struct {
+    uint32_t lane_max;
+    uint32_t wave_max;
+    uint32_t wg_threads;
+    uint32_t use_graph;
+} brr_mapping;
+brr_status brr_plan_get_mapping(const brr_plan *plan, brr_mapping *out);
+brr_status brr_plan_set_mapping(brr_plan *plan, const brr_mapping *m);
+
+/* Shuffles every array of the batch in place, as brr_shuffle would with
+ * inst = inst_base + q. d_offsets: device copy of the plan's offsets (the
+ * plan checks nothing on the device side; they must match). plan = NULL
+ * builds a temporary plan from a synchronous copy of d_offsets. */
+brr_status brr_shuffle_batched(void *d_data, const uint64_t *d_offsets, uint64_t count,
+                               uint32_t elem_bytes, brr_plan *plan, uint64_t seed,
+                               uint64_t inst_base, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Sampling without replacement (partial Fisher-Yates, Algorithm 4 Ensure)  */
+/* ------------------------------------------------------------------------ */
+
+/* d_out[t] = z[n-1-t], t < m, where z is d_data after the first m steps of
+ * the scheduled shuffle of d_data (the last batch cut to the dice needed).
+ * d_data is not modified. m <= n, elem_bytes 4 or 8, n < 2^32. */
+brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_bytes, void *d_out,
+                      const brr_schedule *sched, uint64_t seed, uint64_t inst, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Status                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Waits for `stream`, then returns and clears the first device-detected
+ * error of the current device (BRR_OK if none). */
+brr_status brr_sync_status(void *stream);
+
+/* Static description of a status code. */
+const char *brr_strerror(brr_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BRR_H */

@@ -80,6 +80,8 @@ def lib():
         L.orc_threshold.restype = ctypes.c_int
         L.orc_dice.argtypes = [p, p, u64, ctypes.c_uint, u64, u64]
         L.orc_dice.restype = ctypes.c_int
+        L.orc_dice_group.argtypes = [p, ctypes.c_uint, u64, u64, u64, u64, p]
+        L.orc_dice_group.restype = ctypes.c_int
         L.orc_dice_const.argtypes = [u32, p, u64, ctypes.c_uint, u64, u64]
         L.orc_dice_const.restype = ctypes.c_int
         L.orc_schedule_paper.argtypes = [ctypes.c_int, ctypes.POINTER(Schedule)]
@@ -139,6 +141,14 @@ def dice(bounds: np.ndarray, k: int, seed: int, inst: int = 0):
     bounds = np.ascontiguousarray(bounds, dtype=np.uint32)
     out = np.zeros(bounds.size, dtype=np.uint32)
     err = lib().orc_dice(_ptr(bounds), _ptr(out), bounds.size, k, seed, inst)
+    return err, out
+
+
+def dice_group(group_bounds, S: int, s: int, seed: int, inst: int = 0):
+    """Dice of group s (of S) alone; group_bounds are its kk bounds."""
+    b = np.ascontiguousarray(group_bounds, dtype=np.uint32)
+    out = np.zeros(b.size, dtype=np.uint32)
+    err = lib().orc_dice_group(_ptr(b), b.size, S, s, seed, inst, _ptr(out))
     return err, out
 
 

@@ -179,6 +179,21 @@ int orc_dice(const uint32_t *bounds, uint32_t *out, uint64_t count, unsigned k, 
     return status;
 }
 
+/* Group s alone of a stream with S groups (its kk bounds given): the dice
+ * that orc_dice writes for it. Lets a test check single groups of a stream
+ * too long to roll on the CPU in full. */
+int orc_dice_group(const uint32_t *group_bounds, unsigned kk, uint64_t S, uint64_t s,
+                   uint64_t seed, uint64_t inst, uint32_t *out)
+{
+    if (kk == 0 || kk > 64) return ORC_EINVAL;
+    uint64_t b[64], a[64];
+    for (unsigned i = 0; i < kk; ++i) b[i] = group_bounds[i];
+    const int err = roll_group_alg3(b, kk, seed, inst, S, s, a);
+    if (err) return err;
+    for (unsigned i = 0; i < kk; ++i) out[i] = (uint32_t)a[i];
+    return ORC_OK;
+}
+
 /* Sampling with replacement from [0, bound): Algorithm 2, with the threshold
  * of a full group and of the last short group computed once up front. */
 int orc_dice_const(uint32_t bound, uint32_t *out, uint64_t count, unsigned k, uint64_t seed,

@@ -1,0 +1,211 @@
+"""Thin ctypes binding of libbrr (include/brr.h), same names as the C ABI.
+
+Argument marshalling only: every step of every operation runs in the HIP
+kernels of libbrr.so. Device buffers are passed as torch tensors (their
+data_ptr) or as raw integer addresses; streams default to torch's current
+stream on the current device. There is no fallback: importing this module
+raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbrr.so")
+
+BRR_OK, BRR_EINVAL, BRR_EOVERFLOW, BRR_ENOMEM, BRR_EHIP, BRR_EDEVICE = range(6)
+BRR_MAX_STEPS = 16
+BRR_MAX_K = 20
+
+# every symbol include/brr.h declares
+EXPORTS = (
+    "brr_schedule_paper", "brr_schedule_batches", "brr_schedule_check", "brr_dice",
+    "brr_dice_const", "brr_shuffle", "brr_plan_create", "brr_plan_destroy",
+    "brr_plan_get_mapping", "brr_plan_set_mapping", "brr_shuffle_batched", "brr_sample",
+    "brr_sync_status", "brr_strerror",
+)
+
+
+class BrrError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {brr_strerror(status)} (status {status})")
+
+
+class brr_step(ctypes.Structure):
+    _fields_ = [("n_above", ctypes.c_uint64), ("k", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("u0", ctypes.c_uint64)]
+
+
+class brr_schedule(ctypes.Structure):
+    _fields_ = [("nsteps", ctypes.c_uint32), ("tail", ctypes.c_uint32),
+                ("u_tail", ctypes.c_uint64), ("step", brr_step * BRR_MAX_STEPS)]
+
+    def steps(self):
+        return [(int(s.n_above), int(s.k), int(s.u0)) for s in self.step[: self.nsteps]]
+
+    @classmethod
+    def from_steps(cls, steps, tail=True, u_tail=720):
+        s = cls()
+        s.nsteps = len(steps)
+        for g, (above, k, u0) in enumerate(steps):
+            s.step[g].n_above, s.step[g].k, s.step[g].u0 = above, k, u0
+        s.tail = 1 if tail else 0
+        s.u_tail = u_tail
+        return s
+
+
+class brr_mapping(ctypes.Structure):
+    _fields_ = [("lane_max", ctypes.c_uint32), ("wave_max", ctypes.c_uint32),
+                ("wg_threads", ctypes.c_uint32), ("use_graph", ctypes.c_uint32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    u64, u32, p, st = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+    sched_p = ctypes.POINTER(brr_schedule)
+    sig = {
+        "brr_schedule_paper": (st, [ctypes.c_int, sched_p]),
+        "brr_schedule_batches": (u64, [sched_p, u64, u64]),
+        "brr_schedule_check": (st, [sched_p, u64]),
+        "brr_dice": (st, [p, p, u64, u32, u64, u64, p]),
+        "brr_dice_const": (st, [u32, p, u64, u32, u64, u64, p]),
+        "brr_shuffle": (st, [p, u64, u32, sched_p, u64, u64, p]),
+        "brr_plan_create": (st, [ctypes.POINTER(p), p, u64, u32, sched_p]),
+        "brr_plan_destroy": (None, [p]),
+        "brr_plan_get_mapping": (st, [p, ctypes.POINTER(brr_mapping)]),
+        "brr_plan_set_mapping": (st, [p, ctypes.POINTER(brr_mapping)]),
+        "brr_shuffle_batched": (st, [p, p, u64, u32, p, u64, u64, p]),
+        "brr_sample": (st, [p, u64, u64, u32, p, sched_p, u64, u64, p]),
+        "brr_sync_status": (st, [p]),
+        "brr_strerror": (ctypes.c_char_p, [st]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def _addr(x):
+    """Device address of a tensor (data_ptr) or an integer address."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _sched(s):
+    return ctypes.byref(s) if s is not None else None
+
+
+def check(status: int, what: str = "brr") -> None:
+    if status != BRR_OK:
+        raise BrrError(status, what)
+
+
+def brr_strerror(status: int) -> str:
+    return lib.brr_strerror(status).decode()
+
+
+def brr_schedule_paper(max_k: int) -> brr_schedule:
+    s = brr_schedule()
+    check(lib.brr_schedule_paper(max_k, ctypes.byref(s)), "brr_schedule_paper")
+    return s
+
+
+def brr_schedule_batches(sched: brr_schedule, n: int, steps: int) -> int:
+    return int(lib.brr_schedule_batches(ctypes.byref(sched), n, steps))
+
+
+def brr_schedule_check(sched: brr_schedule, n: int) -> int:
+    return lib.brr_schedule_check(ctypes.byref(sched), n)
+
+
+def brr_dice(bounds, out, count: int, k: int, seed: int, inst: int = 0, stream=None) -> int:
+    return lib.brr_dice(_addr(bounds), _addr(out), count, k, seed, inst, _stream(stream))
+
+
+def brr_dice_const(bound: int, out, count: int, k: int, seed: int, inst: int = 0,
+                   stream=None) -> int:
+    return lib.brr_dice_const(bound, _addr(out), count, k, seed, inst, _stream(stream))
+
+
+def brr_shuffle(data, n: int, elem_bytes: int, sched=None, seed: int = 0, inst: int = 0,
+                stream=None) -> int:
+    return lib.brr_shuffle(_addr(data), n, elem_bytes, _sched(sched), seed, inst, _stream(stream))
+
+
+def brr_sample(data, n: int, m: int, elem_bytes: int, out, sched=None, seed: int = 0,
+               inst: int = 0, stream=None) -> int:
+    return lib.brr_sample(_addr(data), n, m, elem_bytes, _addr(out), _sched(sched), seed, inst,
+                          _stream(stream))
+
+
+class Plan:
+    """Owns a brr_plan* (brr_plan_create / brr_plan_destroy)."""
+
+    def __init__(self, h_offsets, elem_bytes: int, sched=None):
+        import numpy as np
+
+        off = np.ascontiguousarray(h_offsets, dtype=np.uint64)
+        self.count = off.size - 1
+        self.elem_bytes = elem_bytes
+        self.ptr = ctypes.c_void_p()
+        check(lib.brr_plan_create(ctypes.byref(self.ptr), off.ctypes.data_as(ctypes.c_void_p),
+                                  self.count, elem_bytes, _sched(sched)), "brr_plan_create")
+
+    def mapping(self) -> brr_mapping:
+        m = brr_mapping()
+        check(lib.brr_plan_get_mapping(self.ptr, ctypes.byref(m)), "brr_plan_get_mapping")
+        return m
+
+    def set_mapping(self, m: brr_mapping) -> int:
+        return lib.brr_plan_set_mapping(self.ptr, ctypes.byref(m))
+
+    def close(self):
+        if self.ptr:
+            lib.brr_plan_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def brr_plan_create(h_offsets, elem_bytes: int, sched=None) -> Plan:
+    return Plan(h_offsets, elem_bytes, sched)
+
+
+def brr_plan_destroy(plan: Plan) -> None:
+    plan.close()
+
+
+def brr_shuffle_batched(data, d_offsets, count: int, elem_bytes: int, plan=None, seed: int = 0,
+                        inst_base: int = 0, stream=None) -> int:
+    pp = plan.ptr if plan is not None else None
+    return lib.brr_shuffle_batched(_addr(data), _addr(d_offsets), count, elem_bytes, pp, seed,
+                                   inst_base, _stream(stream))
+
+
+def brr_sync_status(stream=None) -> int:
+    return lib.brr_sync_status(_stream(stream))

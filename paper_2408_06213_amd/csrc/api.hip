@@ -1,0 +1,587 @@
+// Host side of libbrr: argument checks, schedules, the per-device status
+// word, plans for batched shuffles (size classes, scratch, hip graphs) and
+// the extern "C" entry points declared in brr.h.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "brr.h"
+#include "internal.hpp"
+
+using namespace brr;
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceState {
+    bool checked = false;
+    bool ok = false;
+    uint32_t *status = nullptr;
+};
+
+std::mutex g_mu;
+DeviceState g_dev[kMaxDevices];
+
+// Checks once per device that it is a gfx950 and allocates its status word.
+brr_status device_ready(uint32_t **status_out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BRR_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState &d = g_dev[dev];
+    if (!d.checked) {
+        d.checked = true;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return BRR_EDEVICE;
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BRR_EDEVICE;
+        if (hipMalloc(reinterpret_cast<void **>(&d.status), sizeof(uint32_t)) != hipSuccess)
+            return BRR_ENOMEM;
+        if (hipMemset(d.status, 0, sizeof(uint32_t)) != hipSuccess) return BRR_EHIP;
+        if (hipDeviceSynchronize() != hipSuccess) return BRR_EHIP;
+        if (prepare_shuffle_kernels() != hipSuccess) return BRR_EHIP;
+        d.ok = true;
+    }
+    if (!d.ok) return BRR_EDEVICE;
+    if (status_out) *status_out = d.status;
+    return BRR_OK;
+}
+
+brr_status hip_status(hipError_t e) { return e == hipSuccess ? BRR_OK : BRR_EHIP; }
+
+// n^(falling k), or 2^64 + 1 for anything above 2^64.
+u128 falling(uint64_t n, uint64_t k)
+{
+    const u128 cap = ((u128)1 << 64) + 1;
+    u128 p = 1;
+    for (uint64_t l = 0; l < k; ++l) {
+        p *= (u128)(n - l);
+        if (p > cap) return cap;
+    }
+    return p;
+}
+
+const brr_schedule &paper6()
+{
+    static brr_schedule s = [] {
+        brr_schedule t;
+        brr_schedule_paper(6, &t);
+        return t;
+    }();
+    return s;
+}
+
+// Walks the batches of the first `steps` steps of an n-element shuffle one
+// segment at a time. With check set, verifies that the first (largest)
+// batch of every segment has a product of at most 2^64 and that a given
+// upper bound covers it. Returns the number of batches, or sets *err.
+uint64_t walk_schedule(const brr_schedule &sc, uint64_t n, uint64_t steps, bool check,
+                       brr_status *err)
+{
+    const u128 two64 = (u128)1 << 64;
+    uint64_t i = n, s = 0, done = 0;
+    for (uint32_t g = 0; g < sc.nsteps && done < steps; ++g) {
+        const uint64_t thr = sc.step[g].n_above, k = sc.step[g].k;
+        if (i <= thr) continue;
+        const uint64_t cnt = (i - thr + k - 1) / k;
+        const uint64_t left = steps - done;
+        const uint64_t first_k = std::min<uint64_t>(k, left);
+        if (check) {
+            const u128 p = falling(i, first_k);
+            if (p > two64) { *err = BRR_EOVERFLOW; return 0; }
+            if (sc.step[g].u0 && (u128)sc.step[g].u0 < p) { *err = BRR_EINVAL; return 0; }
+        }
+        uint64_t nb = cnt;
+        if (nb * k > left) nb = left / k;
+        s += nb;
+        i -= nb * k;
+        done += nb * k;
+        if (nb < cnt && done < steps) {
+            const uint64_t kk = steps - done;
+            s += 1;
+            i -= kk;
+            done += kk;
+        }
+    }
+    if (sc.tail && i > 1 && done < steps) {
+        const uint64_t kk = std::min<uint64_t>(i - 1, steps - done);
+        if (check) {
+            const u128 p = falling(i, kk);
+            if (p > two64) { *err = BRR_EOVERFLOW; return 0; }
+            if (sc.u_tail && (u128)sc.u_tail < p) { *err = BRR_EINVAL; return 0; }
+        }
+        s += 1;
+        done += kk;
+    }
+    if (check && done < steps) { *err = BRR_EINVAL; return 0; }
+    return s;
+}
+
+brr_status check_structure(const brr_schedule &sc)
+{
+    if (sc.nsteps == 0 || sc.nsteps > BRR_MAX_STEPS) return BRR_EINVAL;
+    for (uint32_t g = 0; g < sc.nsteps; ++g) {
+        const brr_step &st = sc.step[g];
+        if (st.k == 0 || st.k > BRR_MAX_K) return BRR_EINVAL;
+        if (st.n_above + 1 < st.k) return BRR_EINVAL;
+        if (g > 0 && st.n_above > sc.step[g - 1].n_above) return BRR_EINVAL;
+    }
+    return BRR_OK;
+}
+
+brr_status check_for(const brr_schedule &sc, uint64_t n, uint64_t steps)
+{
+    brr_status e = check_structure(sc);
+    if (e != BRR_OK) return e;
+    if (n <= 1) return BRR_OK;
+    e = BRR_OK;
+    walk_schedule(sc, n, steps, true, &e);
+    return e;
+}
+
+DevSched to_dev(const brr_schedule &sc)
+{
+    DevSched d;
+    std::memset(&d, 0, sizeof d);
+    d.nsteps = sc.nsteps;
+    d.tail = sc.tail;
+    for (uint32_t g = 0; g < sc.nsteps; ++g) {
+        d.thr[g] = (uint32_t)std::min<uint64_t>(sc.step[g].n_above, 0xFFFFFFFFull);
+        d.k[g] = sc.step[g].k;
+        d.u[g] = sc.step[g].u0;
+    }
+    d.u_tail = sc.u_tail;
+    return d;
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// Plans
+// ---------------------------------------------------------------------------
+
+struct brr_plan {
+    int device = -1;
+    uint32_t eb = 4;
+    uint64_t count = 0;
+    brr_schedule sched;
+    DevSched ds;
+    brr_mapping map;
+    std::vector<uint64_t> h_off;
+    // classification (made on first run, after the mapping is final)
+    bool classified = false;
+    uint32_t n_wave = 0, n_wg = 0, n_big = 0;
+    uint32_t wave_max_n = 0, wg_max_n = 0;
+    uint32_t *d_items = nullptr;   // [wave items | wg items | big items]
+    uint64_t *d_big_off = nullptr; // scratch byte offset of each big item
+    void *d_scratch = nullptr;
+    // graph of the launch sequence, bound to the buffers of the last run
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *g_data = nullptr;
+    const uint64_t *g_offsets = nullptr;
+    uint64_t g_seed = 0, g_inst = 0;
+};
+
+namespace {
+
+void release(brr_plan *p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_big_off) (void)hipFree(p->d_big_off);
+    if (p->d_scratch) (void)hipFree(p->d_scratch);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->capture_stream = nullptr;
+    p->d_items = nullptr;
+    p->d_big_off = nullptr;
+    p->d_scratch = nullptr;
+}
+
+brr_status classify(brr_plan *p)
+{
+    std::vector<uint32_t> wave, wg, big;
+    std::vector<uint64_t> big_off;
+    uint64_t scratch = 0;
+    const uint32_t wave_cap = std::min<uint32_t>(p->map.wave_max, wave_tier_max_n());
+    const uint32_t wg_cap = lds_tier_max_n();
+    for (uint64_t q = 0; q < p->count; ++q) {
+        const uint64_t n = p->h_off[q + 1] - p->h_off[q];
+        if (n <= 1) continue;
+        if (n <= wave_cap) {
+            wave.push_back((uint32_t)q);
+            p->wave_max_n = std::max<uint32_t>(p->wave_max_n, (uint32_t)n);
+        } else if (n <= wg_cap) {
+            wg.push_back((uint32_t)q);
+            p->wg_max_n = std::max<uint32_t>(p->wg_max_n, (uint32_t)n);
+        } else {
+            big.push_back((uint32_t)q);
+            big_off.push_back(scratch);
+            scratch += global_scratch_bytes(n, p->eb);
+        }
+    }
+    p->n_wave = (uint32_t)wave.size();
+    p->n_wg = (uint32_t)wg.size();
+    p->n_big = (uint32_t)big.size();
+    std::vector<uint32_t> items;
+    items.reserve(wave.size() + wg.size() + big.size());
+    items.insert(items.end(), wave.begin(), wave.end());
+    items.insert(items.end(), wg.begin(), wg.end());
+    items.insert(items.end(), big.begin(), big.end());
+    if (!items.empty()) {
+        if (hipMalloc(reinterpret_cast<void **>(&p->d_items), items.size() * 4) != hipSuccess)
+            return BRR_ENOMEM;
+        if (hipMemcpy(p->d_items, items.data(), items.size() * 4, hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return BRR_EHIP;
+    }
+    if (!big.empty()) {
+        if (hipMalloc(reinterpret_cast<void **>(&p->d_big_off), big_off.size() * 8) != hipSuccess)
+            return BRR_ENOMEM;
+        if (hipMemcpy(p->d_big_off, big_off.data(), big_off.size() * 8, hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return BRR_EHIP;
+        if (hipMalloc(&p->d_scratch, scratch) != hipSuccess) return BRR_ENOMEM;
+    }
+    p->classified = true;
+    return BRR_OK;
+}
+
+hipError_t enqueue(brr_plan *p, void *data, const uint64_t *offsets, uint64_t seed, uint64_t inst,
+                   hipStream_t s)
+{
+    hipError_t e = launch_batched_wave(data, offsets, p->d_items, p->n_wave, p->wave_max_n, p->eb,
+                                       p->ds, seed, inst, s);
+    if (e != hipSuccess) return e;
+    e = launch_batched_wg(data, offsets, p->d_items + p->n_wave, p->n_wg, p->wg_max_n, p->eb,
+                          p->ds, seed, inst, s);
+    if (e != hipSuccess) return e;
+    return launch_batched_big(data, offsets, p->d_items + p->n_wave + p->n_wg, p->n_big, p->eb,
+                              p->ds, seed, inst, p->d_scratch, p->d_big_off, s);
+}
+
+brr_status run_plan(brr_plan *p, void *data, const uint64_t *offsets, uint64_t seed, uint64_t inst,
+                    hipStream_t s)
+{
+    if (!p->classified) {
+        const brr_status st = classify(p);
+        if (st != BRR_OK) return st;
+    }
+    if (!p->map.use_graph) return hip_status(enqueue(p, data, offsets, seed, inst, s));
+    const bool rebind = !p->exec || p->g_data != data || p->g_offsets != offsets ||
+                        p->g_seed != seed || p->g_inst != inst;
+    if (rebind) {
+        if (!p->capture_stream &&
+            hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            return BRR_EHIP;
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return BRR_EHIP;
+        const hipError_t le = enqueue(p, data, offsets, seed, inst, p->capture_stream);
+        const hipError_t ce = hipStreamEndCapture(p->capture_stream, &g);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return BRR_EHIP;
+        }
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        p->graph = g;
+        p->exec = nullptr;
+        if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) return BRR_EHIP;
+        p->g_data = data;
+        p->g_offsets = offsets;
+        p->g_seed = seed;
+        p->g_inst = inst;
+    }
+    return hip_status(hipGraphLaunch(p->exec, s));
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// extern "C" entry points
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+brr_status brr_schedule_paper(int max_k, brr_schedule *out)
+{
+    if (!out) return BRR_EINVAL;
+    brr_schedule s;
+    std::memset(&s, 0, sizeof s);
+    if (max_k == 1) {
+        s.nsteps = 1;
+        s.step[0] = brr_step{1, 1, 0, 0};
+    } else if (max_k == 2) {
+        s.nsteps = 2;
+        s.step[0] = brr_step{1ull << 30, 1, 0, 0};
+        s.step[1] = brr_step{2, 2, 0, 1ull << 60};
+        s.tail = 1;
+        s.u_tail = 720;
+    } else if (max_k == 6) {
+        // one die above 2^30 elements, then k = 2..6 dice while more than
+        // 2^19, 2^14, 2^11, 2^9, 6 elements remain (k = 2 from 2^30 down),
+        // each k with the paper's upper bound on its bound product
+        const uint64_t above[6] = {1ull << 30, 1ull << 19, 1ull << 14, 1ull << 11, 1ull << 9, 6};
+        const uint64_t bound[6] = {0, 1ull << 60, 1ull << 57, 1ull << 56, 1ull << 55, 1ull << 54};
+        s.nsteps = 6;
+        for (uint32_t g = 0; g < 6; ++g) s.step[g] = brr_step{above[g], g + 1, 0, bound[g]};
+        s.tail = 1;
+        s.u_tail = 720;
+    } else {
+        return BRR_EINVAL;
+    }
+    *out = s;
+    return BRR_OK;
+}
+
+uint64_t brr_schedule_batches(const brr_schedule *sched, uint64_t n, uint64_t steps)
+{
+    if (!sched || check_structure(*sched) != BRR_OK) return 0;
+    brr_status e = BRR_OK;
+    return walk_schedule(*sched, n, steps, false, &e);
+}
+
+brr_status brr_schedule_check(const brr_schedule *sched, uint64_t n)
+{
+    if (!sched) return BRR_EINVAL;
+    return check_for(*sched, n, n ? n - 1 : 0);
+}
+
+brr_status brr_dice(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
+                    uint64_t seed, uint64_t inst, void *stream)
+{
+    if (k < 1 || k > 8) return BRR_EINVAL;
+    if (count == 0) return BRR_OK;
+    if (!d_bounds || !d_out) return BRR_EINVAL;
+    uint32_t *status = nullptr;
+    const brr_status st = device_ready(&status);
+    if (st != BRR_OK) return st;
+    return hip_status(launch_dice(d_bounds, d_out, count, k, make_key(seed, inst), status,
+                                  static_cast<hipStream_t>(stream)));
+}
+
+brr_status brr_dice_const(uint32_t bound, uint32_t *d_out, uint64_t count, uint32_t k,
+                          uint64_t seed, uint64_t inst, void *stream)
+{
+    if (k < 1 || k > 8) return BRR_EINVAL;
+    if (count == 0) return BRR_OK;
+    if (!d_out || bound == 0) return BRR_EINVAL;
+    const u128 two64 = (u128)1 << 64;
+    u128 p_full = 1;
+    for (uint32_t i = 0; i < k; ++i) p_full *= bound;
+    if (p_full > two64 && count >= k) return BRR_EOVERFLOW;
+    const uint64_t S = (count + k - 1) / k;
+    const uint64_t k_last = count - (S - 1) * k;
+    u128 p_last = 1;
+    for (uint64_t i = 0; i < k_last; ++i) p_last *= bound;
+    if (p_last > two64) return BRR_EOVERFLOW;
+    const uint64_t t_full = p_full > two64 ? 0 : (uint64_t)(two64 % p_full);
+    const uint64_t t_last = (uint64_t)(two64 % p_last);
+    const brr_status st = device_ready(nullptr);
+    if (st != BRR_OK) return st;
+    return hip_status(launch_dice_const(bound, d_out, count, k, make_key(seed, inst), t_full,
+                                        t_last, static_cast<hipStream_t>(stream)));
+}
+
+brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_schedule *sched,
+                       uint64_t seed, uint64_t inst, void *stream)
+{
+    if (elem_bytes != 4 && elem_bytes != 8) return BRR_EINVAL;
+    if (n <= 1) return BRR_OK;
+    if (!d_data || n > 0xFFFFFFFFull) return BRR_EINVAL;
+    const brr_schedule &sc = sched ? *sched : paper6();
+    brr_status st = check_for(sc, n, n - 1);
+    if (st != BRR_OK) return st;
+    st = device_ready(nullptr);
+    if (st != BRR_OK) return st;
+    const DevSched ds = to_dev(sc);
+    const StreamKey key = make_key(seed, inst);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n <= lds_tier_max_n())
+        return hip_status(
+            launch_lds_single(d_data, (uint32_t)n, (uint32_t)(n - 1), 0, elem_bytes, nullptr, ds,
+                              key, s));
+    void *scratch = nullptr;
+    if (hipMallocAsync(&scratch, global_scratch_bytes(n, elem_bytes), s) != hipSuccess)
+        return BRR_ENOMEM;
+    const hipError_t e = launch_global_single(d_data, (uint32_t)n, (uint32_t)(n - 1), 0,
+                                              elem_bytes, nullptr, ds, key, scratch, s);
+    (void)hipFreeAsync(scratch, s);
+    return hip_status(e);
+}
+
+brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_bytes, void *d_out,
+                      const brr_schedule *sched, uint64_t seed, uint64_t inst, void *stream)
+{
+    if (elem_bytes != 4 && elem_bytes != 8) return BRR_EINVAL;
+    if (m > n) return BRR_EINVAL;
+    if (m == 0) return BRR_OK;
+    if (!d_data || !d_out || n > 0xFFFFFFFFull) return BRR_EINVAL;
+    const brr_schedule &sc = sched ? *sched : paper6();
+    const uint64_t steps = std::min<uint64_t>(m, n - 1);
+    brr_status st = check_for(sc, n, steps);
+    if (st != BRR_OK) return st;
+    st = device_ready(nullptr);
+    if (st != BRR_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n == 1) // one element, no step: the sample is the element itself
+        return hip_status(hipMemcpyAsync(d_out, d_data, elem_bytes, hipMemcpyDeviceToDevice, s));
+    const DevSched ds = to_dev(sc);
+    const StreamKey key = make_key(seed, inst);
+    void *data = const_cast<void *>(d_data); // only read when an output buffer is given
+    const uint32_t out_lo = (uint32_t)(n - m);
+    if (n <= lds_tier_max_n())
+        return hip_status(launch_lds_single(data, (uint32_t)n, (uint32_t)steps, out_lo, elem_bytes,
+                                            d_out, ds, key, s));
+    void *scratch = nullptr;
+    if (hipMallocAsync(&scratch, global_scratch_bytes(n, elem_bytes), s) != hipSuccess)
+        return BRR_ENOMEM;
+    const hipError_t e = launch_global_single(data, (uint32_t)n, (uint32_t)steps, out_lo,
+                                              elem_bytes, d_out, ds, key, scratch, s);
+    (void)hipFreeAsync(scratch, s);
+    return hip_status(e);
+}
+
+brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t count,
+                           uint32_t elem_bytes, const brr_schedule *sched)
+{
+    if (!out) return BRR_EINVAL;
+    *out = nullptr;
+    if (elem_bytes != 4 && elem_bytes != 8) return BRR_EINVAL;
+    if (count > 0xFFFFFFFFull || (count && !h_offsets)) return BRR_EINVAL;
+    const brr_schedule &sc = sched ? *sched : paper6();
+    uint64_t max_n = 0;
+    for (uint64_t q = 0; q < count; ++q) {
+        if (h_offsets[q + 1] < h_offsets[q]) return BRR_EINVAL;
+        max_n = std::max<uint64_t>(max_n, h_offsets[q + 1] - h_offsets[q]);
+    }
+    if (max_n > 0xFFFFFFFFull) return BRR_EINVAL;
+    // the largest product of every segment occurs in the largest shuffle
+    brr_status st = check_for(sc, max_n, max_n ? max_n - 1 : 0);
+    if (st != BRR_OK) return st;
+    st = device_ready(nullptr);
+    if (st != BRR_OK) return st;
+    brr_plan *p = new (std::nothrow) brr_plan();
+    if (!p) return BRR_ENOMEM;
+    try {
+        (void)hipGetDevice(&p->device);
+        p->eb = elem_bytes;
+        p->count = count;
+        p->sched = sc;
+        p->ds = to_dev(sc);
+        p->map = brr_mapping{0, wave_tier_max_n(), 1024, 1};
+        p->h_off.assign(h_offsets, h_offsets + (count ? count + 1 : 0));
+    } catch (...) {
+        delete p;
+        return BRR_ENOMEM;
+    }
+    *out = p;
+    return BRR_OK;
+}
+
+void brr_plan_destroy(brr_plan *plan)
+{
+    if (!plan) return;
+    release(plan);
+    delete plan;
+}
+
+brr_status brr_plan_get_mapping(const brr_plan *plan, brr_mapping *out)
+{
+    if (!plan || !out) return BRR_EINVAL;
+    *out = plan->map;
+    return BRR_OK;
+}
+
+brr_status brr_plan_set_mapping(brr_plan *plan, const brr_mapping *m)
+{
+    if (!plan || !m) return BRR_EINVAL;
+    if (plan->classified) return BRR_EINVAL; // the mapping is fixed by the first run
+    if (m->lane_max != 0) return BRR_EINVAL; // one-lane tier not offered by this build
+    if (m->wave_max > wave_tier_max_n()) return BRR_EINVAL;
+    if (m->wg_threads != 1024) return BRR_EINVAL;
+    plan->map = *m;
+    return BRR_OK;
+}
+
+brr_status brr_shuffle_batched(void *d_data, const uint64_t *d_offsets, uint64_t count,
+                               uint32_t elem_bytes, brr_plan *plan, uint64_t seed,
+                               uint64_t inst_base, void *stream)
+{
+    if (elem_bytes != 4 && elem_bytes != 8) return BRR_EINVAL;
+    if (count == 0) return BRR_OK;
+    if (!d_data || !d_offsets) return BRR_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (plan) {
+        if (plan->eb != elem_bytes || plan->count != count) return BRR_EINVAL;
+        int dev = -1;
+        (void)hipGetDevice(&dev);
+        if (dev != plan->device) return BRR_EINVAL;
+        try {
+            return run_plan(plan, d_data, d_offsets, seed, inst_base, s);
+        } catch (...) {
+            return BRR_ENOMEM;
+        }
+    }
+    // no plan: classify from a host copy of the offsets, run, wait, release
+    std::vector<uint64_t> h;
+    try {
+        h.resize(count + 1);
+    } catch (...) {
+        return BRR_ENOMEM;
+    }
+    if (hipMemcpyAsync(h.data(), d_offsets, (count + 1) * 8, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return BRR_EHIP;
+    brr_plan *tmp = nullptr;
+    brr_status st = brr_plan_create(&tmp, h.data(), count, elem_bytes, nullptr);
+    if (st != BRR_OK) return st;
+    tmp->map.use_graph = 0;
+    try {
+        st = run_plan(tmp, d_data, d_offsets, seed, inst_base, s);
+    } catch (...) {
+        st = BRR_ENOMEM;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && st == BRR_OK) st = BRR_EHIP;
+    brr_plan_destroy(tmp);
+    return st;
+}
+
+brr_status brr_sync_status(void *stream)
+{
+    uint32_t *status = nullptr;
+    brr_status st = device_ready(&status);
+    if (st != BRR_OK) return st;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return BRR_EHIP;
+    uint32_t v = 0;
+    if (hipMemcpy(&v, status, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return BRR_EHIP;
+    if (v == 0) return BRR_OK;
+    if (hipMemset(status, 0, sizeof v) != hipSuccess) return BRR_EHIP;
+    if (hipDeviceSynchronize() != hipSuccess) return BRR_EHIP;
+    return (v & kDevZeroBound) ? BRR_EINVAL : BRR_EOVERFLOW;
+}
+
+const char *brr_strerror(brr_status status)
+{
+    switch (status) {
+    case BRR_OK: return "ok";
+    case BRR_EINVAL: return "invalid argument (null pointer, k, zero bound, m > n or schedule)";
+    case BRR_EOVERFLOW: return "bound product above 2^64";
+    case BRR_ENOMEM: return "device memory allocation failed";
+    case BRR_EHIP: return "HIP runtime error";
+    case BRR_EDEVICE: return "no usable gfx950 device";
+    default: return "unknown status";
+    }
+}
+
+} // extern "C"

@@ -1,0 +1,142 @@
+// Device-side building blocks shared by the dice and shuffle kernels of
+// libbrr (gfx950, wave64). Everything here is exact integer arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace brr {
+
+// Native 4 x u32 vector (16-byte global loads/stores, nontemporal builtins).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Bits of the per-device status word (see brr_sync_status).
+enum : uint32_t { kDevZeroBound = 1u, kDevOverflow = 2u };
+
+// Key of one word stream: the seed halves (Philox key) and the instance
+// halves (upper counter words).
+struct StreamKey {
+    uint32_t seed_lo, seed_hi, inst_lo, inst_hi;
+};
+
+__host__ __device__ inline StreamKey make_key(uint64_t seed, uint64_t inst)
+{
+    return StreamKey{(uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)inst, (uint32_t)(inst >> 32)};
+}
+
+// Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, SC'11): ten
+// rounds, each two 32x32->64 multiplies (one v_mad_u64_u32 each) whose high
+// halves are xored with the other counter words and the round key; the key
+// advances by the Weyl increments between rounds. The key is wave-uniform
+// in every caller, so its schedule stays in scalar registers.
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t m0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t m1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// Words 2*blk (even half) and 2*blk+1 (odd half) of a stream.
+__device__ __forceinline__ void word_pair(uint64_t blk, const StreamKey &key, uint64_t &w_even,
+                                          uint64_t &w_odd)
+{
+    const uint4 x = philox4x32_10((uint32_t)blk, (uint32_t)(blk >> 32), key.inst_lo, key.inst_hi,
+                                  key.seed_lo, key.seed_hi);
+    w_even = (uint64_t)x.x | ((uint64_t)x.y << 32);
+    w_odd = (uint64_t)x.z | ((uint64_t)x.w << 32);
+}
+
+// Word c of a stream.
+__device__ __forceinline__ uint64_t word_at(uint64_t c, const StreamKey &key)
+{
+    uint64_t e, o;
+    word_pair(c >> 1, key, e, o);
+    return (c & 1) ? o : e;
+}
+
+// One link of the Theorem 1 chain for a bound b < 2^32:
+// (a, r) <- b (x) r, a = high 64 bits (< b), r = low 64 bits of b*r.
+// b*r = b*r_hi*2^32 + b*r_lo; two 32x32->64 multiply-adds.
+__device__ __forceinline__ uint32_t mul_roll(uint32_t b, uint64_t &r)
+{
+    const uint64_t lo = (uint64_t)b * (uint32_t)r;
+    const uint64_t hi = (uint64_t)b * (uint32_t)(r >> 32) + (lo >> 32);
+    r = (hi << 32) | (uint32_t)lo;
+    return (uint32_t)(hi >> 32);
+}
+
+// 2^64 mod B for 1 <= B < 2^64: (2^64 - B) mod B.
+__device__ __forceinline__ uint64_t pow2_64_mod(uint64_t B) { return (0 - B) % B; }
+
+// Exact product of u32 bounds as long as it is at most 2^64.
+// p holds the product modulo 2^64; e64 marks a product of exactly 2^64
+// (then p == 0); over marks a product above 2^64; zero marks a zero bound.
+struct BoundProduct {
+    uint64_t p;
+    bool e64, over, zero;
+
+    __device__ __forceinline__ void init(uint32_t b)
+    {
+        p = b;
+        e64 = false;
+        over = false;
+        zero = (b == 0);
+    }
+
+    __device__ __forceinline__ void mul(uint32_t b)
+    {
+        zero |= (b == 0);
+        if (e64) { // 2^64 * b: stays 2^64 for b == 1, exceeds it for b > 1
+            over |= (b > 1);
+            return;
+        }
+        if ((p >> 32) == 0) {
+            p = (uint64_t)(uint32_t)p * b; // < 2^64, exact
+            return;
+        }
+        const uint64_t lo = (uint64_t)(uint32_t)p * b;
+        const uint64_t hi = (uint64_t)(uint32_t)(p >> 32) * b + (lo >> 32);
+        const uint64_t top = hi >> 32; // bits 64.. of the product
+        p = (hi << 32) | (uint32_t)lo;
+        if (top != 0) {
+            if (top == 1 && p == 0)
+                e64 = true;
+            else
+                over = true;
+        }
+    }
+};
+
+// Acceptance of a rolled group with exact product P (Lemire's criterion on
+// the leftover, Theorem 1): returns the threshold t to compare r against.
+// Only called when r < P, so t is computed on the rare slow path.
+__device__ __forceinline__ uint64_t group_threshold(const BoundProduct &P)
+{
+    return P.e64 ? 0 : pow2_64_mod(P.p);
+}
+
+// Wave64 inclusive prefix sum of v across the lanes of the wavefront.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+} // namespace brr

@@ -1,0 +1,121 @@
+// Internal interfaces between the host API (api.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace brr {
+
+// A validated schedule in the form the kernels read (thresholds clamped to
+// 32 bits: every shuffle here has n < 2^32).
+struct DevSched {
+    uint32_t nsteps, tail;
+    uint32_t thr[16];
+    uint32_t k[16];
+    uint64_t u[16];
+    uint64_t u_tail;
+};
+
+// A run of cnt consecutive batches (batch indices s0 .. s0+cnt-1) of k dice
+// each; the first starts with i0 elements left, each next one k fewer. u is
+// the guard of Algorithm 4 (0 = compare against the exact product).
+struct Seg {
+    uint32_t s0, i0, k, cnt;
+    uint64_t u;
+};
+
+constexpr int kMaxSegs = 18; // 16 steps + one truncated batch + the last batch
+
+struct SegTable {
+    Seg seg[kMaxSegs];
+    uint32_t nseg;
+    uint32_t S; // batches in total
+};
+
+// Batches of the first `steps` Fisher-Yates steps of an n-element shuffle
+// under schedule sc (steps = n - 1 for a full shuffle): while more than
+// thr[g] elements remain, batches of k[g] dice; a batch that would pass
+// `steps` keeps only the dice it needs; then, with a tail, one batch of
+// i - 1 dice. Requires thr[g] + 1 >= k[g] (checked on the host).
+__host__ __device__ inline void build_segments(uint32_t n, uint32_t steps, const DevSched &sc,
+                                               SegTable &t)
+{
+    uint32_t i = n, s = 0, done = 0, ns = 0;
+    for (uint32_t g = 0; g < sc.nsteps && done < steps; ++g) {
+        const uint32_t thr = sc.thr[g], k = sc.k[g];
+        if (i <= thr) continue;
+        const uint32_t cnt = (uint32_t)(((uint64_t)(i - thr) + k - 1) / k);
+        const uint32_t left = steps - done;
+        uint32_t nb = cnt;
+        if ((uint64_t)nb * k > left) nb = left / k;
+        if (nb) {
+            t.seg[ns++] = Seg{s, i, k, nb, sc.u[g]};
+            s += nb;
+            i -= nb * k;
+            done += nb * k;
+        }
+        if (nb < cnt && done < steps) {
+            const uint32_t kk = steps - done;
+            t.seg[ns++] = Seg{s, i, kk, 1, sc.u[g]};
+            s += 1;
+            i -= kk;
+            done += kk;
+        }
+    }
+    if (sc.tail && i > 1 && done < steps) {
+        uint32_t kk = i - 1;
+        if (kk > steps - done) kk = steps - done;
+        t.seg[ns++] = Seg{s, i, kk, 1, sc.u_tail};
+        s += 1;
+        done += kk;
+    }
+    t.nseg = ns;
+    t.S = s;
+}
+
+// Kernel launchers (dice.hip, shuffle.hip).
+hipError_t launch_dice(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
+                       StreamKey key, uint32_t *status, hipStream_t stream);
+hipError_t launch_dice_const(uint32_t bound, uint32_t *out, uint64_t count, uint32_t k,
+                             StreamKey key, uint64_t t_full, uint64_t t_last, hipStream_t stream);
+
+// Largest n that one workgroup shuffles with its index arrays in LDS.
+uint32_t lds_tier_max_n();
+// Device scratch bytes that the global tier needs for n elements.
+uint64_t global_scratch_bytes(uint64_t n, uint32_t eb);
+
+// One shuffle (steps = n - 1, out = nullptr, in place) or one sample
+// (out != nullptr: out[n-1-p] = final z[p] for out_lo <= p < n, the input
+// untouched) by one workgroup with its index arrays in LDS;
+// n <= lds_tier_max_n(), 1 <= steps < n, out_lo <= n - steps.
+hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
+                             void *out, const DevSched &sc, StreamKey key, hipStream_t stream);
+
+// The same over the whole device with index arrays in `scratch`
+// (global_scratch_bytes(n, eb) bytes).
+hipError_t launch_global_single(void *data, uint32_t n, uint32_t steps, uint32_t out_lo,
+                                uint32_t eb, void *out, const DevSched &sc, StreamKey key,
+                                void *scratch, hipStream_t stream);
+
+// Batched shuffles of one size class. items: device u32[nitems] of shuffle
+// indices into the CSR offsets. Class 0: one wavefront per shuffle
+// (n <= wave_max); class 1: one workgroup per shuffle with LDS index arrays
+// (n <= lds_tier_max_n()); class 2: one workgroup per shuffle with index
+// arrays in device scratch (scratch_off: device u64[nitems], byte offsets).
+hipError_t launch_batched_wave(void *data, const uint64_t *offsets, const uint32_t *items,
+                               uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
+                               uint64_t seed, uint64_t inst_base, hipStream_t stream);
+hipError_t launch_batched_wg(void *data, const uint64_t *offsets, const uint32_t *items,
+                             uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
+                             uint64_t seed, uint64_t inst_base, hipStream_t stream);
+hipError_t launch_batched_big(void *data, const uint64_t *offsets, const uint32_t *items,
+                              uint32_t nitems, uint32_t eb, const DevSched &sc, uint64_t seed,
+                              uint64_t inst_base, void *scratch, const uint64_t *scratch_off,
+                              hipStream_t stream);
+uint32_t wave_tier_max_n();
+// Raises the dynamic-LDS limit of the LDS-tier kernels (once per device).
+hipError_t prepare_shuffle_kernels();
+
+} // namespace brr

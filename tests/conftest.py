@@ -32,3 +32,34 @@ def orc():
 
     oracle.lib()
     return oracle
+
+
+def say(*args):
+    """Names the case about to touch the GPU, flushed before it runs."""
+    print("[case]", *args, flush=True)
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """The HIP binding on cuda:0; fails (never falls back) without it."""
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    from paper_2408_06213_amd import brr
+
+    torch.cuda.set_device(0)
+    return brr
+
+
+def to_dev(a):
+    import numpy as np
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def to_host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.cpu().numpy()

@@ -1,0 +1,91 @@
+"""The C ABI library loads and exports every declared symbol; host-side
+schedule logic agrees with the paper's fixtures and with the oracle (two
+independent implementations). No GPU work is launched here."""
+import os
+import re
+
+import pytest
+
+from conftest import ROOT, golden_rows
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "brr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(brr_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2408_06213_amd import brr
+
+    syms = declared_symbols()
+    assert len(syms) >= 14
+    assert sorted(brr.EXPORTS) == syms
+    for s in syms:
+        assert hasattr(brr.lib, s), s
+
+
+def test_strerror():
+    from paper_2408_06213_amd import brr
+
+    for code in range(6):
+        assert brr.brr_strerror(code)
+    assert brr.brr_strerror(2) == "bound product above 2^64"
+
+
+def test_paper_schedules_host():
+    from paper_2408_06213_amd import brr
+
+    s6 = brr.brr_schedule_paper(6)
+    assert s6.steps() == [(2**30, 1, 0), (2**19, 2, 2**60), (2**14, 3, 2**57), (2**11, 4, 2**56),
+                          (2**9, 5, 2**55), (6, 6, 2**54)]
+    assert s6.tail == 1 and s6.u_tail == 720
+    for row in golden_rows("s6_batches.txt"):
+        n, batches = map(int, row.split()[:2])
+        assert brr.brr_schedule_batches(s6, n, n - 1) == batches
+    with pytest.raises(brr.BrrError):
+        brr.brr_schedule_paper(3)
+
+
+@pytest.mark.parametrize("max_k", [1, 2, 6])
+def test_host_batch_counts_match_oracle(orc, max_k):
+    from paper_2408_06213_amd import brr
+
+    s = brr.brr_schedule_paper(max_k)
+    o = orc.schedule_paper(max_k)
+    for n in list(range(2, 80)) + [255, 256, 257, 4097, 10000, 65536, 100003, 2**20 + 7]:
+        for steps in {n - 1, max(1, n // 3), 1}:
+            assert brr.brr_schedule_batches(s, n, steps) == orc.count_batches(n, steps, o), (n, steps)
+
+
+def test_schedule_check_host():
+    from paper_2408_06213_amd import brr
+
+    s6 = brr.brr_schedule_paper(6)
+    assert brr.brr_schedule_check(s6, 10000) == brr.BRR_OK
+    assert brr.brr_schedule_check(s6, 2**26) == brr.BRR_OK
+    bad = brr.brr_schedule.from_steps([(19, 20, 0)], tail=True, u_tail=0)
+    assert brr.brr_schedule_check(bad, 100) == brr.BRR_EOVERFLOW
+    bad = brr.brr_schedule.from_steps([(6, 6, 1000)])
+    assert brr.brr_schedule_check(bad, 100) == brr.BRR_EINVAL
+    bad = brr.brr_schedule.from_steps([(6, 6, 2**54)], tail=False)
+    assert brr.brr_schedule_check(bad, 100) == brr.BRR_EINVAL
+    bad = brr.brr_schedule.from_steps([(3, 6, 0)])  # threshold below k - 1
+    assert brr.brr_schedule_check(bad, 100) == brr.BRR_EINVAL
+    bad = brr.brr_schedule.from_steps([(100, 2, 0), (200, 3, 0)])  # thresholds increase
+    assert brr.brr_schedule_check(bad, 1000) == brr.BRR_EINVAL
+
+
+def test_host_argument_errors_need_no_device():
+    from paper_2408_06213_amd import brr
+
+    # rejected before any device work
+    assert brr.lib.brr_dice(None, None, 10, 0, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_dice(None, None, 10, 9, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_dice(None, None, 0, 4, 1, 0, None) == brr.BRR_OK
+    assert brr.lib.brr_dice(None, None, 10, 4, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_dice_const(0, 1, 10, 2, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_shuffle(None, 10, 3, None, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_shuffle(None, 1, 4, None, 1, 0, None) == brr.BRR_OK
+    assert brr.lib.brr_sample(None, 5, 6, 4, None, None, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_sample(None, 5, 0, 4, None, None, 1, 0, None) == brr.BRR_OK

@@ -1,0 +1,123 @@
+"""GPU parity of the dice-stream kernels (brr_dice, brr_dice_const) with the
+CPU oracle: bit-exact, through the C ABI."""
+import numpy as np
+import pytest
+
+from conftest import say, to_dev, to_host
+from paper_2408_06213_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+# bound width per k so that a group's product stays <= 2^64
+BITS = {1: 32, 2: 32, 3: 21, 4: 16, 5: 12, 6: 10, 7: 9, 8: 8}
+
+
+def run_dice(gpu, bounds_np, k, seed, inst, offset=0):
+    n = bounds_np.size
+    b = to_dev(np.concatenate([np.zeros(offset, np.uint32), bounds_np]))
+    out = to_dev(np.zeros(n + offset, np.uint32))
+    bp = b.data_ptr() + 4 * offset
+    op = out.data_ptr() + 4 * offset
+    gpu.check(gpu.brr_dice(bp, op, n, k, seed, inst), "brr_dice")
+    st = gpu.brr_sync_status()
+    return st, to_host(out)[offset:]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_dice_parity_ragged_counts(gpu, orc, k):
+    rng = np.random.default_rng(100 + k)
+    for count in (1, 2, 3, 4 * k - 1, 4 * k, 4 * k + 1, 1000 + 7, 65536 + 3, 300001):
+        say("dice", k, count)
+        bounds = rng.integers(1, 1 << BITS[k], size=count, dtype=np.uint64).astype(np.uint32)
+        st, got = run_dice(gpu, bounds, k, seed=11, inst=3)
+        err, want = orc.dice(bounds, k, 11, 3)
+        assert st == 0 and err == 0
+        assert np.array_equal(got, want), (k, count)
+
+
+@pytest.mark.parametrize("k", [1, 3, 4])
+def test_dice_unaligned_buffers(gpu, orc, k):
+    bounds = workloads.dice_bounds(5003, seed=2)
+    say("dice unaligned", k)
+    st, got = run_dice(gpu, bounds, k, seed=5, inst=0, offset=1)
+    assert st == 0
+    assert np.array_equal(got, orc.dice(bounds, k, 5, 0)[1])
+
+
+def test_dice_rejection_heavy(gpu, orc):
+    """Pairs with product 2^63 + 2^31 - 1 reject about half of all words."""
+    bounds = np.tile(np.array([2**31 + 1, 2**32 - 1], np.uint32), 20000)
+    say("dice rejection heavy")
+    st, got = run_dice(gpu, bounds, 2, seed=1, inst=9)
+    assert st == 0
+    assert np.array_equal(got, orc.dice(bounds, 2, 1, 9)[1])
+
+
+def test_dice_product_exactly_2_64(gpu, orc):
+    bounds = np.tile(np.array([2**31, 2**31, 4], np.uint32), 777)
+    say("dice product 2^64")
+    st, got = run_dice(gpu, bounds, 3, seed=3, inst=0)
+    assert st == 0
+    assert np.array_equal(got, orc.dice(bounds, 3, 3, 0)[1])
+
+
+def test_dice_device_errors(gpu):
+    say("dice zero bound")
+    b = workloads.dice_bounds(4096, seed=4)
+    b[1234] = 0
+    st, _ = run_dice(gpu, b, 4, seed=1, inst=0)
+    assert st == gpu.BRR_EINVAL
+    assert gpu.brr_sync_status() == gpu.BRR_OK  # cleared after being read
+    say("dice overflow")
+    b = np.full(4096, 2**32 - 1, np.uint32)
+    st, _ = run_dice(gpu, b, 3, seed=1, inst=0)
+    assert st == gpu.BRR_EOVERFLOW
+    assert gpu.brr_sync_status() == gpu.BRR_OK
+
+
+@pytest.mark.parametrize("bound,k,count", [(6, 4, 100003), (2**16 - 1, 4, 4099), (2**31 + 1, 2, 5000),
+                                           (1, 3, 10), (2**32 - 1, 1, 3001), (10, 8, 1234),
+                                           (2**16, 4, 999)])
+def test_dice_const_parity(gpu, orc, bound, k, count):
+    say("dice_const", bound, k, count)
+    out = to_dev(np.zeros(count, np.uint32))
+    gpu.check(gpu.brr_dice_const(bound, out, count, k, 21, 4), "brr_dice_const")
+    err, want = orc.dice_const(bound, count, k, 21, 4)
+    assert err == 0
+    assert np.array_equal(to_host(out), want)
+    # Algorithm 2 and Algorithm 3 agree on the device too
+    st, got = run_dice(gpu, np.full(count, bound, np.uint32), k, 21, 4)
+    assert st == 0 and np.array_equal(got, want)
+
+
+def test_dice_const_overflow_rejected_on_host(gpu):
+    out = to_dev(np.zeros(16, np.uint32))
+    assert gpu.brr_dice_const(2**32 - 1, out, 16, 3, 1, 0) == gpu.BRR_EOVERFLOW
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_dice_full_size_sampled(gpu, orc, k):
+    """2^28 rolls, bounds in [1, 2^16) from seed 7 (the benchmark's stream):
+    every output below its bound; 20000 random groups plus the first and
+    last 500 checked one by one against the oracle."""
+    import torch
+
+    count = 1 << 28
+    say("dice full size", k)
+    bounds = workloads.dice_bounds(count, seed=7)
+    b = to_dev(bounds)
+    out = torch.empty(count, dtype=torch.uint32, device="cuda")
+    gpu.check(gpu.brr_dice(b, out, count, k, 7, 0), "brr_dice")
+    assert gpu.brr_sync_status() == 0
+    got = to_host(out)
+    del b, out
+    assert np.all(got < bounds)
+    S = -(-count // k)
+    rng = np.random.default_rng(k)
+    groups = np.concatenate([np.arange(500), np.arange(S - 500, S), rng.integers(0, S, 20000)])
+    for g in groups:
+        lo, hi = int(g) * k, min(count, int(g) * k + k)
+        err, want = orc.dice_group(bounds[lo:hi], S, int(g), 7, 0)
+        assert err == 0
+        assert np.array_equal(got[lo:hi], want), (k, int(g))

@@ -1,0 +1,178 @@
+"""GPU parity of shuffles, batched shuffles and samples with the CPU oracle:
+bit-exact permutations, through the C ABI."""
+import numpy as np
+import pytest
+
+from conftest import say, to_dev, to_host
+from paper_2408_06213_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+LDS_SIZES = [2, 3, 4, 5, 6, 7, 8, 13, 64, 100, 255, 256, 257, 511, 512, 513, 1000, 4096, 10000,
+             16383, 16384]
+GLOBAL_SIZES = [16385, 20000, 65536, 100003, 1 << 20]
+
+
+def both_schedules(gpu, orc, max_k):
+    return gpu.brr_schedule_paper(max_k), orc.schedule_paper(max_k)
+
+
+def gpu_shuffle(gpu, data_np, sched, seed, inst):
+    d = to_dev(data_np)
+    gpu.check(gpu.brr_shuffle(d, data_np.size, data_np.itemsize, sched, seed, inst), "brr_shuffle")
+    assert gpu.brr_sync_status() == 0
+    return to_host(d)
+
+
+@pytest.mark.parametrize("max_k", [6, 2, 1])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("tier", ["lds", "global"])
+def test_shuffle_parity(gpu, orc, max_k, dtype, tier):
+    gs, os_ = both_schedules(gpu, orc, max_k)
+    sizes = LDS_SIZES if tier == "lds" else GLOBAL_SIZES
+    for n in sizes:
+        say("shuffle", tier, max_k, np.dtype(dtype).name, n)
+        a = np.arange(n, dtype=dtype) * 3 + 1
+        got = gpu_shuffle(gpu, a, gs, seed=1234, inst=n)
+        want = a.copy()
+        assert orc.shuffle(want, os_, 1234, n) == 0
+        assert np.array_equal(got, want), (tier, max_k, n)
+
+
+def test_shuffle_config_10000(gpu, orc):
+    """A[i] = i, n = 10,000, seed 42: shuffle_6 and the unbatched form."""
+    for max_k in (6, 1):
+        gs, os_ = both_schedules(gpu, orc, max_k)
+        say("shuffle n=10000 seed 42", max_k)
+        a = np.arange(10000, dtype=np.uint32)
+        got = gpu_shuffle(gpu, a, gs, seed=42, inst=0)
+        want = a.copy()
+        assert orc.shuffle(want, os_, 42, 0) == 0
+        assert np.array_equal(got, want)
+
+
+def test_shuffle_custom_schedules(gpu, orc):
+    """Schedules other than the paper's: larger batches at small sizes (up to
+    8 dice below 146 elements, 7-dice last batch) and exact-product guards."""
+    steps = [(2**19, 2, 2**60), (26573, 3, 0), (3225, 4, 0), (815, 5, 0), (305, 6, 0), (146, 7, 0),
+             (8, 8, 0)]
+    gs = gpu.brr_schedule.from_steps(steps, tail=True, u_tail=0)
+    os_ = orc.Schedule.from_segments(steps, tail=True, u_tail=0)
+    for n in (9, 100, 147, 1000, 16384, 50000):
+        say("shuffle custom", n)
+        a = np.arange(n, dtype=np.uint32)
+        got = gpu_shuffle(gpu, a, gs, seed=77, inst=1)
+        want = a.copy()
+        assert orc.shuffle(want, os_, 77, 1) == 0
+        assert np.array_equal(got, want), n
+
+
+def test_shuffle_trivial_sizes(gpu):
+    import torch
+
+    d = torch.arange(1, dtype=torch.int32, device="cuda")
+    assert gpu.brr_shuffle(d, 1, 4, None, 1, 0) == 0
+    assert gpu.brr_shuffle(d, 0, 4, None, 1, 0) == 0
+    assert int(d[0]) == 0
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_sample_parity(gpu, orc, dtype):
+    s6g, s6o = both_schedules(gpu, orc, 6)
+    rng = np.random.default_rng(9)
+    cases = [(2, 1), (2, 2), (5, 5), (5, 4), (10, 3), (256, 25), (1000, 1), (10000, 1000),
+             (16384, 16384), (16384, 1638), (16385, 1638), (100003, 10000), (1 << 20, 104857),
+             (1 << 20, 1), (70000, 69999), (70000, 70000)]
+    for n, m in cases:
+        say("sample", np.dtype(dtype).name, n, m)
+        data = rng.integers(0, 2**31, size=n).astype(dtype)
+        d = to_dev(data)
+        out = to_dev(np.zeros(m, dtype))
+        gpu.check(gpu.brr_sample(d, n, m, data.itemsize, out, s6g, 31, n), "brr_sample")
+        assert gpu.brr_sync_status() == 0
+        err, want = orc.sample(data, m, s6o, 31, n)
+        assert err == 0
+        assert np.array_equal(to_host(out), want), (n, m)
+        assert np.array_equal(to_host(d), data)  # input untouched
+
+
+def run_batched(gpu, sizes, dtype, seed, inst_base, plan=True, graph=True, reps=1):
+    off = workloads.csr_offsets(sizes)
+    data = workloads.iota_segments(sizes, dtype)
+    d = to_dev(data)
+    d_off = to_dev(off)
+    p = None
+    if plan:
+        p = gpu.Plan(off, data.itemsize)
+        if not graph:
+            m = p.mapping()
+            m.use_graph = 0
+            gpu.check(p.set_mapping(m), "set_mapping")
+    results = []
+    for _ in range(reps):
+        d.copy_(to_dev(data))
+        gpu.check(gpu.brr_shuffle_batched(d, d_off, len(sizes), data.itemsize, p, seed, inst_base),
+                  "brr_shuffle_batched")
+        assert gpu.brr_sync_status() == 0
+        results.append(to_host(d))
+    if p is not None:
+        p.close()
+    return data, off, results
+
+
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_batched_ragged_parity(gpu, orc, graph, dtype):
+    rng = np.random.default_rng(5)
+    sizes = np.concatenate([[0, 1, 2, 3, 512, 513, 16384, 16385],
+                            np.floor(2 ** rng.uniform(1, 16.2, size=300))]).astype(np.uint64)
+    say("batched ragged", graph, np.dtype(dtype).name)
+    data, off, results = run_batched(gpu, sizes, dtype, seed=3, inst_base=1000, graph=graph, reps=3)
+    want = data.copy()
+    assert orc.shuffle_batched(want, off, orc.schedule_paper(6), 3, 1000) == 0
+    for got in results:  # every replay of the graph is checked
+        assert np.array_equal(got, want)
+
+
+def test_batched_without_plan(gpu, orc):
+    sizes = np.array([7, 300, 5000, 40000, 2, 64], dtype=np.uint64)
+    say("batched no plan")
+    data, off, results = run_batched(gpu, sizes, np.uint32, seed=8, inst_base=0, plan=False)
+    want = data.copy()
+    assert orc.shuffle_batched(want, off, orc.schedule_paper(6), 8, 0) == 0
+    assert np.array_equal(results[0], want)
+
+
+@pytest.mark.slow
+def test_batched_equal_size_full(gpu, orc):
+    """65,536 shuffles of n = 256 (values 0..255), seed 1, instance = id."""
+    sizes = np.full(65536, 256, dtype=np.uint64)
+    say("batched 65536 x 256")
+    data, off, results = run_batched(gpu, sizes, np.uint32, seed=1, inst_base=0, reps=2)
+    want = data.copy()
+    assert orc.shuffle_batched(want, off, orc.schedule_paper(6), 1, 0) == 0
+    for got in results:
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.slow
+def test_batched_ragged_full(gpu, orc):
+    """20,000 shuffles, n log-uniform in [16, 65536) (seed 3), u32 payload."""
+    sizes = workloads.ragged_sizes(20000, seed=3)
+    say("batched ragged 20000", int(sizes.sum()))
+    data, off, results = run_batched(gpu, sizes, np.uint32, seed=3, inst_base=0)
+    want = data.copy()
+    assert orc.shuffle_batched(want, off, orc.schedule_paper(6), 3, 0) == 0
+    assert np.array_equal(results[0], want)
+
+
+@pytest.mark.slow
+def test_shuffle_2_26(gpu, orc):
+    n = 1 << 26
+    s6g, s6o = both_schedules(gpu, orc, 6)
+    say("shuffle 2^26")
+    a = np.arange(n, dtype=np.uint32)
+    got = gpu_shuffle(gpu, a, s6g, seed=42, inst=0)
+    want = a.copy()
+    assert orc.shuffle(want, s6o, 42, 0) == 0
+    assert np.array_equal(got, want)
