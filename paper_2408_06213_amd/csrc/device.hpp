@@ -9,6 +9,7 @@ namespace brr {
 
 // Native 4 x u32 vector (16-byte global loads/stores, nontemporal builtins).
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // Bits of the per-device status word (see brr_sync_status).
 enum : uint32_t { kDevZeroBound = 1u, kDevOverflow = 2u };
@@ -29,7 +30,7 @@ __host__ __device__ inline StreamKey make_key(uint64_t seed, uint64_t inst)
 // halves are xored with the other counter words and the round key; the key
 // advances by the Weyl increments between rounds. The key is wave-uniform
 // in every caller, so its schedule stays in scalar registers.
-__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+__host__ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -69,7 +70,7 @@ __device__ __forceinline__ uint64_t word_at(uint64_t c, const StreamKey &key)
 // One link of the Theorem 1 chain for a bound b < 2^32:
 // (a, r) <- b (x) r, a = high 64 bits (< b), r = low 64 bits of b*r.
 // b*r = b*r_hi*2^32 + b*r_lo; two 32x32->64 multiply-adds.
-__device__ __forceinline__ uint32_t mul_roll(uint32_t b, uint64_t &r)
+__host__ __device__ __forceinline__ uint32_t mul_roll(uint32_t b, uint64_t &r)
 {
     const uint64_t lo = (uint64_t)b * (uint32_t)r;
     const uint64_t hi = (uint64_t)b * (uint32_t)(r >> 32) + (lo >> 32);
@@ -77,8 +78,30 @@ __device__ __forceinline__ uint32_t mul_roll(uint32_t b, uint64_t &r)
     return (uint32_t)(hi >> 32);
 }
 
-// 2^64 mod B for 1 <= B < 2^64: (2^64 - B) mod B.
-__device__ __forceinline__ uint64_t pow2_64_mod(uint64_t B) { return (0 - B) % B; }
+// 2^64 mod B for 1 <= B < 2^64 (Lemire's threshold of a bound product).
+// For 2^32 < B <= 2^62 the quotient q = floor(2^64 / B) < 2^32 comes from
+// one f64 division: (double)B and the quotient are each rounded to nearest,
+// so qd is within q * 2^-52 < 2^-20 of 2^64 / B and floor(qd) - 1 is one of
+// q - 2, q - 1, q. Then 2^64 - q0 * B = t + (q - q0) * B < 3B (no wrap) and
+// at most two subtractions of B give t exactly. Above 2^62, q < 4 and the
+// remainder follows from 2^64 - B by at most two subtractions. Small B (only
+// reached with probability below 2^-32 per roll) uses the integer remainder.
+__host__ __device__ __forceinline__ uint64_t pow2_64_mod(uint64_t B)
+{
+    if (B > (1ull << 62)) {
+        uint64_t t = 0 - B;
+        if (t >= B) t -= B;
+        if (t >= B) t -= B;
+        return t;
+    }
+    if (B <= (1ull << 32)) return (0 - B) % B;
+    const double qd = 18446744073709551616.0 / (double)B;
+    const uint32_t q0 = (uint32_t)qd - 1u;
+    uint64_t t = 0 - (uint64_t)q0 * B;
+    if (t >= B) t -= B;
+    if (t >= B) t -= B;
+    return t;
+}
 
 // Exact product of u32 bounds as long as it is at most 2^64.
 // p holds the product modulo 2^64; e64 marks a product of exactly 2^64
@@ -87,7 +110,7 @@ struct BoundProduct {
     uint64_t p;
     bool e64, over, zero;
 
-    __device__ __forceinline__ void init(uint32_t b)
+    __host__ __device__ __forceinline__ void init(uint32_t b)
     {
         p = b;
         e64 = false;
@@ -95,7 +118,7 @@ struct BoundProduct {
         zero = (b == 0);
     }
 
-    __device__ __forceinline__ void mul(uint32_t b)
+    __host__ __device__ __forceinline__ void mul(uint32_t b)
     {
         zero |= (b == 0);
         if (e64) { // 2^64 * b: stays 2^64 for b == 1, exceeds it for b > 1
@@ -122,7 +145,7 @@ struct BoundProduct {
 // Acceptance of a rolled group with exact product P (Lemire's criterion on
 // the leftover, Theorem 1): returns the threshold t to compare r against.
 // Only called when r < P, so t is computed on the rare slow path.
-__device__ __forceinline__ uint64_t group_threshold(const BoundProduct &P)
+__host__ __device__ __forceinline__ uint64_t group_threshold(const BoundProduct &P)
 {
     return P.e64 ? 0 : pow2_64_mod(P.p);
 }

@@ -4,11 +4,13 @@
 // threshold 2^64 mod P computed and the group rerolled while r stays below
 // it. The constant-bound form uses Algorithm 2 with t precomputed.
 //
-// Work mapping: one lane owns a "quad" of 4 consecutive groups = 4K rolls,
-// read and written as K 16-byte vectors, and draws its 4 words from two
-// Philox blocks (block = 2 words, and group g's first word is word g). The
-// at most 4 groups past the last full quad (including a short last group)
-// go to the lanes after the last quad, one group each.
+// Work mapping: a wavefront owns a tile of 64*G consecutive groups; lane L
+// takes groups g0 + 64j + L (j < G), so every load and store instruction of
+// the wave covers one contiguous span of 64*K*4 bytes. Group g reads word g
+// on its first attempt; words 2m and 2m+1 are the two halves of Philox block
+// m, so lanes L and L^1 each compute one block per pair of their groups and
+// swap the half the other one needs (a DPP lane swap). Rerolls read word
+// a*S + g on attempt a.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -17,6 +19,68 @@ namespace brr {
 namespace {
 
 constexpr uint64_t kMaxAttempts = 1024;
+constexpr int kGroupsPerLane = 4;
+
+// Value of lane L^1 (swap within lane pairs, quad_perm [1,0,3,2]).
+__device__ __forceinline__ uint64_t swap_lane_pair(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, 0xB1, 0xF, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), 0xB1, 0xF, 0xF, false);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// First-attempt words of this lane's G groups g0 + 64j + lane.
+template <int G>
+__device__ __forceinline__ void tile_words(uint64_t g0, uint32_t lane, const StreamKey &key,
+                                           uint64_t *r)
+{
+#pragma unroll
+    for (int t = 0; t < G / 2; ++t) {
+        // even lanes: block of their group 2t (and the next lane's);
+        // odd lanes: block of the previous lane's group 2t+1 (and theirs)
+        const uint64_t gb = g0 + 64 * (2 * t + (lane & 1)) + (lane & ~1u);
+        uint64_t we, wo;
+        word_pair(gb >> 1, key, we, wo);
+        const uint64_t recv = swap_lane_pair((lane & 1) ? we : wo);
+        r[2 * t] = (lane & 1) ? recv : we;
+        r[2 * t + 1] = (lane & 1) ? wo : recv;
+    }
+}
+
+template <int K, bool VEC>
+__device__ __forceinline__ void load_group(const uint32_t *__restrict__ p, uint32_t *b)
+{
+    if (VEC && K == 4) {
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        b[0] = v.x;
+        b[1] = v.y;
+        b[2] = v.z;
+        b[3] = v.w;
+    } else if (VEC && K == 2) {
+        const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+        b[0] = v.x;
+        b[1] = v.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) b[i] = __builtin_nontemporal_load(p + i);
+    }
+}
+
+template <int K, bool VEC>
+__device__ __forceinline__ void store_group(uint32_t *__restrict__ p, const uint32_t *a)
+{
+    if (VEC && K == 4) {
+        const u32x4 v = {a[0], a[1], a[2], a[3]};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+    } else if (VEC && K == 2) {
+        const u32x2 v = {a[0], a[1]};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(p));
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) __builtin_nontemporal_store(a[i], p + i);
+    }
+}
 
 template <int K>
 __device__ __forceinline__ void check_group(const uint32_t *b, int kk, uint64_t r, bool &need,
@@ -39,10 +103,10 @@ __device__ __forceinline__ void check_group(const uint32_t *b, int kk, uint64_t 
     }
 }
 
-// Rolls group `g` again from attempt 1 on until accepted.
+// Rolls group g again from attempt 1 on until accepted.
 template <int K>
 __device__ __forceinline__ void reroll_group(const uint32_t *b, int kk, uint32_t *a, uint64_t t,
-                                          uint64_t S, uint64_t g, StreamKey key)
+                                             uint64_t S, uint64_t g, const StreamKey &key)
 {
     // each attempt is rejected with probability t / 2^64 < 1/2; the cap only
     // bounds the loop against corrupted inputs
@@ -57,139 +121,101 @@ __device__ __forceinline__ void reroll_group(const uint32_t *b, int kk, uint32_t
     } while (r < t && attempt <= kMaxAttempts);
 }
 
-template <int K, bool VEC>
+template <int K, int G, bool VEC>
 __global__ __launch_bounds__(256) void dice_kernel(const uint32_t *__restrict__ bounds,
                                                    uint32_t *__restrict__ out, uint64_t count,
-                                                   uint64_t S, uint64_t nquads, StreamKey key,
+                                                   uint64_t S, uint64_t full, StreamKey key,
                                                    uint32_t *status)
 {
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t g0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * G);
+    if (g0 >= S) return; // the whole wavefront leaves together
+    uint64_t r[G];
+    tile_words<G>(g0, lane, key, r);
+    uint32_t b[G][K], a[G][K];
     uint32_t err = 0;
-    if (tid < nquads) {
-        uint32_t b[4 * K], a[4 * K];
-        const uint64_t base = tid * 4 * K;
-        if (VEC) {
-            const u32x4 *src = reinterpret_cast<const u32x4 *>(bounds + base);
+    if (g0 + 64 * G <= full) { // every group of the tile has K dice
 #pragma unroll
-            for (int v = 0; v < K; ++v) {
-                const u32x4 x = __builtin_nontemporal_load(src + v);
-                b[4 * v + 0] = x.x;
-                b[4 * v + 1] = x.y;
-                b[4 * v + 2] = x.z;
-                b[4 * v + 3] = x.w;
-            }
-        } else {
+        for (int j = 0; j < G; ++j) load_group<K, VEC>(bounds + K * (g0 + 64 * j + lane), b[j]);
 #pragma unroll
-            for (int i = 0; i < 4 * K; ++i) b[i] = bounds[base + i];
-        }
-        uint64_t r[4];
-        word_pair(2 * tid, key, r[0], r[1]);
-        word_pair(2 * tid + 1, key, r[2], r[3]);
+        for (int j = 0; j < G; ++j)
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
+            for (int i = 0; i < K; ++i) a[j][i] = mul_roll(b[j][i], r[j]);
 #pragma unroll
-            for (int i = 0; i < K; ++i) a[g * K + i] = mul_roll(b[g * K + i], r[g]);
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
+        for (int j = 0; j < G; ++j) {
             bool need;
             uint64_t t;
-            check_group<K>(b + g * K, K, r[g], need, t, err);
-            if (need) reroll_group<K>(b + g * K, K, a + g * K, t, S, 4 * tid + g, key);
+            check_group<K>(b[j], K, r[j], need, t, err);
+            if (need) reroll_group<K>(b[j], K, a[j], t, S, g0 + 64 * j + lane, key);
         }
-        if (VEC) {
-            u32x4 *dst = reinterpret_cast<u32x4 *>(out + base);
 #pragma unroll
-            for (int v = 0; v < K; ++v) {
-                const u32x4 o = {a[4 * v + 0], a[4 * v + 1], a[4 * v + 2], a[4 * v + 3]};
-                __builtin_nontemporal_store(o, dst + v);
-            }
-        } else {
+        for (int j = 0; j < G; ++j) store_group<K, VEC>(out + K * (g0 + 64 * j + lane), a[j]);
+    } else { // last tile: short or missing groups
 #pragma unroll
-            for (int i = 0; i < 4 * K; ++i) out[base + i] = a[i];
-        }
-    } else {
-        const uint64_t g = 4 * nquads + (tid - nquads);
-        if (g < S) {
-            const uint64_t first = g * K;
-            const int kk = (int)((count - first < (uint64_t)K) ? count - first : K);
-            uint32_t b[K], a[K];
+        for (int j = 0; j < G; ++j) {
+            const uint64_t g = g0 + 64 * j + lane;
+            const int kk = (g < full) ? K : (g < S ? (int)(count - K * g) : 0);
+            if (kk == 0) continue;
 #pragma unroll
-            for (int i = 0; i < K; ++i) b[i] = (i < kk) ? bounds[first + i] : 1u;
-            uint64_t r = word_at(g, key);
+            for (int i = 0; i < K; ++i) b[j][i] = (i < kk) ? bounds[K * g + i] : 1u;
 #pragma unroll
             for (int i = 0; i < K; ++i)
-                if (i < kk) a[i] = mul_roll(b[i], r);
+                if (i < kk) a[j][i] = mul_roll(b[j][i], r[j]);
             bool need;
             uint64_t t;
-            check_group<K>(b, kk, r, need, t, err);
-            if (need) reroll_group<K>(b, kk, a, t, S, g, key);
+            check_group<K>(b[j], kk, r[j], need, t, err);
+            if (need) reroll_group<K>(b[j], kk, a[j], t, S, g, key);
 #pragma unroll
             for (int i = 0; i < K; ++i)
-                if (i < kk) out[first + i] = a[i];
+                if (i < kk) out[K * g + i] = a[j][i];
         }
     }
     if (err) atomicOr(status, err);
 }
 
 // Constant bound (Algorithm 2): t_full is 2^64 mod bound^K, t_last the same
-// for the short last group of k_last dice.
-template <int K, bool VEC>
+// for the short last group.
+template <int K, int G, bool VEC>
 __global__ __launch_bounds__(256) void dice_const_kernel(uint32_t bound, uint32_t *__restrict__ out,
-                                                         uint64_t count, uint64_t S,
-                                                         uint64_t nquads, StreamKey key,
-                                                         uint64_t t_full, uint64_t t_last)
+                                                         uint64_t count, uint64_t S, uint64_t full,
+                                                         StreamKey key, uint64_t t_full,
+                                                         uint64_t t_last)
 {
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid < nquads) {
-        uint32_t a[4 * K];
-        uint64_t r[4];
-        word_pair(2 * tid, key, r[0], r[1]);
-        word_pair(2 * tid + 1, key, r[2], r[3]);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t g0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * G);
+    if (g0 >= S) return;
+    uint64_t r[G];
+    tile_words<G>(g0, lane, key, r);
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            uint64_t rr = r[g];
+    for (int j = 0; j < G; ++j) {
+        const uint64_t g = g0 + 64 * j + lane;
+        const int kk = (g < full) ? K : (g < S ? (int)(count - K * g) : 0);
+        if (kk == 0) continue;
+        const uint64_t t = (kk == K) ? t_full : t_last;
+        uint32_t a[K];
+        uint64_t rr = r[j];
 #pragma unroll
-            for (int i = 0; i < K; ++i) a[g * K + i] = mul_roll(bound, rr);
-            const uint64_t G = 4 * tid + g;
-            const uint64_t t = (G + 1 == S) ? t_last : t_full;
-            for (uint64_t attempt = 1; rr < t && attempt <= kMaxAttempts; ++attempt) {
-                rr = word_at(attempt * S + G, key);
-#pragma unroll
-                for (int i = 0; i < K; ++i) a[g * K + i] = mul_roll(bound, rr);
-            }
-        }
-        const uint64_t base = tid * 4 * K;
-        if (VEC) {
-            u32x4 *dst = reinterpret_cast<u32x4 *>(out + base);
-#pragma unroll
-            for (int v = 0; v < K; ++v) {
-                const u32x4 o = {a[4 * v + 0], a[4 * v + 1], a[4 * v + 2], a[4 * v + 3]};
-                __builtin_nontemporal_store(o, dst + v);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4 * K; ++i) out[base + i] = a[i];
-        }
-    } else {
-        const uint64_t g = 4 * nquads + (tid - nquads);
-        if (g < S) {
-            const uint64_t first = g * K;
-            const int kk = (int)((count - first < (uint64_t)K) ? count - first : K);
-            const uint64_t t = (g + 1 == S) ? t_last : t_full;
-            uint32_t a[K];
-            uint64_t attempt = 0, r;
-            do {
-                r = word_at(attempt * S + g, key);
-#pragma unroll
-                for (int i = 0; i < K; ++i)
-                    if (i < kk) a[i] = mul_roll(bound, r);
-                ++attempt;
-            } while (r < t && attempt <= kMaxAttempts);
+        for (int i = 0; i < K; ++i)
+            if (i < kk) a[i] = mul_roll(bound, rr);
+        for (uint64_t attempt = 1; rr < t && attempt <= kMaxAttempts; ++attempt) {
+            rr = word_at(attempt * S + g, key);
 #pragma unroll
             for (int i = 0; i < K; ++i)
-                if (i < kk) out[first + i] = a[i];
+                if (i < kk) a[i] = mul_roll(bound, rr);
         }
+        if (kk == K)
+            store_group<K, VEC>(out + K * g, a);
+        else
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (i < kk) out[K * g + i] = a[i];
     }
+}
+
+uint32_t tile_blocks(uint64_t S)
+{
+    const uint64_t waves = (S + 64 * kGroupsPerLane - 1) / (64 * kGroupsPerLane);
+    return (uint32_t)((waves + 3) / 4); // 4 wavefronts per 256-thread block
 }
 
 template <int K>
@@ -197,16 +223,14 @@ hipError_t launch_dice_k(const uint32_t *bounds, uint32_t *out, uint64_t count, 
                          uint32_t *status, hipStream_t stream)
 {
     const uint64_t S = (count + K - 1) / K;
-    const uint64_t nquads = (count / K) / 4;
-    const uint64_t lanes = nquads + (S - 4 * nquads);
-    const uint64_t blocks = (lanes + 255) / 256;
+    const uint64_t full = count / K;
     const bool vec = ((((uintptr_t)bounds) | ((uintptr_t)out)) & 15) == 0;
     if (vec)
-        dice_kernel<K, true><<<dim3((uint32_t)blocks), dim3(256), 0, stream>>>(bounds, out, count, S,
-                                                                              nquads, key, status);
+        dice_kernel<K, kGroupsPerLane, true><<<tile_blocks(S), 256, 0, stream>>>(
+            bounds, out, count, S, full, key, status);
     else
-        dice_kernel<K, false><<<dim3((uint32_t)blocks), dim3(256), 0, stream>>>(
-            bounds, out, count, S, nquads, key, status);
+        dice_kernel<K, kGroupsPerLane, false><<<tile_blocks(S), 256, 0, stream>>>(
+            bounds, out, count, S, full, key, status);
     return hipGetLastError();
 }
 
@@ -215,16 +239,14 @@ hipError_t launch_dice_const_k(uint32_t bound, uint32_t *out, uint64_t count, St
                                uint64_t t_full, uint64_t t_last, hipStream_t stream)
 {
     const uint64_t S = (count + K - 1) / K;
-    const uint64_t nquads = (count / K) / 4;
-    const uint64_t lanes = nquads + (S - 4 * nquads);
-    const uint64_t blocks = (lanes + 255) / 256;
+    const uint64_t full = count / K;
     const bool vec = (((uintptr_t)out) & 15) == 0;
     if (vec)
-        dice_const_kernel<K, true><<<dim3((uint32_t)blocks), dim3(256), 0, stream>>>(
-            bound, out, count, S, nquads, key, t_full, t_last);
+        dice_const_kernel<K, kGroupsPerLane, true><<<tile_blocks(S), 256, 0, stream>>>(
+            bound, out, count, S, full, key, t_full, t_last);
     else
-        dice_const_kernel<K, false><<<dim3((uint32_t)blocks), dim3(256), 0, stream>>>(
-            bound, out, count, S, nquads, key, t_full, t_last);
+        dice_const_kernel<K, kGroupsPerLane, false><<<tile_blocks(S), 256, 0, stream>>>(
+            bound, out, count, S, full, key, t_full, t_last);
     return hipGetLastError();
 }
 
