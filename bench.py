@@ -65,7 +65,7 @@ def time_launches(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per step
 
 
-def secondary(brr, workloads, up, steps):
+def secondary(brr, workloads, up, steps, only=None):
     import numpy as np
 
     out = {}
@@ -87,10 +87,15 @@ def secondary(brr, workloads, up, steps):
         res["hbm_frac_k6"] = 2 * 4 * data.size / (res["k6"]["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS
         out[tag] = res
 
-    batched(np.full(65536, 256, dtype=np.uint64), "equal_65536x256_u32")
-    batched(workloads.ragged_sizes(20000, seed=3), "ragged_20000_u32")
+    if only in (None, "equal"):
+        batched(np.full(65536, 256, dtype=np.uint64), "equal_65536x256_u32")
+    if only in (None, "ragged"):
+        batched(workloads.ragged_sizes(20000, seed=3), "ragged_20000_u32")
 
-    for n, tag in ((10000, "single_10000_u32"), (1 << 26, "single_2p26_u32")):
+    singles = ((10000, "single_10000_u32", "single10000"), (1 << 26, "single_2p26_u32", "single2p26"))
+    for n, tag, key in singles:
+        if only not in (None, key):
+            continue
         a = up(np.arange(n, dtype=np.uint32))
         res = {}
         for name, sched in (("k6", s6), ("k1", s1)):
@@ -110,6 +115,8 @@ def main():
     ap.add_argument("--k", type=int, default=4, help="dice per word of the timed stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--only", choices=["equal", "ragged", "single10000", "single2p26"],
+                    help="run one shuffle workload only (for profiling); prints its timings")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -129,6 +136,10 @@ def main():
 
     def up(a):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    if args.only:
+        print(json.dumps(secondary(brr, workloads, up, args.steps, args.only)), flush=True)
+        return
 
     bounds_np = workloads.dice_bounds(COUNT, seed=7)
     bounds = up(bounds_np)

@@ -51,7 +51,11 @@ brr_status device_ready(uint32_t **status_out)
     return BRR_OK;
 }
 
-brr_status hip_status(hipError_t e) { return e == hipSuccess ? BRR_OK : BRR_EHIP; }
+brr_status hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return BRR_OK;
+    return e == hipErrorOutOfMemory ? BRR_ENOMEM : BRR_EHIP;
+}
 
 // n^(falling k), or 2^64 + 1 for anything above 2^64.
 u128 falling(uint64_t n, uint64_t k)
@@ -158,6 +162,33 @@ DevSched to_dev(const brr_schedule &sc)
     return d;
 }
 
+// One shuffle or sample through the device-wide tier, with stream-ordered
+// scratch.
+hipError_t run_one_gtier(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
+                         void *out, const DevSched &ds, uint64_t seed, uint64_t inst, hipStream_t s)
+{
+    SegTable st;
+    build_segments(n, steps, ds, st);
+    const GItem it{0, 0, inst, n, steps, out_lo, 0, out};
+    GTierArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.data = data;
+    a.eb = eb;
+    a.seed = seed;
+    a.nitems = 1;
+    a.npos = n;
+    a.npairs = (st.S + 1) / 2;
+    a.one_item = &it;
+    a.one_seg = &st;
+    void *scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, gtier_scratch_bytes(n, eb), s);
+    if (e != hipSuccess) return e;
+    a.scratch = scratch;
+    e = launch_gtier(a, s);
+    const hipError_t f = hipFreeAsync(scratch, s);
+    return e != hipSuccess ? e : f;
+}
+
 } // namespace
 
 // ---------------------------------------------------------------------------
@@ -174,10 +205,16 @@ struct brr_plan {
     std::vector<uint64_t> h_off;
     // classification (made on first run, after the mapping is final)
     bool classified = false;
-    uint32_t n_wave = 0, n_wg = 0, n_big = 0;
+    uint32_t n_wave = 0, n_wg = 0, n_peel = 0, n_big = 0;
     uint32_t wave_max_n = 0, wg_max_n = 0;
-    uint32_t *d_items = nullptr;   // [wave items | wg items | big items]
-    uint64_t *d_big_off = nullptr; // scratch byte offset of each big item
+    uint32_t *d_items = nullptr; // [wave items | wg items | peel items]
+    // device-wide tier for the shuffles too large for LDS
+    GItem *d_gitems = nullptr;
+    SegTable *d_gsegs = nullptr;
+    uint64_t *d_gbase = nullptr; // pos_base[n_big + 1] | pair_base[n_big + 1]
+    uint32_t *d_gtile = nullptr; // item of each position tile | of each pair tile
+    uint64_t g_pos_tiles = 0;
+    uint64_t g_npos = 0, g_npairs = 0;
     void *d_scratch = nullptr;
     // graph of the launch sequence, bound to the buffers of the last run
     hipStream_t capture_stream = nullptr;
@@ -196,21 +233,38 @@ void release(brr_plan *p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     if (p->d_items) (void)hipFree(p->d_items);
-    if (p->d_big_off) (void)hipFree(p->d_big_off);
+    if (p->d_gitems) (void)hipFree(p->d_gitems);
+    if (p->d_gsegs) (void)hipFree(p->d_gsegs);
+    if (p->d_gbase) (void)hipFree(p->d_gbase);
+    if (p->d_gtile) (void)hipFree(p->d_gtile);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
     p->exec = nullptr;
     p->graph = nullptr;
     p->capture_stream = nullptr;
     p->d_items = nullptr;
-    p->d_big_off = nullptr;
+    p->d_gitems = nullptr;
+    p->d_gsegs = nullptr;
+    p->d_gbase = nullptr;
+    p->d_gtile = nullptr;
     p->d_scratch = nullptr;
+}
+
+template <typename T> brr_status upload(T **dst, const std::vector<T> &src)
+{
+    if (src.empty()) return BRR_OK;
+    if (hipMalloc(reinterpret_cast<void **>(dst), src.size() * sizeof(T)) != hipSuccess)
+        return BRR_ENOMEM;
+    if (hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return BRR_EHIP;
+    return BRR_OK;
 }
 
 brr_status classify(brr_plan *p)
 {
-    std::vector<uint32_t> wave, wg, big;
-    std::vector<uint64_t> big_off;
-    uint64_t scratch = 0;
+    std::vector<uint32_t> wave, wg, peel;
+    std::vector<GItem> gitems;
+    std::vector<SegTable> gsegs;
+    std::vector<uint64_t> pos_base(1, 0), pair_base(1, 0);
     const uint32_t wave_cap = std::min<uint32_t>(p->map.wave_max, wave_tier_max_n());
     const uint32_t wg_cap = lds_tier_max_n();
     for (uint64_t q = 0; q < p->count; ++q) {
@@ -222,34 +276,51 @@ brr_status classify(brr_plan *p)
         } else if (n <= wg_cap) {
             wg.push_back((uint32_t)q);
             p->wg_max_n = std::max<uint32_t>(p->wg_max_n, (uint32_t)n);
+        } else if (n <= peel_tier_max_n()) {
+            peel.push_back((uint32_t)q);
         } else {
-            big.push_back((uint32_t)q);
-            big_off.push_back(scratch);
-            scratch += global_scratch_bytes(n, p->eb);
+            SegTable st;
+            build_segments((uint32_t)n, (uint32_t)(n - 1), p->ds, st);
+            gitems.push_back(GItem{p->h_off[q], pos_base.back(), q, (uint32_t)n,
+                                   (uint32_t)(n - 1), 0, 0, nullptr});
+            gsegs.push_back(st);
+            pos_base.push_back(pos_base.back() + n);
+            pair_base.push_back(pair_base.back() + (st.S + 1) / 2);
         }
     }
     p->n_wave = (uint32_t)wave.size();
     p->n_wg = (uint32_t)wg.size();
-    p->n_big = (uint32_t)big.size();
-    std::vector<uint32_t> items;
-    items.reserve(wave.size() + wg.size() + big.size());
-    items.insert(items.end(), wave.begin(), wave.end());
+    p->n_peel = (uint32_t)peel.size();
+    p->n_big = (uint32_t)gitems.size();
+    std::vector<uint32_t> items(wave);
     items.insert(items.end(), wg.begin(), wg.end());
-    items.insert(items.end(), big.begin(), big.end());
-    if (!items.empty()) {
-        if (hipMalloc(reinterpret_cast<void **>(&p->d_items), items.size() * 4) != hipSuccess)
+    items.insert(items.end(), peel.begin(), peel.end());
+    brr_status st = upload(&p->d_items, items);
+    if (st != BRR_OK) return st;
+    if (p->n_big) {
+        std::vector<uint64_t> bases(pos_base);
+        bases.insert(bases.end(), pair_base.begin(), pair_base.end());
+        if ((st = upload(&p->d_gitems, gitems)) != BRR_OK) return st;
+        if ((st = upload(&p->d_gsegs, gsegs)) != BRR_OK) return st;
+        if ((st = upload(&p->d_gbase, bases)) != BRR_OK) return st;
+        p->g_npos = pos_base.back();
+        p->g_npairs = pair_base.back();
+        // owner of the first index of every tile, positions then pairs
+        const uint32_t sh = gtier_tile_shift();
+        std::vector<uint32_t> tiles;
+        for (int which = 0; which < 2; ++which) {
+            const std::vector<uint64_t> &base = which ? pair_base : pos_base;
+            const uint64_t ntiles = (base.back() + (1ull << sh) - 1) >> sh;
+            if (!which) p->g_pos_tiles = ntiles;
+            uint32_t i = 0;
+            for (uint64_t t = 0; t < ntiles; ++t) {
+                while (i + 1 < p->n_big && base[i + 1] <= (t << sh)) ++i;
+                tiles.push_back(i);
+            }
+        }
+        if ((st = upload(&p->d_gtile, tiles)) != BRR_OK) return st;
+        if (hipMalloc(&p->d_scratch, gtier_scratch_bytes(p->g_npos, p->eb)) != hipSuccess)
             return BRR_ENOMEM;
-        if (hipMemcpy(p->d_items, items.data(), items.size() * 4, hipMemcpyHostToDevice) !=
-            hipSuccess)
-            return BRR_EHIP;
-    }
-    if (!big.empty()) {
-        if (hipMalloc(reinterpret_cast<void **>(&p->d_big_off), big_off.size() * 8) != hipSuccess)
-            return BRR_ENOMEM;
-        if (hipMemcpy(p->d_big_off, big_off.data(), big_off.size() * 8, hipMemcpyHostToDevice) !=
-            hipSuccess)
-            return BRR_EHIP;
-        if (hipMalloc(&p->d_scratch, scratch) != hipSuccess) return BRR_ENOMEM;
     }
     p->classified = true;
     return BRR_OK;
@@ -264,8 +335,26 @@ hipError_t enqueue(brr_plan *p, void *data, const uint64_t *offsets, uint64_t se
     e = launch_batched_wg(data, offsets, p->d_items + p->n_wave, p->n_wg, p->wg_max_n, p->eb,
                           p->ds, seed, inst, s);
     if (e != hipSuccess) return e;
-    return launch_batched_big(data, offsets, p->d_items + p->n_wave + p->n_wg, p->n_big, p->eb,
-                              p->ds, seed, inst, p->d_scratch, p->d_big_off, s);
+    e = launch_batched_peel(data, offsets, p->d_items + p->n_wave + p->n_wg, p->n_peel, p->eb,
+                            p->ds, seed, inst, s);
+    if (e != hipSuccess || p->n_big == 0) return e;
+    GTierArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.data = data;
+    a.eb = p->eb;
+    a.seed = seed;
+    a.inst_base = inst;
+    a.nitems = p->n_big;
+    a.npos = p->g_npos;
+    a.npairs = p->g_npairs;
+    a.items = p->d_gitems;
+    a.segs = p->d_gsegs;
+    a.pos_base = p->d_gbase;
+    a.pair_base = p->d_gbase + p->n_big + 1;
+    a.pos_tile = p->d_gtile;
+    a.pair_tile = p->d_gtile + p->g_pos_tiles;
+    a.scratch = p->d_scratch;
+    return launch_gtier(a, s);
 }
 
 brr_status run_plan(brr_plan *p, void *data, const uint64_t *offsets, uint64_t seed, uint64_t inst,
@@ -410,13 +499,8 @@ brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_
         return hip_status(
             launch_lds_single(d_data, (uint32_t)n, (uint32_t)(n - 1), 0, elem_bytes, nullptr, ds,
                               key, s));
-    void *scratch = nullptr;
-    if (hipMallocAsync(&scratch, global_scratch_bytes(n, elem_bytes), s) != hipSuccess)
-        return BRR_ENOMEM;
-    const hipError_t e = launch_global_single(d_data, (uint32_t)n, (uint32_t)(n - 1), 0,
-                                              elem_bytes, nullptr, ds, key, scratch, s);
-    (void)hipFreeAsync(scratch, s);
-    return hip_status(e);
+    return hip_status(run_one_gtier(d_data, (uint32_t)n, (uint32_t)(n - 1), 0, elem_bytes, nullptr,
+                                    ds, seed, inst, s));
 }
 
 brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_bytes, void *d_out,
@@ -442,13 +526,8 @@ brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_
     if (n <= lds_tier_max_n())
         return hip_status(launch_lds_single(data, (uint32_t)n, (uint32_t)steps, out_lo, elem_bytes,
                                             d_out, ds, key, s));
-    void *scratch = nullptr;
-    if (hipMallocAsync(&scratch, global_scratch_bytes(n, elem_bytes), s) != hipSuccess)
-        return BRR_ENOMEM;
-    const hipError_t e = launch_global_single(data, (uint32_t)n, (uint32_t)steps, out_lo,
-                                              elem_bytes, d_out, ds, key, scratch, s);
-    (void)hipFreeAsync(scratch, s);
-    return hip_status(e);
+    return hip_status(run_one_gtier(data, (uint32_t)n, (uint32_t)steps, out_lo, elem_bytes, d_out,
+                                    ds, seed, inst, s));
 }
 
 brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t count,

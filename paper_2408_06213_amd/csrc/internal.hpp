@@ -83,8 +83,10 @@ hipError_t launch_dice_const(uint32_t bound, uint32_t *out, uint64_t count, uint
 
 // Largest n that one workgroup shuffles with its index arrays in LDS.
 uint32_t lds_tier_max_n();
-// Device scratch bytes that the global tier needs for n elements.
-uint64_t global_scratch_bytes(uint64_t n, uint32_t eb);
+// Largest n of the one-wavefront-per-shuffle tier.
+uint32_t wave_tier_max_n();
+// Raises the dynamic-LDS limit of the LDS-tier kernels (once per device).
+hipError_t prepare_shuffle_kernels();
 
 // One shuffle (steps = n - 1, out = nullptr, in place) or one sample
 // (out != nullptr: out[n-1-p] = final z[p] for out_lo <= p < n, the input
@@ -93,29 +95,54 @@ uint64_t global_scratch_bytes(uint64_t n, uint32_t eb);
 hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
                              void *out, const DevSched &sc, StreamKey key, hipStream_t stream);
 
-// The same over the whole device with index arrays in `scratch`
-// (global_scratch_bytes(n, eb) bytes).
-hipError_t launch_global_single(void *data, uint32_t n, uint32_t steps, uint32_t out_lo,
-                                uint32_t eb, void *out, const DevSched &sc, StreamKey key,
-                                void *scratch, hipStream_t stream);
+// One item of the device-wide tier: the array at element offset data_off of
+// the shared data pointer, n elements, the first `steps` Fisher-Yates steps
+// (n - 1 for a shuffle), its positions at pos_base in the index arrays, its
+// word-stream instance. out == nullptr: shuffle in place; else a sample:
+// out[n-1-p] = final z[p] for out_lo <= p < n.
+struct GItem {
+    uint64_t data_off, pos_base, inst;
+    uint32_t n, steps, out_lo, pad;
+    void *out;
+};
+
+// A device-wide problem: items, their segment tables and the prefix sums of
+// their positions and batch pairs (device arrays of nitems + 1), or, for a
+// single item, host copies of its descriptor (one_item/one_seg).
+struct GTierArgs {
+    void *data;
+    uint32_t eb;
+    uint64_t seed;
+    uint64_t inst_base; // item q uses instance inst_base + items[q].inst
+    uint32_t nitems;
+    uint64_t npos, npairs;
+    const GItem *items;      // device
+    const SegTable *segs;    // device
+    const uint64_t *pos_base, *pair_base; // device
+    const uint32_t *pos_tile, *pair_tile; // device: item of index 2^shift * t
+    const GItem *one_item;   // host, nitems == 1
+    const SegTable *one_seg; // host, nitems == 1
+    void *scratch;           // gtier_scratch_bytes(npos, eb)
+};
+uint64_t gtier_scratch_bytes(uint64_t npos, uint32_t eb);
+uint32_t gtier_tile_shift(); // log2 of the indices per tile-table entry
+hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream);
 
 // Batched shuffles of one size class. items: device u32[nitems] of shuffle
-// indices into the CSR offsets. Class 0: one wavefront per shuffle
-// (n <= wave_max); class 1: one workgroup per shuffle with LDS index arrays
-// (n <= lds_tier_max_n()); class 2: one workgroup per shuffle with index
-// arrays in device scratch (scratch_off: device u64[nitems], byte offsets).
+// indices into the CSR offsets. Wave tier: one wavefront per shuffle
+// (n <= wave_tier_max_n()); workgroup tier: one workgroup per shuffle with
+// LDS index arrays (n <= lds_tier_max_n()).
 hipError_t launch_batched_wave(void *data, const uint64_t *offsets, const uint32_t *items,
                                uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
                                uint64_t seed, uint64_t inst_base, hipStream_t stream);
 hipError_t launch_batched_wg(void *data, const uint64_t *offsets, const uint32_t *items,
                              uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
                              uint64_t seed, uint64_t inst_base, hipStream_t stream);
-hipError_t launch_batched_big(void *data, const uint64_t *offsets, const uint32_t *items,
-                              uint32_t nitems, uint32_t eb, const DevSched &sc, uint64_t seed,
-                              uint64_t inst_base, void *scratch, const uint64_t *scratch_off,
-                              hipStream_t stream);
-uint32_t wave_tier_max_n();
-// Raises the dynamic-LDS limit of the LDS-tier kernels (once per device).
-hipError_t prepare_shuffle_kernels();
+// Peel tier: one workgroup per in-place shuffle of lds_tier_max_n() < n <=
+// peel_tier_max_n(), processed top-down in LDS-sized peels.
+uint32_t peel_tier_max_n();
+hipError_t launch_batched_peel(void *data, const uint64_t *offsets, const uint32_t *items,
+                               uint32_t nitems, uint32_t eb, const DevSched &sc, uint64_t seed,
+                               uint64_t inst_base, hipStream_t stream);
 
 } // namespace brr

@@ -24,6 +24,8 @@
 // position; one gather of the original array finishes the shuffle.
 // A sample of m of n runs only the steps p >= n - m and gathers those
 // positions into the output (the input is untouched).
+#include <cstring>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -38,6 +40,7 @@ constexpr int kWgThreads = 1024; // workgroup tier and single-workgroup global t
 constexpr int kWgP = 16;         // positions per thread in the workgroup tier
 constexpr uint32_t kScanTile = 1024 * 16;
 constexpr uint64_t kMaxAttempts = 1024;
+constexpr int kTileShift = 8; // 256 indices per tile of the item tables
 
 __device__ __forceinline__ void batch_at(uint32_t s, const Seg *seg, uint32_t nseg, uint32_t &i,
                                          uint32_t &k, uint64_t &u)
@@ -253,10 +256,183 @@ __global__ __launch_bounds__(BLOCK) void k_lds_batched(Elem *data, const uint64_
                                  make_key(seed, inst_base + q), smem, wsum);
 }
 
+constexpr uint32_t kPeel = 8192;       // positions per peel
+constexpr uint32_t kPeelHashBits = 12; // 4096 chains, load factor <= 2
+constexpr uint32_t kPeelTierMax = 1u << 20;
+
+__device__ __forceinline__ uint32_t peel_hash(uint32_t q)
+{
+    return (q * 2654435761u) >> (32 - kPeelHashBits);
+}
+
+struct PeelState {
+    const uint32_t *qof;  // target of the step at local position p' (= p - i_end)
+    const uint16_t *nxt;  // next entry of the same chain
+    const uint32_t *table; // chain heads (local positions)
+    uint32_t i_end, H;
+};
+
+// Smallest step p'' (global position) targeting q with lo < p'' (kNone32 if
+// none), among the steps of the peel.
+__device__ __forceinline__ uint32_t peel_min_above(const PeelState &ps, uint32_t q, uint32_t lo)
+{
+    uint32_t best = kNone32;
+    uint32_t e = ps.table[peel_hash(q)];
+    for (uint32_t guard = 0; e != kNone32 && guard < ps.H; ++guard) {
+        const uint32_t pg = ps.i_end + e;
+        if (ps.qof[e] == q && pg > lo && pg < best) best = pg;
+        const uint16_t nx = ps.nxt[e];
+        e = (nx == kNone16) ? kNone32 : nx;
+    }
+    return best;
+}
+
+// Whether some step of the peel below position p targets q.
+__device__ __forceinline__ bool peel_any_below(const PeelState &ps, uint32_t q, uint32_t p)
+{
+    uint32_t e = ps.table[peel_hash(q)];
+    for (uint32_t guard = 0; e != kNone32 && guard < ps.H; ++guard) {
+        if (ps.qof[e] == q && ps.i_end + e < p) return true;
+        const uint16_t nx = ps.nxt[e];
+        e = (nx == kNone16) ? kNone32 : nx;
+    }
+    return false;
+}
+
+// End of the head chain x -> min T_H(x) -> ... (x inside the peel).
+__device__ __forceinline__ uint32_t peel_walk(const PeelState &ps, uint32_t x)
+{
+    for (uint32_t guard = 0; guard < ps.H; ++guard) {
+        const uint32_t h = peel_min_above(ps, x, x);
+        if (h == kNone32) break;
+        x = h;
+    }
+    return x;
+}
+
+template <typename Elem>
+__global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const uint64_t *offsets,
+                                                             const uint32_t *items, DevSched sc,
+                                                             uint64_t seed, uint64_t inst_base)
+{
+    constexpr uint32_t PEEL = kPeel;
+    constexpr int P = PEEL / kWgThreads;
+    __shared__ uint32_t qof[kPeel];
+    __shared__ uint16_t nxt[kPeel];
+    __shared__ uint32_t table[1u << kPeelHashBits];
+    __shared__ SegTable st;
+    __shared__ uint32_t next_s, next_i;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t q_item = items[blockIdx.x];
+    const uint64_t off = offsets[q_item];
+    const uint32_t n = (uint32_t)(offsets[q_item + 1] - off);
+    if (n <= 1) return;
+    Elem *z = data + off;
+    const StreamKey key = make_key(seed, inst_base + q_item);
+    if (tid == 0) build_segments(n, n - 1, sc, st);
+    __syncthreads();
+    uint32_t s_begin = 0, i_begin = n;
+    while (s_begin < st.S) {
+        if (tid == 0) { // whole batches, at most PEEL positions, a segment at a time
+            uint32_t s = s_begin, i = i_begin, g = 0;
+            while (g + 1 < st.nseg && s >= st.seg[g + 1].s0) ++g;
+            for (; g < st.nseg && s < st.S; ++g) {
+                const Seg &sg = st.seg[g];
+                const uint32_t left = sg.s0 + sg.cnt - s;
+                uint32_t nb = (PEEL - (i_begin - i)) / sg.k;
+                if (nb > left) nb = left;
+                s += nb;
+                i -= nb * sg.k;
+                if (nb < left) break;
+            }
+            next_s = s;
+            next_i = i;
+        }
+        for (uint32_t x = tid; x < (1u << kPeelHashBits); x += kWgThreads) table[x] = kNone32;
+        __syncthreads();
+        const uint32_t s_end = next_s, i_end = next_i, H = i_begin - i_end;
+        for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += kWgThreads) {
+            uint64_t w[2];
+            word_pair(m, key, w[0], w[1]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t s = 2 * m + h;
+                if (s < s_begin || s >= s_end) continue;
+                uint32_t i, k;
+                uint64_t u;
+                batch_at(s, st.seg, st.nseg, i, k, u);
+                uint64_t r = accept_word(i, k, u, w[h], st.S, s, key);
+                for (uint32_t l = 0; l < k; ++l) qof[i - 1 - l - i_end] = mul_roll(i - l, r);
+            }
+        }
+        __syncthreads();
+        for (uint32_t e = tid; e < H; e += kWgThreads) {
+            const uint32_t q = qof[e];
+            if (q != i_end + e) {
+                const uint32_t old = atomicExch(&table[peel_hash(q)], e);
+                nxt[e] = (old == kNone32) ? kNone16 : (uint16_t)old;
+            }
+        }
+        __syncthreads();
+        const PeelState ps{qof, nxt, table, i_end, H};
+        // sources first (LDS only), then all gathers back to back
+        uint32_t src[P], ext_q[P], ext_src[P];
+        uint32_t ext_mask = 0;
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const uint32_t e = tid + r * kWgThreads;
+            if (e >= H) continue;
+            const uint32_t p = i_end + e, q = qof[e];
+            if (q == p) {
+                src[r] = peel_walk(ps, p);
+            } else {
+                const uint32_t sc = peel_min_above(ps, q, p);
+                src[r] = (sc == kNone32) ? q : peel_walk(ps, sc);
+            }
+            // the smallest step into a target below the peel deposits V(p) there
+            if (q < i_end && !peel_any_below(ps, q, p)) {
+                ext_mask |= 1u << r;
+                ext_q[r] = q;
+                ext_src[r] = peel_walk(ps, p);
+            }
+        }
+        Elem val[P], ext_val[P];
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            if (tid + r * kWgThreads < H) val[r] = z[src[r]];
+            if (ext_mask & (1u << r)) ext_val[r] = z[ext_src[r]];
+        }
+        // Every read of z precedes every write. Only this workgroup touches
+        // its array, with plain loads and stores; its wavefronts share the
+        // CU's vector cache, so workgroup-scope ordering suffices.
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const uint32_t e = tid + r * kWgThreads;
+            if (e >= H) continue;
+            z[i_end + e] = val[r];
+            if (ext_mask & (1u << r)) z[ext_q[r]] = ext_val[r];
+        }
+        __syncthreads(); // the next peel reads what this one wrote
+        s_begin = s_end;
+        i_begin = i_end;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Global tier: the same steps with every array in device scratch.
-// Layout for n: jj u32[n] | slot u32[n] | cnt u32[n+1] | head u32[n] |
-//               bucket u32[n] | tiles u32[ntiles] | tmp Elem[n].
+// Device-wide tier: any number of shuffles/samples ("items") too large for
+// LDS, processed together by grid-wide kernels. Item i owns positions
+// pos_base[i] .. pos_base[i+1]-1 of the concatenated index arrays and batch
+// pairs pair_base[i] .. pair_base[i+1]-1.
+//   dice:    jj[x] = j_p; slot[x] = rank of step p among the steps into j_p
+//   scan:    cnt = exclusive prefix of the per-target counts, over all items
+//            (item i's last target ends where item i+1's first begins)
+//   scatter: bucket[cnt[target] + slot] = p
+//   head:    one sequential pass over targets: head[x] = min of bucket(x),
+//            and for every step p in bucket(x) its successor there (stored
+//            in slot[], which is dead after the scatter)
+//   resolve: source of every output position, gathered from the input
+//   copy:    in-place shuffles copy the gathered values back
 // ---------------------------------------------------------------------------
 
 struct GArrays {
@@ -264,226 +440,239 @@ struct GArrays {
     void *tmp;
 };
 
-__host__ __device__ inline uint64_t align16(uint64_t x) { return (x + 15) & ~(uint64_t)15; }
+__host__ __device__ inline uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
-__host__ __device__ inline uint32_t scan_tiles(uint32_t n) { return (n + 1 + kScanTile - 1) / kScanTile; }
+__host__ __device__ inline uint64_t scan_tiles(uint64_t len) { return (len + kScanTile - 1) / kScanTile; }
 
-__host__ __device__ inline uint64_t garrays_bytes(uint64_t n, uint32_t eb)
+__host__ __device__ inline uint64_t garrays_bytes(uint64_t npos, uint32_t eb)
 {
-    const uint64_t w = align16(4 * n);
-    return 4 * w + align16(4 * (n + 1)) + align16(4 * (uint64_t)scan_tiles((uint32_t)n)) +
-           align16(eb * n);
+    const uint64_t w = align256(4 * npos);
+    return 4 * w + align256(4 * (npos + 1)) + align256(4 * scan_tiles(npos + 1)) +
+           align256(eb * npos);
 }
 
-__host__ __device__ inline GArrays garrays(void *base, uint32_t n)
+__host__ __device__ inline GArrays garrays(void *base, uint64_t npos)
 {
     char *p = static_cast<char *>(base);
-    const uint64_t w = align16(4 * (uint64_t)n);
+    const uint64_t w = align256(4 * npos);
     GArrays g;
     g.jj = reinterpret_cast<uint32_t *>(p);
     p += w;
     g.slot = reinterpret_cast<uint32_t *>(p);
     p += w;
     g.cnt = reinterpret_cast<uint32_t *>(p);
-    p += align16(4 * ((uint64_t)n + 1));
+    p += align256(4 * (npos + 1));
     g.head = reinterpret_cast<uint32_t *>(p);
     p += w;
     g.bucket = reinterpret_cast<uint32_t *>(p);
     p += w;
     g.tiles = reinterpret_cast<uint32_t *>(p);
-    p += align16(4 * (uint64_t)scan_tiles(n));
+    p += align256(4 * scan_tiles(npos + 1));
     g.tmp = p;
     return g;
 }
 
-// Phase helpers, each over items idx = start, start+stride, ... < end.
-__device__ __forceinline__ void g_init_range(const GArrays &g, uint32_t n, uint32_t start,
-                                             uint32_t stride)
+// Everything the device-wide kernels read about the items. With one item
+// the descriptor travels by value (items/segs/bases may then be null).
+struct GProblem {
+    const GItem *items;
+    const SegTable *segs;
+    const uint64_t *pos_base;  // nitems + 1
+    const uint64_t *pair_base; // nitems + 1
+    const uint32_t *pos_tile;  // item of position 256*t, for every tile t
+    const uint32_t *pair_tile; // item of batch pair 256*t
+    uint32_t nitems;
+    uint64_t npos, npairs;
+    uint64_t inst_base; // added to every item's instance
+    GItem one;
+    SegTable one_seg;
+};
+
+// Item that owns index x: the tile table names the owner of the tile's
+// first index; items that start inside the tile are stepped over (every
+// item of this tier is longer than a tile, so at most one step is taken).
+__device__ __forceinline__ uint32_t find_item(const uint32_t *tile, const uint64_t *base,
+                                              uint32_t nitems, uint64_t x)
 {
-    for (uint32_t x = start; x <= n; x += stride) {
-        g.cnt[x] = 0;
-        if (x < n) g.head[x] = kNone32;
-    }
+    uint32_t i = tile[x >> kTileShift];
+    while (i + 1 < nitems && base[i + 1] <= x) ++i;
+    return i;
 }
 
-__device__ __forceinline__ void g_dice_range(const GArrays &g, const Seg *seg, uint32_t nseg,
-                                             uint32_t S, const StreamKey &key, uint32_t start,
-                                             uint32_t stride)
+__device__ __forceinline__ const GItem &item_at(const GProblem &P, uint32_t i)
 {
-    for (uint32_t m = start; 2 * m < S; m += stride) {
-        uint64_t w[2];
-        word_pair(m, key, w[0], w[1]);
+    return P.items ? P.items[i] : P.one;
+}
+
+__device__ __forceinline__ const SegTable &segs_at(const GProblem &P, uint32_t i)
+{
+    return P.segs ? P.segs[i] : P.one_seg;
+}
+
+__device__ __forceinline__ uint32_t item_of_pos(const GProblem &P, uint64_t x)
+{
+    return P.items ? find_item(P.pos_tile, P.pos_base, P.nitems, x) : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_gp_init(uint32_t *cnt, uint64_t len)
+{
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < len;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        cnt[x] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t seed)
+{
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < P.npairs;
+         w += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = P.items ? find_item(P.pair_tile, P.pair_base, P.nitems, w) : 0u;
+        const GItem &it = item_at(P, i);
+        const SegTable &st = segs_at(P, i);
+        const uint32_t m = (uint32_t)(w - (P.items ? P.pair_base[i] : 0));
+        const StreamKey key = make_key(seed, P.inst_base + it.inst);
+        uint64_t wd[2];
+        word_pair(m, key, wd[0], wd[1]);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t s = 2 * m + h;
-            if (s < S) {
-                uint32_t i, k;
-                uint64_t u;
-                batch_at(s, seg, nseg, i, k, u);
-                uint64_t r = accept_word(i, k, u, w[h], S, s, key);
-                for (uint32_t l = 0; l < k; ++l) {
-                    const uint32_t p = i - 1 - l;
-                    const uint32_t a = mul_roll(i - l, r);
-                    g.jj[p] = a;
-                    if (a < p) {
-                        g.slot[p] = atomicAdd(&g.cnt[a], 1u);
-                        atomicMin(&g.head[a], p);
-                    }
-                }
+            if (s >= st.S) break;
+            uint32_t i0, k;
+            uint64_t u;
+            batch_at(s, st.seg, st.nseg, i0, k, u);
+            uint64_t r = accept_word(i0, k, u, wd[h], st.S, s, key);
+            for (uint32_t l = 0; l < k; ++l) {
+                const uint32_t p = i0 - 1 - l;
+                const uint32_t a = mul_roll(i0 - l, r);
+                g.jj[it.pos_base + p] = a;
+                if (a < p) g.slot[it.pos_base + p] = atomicAdd(&g.cnt[it.pos_base + a], 1u);
             }
         }
     }
 }
 
-__device__ __forceinline__ void g_scatter_range(const GArrays &g, uint32_t n, uint32_t lo,
-                                                uint32_t start, uint32_t stride)
-{
-    for (uint32_t p = lo + start; p < n; p += stride) {
-        const uint32_t q = g.jj[p];
-        if (q < p) g.bucket[g.cnt[q] + g.slot[p]] = p;
-    }
-}
-
-template <typename Elem>
-__device__ __forceinline__ void g_resolve_range(const GArrays &g, const Elem *z, Elem *dst,
-                                                bool reversed, uint32_t n, uint32_t lo,
-                                                uint32_t out_lo, uint32_t start, uint32_t stride)
-{
-    for (uint32_t p = out_lo + start; p < n; p += stride) {
-        const uint32_t q = (p >= lo) ? g.jj[p] : p;
-        uint32_t src;
-        uint32_t x = p;
-        bool walk = true;
-        if (p >= lo && q != p) {
-            uint32_t sc = kNone32;
-            for (uint32_t e = g.cnt[q], e1 = g.cnt[q + 1]; e < e1; ++e) {
-                const uint32_t v = g.bucket[e];
-                if (v > p && v < sc) sc = v;
-            }
-            if (sc == kNone32) {
-                walk = false;
-                src = q;
-            } else {
-                x = sc;
-            }
-        }
-        if (walk) {
-            uint32_t h;
-            for (uint32_t it = 0; it < n && (h = g.head[x]) != kNone32; ++it) x = h;
-            src = x;
-        }
-        dst[reversed ? n - 1 - p : p] = z[src];
-    }
-}
-
-// Device-wide kernels (grid-stride loops).
-__global__ __launch_bounds__(256) void k_g_init(GArrays g, uint32_t n)
-{
-    g_init_range(g, n, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-}
-
-__global__ __launch_bounds__(256) void k_g_dice(GArrays g, SegTable st, StreamKey key)
-{
-    __shared__ Seg seg[kMaxSegs];
-    if (threadIdx.x < st.nseg) seg[threadIdx.x] = st.seg[threadIdx.x];
-    __syncthreads();
-    g_dice_range(g, seg, st.nseg, st.S, key, blockIdx.x * blockDim.x + threadIdx.x,
-                 gridDim.x * blockDim.x);
-}
-
-__global__ __launch_bounds__(1024) void k_g_scan_tiles(GArrays g, uint32_t len)
+__global__ __launch_bounds__(1024) void k_gp_scan_tiles(const uint32_t *a, uint32_t *tiles,
+                                                        uint64_t len)
 {
     __shared__ uint32_t wsum[16];
-    const uint32_t b0 = blockIdx.x * kScanTile;
-    const uint32_t cnt = min(kScanTile, len - b0);
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanTile;
+    const uint32_t n = (uint32_t)min((uint64_t)kScanTile, len - b0);
     uint32_t local = 0;
-    for (uint32_t x = threadIdx.x; x < cnt; x += 1024) local += g.cnt[b0 + x];
+    for (uint32_t x = threadIdx.x; x < n; x += 1024) local += a[b0 + x];
     local = wave_inclusive_scan(local);
     if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = local;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t t = 0;
         for (int w = 0; w < 16; ++w) t += wsum[w];
-        g.tiles[blockIdx.x] = t;
+        tiles[blockIdx.x] = t;
     }
 }
 
-__global__ __launch_bounds__(1024) void k_g_scan_sums(GArrays g, uint32_t ntiles)
+__global__ __launch_bounds__(1024) void k_gp_scan_sums(uint32_t *tiles, uint32_t ntiles)
 {
     __shared__ uint32_t wsum[16];
-    block_scan_array<1024>(g.tiles, ntiles, 0, wsum);
+    block_scan_array<1024>(tiles, ntiles, 0, wsum);
 }
 
-__global__ __launch_bounds__(1024) void k_g_scan_apply(GArrays g, uint32_t len)
+// Exclusive scan of one tile of kScanTile counts starting at the tile's
+// base: coalesced loads into LDS, an LDS scan, coalesced stores.
+__global__ __launch_bounds__(1024) void k_gp_scan_apply(uint32_t *a, const uint32_t *tiles,
+                                                        uint64_t len)
 {
+    __shared__ uint32_t buf[kScanTile];
     __shared__ uint32_t wsum[16];
-    const uint32_t b0 = blockIdx.x * kScanTile;
-    const uint32_t cnt = min(kScanTile, len - b0);
-    block_scan_array<1024>(g.cnt + b0, cnt, g.tiles[blockIdx.x], wsum);
-}
-
-__global__ __launch_bounds__(256) void k_g_scatter(GArrays g, uint32_t n, uint32_t lo)
-{
-    g_scatter_range(g, n, lo, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-}
-
-template <typename Elem>
-__global__ __launch_bounds__(256) void k_g_resolve(GArrays g, const Elem *z, Elem *dst,
-                                                   int reversed, uint32_t n, uint32_t lo,
-                                                   uint32_t out_lo)
-{
-    g_resolve_range<Elem>(g, z, dst, reversed != 0, n, lo, out_lo,
-                          blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-}
-
-template <typename Elem>
-__global__ __launch_bounds__(256) void k_g_copy(Elem *z, const Elem *tmp, uint32_t n)
-{
-    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
-        z[p] = tmp[p];
-}
-
-// Barrier between phases that communicate through device memory, including
-// atomics performed in L2: an agent-scope fence on each side makes the
-// writes visible and drops stale lines from the CU's vector cache.
-__device__ __forceinline__ void phase_barrier()
-{
-    __threadfence();
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanTile;
+    const uint32_t n = (uint32_t)min((uint64_t)kScanTile, len - b0);
+    for (uint32_t x = threadIdx.x; x < n; x += 1024) buf[x] = a[b0 + x];
     __syncthreads();
-    __threadfence();
+    block_scan_array<1024>(buf, n, tiles[blockIdx.x], wsum);
+    for (uint32_t x = threadIdx.x; x < n; x += 1024) a[b0 + x] = buf[x];
 }
 
-// One workgroup per shuffle with arrays in scratch (batched, large n).
-template <typename Elem>
-__global__ __launch_bounds__(kWgThreads) void k_big_batched(Elem *data, const uint64_t *offsets,
-                                                            const uint32_t *items, DevSched sc,
-                                                            uint64_t seed, uint64_t inst_base,
-                                                            char *scratch,
-                                                            const uint64_t *scratch_off)
+__global__ __launch_bounds__(256) void k_gp_scatter(GProblem P, GArrays g)
 {
-    __shared__ SegTable st;
-    __shared__ uint32_t wsum[kWgThreads / 64];
-    const uint32_t q = items[blockIdx.x];
-    const uint64_t off = offsets[q];
-    const uint32_t n = (uint32_t)(offsets[q + 1] - off);
-    if (n <= 1) return;
-    Elem *z = data + off;
-    const GArrays g = garrays(scratch + scratch_off[blockIdx.x], n);
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const GItem &it = item_at(P, item_of_pos(P, x));
+        const uint32_t p = (uint32_t)(x - it.pos_base);
+        if (p < it.n - it.steps) continue;
+        const uint32_t q = g.jj[x];
+        if (q < p) g.bucket[g.cnt[it.pos_base + q] + g.slot[x]] = p;
+    }
+}
+
+// Targets in order: head of each bucket, and each step's successor among the
+// steps into the same target (kNone32 for the largest).
+__global__ __launch_bounds__(256) void k_gp_head(GProblem P, GArrays g)
+{
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t b0 = g.cnt[x], b1 = g.cnt[x + 1];
+        uint32_t h = kNone32;
+        for (uint32_t e = b0; e < b1; ++e) h = min(h, g.bucket[e]);
+        g.head[x] = h;
+        if (b1 > b0) {
+            const GItem &it = item_at(P, item_of_pos(P, x));
+            for (uint32_t e = b0; e < b1; ++e) {
+                const uint32_t v = g.bucket[e];
+                uint32_t sc = kNone32;
+                for (uint32_t f = b0; f < b1; ++f) {
+                    const uint32_t w2 = g.bucket[f];
+                    if (w2 > v && w2 < sc) sc = w2;
+                }
+                g.slot[it.pos_base + v] = sc;
+            }
+        }
+    }
+}
+
+template <typename Elem>
+__global__ __launch_bounds__(256) void k_gp_resolve(GProblem P, GArrays g, const Elem *data)
+{
     Elem *tmp = static_cast<Elem *>(g.tmp);
-    const StreamKey key = make_key(seed, inst_base + q);
-    const uint32_t tid = threadIdx.x;
-    if (tid == 0) build_segments(n, n - 1, sc, st);
-    g_init_range(g, n, tid, kWgThreads);
-    phase_barrier();
-    g_dice_range(g, st.seg, st.nseg, st.S, key, tid, kWgThreads);
-    phase_barrier();
-    block_scan_array<kWgThreads>(g.cnt, n + 1, 0, wsum);
-    phase_barrier();
-    g_scatter_range(g, n, 1, tid, kWgThreads);
-    phase_barrier();
-    g_resolve_range<Elem>(g, z, tmp, false, n, 1, 0, tid, kWgThreads);
-    phase_barrier();
-    for (uint32_t p = tid; p < n; p += kWgThreads) z[p] = tmp[p];
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const GItem &it = item_at(P, item_of_pos(P, x));
+        const uint32_t p = (uint32_t)(x - it.pos_base);
+        if (p < it.out_lo) continue;
+        const uint32_t lo = it.n - it.steps;
+        const uint32_t q = (p >= lo) ? g.jj[x] : p;
+        uint32_t y = p, src;
+        bool walk = true;
+        if (p >= lo && q != p) {
+            const uint32_t sc = g.slot[x];
+            if (sc == kNone32) {
+                walk = false;
+                src = q;
+            } else {
+                y = sc;
+            }
+        }
+        if (walk) {
+            uint32_t h;
+            for (uint32_t guard = 0; guard < it.n && (h = g.head[it.pos_base + y]) != kNone32;
+                 ++guard)
+                y = h;
+            src = y;
+        }
+        const Elem v = data[it.data_off + src];
+        if (it.out)
+            static_cast<Elem *>(it.out)[it.n - 1 - p] = v;
+        else
+            tmp[x] = v;
+    }
+}
+
+template <typename Elem>
+__global__ __launch_bounds__(256) void k_gp_copy(GProblem P, GArrays g, Elem *data)
+{
+    const Elem *tmp = static_cast<const Elem *>(g.tmp);
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const GItem &it = item_at(P, item_of_pos(P, x));
+        if (it.out) continue;
+        data[it.data_off + (x - it.pos_base)] = tmp[x];
+    }
 }
 
 uint32_t grid_for(uint64_t work, uint32_t block)
@@ -495,42 +684,34 @@ uint32_t grid_for(uint64_t work, uint32_t block)
 }
 
 template <typename Elem>
+hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratch,
+                      hipStream_t stream)
+{
+    const GArrays g = garrays(scratch, P.npos);
+    const uint64_t len = P.npos + 1;
+    const uint64_t ntiles = scan_tiles(len);
+    k_gp_init<<<grid_for(len, 256), 256, 0, stream>>>(g.cnt, len);
+    k_gp_dice<<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
+    k_gp_scan_tiles<<<(uint32_t)ntiles, 1024, 0, stream>>>(g.cnt, g.tiles, len);
+    k_gp_scan_sums<<<1, 1024, 0, stream>>>(g.tiles, (uint32_t)ntiles);
+    k_gp_scan_apply<<<(uint32_t)ntiles, 1024, 0, stream>>>(g.cnt, g.tiles, len);
+    k_gp_scatter<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
+    k_gp_head<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
+    k_gp_resolve<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,
+                                                                  static_cast<const Elem *>(data));
+    k_gp_copy<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, static_cast<Elem *>(data));
+    return hipGetLastError();
+}
+
+template <typename Elem>
 hipError_t lds_single_t(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, void *out,
                         const DevSched &sc, StreamKey key, hipStream_t stream)
 {
     SegTable st;
     build_segments(n, steps, sc, st);
     const uint32_t bytes = lds_bytes(n);
-    k_lds_single<Elem, kWgThreads, kWgP><<<1, kWgThreads, bytes, stream>>>(static_cast<Elem *>(data), n, steps, out_lo,
-                                           static_cast<Elem *>(out), st, key);
-    return hipGetLastError();
-}
-
-template <typename Elem>
-hipError_t global_single_t(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, void *out,
-                           const DevSched &sc, StreamKey key, void *scratch, hipStream_t stream)
-{
-    SegTable st;
-    build_segments(n, steps, sc, st);
-    const GArrays g = garrays(scratch, n);
-    const uint32_t lo = n - steps;
-    if (!out) out_lo = 0;
-    Elem *z = static_cast<Elem *>(data);
-    k_g_init<<<grid_for((uint64_t)n + 1, 256), 256, 0, stream>>>(g, n);
-    k_g_dice<<<grid_for((st.S + 1) / 2, 256), 256, 0, stream>>>(g, st, key);
-    const uint32_t ntiles = scan_tiles(n);
-    k_g_scan_tiles<<<ntiles, 1024, 0, stream>>>(g, n + 1);
-    k_g_scan_sums<<<1, 1024, 0, stream>>>(g, ntiles);
-    k_g_scan_apply<<<ntiles, 1024, 0, stream>>>(g, n + 1);
-    k_g_scatter<<<grid_for(steps, 256), 256, 0, stream>>>(g, n, lo);
-    if (out) {
-        k_g_resolve<Elem><<<grid_for(n - out_lo, 256), 256, 0, stream>>>(
-            g, z, static_cast<Elem *>(out), 1, n, lo, out_lo);
-    } else {
-        Elem *tmp = static_cast<Elem *>(g.tmp);
-        k_g_resolve<Elem><<<grid_for(n, 256), 256, 0, stream>>>(g, z, tmp, 0, n, lo, 0);
-        k_g_copy<Elem><<<grid_for(n, 256), 256, 0, stream>>>(z, tmp, n);
-    }
+    k_lds_single<Elem, kWgThreads, kWgP><<<1, kWgThreads, bytes, stream>>>(
+        static_cast<Elem *>(data), n, steps, out_lo, static_cast<Elem *>(out), st, key);
     return hipGetLastError();
 }
 
@@ -541,14 +722,37 @@ hipError_t batched_lds_t(void *data, const uint64_t *offsets, const uint32_t *it
 {
     if (nitems == 0) return hipSuccess;
     const uint32_t bytes = lds_bytes(max_n);
-    k_lds_batched<Elem, BLOCK, P><<<nitems, BLOCK, bytes, stream>>>(static_cast<Elem *>(data), offsets, items, sc, seed,
-                                           inst_base);
+    k_lds_batched<Elem, BLOCK, P><<<nitems, BLOCK, bytes, stream>>>(static_cast<Elem *>(data),
+                                                                  offsets, items, sc, seed,
+                                                                  inst_base);
+    return hipGetLastError();
+}
+
+template <typename Elem>
+hipError_t batched_peel_t(void *data, const uint64_t *offsets, const uint32_t *items,
+                          uint32_t nitems, const DevSched &sc, uint64_t seed, uint64_t inst_base,
+                          hipStream_t stream)
+{
+    if (nitems == 0) return hipSuccess;
+    k_peel_batched<Elem><<<nitems, kWgThreads, 0, stream>>>(static_cast<Elem *>(data), offsets,
+                                                           items, sc, seed, inst_base);
     return hipGetLastError();
 }
 
 } // namespace
 
 uint32_t lds_tier_max_n() { return kWgThreads * kWgP; }
+uint32_t peel_tier_max_n() { return kPeelTierMax; }
+
+hipError_t launch_batched_peel(void *data, const uint64_t *offsets, const uint32_t *items,
+                               uint32_t nitems, uint32_t eb, const DevSched &sc, uint64_t seed,
+                               uint64_t inst_base, hipStream_t stream)
+{
+    return eb == 4 ? batched_peel_t<uint32_t>(data, offsets, items, nitems, sc, seed, inst_base,
+                                              stream)
+                   : batched_peel_t<uint64_t>(data, offsets, items, nitems, sc, seed, inst_base,
+                                              stream);
+}
 
 hipError_t prepare_shuffle_kernels()
 {
@@ -567,8 +771,10 @@ hipError_t prepare_shuffle_kernels()
     }
     return hipSuccess;
 }
+
 uint32_t wave_tier_max_n() { return 64 * kWaveP; }
-uint64_t global_scratch_bytes(uint64_t n, uint32_t eb) { return garrays_bytes(n, eb); }
+uint64_t gtier_scratch_bytes(uint64_t npos, uint32_t eb) { return garrays_bytes(npos, eb); }
+uint32_t gtier_tile_shift() { return kTileShift; }
 
 hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
                              void *out, const DevSched &sc, StreamKey key, hipStream_t stream)
@@ -579,14 +785,28 @@ hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t ou
                    : lds_single_t<uint64_t>(data, n, steps, out_lo, out, sc, key, stream);
 }
 
-hipError_t launch_global_single(void *data, uint32_t n, uint32_t steps, uint32_t out_lo,
-                                uint32_t eb, void *out, const DevSched &sc, StreamKey key,
-                                void *scratch, hipStream_t stream)
+hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream)
 {
-    if (steps == 0 || steps >= n || out_lo > n - steps) return hipErrorInvalidValue;
-    return eb == 4 ? global_single_t<uint32_t>(data, n, steps, out_lo, out, sc, key, scratch, stream)
-                   : global_single_t<uint64_t>(data, n, steps, out_lo, out, sc, key, scratch,
-                                               stream);
+    if (a.nitems == 0) return hipSuccess;
+    GProblem P;
+    std::memset(&P, 0, sizeof P);
+    P.nitems = a.nitems;
+    P.npos = a.npos;
+    P.npairs = a.npairs;
+    P.inst_base = a.inst_base;
+    if (a.nitems == 1 && a.one_item) {
+        P.one = *a.one_item;
+        P.one_seg = *a.one_seg;
+    } else {
+        P.items = a.items;
+        P.segs = a.segs;
+        P.pos_base = a.pos_base;
+        P.pair_base = a.pair_base;
+        P.pos_tile = a.pos_tile;
+        P.pair_tile = a.pair_tile;
+    }
+    return a.eb == 4 ? gproblem_t<uint32_t>(P, a.data, a.seed, a.scratch, stream)
+                     : gproblem_t<uint64_t>(P, a.data, a.seed, a.scratch, stream);
 }
 
 hipError_t launch_batched_wave(void *data, const uint64_t *offsets, const uint32_t *items,
@@ -609,23 +829,6 @@ hipError_t launch_batched_wg(void *data, const uint64_t *offsets, const uint32_t
                                                                sc, seed, inst_base, stream)
                    : batched_lds_t<uint64_t, kWgThreads, kWgP>(data, offsets, items, nitems, max_n,
                                                                sc, seed, inst_base, stream);
-}
-
-hipError_t launch_batched_big(void *data, const uint64_t *offsets, const uint32_t *items,
-                              uint32_t nitems, uint32_t eb, const DevSched &sc, uint64_t seed,
-                              uint64_t inst_base, void *scratch, const uint64_t *scratch_off,
-                              hipStream_t stream)
-{
-    if (nitems == 0) return hipSuccess;
-    if (eb == 4)
-        k_big_batched<uint32_t><<<nitems, kWgThreads, 0, stream>>>(
-            static_cast<uint32_t *>(data), offsets, items, sc, seed, inst_base,
-            static_cast<char *>(scratch), scratch_off);
-    else
-        k_big_batched<uint64_t><<<nitems, kWgThreads, 0, stream>>>(
-            static_cast<uint64_t *>(data), offsets, items, sc, seed, inst_base,
-            static_cast<char *>(scratch), scratch_off);
-    return hipGetLastError();
 }
 
 } // namespace brr
