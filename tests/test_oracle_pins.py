@@ -417,3 +417,17 @@ def test_sample_chi2_ordered_pairs(orc):
     assert cells.size == 20
     stat = float(((cells - trials / 20) ** 2 / (trials / 20)).sum())
     assert stat < chi2.ppf(1 - 1e-3, 19)
+
+
+def test_dice_group_equals_stream(orc):
+    """The single-group entry (used to sample long streams) reproduces the
+    whole-stream oracle group by group, short last group included."""
+    rng = np.random.default_rng(77)
+    for k, count in ((1, 301), (3, 1000), (4, 1003)):
+        bounds = rng.integers(1, 1 << 16, size=count, dtype=np.uint32)
+        err, out = orc.dice(bounds, k, 9, 2)
+        assert err == 0
+        S = -(-count // k)
+        for g in range(S):
+            e, got = orc.dice_group(bounds[g * k:(g + 1) * k], S, g, 9, 2)
+            assert e == 0 and np.array_equal(got, out[g * k:(g + 1) * k])
