@@ -102,6 +102,34 @@ uint64_t brr_schedule_batches(const brr_schedule *sched, uint64_t n, uint64_t st
 brr_status brr_schedule_check(const brr_schedule *sched, uint64_t n);
 
 /* ------------------------------------------------------------------------ */
+/* Planning: the cost model of Sec. 6.1 and schedules derived from it        */
+/* ------------------------------------------------------------------------ */
+
+/* Expected cost per die of a batch of k dice at size n with L-bit words
+ * (Sec. 6.1): ((c_rng + k) / (1 - p2) + (c_div + k - 1) * p1) / k with
+ * p1 = n^(falling k) / 2^L and p2 = (2^L mod n^(falling k)) / 2^L, in units
+ * of one multiplication. +inf when n^(falling k) > 2^L; NaN for k = 0 or
+ * L outside 1..64. */
+double brr_cost_per_die(uint64_t n, uint32_t k, uint32_t L, double c_rng, double c_div);
+
+/* n_k for k = 2..kmax (Table 2): the largest n such that a batch of k costs
+ * less per die than a batch of k - 1 at every size from k up to n.
+ * out_nk: host u64[kmax + 1], entries 0 and 1 set to 0. With L = 64,
+ * c_rng = 2, c_div = 16 this is the paper's table. 8 <= L <= 64,
+ * 2 <= kmax <= BRR_MAX_K. */
+brr_status brr_cost_thresholds(uint32_t L, uint32_t kmax, double c_rng, double c_div,
+                               uint64_t *out_nk);
+
+/* A schedule from the cost model (64-bit words): one die above n_2, then k
+ * dice while more than n_{k+1} elements remain (k up to kmax), guards
+ * u_k = n_k^k, and a last batch of at most kmax - 1 dice. pow2 != 0 rounds
+ * each n_k down to a power of two first, as the paper does for its
+ * experiments (Sec. 6.1): kmax = 6, c_rng = 2, c_div = 16, pow2 = 1 gives
+ * shuffle_6 exactly. */
+brr_status brr_schedule_from_costs(uint32_t kmax, double c_rng, double c_div, int pow2,
+                                   brr_schedule *out);
+
+/* ------------------------------------------------------------------------ */
 /* Dice streams (Theorem 1; Algorithm 3 per group, Algorithm 2 for a constant) */
 /* ------------------------------------------------------------------------ */
 
@@ -169,6 +197,44 @@ brr_status brr_plan_set_mapping(brr_plan *plan, const brr_mapping *m);
 brr_status brr_shuffle_batched(void *d_data, const uint64_t *d_offsets, uint64_t count,
                                uint32_t elem_bytes, brr_plan *plan, uint64_t seed,
                                uint64_t inst_base, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Autotuning (batch sizes are hardware-dependent, Sec. 6.1)                */
+/* ------------------------------------------------------------------------ */
+
+/* Times brr_dice for every k = 1..8 with max_bound^k <= 2^64 on a synthetic
+ * stream of min(count, 2^26) bounds uniform in [1, max_bound] (device
+ * scratch from the stream-ordered allocator), and returns the fastest k.
+ * ms_per_k: host float[9] or NULL; entry k gets the time of one stream
+ * (0 for k not tried). Results are cached per (bit length of max_bound,
+ * count rounded to a power of two). Synchronizes `stream`. */
+brr_status brr_dice_autotune(uint32_t max_bound, uint64_t count, void *stream, uint32_t *best_k,
+                             float *ms_per_k);
+
+typedef struct {
+    uint32_t candidates; /* configurations timed */
+    float ms_best;       /* time of one batch under the chosen configuration */
+    float ms_default;    /* time under the plan's configuration before tuning */
+    brr_schedule schedule;
+    brr_mapping mapping;
+} brr_tune_report;
+
+/* Chooses the plan's schedule and size-class mapping by timing candidates on
+ * a device copy of the batch (the caller's data is not modified): the plan's
+ * own configuration, the paper's schedules and schedules derived from the
+ * cost model (brr_schedule_from_costs) for several maximum batch sizes and
+ * generator/division cost ratios, under wavefront-tier limits of 64..512.
+ * Every candidate is exactly uniform (Theorem 1 holds for any schedule), so
+ * the choice changes only speed and the word stream consumed. The plan then
+ * uses the chosen configuration (brr_plan_get_schedule / get_mapping report
+ * it). Must precede the plan's first run; synchronizes `stream`. report may
+ * be NULL. */
+brr_status brr_plan_autotune(brr_plan *plan, const void *d_data, const uint64_t *d_offsets,
+                             uint64_t seed, uint64_t inst_base, void *stream,
+                             brr_tune_report *report);
+
+/* The schedule a plan uses (its creation argument, or the autotuner's choice). */
+brr_status brr_plan_get_schedule(const brr_plan *plan, brr_schedule *out);
 
 /* ------------------------------------------------------------------------ */
 /* Sampling without replacement (partial Fisher-Yates, Algorithm 4 Ensure)  */

@@ -23,7 +23,8 @@ EXPORTS = (
     "brr_schedule_paper", "brr_schedule_batches", "brr_schedule_check", "brr_dice",
     "brr_dice_const", "brr_shuffle", "brr_plan_create", "brr_plan_destroy",
     "brr_plan_get_mapping", "brr_plan_set_mapping", "brr_shuffle_batched", "brr_sample",
-    "brr_sync_status", "brr_strerror",
+    "brr_sync_status", "brr_strerror", "brr_cost_per_die", "brr_cost_thresholds",
+    "brr_schedule_from_costs", "brr_dice_autotune", "brr_plan_autotune", "brr_plan_get_schedule",
 )
 
 
@@ -61,6 +62,12 @@ class brr_mapping(ctypes.Structure):
                 ("wg_threads", ctypes.c_uint32), ("use_graph", ctypes.c_uint32)]
 
 
+class brr_tune_report(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_uint32), ("ms_best", ctypes.c_float),
+                ("ms_default", ctypes.c_float), ("schedule", brr_schedule),
+                ("mapping", brr_mapping)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
@@ -81,7 +88,14 @@ def _load():
         "brr_shuffle_batched": (st, [p, p, u64, u32, p, u64, u64, p]),
         "brr_sample": (st, [p, u64, u64, u32, p, sched_p, u64, u64, p]),
         "brr_sync_status": (st, [p]),
+        "brr_cost_per_die": (ctypes.c_double, [u64, u32, u32, ctypes.c_double, ctypes.c_double]),
+        "brr_cost_thresholds": (st, [u32, u32, ctypes.c_double, ctypes.c_double, p]),
+        "brr_schedule_from_costs": (st, [u32, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                         sched_p]),
         "brr_strerror": (ctypes.c_char_p, [st]),
+        "brr_dice_autotune": (st, [u32, u64, p, ctypes.POINTER(u32), p]),
+        "brr_plan_autotune": (st, [p, p, p, u64, u64, p, ctypes.POINTER(brr_tune_report)]),
+        "brr_plan_get_schedule": (st, [p, sched_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -139,6 +153,24 @@ def brr_schedule_check(sched: brr_schedule, n: int) -> int:
     return lib.brr_schedule_check(ctypes.byref(sched), n)
 
 
+def brr_cost_per_die(n: int, k: int, L: int = 64, c_rng: float = 2.0, c_div: float = 16.0) -> float:
+    return float(lib.brr_cost_per_die(n, k, L, c_rng, c_div))
+
+
+def brr_cost_thresholds(L: int, kmax: int, c_rng: float = 2.0, c_div: float = 16.0):
+    out = (ctypes.c_uint64 * (kmax + 1))()
+    check(lib.brr_cost_thresholds(L, kmax, c_rng, c_div, out), "brr_cost_thresholds")
+    return {k: int(out[k]) for k in range(2, kmax + 1)}
+
+
+def brr_schedule_from_costs(kmax: int, c_rng: float = 2.0, c_div: float = 16.0,
+                            pow2: bool = True) -> brr_schedule:
+    s = brr_schedule()
+    check(lib.brr_schedule_from_costs(kmax, c_rng, c_div, 1 if pow2 else 0, ctypes.byref(s)),
+          "brr_schedule_from_costs")
+    return s
+
+
 def brr_dice(bounds, out, count: int, k: int, seed: int, inst: int = 0, stream=None) -> int:
     return lib.brr_dice(_addr(bounds), _addr(out), count, k, seed, inst, _stream(stream))
 
@@ -180,6 +212,18 @@ class Plan:
     def set_mapping(self, m: brr_mapping) -> int:
         return lib.brr_plan_set_mapping(self.ptr, ctypes.byref(m))
 
+    def schedule(self) -> brr_schedule:
+        out = brr_schedule()
+        check(lib.brr_plan_get_schedule(self.ptr, ctypes.byref(out)), "brr_plan_get_schedule")
+        return out
+
+    def autotune(self, data, d_offsets, seed: int = 0, inst_base: int = 0,
+                 stream=None) -> brr_tune_report:
+        rep = brr_tune_report()
+        check(lib.brr_plan_autotune(self.ptr, _addr(data), _addr(d_offsets), seed, inst_base,
+                                    _stream(stream), ctypes.byref(rep)), "brr_plan_autotune")
+        return rep
+
     def close(self):
         if self.ptr:
             lib.brr_plan_destroy(self.ptr)
@@ -205,6 +249,25 @@ def brr_shuffle_batched(data, d_offsets, count: int, elem_bytes: int, plan=None,
     pp = plan.ptr if plan is not None else None
     return lib.brr_shuffle_batched(_addr(data), _addr(d_offsets), count, elem_bytes, pp, seed,
                                    inst_base, _stream(stream))
+
+
+def brr_dice_autotune(max_bound: int, count: int, stream=None, with_times: bool = False):
+    k = ctypes.c_uint32()
+    times = (ctypes.c_float * 9)() if with_times else None
+    check(lib.brr_dice_autotune(max_bound, count, _stream(stream), ctypes.byref(k), times),
+          "brr_dice_autotune")
+    if with_times:
+        return int(k.value), {i: float(times[i]) for i in range(1, 9) if times[i] > 0}
+    return int(k.value)
+
+
+def brr_plan_autotune(plan: Plan, data, d_offsets, seed: int = 0, inst_base: int = 0,
+                      stream=None) -> brr_tune_report:
+    return plan.autotune(data, d_offsets, seed, inst_base, stream)
+
+
+def brr_plan_get_schedule(plan: Plan) -> brr_schedule:
+    return plan.schedule()
 
 
 def brr_sync_status(stream=None) -> int:

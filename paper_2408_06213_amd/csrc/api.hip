@@ -3,6 +3,7 @@
 // the extern "C" entry points declared in brr.h.
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -661,6 +662,214 @@ const char *brr_strerror(brr_status status)
     case BRR_EDEVICE: return "no usable gfx950 device";
     default: return "unknown status";
     }
+}
+
+} // extern "C"
+
+namespace {
+
+__global__ void k_add_one(uint32_t *a, uint64_t n)
+{
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        a[x] += 1;
+}
+
+// Average time of `reps` launches of fn on stream s, after one warm-up.
+template <class F> float time_ms(F &&fn, hipStream_t s, int reps, brr_status *st)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        *st = BRR_EHIP;
+        return 0;
+    }
+    *st = fn();
+    float ms = 0;
+    if (*st == BRR_OK) {
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && *st == BRR_OK; ++r) *st = fn();
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) *st = BRR_EHIP;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms / reps;
+}
+
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, uint32_t> g_dice_k; // (bit length, log2 count) -> k
+
+bool same_steps(const brr_schedule &a, const brr_schedule &b)
+{
+    if (a.nsteps != b.nsteps || a.tail != b.tail) return false;
+    for (uint32_t g = 0; g < a.nsteps; ++g)
+        if (a.step[g].n_above != b.step[g].n_above || a.step[g].k != b.step[g].k) return false;
+    return true;
+}
+
+} // namespace
+
+extern "C" {
+
+brr_status brr_dice_autotune(uint32_t max_bound, uint64_t count, void *stream, uint32_t *best_k,
+                             float *ms_per_k)
+{
+    if (!best_k || max_bound == 0 || count == 0) return BRR_EINVAL;
+    brr_status st = device_ready(nullptr);
+    if (st != BRR_OK) return st;
+    const uint64_t n = std::min<uint64_t>(count, 1ull << 26);
+    int bits = 0;
+    while (bits < 32 && (max_bound >> bits)) ++bits;
+    int lg = 0;
+    while ((1ull << (lg + 1)) <= n) ++lg;
+    if (!ms_per_k) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_dice_k.find({bits, lg});
+        if (it != g_dice_k.end()) {
+            *best_k = it->second;
+            return BRR_OK;
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *bounds = nullptr, *out = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&bounds), n * 4, s) != hipSuccess) return BRR_ENOMEM;
+    if (hipMallocAsync(reinterpret_cast<void **>(&out), n * 4, s) != hipSuccess) {
+        (void)hipFreeAsync(bounds, s);
+        return BRR_ENOMEM;
+    }
+    // bounds uniform in [1, max_bound]: rolled by this library, then shifted
+    st = brr_dice_const(max_bound, bounds, n, 1, 0x5eedull, ~0ull, stream);
+    if (st == BRR_OK) {
+        k_add_one<<<1024, 256, 0, s>>>(bounds, n);
+        if (hipGetLastError() != hipSuccess) st = BRR_EHIP;
+    }
+    const u128 two64 = (u128)1 << 64;
+    float best = 0;
+    uint32_t bk = 1;
+    if (ms_per_k)
+        for (int k = 0; k <= 8; ++k) ms_per_k[k] = 0;
+    for (uint32_t k = 1; k <= 8 && st == BRR_OK; ++k) {
+        u128 p = 1;
+        for (uint32_t i = 0; i < k; ++i) p *= max_bound;
+        if (p > two64) break;
+        const float ms = time_ms([&] { return brr_dice(bounds, out, n, k, 1, 0, stream); }, s, 3, &st);
+        if (st != BRR_OK) break;
+        if (ms_per_k) ms_per_k[k] = ms;
+        if (k == 1 || ms < best) {
+            best = ms;
+            bk = k;
+        }
+    }
+    (void)hipFreeAsync(bounds, s);
+    (void)hipFreeAsync(out, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == BRR_OK) st = BRR_EHIP;
+    if (st != BRR_OK) return st;
+    *best_k = bk;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_dice_k[{bits, lg}] = bk;
+    return BRR_OK;
+}
+
+brr_status brr_plan_get_schedule(const brr_plan *plan, brr_schedule *out)
+{
+    if (!plan || !out) return BRR_EINVAL;
+    *out = plan->sched;
+    return BRR_OK;
+}
+
+brr_status brr_plan_autotune(brr_plan *plan, const void *d_data, const uint64_t *d_offsets,
+                             uint64_t seed, uint64_t inst_base, void *stream,
+                             brr_tune_report *report)
+{
+    if (!plan || !d_data || !d_offsets) return BRR_EINVAL;
+    if (plan->classified) return BRR_EINVAL; // must precede the first run
+    brr_status st = device_ready(nullptr);
+    if (st != BRR_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t total = plan->count ? plan->h_off[plan->count] : 0;
+    uint64_t max_n = 0;
+    for (uint64_t q = 0; q < plan->count; ++q)
+        max_n = std::max<uint64_t>(max_n, plan->h_off[q + 1] - plan->h_off[q]);
+    // candidate schedules: the plan's, the paper's, and cost-model ones
+    std::vector<brr_schedule> scheds{plan->sched};
+    auto add = [&](const brr_schedule &c) {
+        if (check_for(c, max_n, max_n ? max_n - 1 : 0) != BRR_OK) return;
+        for (const brr_schedule &o : scheds)
+            if (same_steps(o, c)) return;
+        scheds.push_back(c);
+    };
+    for (int mk : {6, 2, 1}) {
+        brr_schedule c;
+        if (brr_schedule_paper(mk, &c) == BRR_OK) add(c);
+    }
+    const double ratios[][2] = {{2, 16}, {1, 16}, {4, 16}, {8, 16}, {2, 64}};
+    for (uint32_t kmax = 3; kmax <= 8; ++kmax)
+        for (const auto &r : ratios) {
+            brr_schedule c;
+            if (brr_schedule_from_costs(kmax, r[0], r[1], 1, &c) == BRR_OK) add(c);
+        }
+    // a device copy to shuffle while timing
+    void *work = nullptr;
+    if (total && hipMallocAsync(&work, total * plan->eb, s) != hipSuccess) return BRR_ENOMEM;
+    if (total && hipMemcpyAsync(work, d_data, total * plan->eb, hipMemcpyDeviceToDevice, s) !=
+                     hipSuccess)
+        st = BRR_EHIP;
+    auto time_config = [&](const brr_schedule &sc, uint32_t wave_max, float *ms) -> brr_status {
+        brr_plan *t = nullptr;
+        brr_status e = brr_plan_create(&t, plan->h_off.data(), plan->count, plan->eb, &sc);
+        if (e != BRR_OK) return e;
+        t->map = plan->map;
+        t->map.wave_max = wave_max;
+        t->map.use_graph = 0;
+        *ms = time_ms(
+            [&] { return brr_shuffle_batched(work, d_offsets, plan->count, plan->eb, t, seed,
+                                             inst_base, stream); },
+            s, 2, &e);
+        if (hipStreamSynchronize(s) != hipSuccess && e == BRR_OK) e = BRR_EHIP;
+        brr_plan_destroy(t);
+        return e;
+    };
+    uint32_t n_tried = 0;
+    float ms_default = 0, best = 0;
+    size_t best_sched = 0;
+    uint32_t best_wave = plan->map.wave_max;
+    if (st == BRR_OK) st = time_config(plan->sched, plan->map.wave_max, &ms_default);
+    ++n_tried;
+    best = ms_default;
+    for (uint32_t wm : {64u, 128u, 256u, 512u}) { // mapping first, under the plan's schedule
+        if (st != BRR_OK || wm == plan->map.wave_max || wm > wave_tier_max_n()) continue;
+        float ms = 0;
+        st = time_config(plan->sched, wm, &ms);
+        ++n_tried;
+        if (st == BRR_OK && ms < best) {
+            best = ms;
+            best_wave = wm;
+        }
+    }
+    for (size_t c = 1; c < scheds.size() && st == BRR_OK; ++c) { // then the schedule
+        float ms = 0;
+        st = time_config(scheds[c], best_wave, &ms);
+        ++n_tried;
+        if (st == BRR_OK && ms < best) {
+            best = ms;
+            best_sched = c;
+        }
+    }
+    if (work) (void)hipFreeAsync(work, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == BRR_OK) st = BRR_EHIP;
+    if (st != BRR_OK) return st;
+    plan->sched = scheds[best_sched];
+    plan->ds = to_dev(plan->sched);
+    plan->map.wave_max = best_wave;
+    if (report) {
+        report->candidates = n_tried;
+        report->ms_best = best;
+        report->ms_default = ms_default;
+        report->schedule = plan->sched;
+        report->mapping = plan->map;
+    }
+    return BRR_OK;
 }
 
 } // extern "C"
