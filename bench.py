@@ -65,6 +65,46 @@ def time_launches(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per step
 
 
+def serving(brr, workloads, up, rates=(1000, 4000, 16000), count=400):
+    """Poisson arrivals at each rate: requests (shuffle or sample, n
+    log-uniform in [2^4, 2^22], u64 payload, m <= n/10) are submitted at their
+    arrival times to a continuous-batching server; p50/p99 latency from
+    submission to completion, and the throughput achieved."""
+    import numpy as np
+
+    out = []
+    for rate in rates:
+        reqs = workloads.serving_requests(count, rate, seed=5)
+        bufs = []
+        for r in reqs:
+            d = up(np.arange(r["n"], dtype=np.uint64))
+            o = up(np.zeros(r["m"], np.uint64)) if r["kind"] == "sample" else None
+            bufs.append((d, o))
+        torch_sync()
+        srv = brr.Server(hbm_budget=8 << 30, max_inflight=64, nstreams=8, seed=11)
+        t0 = time.perf_counter()
+        for r, (d, o) in zip(reqs, bufs):
+            while time.perf_counter() - t0 < r["t"]:
+                pass
+            kind = brr.BRR_REQ_SAMPLE if r["kind"] == "sample" else brr.BRR_REQ_SHUFFLE
+            srv.submit(kind, d, r["n"], 8, session=0, m=r["m"], out=o)
+        srv.drain()
+        st = srv.stats()
+        srv.close()
+        out.append({"offered_req_per_s": rate, "requests": count,
+                    "p50_us": st["p50_us"], "p99_us": st["p99_us"], "mean_us": st["mean_us"],
+                    "req_per_s": st["requests_per_s"], "elems_per_s": st["elements_per_s"],
+                    "peak_inflight": st["peak_inflight"]})
+        del bufs
+    return out
+
+
+def torch_sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
 def secondary(brr, workloads, up, steps, only=None):
     import numpy as np
 
@@ -104,6 +144,8 @@ def secondary(brr, workloads, up, steps, only=None):
             res[name] = {"ms": ms, "elems_per_s": n / (ms * 1e-3)}
         res["speedup_k6_vs_k1"] = res["k1"]["ms"] / res["k6"]["ms"]
         out[tag] = res
+    if only in (None, "serving"):
+        out["serving_u64"] = serving(brr, workloads, up)
     return out
 
 
@@ -115,7 +157,7 @@ def main():
     ap.add_argument("--k", type=int, default=4, help="dice per word of the timed stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--only", choices=["equal", "ragged", "single10000", "single2p26"],
+    ap.add_argument("--only", choices=["equal", "ragged", "single10000", "single2p26", "serving"],
                     help="run one shuffle workload only (for profiling); prints its timings")
     args = ap.parse_args()
 

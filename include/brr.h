@@ -247,6 +247,67 @@ brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_
                       const brr_schedule *sched, uint64_t seed, uint64_t inst, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of shuffle and sample requests              */
+/* ------------------------------------------------------------------------ */
+
+/* A server admits requests in arrival order as in-flight slots and its
+ * device-scratch budget allow, runs them concurrently on a pool of HIP
+ * streams (a session's requests share one stream, in submission order), and
+ * retires them when their completion events fire. Each session's generator
+ * counter lives on the device: request j of session s (j = 0, 1, ...) uses
+ * instance s * 2^40 + j, claimed by a kernel on the session's stream, so a
+ * result depends only on (seed, session, j, inputs), never on the mix it ran
+ * in. A request that needs more scratch than the whole budget still runs,
+ * alone. Shuffles follow brr_shuffle, samples brr_sample, with the server's
+ * schedule. */
+typedef struct brr_server brr_server;
+
+typedef struct {
+    uint64_t hbm_budget;        /* bytes of device scratch in use at once */
+    uint32_t max_inflight;      /* requests on the device at once */
+    uint32_t nstreams;          /* HIP streams (1..64) */
+    uint64_t seed;              /* word-stream seed of every request */
+    const brr_schedule *schedule; /* NULL = shuffle_6; copied */
+} brr_server_config;
+
+#define BRR_REQ_SHUFFLE 1u
+#define BRR_REQ_SAMPLE 2u
+
+typedef struct {
+    uint32_t kind;       /* BRR_REQ_SHUFFLE (in place) or BRR_REQ_SAMPLE */
+    uint32_t elem_bytes; /* 4 or 8 */
+    uint64_t session;    /* < 2^24; names the counter and the stream */
+    void *d_data;        /* device, n elements; must stay valid until completion */
+    uint64_t n;
+    uint64_t m;          /* sample size (samples only), m <= n */
+    void *d_out;         /* device, m elements (samples only) */
+} brr_request;
+
+typedef struct {
+    uint64_t completed, elements; /* requests and elements (shuffled or sampled) */
+    double p50_us, p99_us, mean_us, max_us; /* latency, submission to completion */
+    double wall_s, requests_per_s, elements_per_s; /* first submission to last completion */
+    uint32_t peak_inflight;
+    uint64_t peak_footprint;      /* bytes of scratch admitted at once */
+} brr_server_stats;
+
+brr_status brr_server_create(brr_server **out, const brr_server_config *cfg);
+/* Queues a request; *id names it for brr_server_wait. */
+brr_status brr_server_submit(brr_server *server, const brr_request *req, uint64_t *id);
+/* Waits for one request (BRR_EDEVICE on time-out); its latency in
+ * *latency_us (may be NULL). The id is released. */
+brr_status brr_server_wait(brr_server *server, uint64_t id, double timeout_s, double *latency_us);
+/* Waits until nothing is pending or in flight, releasing finished ids. */
+brr_status brr_server_drain(brr_server *server, double timeout_s);
+brr_status brr_server_get_stats(brr_server *server, brr_server_stats *out);
+brr_status brr_server_reset_stats(brr_server *server);
+/* The device counter of a session (requests claimed so far); synchronizes
+ * the session's stream. */
+brr_status brr_server_session_counter(brr_server *server, uint64_t session, uint64_t *value);
+/* Finishes every queued request, then releases the server. */
+void brr_server_destroy(brr_server *server);
+
+/* ------------------------------------------------------------------------ */
 /* Status                                                                   */
 /* ------------------------------------------------------------------------ */
 

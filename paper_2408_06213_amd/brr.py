@@ -25,7 +25,11 @@ EXPORTS = (
     "brr_plan_get_mapping", "brr_plan_set_mapping", "brr_shuffle_batched", "brr_sample",
     "brr_sync_status", "brr_strerror", "brr_cost_per_die", "brr_cost_thresholds",
     "brr_schedule_from_costs", "brr_dice_autotune", "brr_plan_autotune", "brr_plan_get_schedule",
+    "brr_server_create", "brr_server_submit", "brr_server_wait", "brr_server_drain",
+    "brr_server_get_stats", "brr_server_reset_stats", "brr_server_session_counter",
+    "brr_server_destroy",
 )
+BRR_REQ_SHUFFLE, BRR_REQ_SAMPLE = 1, 2
 
 
 class BrrError(RuntimeError):
@@ -68,6 +72,30 @@ class brr_tune_report(ctypes.Structure):
                 ("mapping", brr_mapping)]
 
 
+class brr_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
+                ("nstreams", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("schedule", ctypes.POINTER(brr_schedule))]
+
+
+class brr_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("elem_bytes", ctypes.c_uint32),
+                ("session", ctypes.c_uint64), ("d_data", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("m", ctypes.c_uint64), ("d_out", ctypes.c_void_p)]
+
+
+class brr_server_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("elements", ctypes.c_uint64),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("requests_per_s", ctypes.c_double),
+                ("elements_per_s", ctypes.c_double), ("peak_inflight", ctypes.c_uint32),
+                ("peak_footprint", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
@@ -96,6 +124,14 @@ def _load():
         "brr_dice_autotune": (st, [u32, u64, p, ctypes.POINTER(u32), p]),
         "brr_plan_autotune": (st, [p, p, p, u64, u64, p, ctypes.POINTER(brr_tune_report)]),
         "brr_plan_get_schedule": (st, [p, sched_p]),
+        "brr_server_create": (st, [ctypes.POINTER(p), ctypes.POINTER(brr_server_config)]),
+        "brr_server_submit": (st, [p, ctypes.POINTER(brr_request), ctypes.POINTER(u64)]),
+        "brr_server_wait": (st, [p, u64, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+        "brr_server_drain": (st, [p, ctypes.c_double]),
+        "brr_server_get_stats": (st, [p, ctypes.POINTER(brr_server_stats)]),
+        "brr_server_reset_stats": (st, [p]),
+        "brr_server_session_counter": (st, [p, u64, ctypes.POINTER(u64)]),
+        "brr_server_destroy": (None, [p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -268,6 +304,58 @@ def brr_plan_autotune(plan: Plan, data, d_offsets, seed: int = 0, inst_base: int
 
 def brr_plan_get_schedule(plan: Plan) -> brr_schedule:
     return plan.schedule()
+
+
+class Server:
+    """Owns a brr_server* (continuous batching of shuffle/sample requests)."""
+
+    def __init__(self, hbm_budget: int = 4 << 30, max_inflight: int = 64, nstreams: int = 8,
+                 seed: int = 0, sched=None):
+        cfg = brr_server_config(hbm_budget, max_inflight, nstreams, seed,
+                                ctypes.pointer(sched) if sched is not None else None)
+        self.ptr = ctypes.c_void_p()
+        check(lib.brr_server_create(ctypes.byref(self.ptr), ctypes.byref(cfg)), "brr_server_create")
+
+    def submit(self, kind: int, data, n: int, elem_bytes: int, session: int = 0, m: int = 0,
+               out=None) -> int:
+        req = brr_request(kind, elem_bytes, session, _addr(data), n, m, _addr(out))
+        rid = ctypes.c_uint64()
+        check(lib.brr_server_submit(self.ptr, ctypes.byref(req), ctypes.byref(rid)),
+              "brr_server_submit")
+        return int(rid.value)
+
+    def wait(self, rid: int, timeout_s: float = 60.0) -> float:
+        lat = ctypes.c_double()
+        check(lib.brr_server_wait(self.ptr, rid, timeout_s, ctypes.byref(lat)), "brr_server_wait")
+        return float(lat.value)
+
+    def drain(self, timeout_s: float = 120.0) -> None:
+        check(lib.brr_server_drain(self.ptr, timeout_s), "brr_server_drain")
+
+    def stats(self) -> dict:
+        st = brr_server_stats()
+        check(lib.brr_server_get_stats(self.ptr, ctypes.byref(st)), "brr_server_get_stats")
+        return st.as_dict()
+
+    def reset_stats(self) -> None:
+        check(lib.brr_server_reset_stats(self.ptr), "brr_server_reset_stats")
+
+    def counter(self, session: int) -> int:
+        v = ctypes.c_uint64()
+        check(lib.brr_server_session_counter(self.ptr, session, ctypes.byref(v)),
+              "brr_server_session_counter")
+        return int(v.value)
+
+    def close(self):
+        if self.ptr:
+            lib.brr_server_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def brr_sync_status(stream=None) -> int:

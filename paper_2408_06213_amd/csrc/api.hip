@@ -163,34 +163,9 @@ DevSched to_dev(const brr_schedule &sc)
     return d;
 }
 
-// One shuffle or sample through the device-wide tier, with stream-ordered
-// scratch.
-hipError_t run_one_gtier(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
-                         void *out, const DevSched &ds, uint64_t seed, uint64_t inst, hipStream_t s)
-{
-    SegTable st;
-    build_segments(n, steps, ds, st);
-    const GItem it{0, 0, inst, n, steps, out_lo, 0, out};
-    GTierArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.data = data;
-    a.eb = eb;
-    a.seed = seed;
-    a.nitems = 1;
-    a.npos = n;
-    a.npairs = (st.S + 1) / 2;
-    a.one_item = &it;
-    a.one_seg = &st;
-    void *scratch = nullptr;
-    hipError_t e = hipMallocAsync(&scratch, gtier_scratch_bytes(n, eb), s);
-    if (e != hipSuccess) return e;
-    a.scratch = scratch;
-    e = launch_gtier(a, s);
-    const hipError_t f = hipFreeAsync(scratch, s);
-    return e != hipSuccess ? e : f;
-}
-
 } // namespace
+
+brr_status brr::ensure_device() { return device_ready(nullptr); }
 
 // ---------------------------------------------------------------------------
 // Plans
@@ -493,15 +468,8 @@ brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_
     if (st != BRR_OK) return st;
     st = device_ready(nullptr);
     if (st != BRR_OK) return st;
-    const DevSched ds = to_dev(sc);
-    const StreamKey key = make_key(seed, inst);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (n <= lds_tier_max_n())
-        return hip_status(
-            launch_lds_single(d_data, (uint32_t)n, (uint32_t)(n - 1), 0, elem_bytes, nullptr, ds,
-                              key, s));
-    return hip_status(run_one_gtier(d_data, (uint32_t)n, (uint32_t)(n - 1), 0, elem_bytes, nullptr,
-                                    ds, seed, inst, s));
+    return hip_status(launch_one(d_data, (uint32_t)n, (uint32_t)(n - 1), 0, elem_bytes, nullptr,
+                                 to_dev(sc), seed, inst, nullptr, static_cast<hipStream_t>(stream)));
 }
 
 brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_bytes, void *d_out,
@@ -520,15 +488,9 @@ brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (n == 1) // one element, no step: the sample is the element itself
         return hip_status(hipMemcpyAsync(d_out, d_data, elem_bytes, hipMemcpyDeviceToDevice, s));
-    const DevSched ds = to_dev(sc);
-    const StreamKey key = make_key(seed, inst);
     void *data = const_cast<void *>(d_data); // only read when an output buffer is given
-    const uint32_t out_lo = (uint32_t)(n - m);
-    if (n <= lds_tier_max_n())
-        return hip_status(launch_lds_single(data, (uint32_t)n, (uint32_t)steps, out_lo, elem_bytes,
-                                            d_out, ds, key, s));
-    return hip_status(run_one_gtier(data, (uint32_t)n, (uint32_t)steps, out_lo, elem_bytes, d_out,
-                                    ds, seed, inst, s));
+    return hip_status(launch_one(data, (uint32_t)n, (uint32_t)steps, (uint32_t)(n - m), elem_bytes,
+                                 d_out, to_dev(sc), seed, inst, nullptr, s));
 }
 
 brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t count,

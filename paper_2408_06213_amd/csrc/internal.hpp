@@ -4,9 +4,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "brr.h"
 #include "device.hpp"
 
 namespace brr {
+
+// Checks once per device that the current device is a gfx950 and sets up
+// the library's per-device state.
+brr_status ensure_device();
 
 // A validated schedule in the form the kernels read (thresholds clamped to
 // 32 bits: every shuffle here has n < 2^32).
@@ -92,8 +97,10 @@ hipError_t prepare_shuffle_kernels();
 // (out != nullptr: out[n-1-p] = final z[p] for out_lo <= p < n, the input
 // untouched) by one workgroup with its index arrays in LDS;
 // n <= lds_tier_max_n(), 1 <= steps < n, out_lo <= n - steps.
+// The stream instance is inst, plus *inst_dev when inst_dev is not null.
 hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
-                             void *out, const DevSched &sc, StreamKey key, hipStream_t stream);
+                             void *out, const DevSched &sc, uint64_t seed, uint64_t inst,
+                             const uint64_t *inst_dev, hipStream_t stream);
 
 // One item of the device-wide tier: the array at element offset data_off of
 // the shared data pointer, n elements, the first `steps` Fisher-Yates steps
@@ -114,6 +121,7 @@ struct GTierArgs {
     uint32_t eb;
     uint64_t seed;
     uint64_t inst_base; // item q uses instance inst_base + items[q].inst
+    const uint64_t *inst_dev; // device; if set, *inst_dev is added to inst_base
     uint32_t nitems;
     uint64_t npos, npairs;
     const GItem *items;      // device
@@ -125,6 +133,14 @@ struct GTierArgs {
     void *scratch;           // gtier_scratch_bytes(npos, eb)
 };
 uint64_t gtier_scratch_bytes(uint64_t npos, uint32_t eb);
+
+// One shuffle (out == nullptr) or sample through the LDS tier or, for
+// n > lds_tier_max_n(), the device-wide tier with stream-ordered scratch of
+// one_scratch_bytes(n, eb) bytes.
+uint64_t one_scratch_bytes(uint64_t n, uint32_t eb);
+hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
+                      void *out, const DevSched &ds, uint64_t seed, uint64_t inst,
+                      const uint64_t *inst_dev, hipStream_t s);
 uint32_t gtier_tile_shift(); // log2 of the indices per tile-table entry
 hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream);
 

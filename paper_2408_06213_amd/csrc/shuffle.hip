@@ -225,16 +225,20 @@ __device__ void lds_tier_run(Elem *z, uint32_t n, uint32_t steps, uint32_t out_l
     }
 }
 
+// inst_dev != nullptr: the instance is read from device memory (a counter
+// claimed on the same stream), added to the key's instance.
 template <typename Elem, int BLOCK, int P>
 __global__ __launch_bounds__(BLOCK) void k_lds_single(Elem *z, uint32_t n, uint32_t steps,
                                                       uint32_t out_lo, Elem *out, SegTable st,
-                                                      StreamKey key)
+                                                      uint64_t seed, uint64_t inst,
+                                                      const uint64_t *inst_dev)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ Seg seg[kMaxSegs];
     __shared__ uint32_t wsum[BLOCK / 64];
     if (threadIdx.x < st.nseg) seg[threadIdx.x] = st.seg[threadIdx.x];
     __syncthreads();
+    const StreamKey key = make_key(seed, inst + (inst_dev ? *inst_dev : 0));
     lds_tier_run<Elem, BLOCK, P>(z, n, steps, out_lo, out, seg, st.nseg, st.S, key, smem, wsum);
 }
 
@@ -483,7 +487,8 @@ struct GProblem {
     const uint32_t *pair_tile; // item of batch pair 256*t
     uint32_t nitems;
     uint64_t npos, npairs;
-    uint64_t inst_base; // added to every item's instance
+    uint64_t inst_base;       // added to every item's instance
+    const uint64_t *inst_dev; // if set, *inst_dev is added as well
     GItem one;
     SegTable one_seg;
 };
@@ -529,7 +534,8 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
         const GItem &it = item_at(P, i);
         const SegTable &st = segs_at(P, i);
         const uint32_t m = (uint32_t)(w - (P.items ? P.pair_base[i] : 0));
-        const StreamKey key = make_key(seed, P.inst_base + it.inst);
+        const uint64_t ib = P.inst_base + (P.inst_dev ? *P.inst_dev : 0);
+        const StreamKey key = make_key(seed, ib + it.inst);
         uint64_t wd[2];
         word_pair(m, key, wd[0], wd[1]);
 #pragma unroll
@@ -705,13 +711,15 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
 
 template <typename Elem>
 hipError_t lds_single_t(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, void *out,
-                        const DevSched &sc, StreamKey key, hipStream_t stream)
+                        const DevSched &sc, uint64_t seed, uint64_t inst, const uint64_t *inst_dev,
+                        hipStream_t stream)
 {
     SegTable st;
     build_segments(n, steps, sc, st);
     const uint32_t bytes = lds_bytes(n);
     k_lds_single<Elem, kWgThreads, kWgP><<<1, kWgThreads, bytes, stream>>>(
-        static_cast<Elem *>(data), n, steps, out_lo, static_cast<Elem *>(out), st, key);
+        static_cast<Elem *>(data), n, steps, out_lo, static_cast<Elem *>(out), st, seed, inst,
+        inst_dev);
     return hipGetLastError();
 }
 
@@ -777,12 +785,49 @@ uint64_t gtier_scratch_bytes(uint64_t npos, uint32_t eb) { return garrays_bytes(
 uint32_t gtier_tile_shift() { return kTileShift; }
 
 hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
-                             void *out, const DevSched &sc, StreamKey key, hipStream_t stream)
+                             void *out, const DevSched &sc, uint64_t seed, uint64_t inst,
+                             const uint64_t *inst_dev, hipStream_t stream)
 {
     if (n > lds_tier_max_n() || steps == 0 || steps >= n || out_lo > n - steps)
         return hipErrorInvalidValue;
-    return eb == 4 ? lds_single_t<uint32_t>(data, n, steps, out_lo, out, sc, key, stream)
-                   : lds_single_t<uint64_t>(data, n, steps, out_lo, out, sc, key, stream);
+    return eb == 4 ? lds_single_t<uint32_t>(data, n, steps, out_lo, out, sc, seed, inst, inst_dev,
+                                            stream)
+                   : lds_single_t<uint64_t>(data, n, steps, out_lo, out, sc, seed, inst, inst_dev,
+                                            stream);
+}
+
+uint64_t one_scratch_bytes(uint64_t n, uint32_t eb)
+{
+    return n <= lds_tier_max_n() ? 0 : gtier_scratch_bytes(n, eb);
+}
+
+hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
+                      void *out, const DevSched &ds, uint64_t seed, uint64_t inst,
+                      const uint64_t *inst_dev, hipStream_t s)
+{
+    if (n <= lds_tier_max_n())
+        return launch_lds_single(data, n, steps, out_lo, eb, out, ds, seed, inst, inst_dev, s);
+    SegTable st;
+    build_segments(n, steps, ds, st);
+    const GItem it{0, 0, inst, n, steps, out_lo, 0, out};
+    GTierArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.data = data;
+    a.eb = eb;
+    a.seed = seed;
+    a.inst_dev = inst_dev;
+    a.nitems = 1;
+    a.npos = n;
+    a.npairs = (st.S + 1) / 2;
+    a.one_item = &it;
+    a.one_seg = &st;
+    void *scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, gtier_scratch_bytes(n, eb), s);
+    if (e != hipSuccess) return e;
+    a.scratch = scratch;
+    e = launch_gtier(a, s);
+    const hipError_t f = hipFreeAsync(scratch, s);
+    return e != hipSuccess ? e : f;
 }
 
 hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream)
@@ -794,6 +839,7 @@ hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream)
     P.npos = a.npos;
     P.npairs = a.npairs;
     P.inst_base = a.inst_base;
+    P.inst_dev = a.inst_dev;
     if (a.nitems == 1 && a.one_item) {
         P.one = *a.one_item;
         P.one_seg = *a.one_seg;

@@ -1,0 +1,106 @@
+"""Serving with continuous batching: every request's result equals the
+oracle's for its (session, place in session) instance, whatever mix,
+interleaving, stream count or budget it ran under."""
+import numpy as np
+import pytest
+
+from conftest import say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SESSION_SHIFT = 40
+
+
+def make_requests(seed, count):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        n = int(2 ** rng.uniform(1, 18))
+        kind = "sample" if rng.random() < 0.5 else "shuffle"
+        m = int(rng.integers(1, max(1, n // 10) + 1)) if kind == "sample" else n
+        dtype = np.uint64 if rng.random() < 0.7 else np.uint32
+        data = rng.integers(0, 2**31, size=n).astype(dtype)
+        reqs.append(dict(kind=kind, n=n, m=m, data=data, session=int(rng.integers(0, 5))))
+    return reqs
+
+
+def run_mix(gpu, reqs, order, **cfg):
+    srv = gpu.Server(**cfg)
+    bufs = {}
+    ids = {}
+    for i in order:
+        r = reqs[i]
+        d = to_dev(r["data"])
+        out = to_dev(np.zeros(r["m"], r["data"].dtype)) if r["kind"] == "sample" else None
+        bufs[i] = (d, out)
+        kind = gpu.BRR_REQ_SAMPLE if r["kind"] == "sample" else gpu.BRR_REQ_SHUFFLE
+        ids[i] = srv.submit(kind, d, r["n"], r["data"].itemsize, r["session"], r["m"], out)
+    for i in order:
+        srv.wait(ids[i])
+    counters = {s: srv.counter(s) for s in {r["session"] for r in reqs}}
+    stats = srv.stats()
+    srv.close()
+    results = {i: to_host(out if out is not None else d) for i, (d, out) in bufs.items()}
+    return results, counters, stats
+
+
+def expected(orc, reqs, order, seed):
+    """Oracle result of each request at instance session * 2^40 + j, where j
+    counts the earlier submissions of its session."""
+    s6 = orc.schedule_paper(6)
+    seen = {}
+    want = {}
+    for i in order:
+        r = reqs[i]
+        j = seen.get(r["session"], 0)
+        seen[r["session"]] = j + 1
+        inst = (r["session"] << SESSION_SHIFT) + j
+        if r["kind"] == "sample":
+            err, out = orc.sample(r["data"], r["m"], s6, seed, inst)
+        else:
+            out = r["data"].copy()
+            err = orc.shuffle(out, s6, seed, inst)
+        assert err == 0
+        want[i] = out
+    return want, seen
+
+
+def test_server_results_match_oracle_in_any_mix(gpu, orc):
+    reqs = make_requests(1, 60)
+    # same order within each session, different interleaving across sessions
+    order_a = list(range(len(reqs)))
+    by_session = {}
+    for i in order_a:
+        by_session.setdefault(reqs[i]["session"], []).append(i)
+    order_b = []
+    for s in sorted(by_session, reverse=True):
+        order_b += by_session[s]
+    want, seen = expected(orc, reqs, order_a, seed=99)
+    say("server mix A")
+    got_a, counters_a, stats_a = run_mix(gpu, reqs, order_a, seed=99, nstreams=8, max_inflight=32)
+    say("server mix B")
+    got_b, counters_b, _ = run_mix(gpu, reqs, order_b, seed=99, nstreams=3, max_inflight=4,
+                                   hbm_budget=1 << 20)
+    for i in range(len(reqs)):
+        assert np.array_equal(got_a[i], want[i]), i
+        assert np.array_equal(got_b[i], want[i]), i
+    assert counters_a == seen == counters_b
+    assert stats_a["completed"] == len(reqs) and stats_a["p99_us"] >= stats_a["p50_us"] > 0
+
+
+def test_server_budget_limits_footprint(gpu):
+    say("server budget")
+    srv = gpu.Server(hbm_budget=64 << 20, max_inflight=16, nstreams=4, seed=3)
+    bufs = []
+    ids = []
+    for s in range(12):
+        d = to_dev(np.arange(1 << 20, dtype=np.uint32))  # needs ~28 MB of scratch each
+        bufs.append(d)
+        ids.append(srv.submit(gpu.BRR_REQ_SHUFFLE, d, 1 << 20, 4, session=s))
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 12
+    assert 0 < st["peak_footprint"] <= 64 << 20
+    for d in bufs:  # each is a permutation
+        assert np.array_equal(np.sort(to_host(d)), np.arange(1 << 20, dtype=np.uint32))
