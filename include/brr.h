@@ -122,11 +122,15 @@ brr_status brr_cost_thresholds(uint32_t L, uint32_t kmax, double c_rng, double c
 
 /* A schedule from the cost model (64-bit words): one die above n_2, then k
  * dice while more than n_{k+1} elements remain (k up to kmax), guards
- * u_k = n_k^k, and a last batch of at most kmax - 1 dice. pow2 != 0 rounds
- * each n_k down to a power of two first, as the paper does for its
- * experiments (Sec. 6.1): kmax = 6, c_rng = 2, c_div = 16, pow2 = 1 gives
- * shuffle_6 exactly. */
-brr_status brr_schedule_from_costs(uint32_t kmax, double c_rng, double c_div, int pow2,
+ * u_k = n_k^k, and a last batch of at most kmax - 1 dice. Flags:
+ * BRR_COSTS_POW2 rounds each n_k down to a power of two first, as the paper
+ * does for its experiments (Sec. 6.1) -- kmax = 6, c_rng = 2, c_div = 16 with
+ * this flag gives shuffle_6 exactly; BRR_COSTS_SMOOTH replaces p2 by its mean
+ * p1 / 2, which makes n_k a bisection (microseconds) instead of the exact
+ * first-crossing scan of brr_cost_thresholds (seconds for k = 2). */
+#define BRR_COSTS_POW2 1
+#define BRR_COSTS_SMOOTH 2
+brr_status brr_schedule_from_costs(uint32_t kmax, double c_rng, double c_div, int flags,
                                    brr_schedule *out);
 
 /* ------------------------------------------------------------------------ */
@@ -235,6 +239,55 @@ brr_status brr_plan_autotune(brr_plan *plan, const void *d_data, const uint64_t 
 
 /* The schedule a plan uses (its creation argument, or the autotuner's choice). */
 brr_status brr_plan_get_schedule(const brr_plan *plan, brr_schedule *out);
+
+/* ------------------------------------------------------------------------ */
+/* Learned plan-cost model                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* A small multilayer perceptron, y = W3' tanh(W2' tanh(W1' x + b1) + b2) + b3
+ * (n_in inputs, two hidden layers of `hidden`, one output, FP32, device
+ * resident), trained by mean squared error with Adam in the library's own
+ * kernels. It predicts the log-time of a batch under a candidate plan from
+ * brr_plan_features; the autotuner uses it to rank candidates. It never
+ * touches random words, rolls or swaps, so outputs stay exactly uniform.
+ * Parameters are laid out W1[n_in][hidden], b1, W2[hidden][hidden], b2,
+ * W3[hidden], b3, row-major, as float. Weights start Glorot-uniform from
+ * `seed`, biases zero. Device pointers d_*: float, row-major [batch][n_in]
+ * inputs, [batch] outputs/targets. */
+typedef struct brr_mlp brr_mlp;
+brr_status brr_mlp_create(brr_mlp **out, uint32_t n_in, uint32_t hidden, uint64_t seed);
+void brr_mlp_destroy(brr_mlp *net);
+uint64_t brr_mlp_num_params(const brr_mlp *net);
+brr_status brr_mlp_get_params(const brr_mlp *net, float *h_out); /* synchronous */
+brr_status brr_mlp_set_params(brr_mlp *net, const float *h_in);  /* synchronous */
+brr_status brr_mlp_get_grads(const brr_mlp *net, float *h_out);  /* synchronous */
+brr_status brr_mlp_forward(brr_mlp *net, const float *d_x, uint32_t batch, float *d_y,
+                           void *stream);
+/* Gradients of mean((y - t)^2) over the batch into the net's gradient
+ * buffer; the loss into *d_loss (device float, may be NULL). */
+brr_status brr_mlp_backward(brr_mlp *net, const float *d_x, const float *d_t, uint32_t batch,
+                            float *d_loss, void *stream);
+brr_status brr_mlp_adam_step(brr_mlp *net, float lr, void *stream);
+/* steps x (backward + Adam) on one batch; final loss to *h_final_loss.
+ * Synchronizes `stream`. */
+brr_status brr_mlp_train(brr_mlp *net, const float *d_x, const float *d_t, uint32_t batch,
+                         uint32_t steps, float lr, float *h_final_loss, void *stream);
+
+#define BRR_PLAN_FEATURES 16
+/* Features of a batch (CSR host offsets) under a schedule and wavefront-tier
+ * limit: log total size, log count, payload width, element fractions by
+ * size band, mean and spread of log2 n, words per step, fractions of dice
+ * in batches of >= 4 and <= 2, largest batch, log wavefront limit, element
+ * fraction in the wavefront tier. out: host float[BRR_PLAN_FEATURES]. */
+brr_status brr_plan_features(const uint64_t *h_offsets, uint64_t count, uint32_t elem_bytes,
+                             const brr_schedule *sched, uint32_t wave_max, float *out);
+
+/* brr_plan_autotune guided by a trained model: every candidate is ranked by
+ * predicted time and only the plan's own configuration and the `top` best
+ * predicted ones are timed. */
+brr_status brr_plan_autotune_learned(brr_plan *plan, brr_mlp *model, uint32_t top,
+                                     const void *d_data, const uint64_t *d_offsets, uint64_t seed,
+                                     uint64_t inst_base, void *stream, brr_tune_report *report);
 
 /* ------------------------------------------------------------------------ */
 /* Sampling without replacement (partial Fisher-Yates, Algorithm 4 Ensure)  */

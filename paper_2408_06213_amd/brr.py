@@ -27,8 +27,12 @@ EXPORTS = (
     "brr_schedule_from_costs", "brr_dice_autotune", "brr_plan_autotune", "brr_plan_get_schedule",
     "brr_server_create", "brr_server_submit", "brr_server_wait", "brr_server_drain",
     "brr_server_get_stats", "brr_server_reset_stats", "brr_server_session_counter",
-    "brr_server_destroy",
+    "brr_server_destroy", "brr_mlp_create", "brr_mlp_destroy", "brr_mlp_num_params",
+    "brr_mlp_get_params", "brr_mlp_set_params", "brr_mlp_get_grads", "brr_mlp_forward",
+    "brr_mlp_backward", "brr_mlp_adam_step", "brr_mlp_train", "brr_plan_features",
+    "brr_plan_autotune_learned",
 )
+BRR_PLAN_FEATURES = 16
 BRR_REQ_SHUFFLE, BRR_REQ_SAMPLE = 1, 2
 
 
@@ -132,6 +136,19 @@ def _load():
         "brr_server_reset_stats": (st, [p]),
         "brr_server_session_counter": (st, [p, u64, ctypes.POINTER(u64)]),
         "brr_server_destroy": (None, [p]),
+        "brr_mlp_create": (st, [ctypes.POINTER(p), u32, u32, u64]),
+        "brr_mlp_destroy": (None, [p]),
+        "brr_mlp_num_params": (u64, [p]),
+        "brr_mlp_get_params": (st, [p, p]),
+        "brr_mlp_set_params": (st, [p, p]),
+        "brr_mlp_get_grads": (st, [p, p]),
+        "brr_mlp_forward": (st, [p, p, u32, p, p]),
+        "brr_mlp_backward": (st, [p, p, p, u32, p, p]),
+        "brr_mlp_adam_step": (st, [p, ctypes.c_float, p]),
+        "brr_mlp_train": (st, [p, p, p, u32, u32, ctypes.c_float, ctypes.POINTER(ctypes.c_float), p]),
+        "brr_plan_features": (st, [p, u64, u32, sched_p, u32, p]),
+        "brr_plan_autotune_learned": (st, [p, p, u32, p, p, u64, u64, p,
+                                           ctypes.POINTER(brr_tune_report)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -199,10 +216,14 @@ def brr_cost_thresholds(L: int, kmax: int, c_rng: float = 2.0, c_div: float = 16
     return {k: int(out[k]) for k in range(2, kmax + 1)}
 
 
+BRR_COSTS_POW2, BRR_COSTS_SMOOTH = 1, 2
+
+
 def brr_schedule_from_costs(kmax: int, c_rng: float = 2.0, c_div: float = 16.0,
-                            pow2: bool = True) -> brr_schedule:
+                            pow2: bool = True, smooth: bool = False) -> brr_schedule:
     s = brr_schedule()
-    check(lib.brr_schedule_from_costs(kmax, c_rng, c_div, 1 if pow2 else 0, ctypes.byref(s)),
+    flags = (BRR_COSTS_POW2 if pow2 else 0) | (BRR_COSTS_SMOOTH if smooth else 0)
+    check(lib.brr_schedule_from_costs(kmax, c_rng, c_div, flags, ctypes.byref(s)),
           "brr_schedule_from_costs")
     return s
 
@@ -356,6 +377,85 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class MLP:
+    """Owns a brr_mlp* (the learned plan-cost model)."""
+
+    def __init__(self, n_in: int = BRR_PLAN_FEATURES, hidden: int = 64, seed: int = 0):
+        self.n_in, self.hidden = n_in, hidden
+        self.ptr = ctypes.c_void_p()
+        check(lib.brr_mlp_create(ctypes.byref(self.ptr), n_in, hidden, seed), "brr_mlp_create")
+        self.nparams = int(lib.brr_mlp_num_params(self.ptr))
+
+    def params(self):
+        import numpy as np
+
+        out = np.zeros(self.nparams, np.float32)
+        check(lib.brr_mlp_get_params(self.ptr, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_params(self, values):
+        import numpy as np
+
+        v = np.ascontiguousarray(values, dtype=np.float32)
+        assert v.size == self.nparams
+        check(lib.brr_mlp_set_params(self.ptr, v.ctypes.data_as(ctypes.c_void_p)))
+
+    def grads(self):
+        import numpy as np
+
+        out = np.zeros(self.nparams, np.float32)
+        check(lib.brr_mlp_get_grads(self.ptr, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def forward(self, d_x, batch: int, d_y, stream=None) -> None:
+        check(lib.brr_mlp_forward(self.ptr, _addr(d_x), batch, _addr(d_y), _stream(stream)),
+              "brr_mlp_forward")
+
+    def backward(self, d_x, d_t, batch: int, d_loss=None, stream=None) -> None:
+        check(lib.brr_mlp_backward(self.ptr, _addr(d_x), _addr(d_t), batch, _addr(d_loss),
+                                   _stream(stream)), "brr_mlp_backward")
+
+    def adam_step(self, lr: float, stream=None) -> None:
+        check(lib.brr_mlp_adam_step(self.ptr, lr, _stream(stream)), "brr_mlp_adam_step")
+
+    def train(self, d_x, d_t, batch: int, steps: int, lr: float, stream=None) -> float:
+        loss = ctypes.c_float()
+        check(lib.brr_mlp_train(self.ptr, _addr(d_x), _addr(d_t), batch, steps, lr,
+                                ctypes.byref(loss), _stream(stream)), "brr_mlp_train")
+        return float(loss.value)
+
+    def close(self):
+        if self.ptr:
+            lib.brr_mlp_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def brr_plan_features(h_offsets, elem_bytes: int, sched=None, wave_max: int = 512):
+    import numpy as np
+
+    off = np.ascontiguousarray(h_offsets, dtype=np.uint64)
+    out = np.zeros(BRR_PLAN_FEATURES, np.float32)
+    check(lib.brr_plan_features(off.ctypes.data_as(ctypes.c_void_p), off.size - 1, elem_bytes,
+                                _sched(sched), wave_max, out.ctypes.data_as(ctypes.c_void_p)),
+          "brr_plan_features")
+    return out
+
+
+def brr_plan_autotune_learned(plan: Plan, model: MLP, top: int, data, d_offsets, seed: int = 0,
+                              inst_base: int = 0, stream=None) -> brr_tune_report:
+    rep = brr_tune_report()
+    check(lib.brr_plan_autotune_learned(plan.ptr, model.ptr, top, _addr(data), _addr(d_offsets),
+                                        seed, inst_base, _stream(stream), ctypes.byref(rep)),
+          "brr_plan_autotune_learned")
+    return rep
 
 
 def brr_sync_status(stream=None) -> int:

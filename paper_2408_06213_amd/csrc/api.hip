@@ -670,6 +670,215 @@ bool same_steps(const brr_schedule &a, const brr_schedule &b)
     return true;
 }
 
+// Plan features for the cost model: sizes, payload, how the schedule
+// batches the steps, and how the mapping splits the sizes into tiers.
+void plan_features(const uint64_t *off, uint64_t count, uint32_t eb, const brr_schedule &sc,
+                   uint32_t wave_max, float *f)
+{
+    const DevSched ds = to_dev(sc);
+    double total = 0, sum_lg = 0, sum_lg2 = 0, words = 0, steps = 0, d_hi = 0, d_lo = 0;
+    double band[5] = {0, 0, 0, 0, 0}, in_wave = 0;
+    uint32_t kmax = 1;
+    for (uint32_t g = 0; g < sc.nsteps; ++g) kmax = std::max(kmax, sc.step[g].k);
+    for (uint64_t q = 0; q < count; ++q) {
+        const uint64_t n = off[q + 1] - off[q];
+        if (n <= 1) continue;
+        const double w = (double)n, lg = std::log2(w);
+        total += w;
+        sum_lg += w * lg;
+        sum_lg2 += w * lg * lg;
+        band[n <= 64 ? 0 : n <= 512 ? 1 : n <= 16384 ? 2 : n <= (1u << 20) ? 3 : 4] += w;
+        if (n <= wave_max) in_wave += w;
+        if (n > 0xFFFFFFFFull) continue;
+        SegTable st;
+        build_segments((uint32_t)n, (uint32_t)(n - 1), ds, st);
+        words += st.S;
+        steps += (double)(n - 1);
+        for (uint32_t g = 0; g < st.nseg; ++g) {
+            const double dice = (double)st.seg[g].cnt * st.seg[g].k;
+            if (st.seg[g].k >= 4) d_hi += dice;
+            if (st.seg[g].k <= 2) d_lo += dice;
+        }
+    }
+    const double mean = total > 0 ? sum_lg / total : 0;
+    const double var = total > 0 ? std::max(0.0, sum_lg2 / total - mean * mean) : 0;
+    f[0] = (float)(std::log2(total + 1) / 32);
+    f[1] = (float)(std::log2((double)count + 1) / 16);
+    f[2] = (float)eb / 8;
+    for (int b = 0; b < 5; ++b) f[3 + b] = total > 0 ? (float)(band[b] / total) : 0.0f;
+    f[8] = (float)(mean / 32);
+    f[9] = (float)(std::sqrt(var) / 8);
+    f[10] = steps > 0 ? (float)(words / steps) : 0.0f;
+    f[11] = steps > 0 ? (float)(d_hi / steps) : 0.0f;
+    f[12] = steps > 0 ? (float)(d_lo / steps) : 0.0f;
+    f[13] = (float)kmax / 8;
+    f[14] = (float)(std::log2((double)std::max<uint32_t>(wave_max, 1)) / 10);
+    f[15] = total > 0 ? (float)(in_wave / total) : 0.0f;
+}
+
+struct Candidate {
+    brr_schedule sched;
+    uint32_t wave_max;
+};
+
+// The plan's own configuration first, then the paper's schedules and
+// cost-model schedules (kmax 3..8, several generator/division cost ratios)
+// under wavefront-tier limits 64..512.
+std::vector<Candidate> candidates(const brr_plan *plan, uint64_t max_n)
+{
+    std::vector<brr_schedule> scheds{plan->sched};
+    auto add = [&](const brr_schedule &c) {
+        if (check_for(c, max_n, max_n ? max_n - 1 : 0) != BRR_OK) return;
+        for (const brr_schedule &o : scheds)
+            if (same_steps(o, c)) return;
+        scheds.push_back(c);
+    };
+    for (int mk : {6, 2, 1}) {
+        brr_schedule c;
+        if (brr_schedule_paper(mk, &c) == BRR_OK) add(c);
+    }
+    const double ratios[][2] = {{2, 16}, {1, 16}, {4, 16}, {8, 16}, {2, 64}};
+    for (uint32_t kmax = 3; kmax <= 8; ++kmax)
+        for (const auto &r : ratios) {
+            brr_schedule c;
+            if (brr_schedule_from_costs(kmax, r[0], r[1], BRR_COSTS_POW2 | BRR_COSTS_SMOOTH, &c) ==
+                BRR_OK)
+                add(c);
+        }
+    std::vector<Candidate> out;
+    out.push_back(Candidate{plan->sched, plan->map.wave_max});
+    for (const brr_schedule &sc : scheds)
+        for (uint32_t wm : {64u, 128u, 256u, 512u}) {
+            if (wm > wave_tier_max_n()) continue;
+            if (same_steps(sc, plan->sched) && wm == plan->map.wave_max) continue;
+            out.push_back(Candidate{sc, wm});
+        }
+    return out;
+}
+
+// Picks the plan's configuration. Without a model: time the wavefront limits
+// under the plan's schedule, then every schedule under the best limit. With
+// a model: rank every candidate by predicted time and time the plan's own
+// configuration and the `top` best predicted ones.
+brr_status tune_plan(brr_plan *plan, brr_mlp *model, uint32_t top, const void *d_data,
+                     const uint64_t *d_offsets, uint64_t seed, uint64_t inst_base, void *stream,
+                     brr_tune_report *report)
+{
+    if (!plan || !d_data || !d_offsets) return BRR_EINVAL;
+    if (plan->classified) return BRR_EINVAL; // must precede the first run
+    brr_status st = device_ready(nullptr);
+    if (st != BRR_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t total = plan->count ? plan->h_off[plan->count] : 0;
+    uint64_t max_n = 0;
+    for (uint64_t q = 0; q < plan->count; ++q)
+        max_n = std::max<uint64_t>(max_n, plan->h_off[q + 1] - plan->h_off[q]);
+    const std::vector<Candidate> cands = candidates(plan, max_n);
+    void *work = nullptr;
+    if (total && hipMallocAsync(&work, total * plan->eb, s) != hipSuccess) return BRR_ENOMEM;
+    if (total && hipMemcpyAsync(work, d_data, total * plan->eb, hipMemcpyDeviceToDevice, s) !=
+                     hipSuccess)
+        st = BRR_EHIP;
+    auto time_config = [&](const Candidate &c, float *ms) -> brr_status {
+        brr_plan *t = nullptr;
+        brr_status e = brr_plan_create(&t, plan->h_off.data(), plan->count, plan->eb, &c.sched);
+        if (e != BRR_OK) return e;
+        t->map = plan->map;
+        t->map.wave_max = c.wave_max;
+        t->map.use_graph = 0;
+        *ms = time_ms(
+            [&] { return brr_shuffle_batched(work, d_offsets, plan->count, plan->eb, t, seed,
+                                             inst_base, stream); },
+            s, 2, &e);
+        if (hipStreamSynchronize(s) != hipSuccess && e == BRR_OK) e = BRR_EHIP;
+        brr_plan_destroy(t);
+        return e;
+    };
+    std::vector<size_t> order; // candidates to time, in order
+    if (model && st == BRR_OK) {
+        const uint32_t F = BRR_PLAN_FEATURES;
+        std::vector<float> feats(cands.size() * F), pred(cands.size());
+        for (size_t c = 0; c < cands.size(); ++c)
+            plan_features(plan->h_off.data(), plan->count, plan->eb, cands[c].sched,
+                          cands[c].wave_max, feats.data() + c * F);
+        float *d_f = nullptr, *d_p = nullptr;
+        if (hipMallocAsync(reinterpret_cast<void **>(&d_f), feats.size() * 4, s) != hipSuccess ||
+            hipMallocAsync(reinterpret_cast<void **>(&d_p), pred.size() * 4, s) != hipSuccess)
+            st = BRR_ENOMEM;
+        if (st == BRR_OK &&
+            hipMemcpyAsync(d_f, feats.data(), feats.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+            st = BRR_EHIP;
+        if (st == BRR_OK) st = brr_mlp_forward(model, d_f, (uint32_t)cands.size(), d_p, stream);
+        if (st == BRR_OK &&
+            hipMemcpyAsync(pred.data(), d_p, pred.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+            st = BRR_EHIP;
+        if (d_f) (void)hipFreeAsync(d_f, s);
+        if (d_p) (void)hipFreeAsync(d_p, s);
+        if (hipStreamSynchronize(s) != hipSuccess && st == BRR_OK) st = BRR_EHIP;
+        std::vector<size_t> rank(cands.size());
+        for (size_t c = 0; c < rank.size(); ++c) rank[c] = c;
+        std::stable_sort(rank.begin(), rank.end(), [&](size_t a, size_t b) { return pred[a] < pred[b]; });
+        order.push_back(0);
+        for (size_t r = 0; r < rank.size() && order.size() < (size_t)top + 1; ++r)
+            if (rank[r] != 0) order.push_back(rank[r]);
+    }
+    uint32_t n_tried = 0;
+    float ms_default = 0, best = 0;
+    size_t best_c = 0;
+    if (model) {
+        for (size_t i = 0; i < order.size() && st == BRR_OK; ++i) {
+            float ms = 0;
+            st = time_config(cands[order[i]], &ms);
+            ++n_tried;
+            if (i == 0) ms_default = best = ms;
+            if (st == BRR_OK && ms < best) {
+                best = ms;
+                best_c = order[i];
+            }
+        }
+    } else {
+        if (st == BRR_OK) st = time_config(cands[0], &ms_default);
+        ++n_tried;
+        best = ms_default;
+        uint32_t best_wave = plan->map.wave_max;
+        for (size_t c = 1; c < cands.size() && st == BRR_OK; ++c) { // limits, plan's schedule
+            if (!same_steps(cands[c].sched, plan->sched)) continue;
+            float ms = 0;
+            st = time_config(cands[c], &ms);
+            ++n_tried;
+            if (st == BRR_OK && ms < best) {
+                best = ms;
+                best_c = c;
+                best_wave = cands[c].wave_max;
+            }
+        }
+        for (size_t c = 1; c < cands.size() && st == BRR_OK; ++c) { // schedules, best limit
+            if (same_steps(cands[c].sched, plan->sched) || cands[c].wave_max != best_wave) continue;
+            float ms = 0;
+            st = time_config(cands[c], &ms);
+            ++n_tried;
+            if (st == BRR_OK && ms < best) {
+                best = ms;
+                best_c = c;
+            }
+        }
+    }
+    if (work) (void)hipFreeAsync(work, s);
+    if (hipStreamSynchronize(s) != hipSuccess && st == BRR_OK) st = BRR_EHIP;
+    if (st != BRR_OK) return st;
+    plan->sched = cands[best_c].sched;
+    plan->ds = to_dev(plan->sched);
+    plan->map.wave_max = cands[best_c].wave_max;
+    if (report) {
+        report->candidates = n_tried;
+        report->ms_best = best;
+        report->ms_default = ms_default;
+        report->schedule = plan->sched;
+        report->mapping = plan->map;
+    }
+    return BRR_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -744,94 +953,25 @@ brr_status brr_plan_autotune(brr_plan *plan, const void *d_data, const uint64_t 
                              uint64_t seed, uint64_t inst_base, void *stream,
                              brr_tune_report *report)
 {
-    if (!plan || !d_data || !d_offsets) return BRR_EINVAL;
-    if (plan->classified) return BRR_EINVAL; // must precede the first run
-    brr_status st = device_ready(nullptr);
-    if (st != BRR_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint64_t total = plan->count ? plan->h_off[plan->count] : 0;
-    uint64_t max_n = 0;
-    for (uint64_t q = 0; q < plan->count; ++q)
-        max_n = std::max<uint64_t>(max_n, plan->h_off[q + 1] - plan->h_off[q]);
-    // candidate schedules: the plan's, the paper's, and cost-model ones
-    std::vector<brr_schedule> scheds{plan->sched};
-    auto add = [&](const brr_schedule &c) {
-        if (check_for(c, max_n, max_n ? max_n - 1 : 0) != BRR_OK) return;
-        for (const brr_schedule &o : scheds)
-            if (same_steps(o, c)) return;
-        scheds.push_back(c);
-    };
-    for (int mk : {6, 2, 1}) {
-        brr_schedule c;
-        if (brr_schedule_paper(mk, &c) == BRR_OK) add(c);
-    }
-    const double ratios[][2] = {{2, 16}, {1, 16}, {4, 16}, {8, 16}, {2, 64}};
-    for (uint32_t kmax = 3; kmax <= 8; ++kmax)
-        for (const auto &r : ratios) {
-            brr_schedule c;
-            if (brr_schedule_from_costs(kmax, r[0], r[1], 1, &c) == BRR_OK) add(c);
-        }
-    // a device copy to shuffle while timing
-    void *work = nullptr;
-    if (total && hipMallocAsync(&work, total * plan->eb, s) != hipSuccess) return BRR_ENOMEM;
-    if (total && hipMemcpyAsync(work, d_data, total * plan->eb, hipMemcpyDeviceToDevice, s) !=
-                     hipSuccess)
-        st = BRR_EHIP;
-    auto time_config = [&](const brr_schedule &sc, uint32_t wave_max, float *ms) -> brr_status {
-        brr_plan *t = nullptr;
-        brr_status e = brr_plan_create(&t, plan->h_off.data(), plan->count, plan->eb, &sc);
-        if (e != BRR_OK) return e;
-        t->map = plan->map;
-        t->map.wave_max = wave_max;
-        t->map.use_graph = 0;
-        *ms = time_ms(
-            [&] { return brr_shuffle_batched(work, d_offsets, plan->count, plan->eb, t, seed,
-                                             inst_base, stream); },
-            s, 2, &e);
-        if (hipStreamSynchronize(s) != hipSuccess && e == BRR_OK) e = BRR_EHIP;
-        brr_plan_destroy(t);
-        return e;
-    };
-    uint32_t n_tried = 0;
-    float ms_default = 0, best = 0;
-    size_t best_sched = 0;
-    uint32_t best_wave = plan->map.wave_max;
-    if (st == BRR_OK) st = time_config(plan->sched, plan->map.wave_max, &ms_default);
-    ++n_tried;
-    best = ms_default;
-    for (uint32_t wm : {64u, 128u, 256u, 512u}) { // mapping first, under the plan's schedule
-        if (st != BRR_OK || wm == plan->map.wave_max || wm > wave_tier_max_n()) continue;
-        float ms = 0;
-        st = time_config(plan->sched, wm, &ms);
-        ++n_tried;
-        if (st == BRR_OK && ms < best) {
-            best = ms;
-            best_wave = wm;
-        }
-    }
-    for (size_t c = 1; c < scheds.size() && st == BRR_OK; ++c) { // then the schedule
-        float ms = 0;
-        st = time_config(scheds[c], best_wave, &ms);
-        ++n_tried;
-        if (st == BRR_OK && ms < best) {
-            best = ms;
-            best_sched = c;
-        }
-    }
-    if (work) (void)hipFreeAsync(work, s);
-    if (hipStreamSynchronize(s) != hipSuccess && st == BRR_OK) st = BRR_EHIP;
-    if (st != BRR_OK) return st;
-    plan->sched = scheds[best_sched];
-    plan->ds = to_dev(plan->sched);
-    plan->map.wave_max = best_wave;
-    if (report) {
-        report->candidates = n_tried;
-        report->ms_best = best;
-        report->ms_default = ms_default;
-        report->schedule = plan->sched;
-        report->mapping = plan->map;
-    }
+    return tune_plan(plan, nullptr, 0, d_data, d_offsets, seed, inst_base, stream, report);
+}
+
+brr_status brr_plan_features(const uint64_t *h_offsets, uint64_t count, uint32_t elem_bytes,
+                             const brr_schedule *sched, uint32_t wave_max, float *out)
+{
+    if (!out || (count && !h_offsets) || (elem_bytes != 4 && elem_bytes != 8)) return BRR_EINVAL;
+    const brr_schedule &sc = sched ? *sched : paper6();
+    if (check_structure(sc) != BRR_OK) return BRR_EINVAL;
+    plan_features(h_offsets, count, elem_bytes, sc, wave_max, out);
     return BRR_OK;
+}
+
+brr_status brr_plan_autotune_learned(brr_plan *plan, brr_mlp *model, uint32_t top,
+                                     const void *d_data, const uint64_t *d_offsets, uint64_t seed,
+                                     uint64_t inst_base, void *stream, brr_tune_report *report)
+{
+    if (!model || top == 0) return BRR_EINVAL;
+    return tune_plan(plan, model, top, d_data, d_offsets, seed, inst_base, stream, report);
 }
 
 } // extern "C"

@@ -3,6 +3,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "brr.h"
 #include "internal.hpp"
@@ -80,6 +83,36 @@ uint64_t threshold_nk(uint32_t k, uint32_t L, double c_rng, double c_div)
     }
 }
 
+// The cost model with p2 replaced by its mean p1 / 2 (2^L mod b is spread
+// over [0, b)): smooth in n, so the first size where k dice stop paying off
+// is found by bisection instead of a scan.
+double smooth_cost(uint64_t n, uint32_t k, uint32_t L, double c_rng, double c_div)
+{
+    const u128 b = falling_le(n, k, L);
+    if (b == 0) return INFINITY;
+    const double p1 = (double)b / two_pow(L);
+    return ((c_rng + k) / (1.0 - p1 / 2) + (c_div + k - 1) * p1) / k;
+}
+
+uint64_t threshold_nk_smooth(uint32_t k, uint32_t L, double c_rng, double c_div)
+{
+    auto ok = [&](uint64_t n) {
+        return smooth_cost(n, k, L, c_rng, c_div) < smooth_cost(n, k - 1, L, c_rng, c_div);
+    };
+    if (!ok(k)) return k - 1;
+    uint64_t lo = k, hi = k;
+    while (ok(hi)) {
+        lo = hi;
+        if (hi > (1ull << 62)) return hi;
+        hi *= 2;
+    }
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        (ok(mid) ? lo : hi) = mid;
+    }
+    return lo;
+}
+
 uint64_t floor_pow2(uint64_t x)
 {
     uint64_t p = 1;
@@ -102,7 +135,23 @@ brr_status brr_cost_thresholds(uint32_t L, uint32_t kmax, double c_rng, double c
 {
     if (!out_nk || L < 8 || L > 64 || kmax < 2 || kmax > BRR_MAX_K) return BRR_EINVAL;
     out_nk[0] = out_nk[1] = 0;
-    for (uint32_t k = 2; k <= kmax; ++k) out_nk[k] = threshold_nk(k, L, c_rng, c_div);
+    for (uint32_t k = 2; k <= kmax; ++k) {
+        // the exact scan takes seconds for k = 2 at L = 64: remember results
+        static std::mutex mu;
+        static std::map<std::tuple<uint32_t, uint32_t, double, double>, uint64_t> memo;
+        const auto key = std::make_tuple(k, L, c_rng, c_div);
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            auto it = memo.find(key);
+            if (it != memo.end()) {
+                out_nk[k] = it->second;
+                continue;
+            }
+        }
+        const uint64_t v = threshold_nk(k, L, c_rng, c_div);
+        std::lock_guard<std::mutex> lock(mu);
+        memo[key] = out_nk[k] = v;
+    }
     return BRR_OK;
 }
 
@@ -114,13 +163,18 @@ brr_status brr_schedule_from_costs(uint32_t kmax, double c_rng, double c_div, in
     std::memset(&s, 0, sizeof s);
     if (kmax == 1) return brr_schedule_paper(1, out);
     uint64_t nk[BRR_MAX_K + 1];
-    const brr_status st = brr_cost_thresholds(64, kmax, c_rng, c_div, nk);
-    if (st != BRR_OK) return st;
+    if (pow2 & BRR_COSTS_SMOOTH) {
+        for (uint32_t k = 2; k <= kmax; ++k) nk[k] = threshold_nk_smooth(k, 64, c_rng, c_div);
+    } else {
+        const brr_status st = brr_cost_thresholds(64, kmax, c_rng, c_div, nk);
+        if (st != BRR_OK) return st;
+    }
     // one die while more than n_2 elements remain, then k dice while more than
     // n_{k+1}, the last k down to n_above = k; guards u_k = n_k^k (a power of
     // two when n_k is one, as in the paper's shuffle_6)
     uint64_t above[BRR_MAX_K + 2];
-    for (uint32_t k = 2; k <= kmax; ++k) above[k] = pow2 ? floor_pow2(nk[k]) : nk[k];
+    for (uint32_t k = 2; k <= kmax; ++k)
+        above[k] = std::max<uint64_t>(k, (pow2 & BRR_COSTS_POW2) ? floor_pow2(nk[k]) : nk[k]);
     // thresholds must not increase with k
     for (uint32_t k = 3; k <= kmax; ++k)
         if (above[k] > above[k - 1]) above[k] = above[k - 1];
