@@ -99,6 +99,67 @@ def serving(brr, workloads, up, rates=(1000, 4000, 16000), count=400):
     return out
 
 
+def tuned_ragged(brr, workloads, up, steps):
+    """20,000 ragged shuffles: the plan's default (shuffle_6), exhaustive
+    autotuning, and the learned tuner (model trained here on measured times
+    of random batches, then timing only its top 3 of ~100 candidates)."""
+    import numpy as np
+
+    from paper_2408_06213_amd import learned
+
+    sizes = workloads.ragged_sizes(20000, seed=3)
+    off = workloads.csr_offsets(sizes)
+    data = workloads.iota_segments(sizes)
+    d, d_off = up(data), up(off)
+    res = {}
+    t0 = time.perf_counter()
+    full = brr.Plan(off, 4)
+    rep = full.autotune(d, d_off, 1, 0)
+    res["exhaustive"] = {"ms_default": rep.ms_default, "ms_best": rep.ms_best,
+                         "timed": rep.candidates, "tune_s": time.perf_counter() - t0,
+                         "schedule": rep.schedule.steps(), "wave_max": rep.mapping.wave_max}
+    run = lambda: brr.check(brr.brr_shuffle_batched(d, d_off, sizes.size, 4, full, 1, 0))
+    res["exhaustive"]["ms_replay"] = time_launches(run, steps, 2)
+    full.close()
+    rng = np.random.default_rng(11)
+    t0 = time.perf_counter()
+    X, y, _ = learned.collect(brr, up, rng, nbatch=12, ncand=30)
+    net, loss = learned.train(brr, up, X, y, steps=3000, lr=3e-3, hidden=64)
+    train_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = brr.Plan(off, 4)
+    rep = brr.brr_plan_autotune_learned(plan, net, 3, d, d_off, 1, 0)
+    res["learned"] = {"ms_default": rep.ms_default, "ms_best": rep.ms_best, "timed": rep.candidates,
+                      "tune_s": time.perf_counter() - t0, "train_samples": int(X.shape[0]),
+                      "train_s": train_s, "train_mse": loss,
+                      "schedule": rep.schedule.steps(), "wave_max": rep.mapping.wave_max}
+    run = lambda: brr.check(brr.brr_shuffle_batched(d, d_off, sizes.size, 4, plan, 1, 0))
+    res["learned"]["ms_replay"] = time_launches(run, steps, 2)
+    res["learned_gain_vs_shuffle_6"] = rep.ms_default / rep.ms_best
+    plan.close()
+    net.close()
+    return res
+
+
+def pmc_pass(brr, workloads, up):
+    """For counter runs: a plain copy of 2^28 int32 (1 GiB read, 1 GiB written)
+    and one 2^28-roll dice stream per k = 1..4."""
+    import numpy as np
+    import torch
+
+    a = torch.arange(COUNT, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.bitwise_or(a, 0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    bounds = up(workloads.dice_bounds(COUNT, seed=7))
+    out = torch.empty(COUNT, dtype=torch.uint32, device="cuda")
+    for k in (1, 2, 3, 4):
+        brr.check(brr.brr_dice(bounds, out, COUNT, k, 7, 0))
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_pass": "copy + dice k=1..4", "source_hash": kernel_source_hash()}))
+
+
 def torch_sync():
     import torch
 
@@ -144,6 +205,8 @@ def secondary(brr, workloads, up, steps, only=None):
             res[name] = {"ms": ms, "elems_per_s": n / (ms * 1e-3)}
         res["speedup_k6_vs_k1"] = res["k1"]["ms"] / res["k6"]["ms"]
         out[tag] = res
+    if only in (None, "tuned"):
+        out["ragged_20000_u32_tuned"] = tuned_ragged(brr, workloads, up, steps)
     if only in (None, "serving"):
         out["serving_u64"] = serving(brr, workloads, up)
     return out
@@ -154,10 +217,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--k", type=int, default=4, help="dice per word of the timed stream")
+    ap.add_argument("--k", default="best",
+                    help="dice per word of the headline stream: 1..4, or 'best' (fastest of 2..4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--only", choices=["equal", "ragged", "single10000", "single2p26", "serving"],
+    ap.add_argument("--only", choices=["equal", "ragged", "single10000", "single2p26", "serving",
+                                       "tuned", "pmc"],
                     help="run one shuffle workload only (for profiling); prints its timings")
     args = ap.parse_args()
 
@@ -179,6 +244,9 @@ def main():
     def up(a):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
+    if args.only == "pmc":
+        pmc_pass(brr, workloads, up)
+        return
     if args.only:
         print(json.dumps(secondary(brr, workloads, up, args.steps, args.only)), flush=True)
         return
@@ -190,14 +258,13 @@ def main():
     def step(k):
         return lambda: brr.check(brr.brr_dice(bounds, out, COUNT, k, 7, 0), "brr_dice")
 
-    ms = time_launches(step(args.k), args.steps, args.warmup)
+    ms_k = {k: time_launches(step(k), args.steps, args.warmup) for k in (1, 2, 3, 4)}
     brr.check(brr.brr_sync_status(), "device status")
-    ms_k = {}
-    for k in (1, 2, 3, 4):
-        ms_k[k] = ms if k == args.k else time_launches(step(k), max(5, args.steps // 2), 2)
+    k_head = min((2, 3, 4), key=lambda k: ms_k[k]) if args.k == "best" else int(args.k)
+    ms = ms_k[k_head]
     value = COUNT / (ms * 1e-3)
     achieved = BYTES_PER_ROLL * COUNT / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.k)
+    traffic = measured_traffic(k_head)
 
     rec = {
         "metric": "dice rolls/s and shuffled elems/s, batched vs k=1 on GPU, bit-exact; % roofline",
@@ -214,9 +281,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"flat dice stream: 2^28 u32 bounds uniform in [1,2^16) (seed 7), "
-                        f"k={args.k} dice per 64-bit Philox4x32-10 word",
+                        f"k={k_head} dice per 64-bit Philox4x32-10 word"
+                        + (" (fastest of k=2..4)" if args.k == "best" else ""),
             "count": COUNT,
-            "k": args.k,
+            "k": k_head,
         },
         "roofline": {
             "bound": "hbm",
@@ -241,7 +309,7 @@ def main():
         import oracle
 
         t0 = time.perf_counter()
-        err, _ = oracle.dice(bounds_np, args.k, 7, 0)
+        err, _ = oracle.dice(bounds_np, k_head, 7, 0)
         dt = time.perf_counter() - t0
         assert err == 0
         rec["cpu_baseline"] = {
@@ -249,7 +317,7 @@ def main():
             "unit": "rolls/s",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"the whole 2^28-roll stream at k={args.k}, plain C oracle, one thread "
+            "sample": f"the whole 2^28-roll stream at k={k_head}, plain C oracle, one thread "
                       f"({dt:.1f} s)",
         }
     print(json.dumps(rec), flush=True)
