@@ -18,9 +18,10 @@
  * function of (inputs, seed, inst, schedule), independent of launch shape.
  *
  * Conventions for every entry point:
- *  - Pointers named d_* are device pointers (HIP device memory, 16-byte
- *    aligned for full speed; other alignments take a slower path). Pointers
- *    named h_* and struct pointers are host pointers read during the call.
+ *  - Pointers named d_* are device pointers (HIP device memory, aligned to
+ *    their element size, else BRR_EINVAL; 16-byte alignment is fastest).
+ *    Pointers named h_* and struct pointers are host pointers read during
+ *    the call.
  *  - The caller owns every buffer. The library keeps no pointer after a call
  *    returns, except that a brr_plan remembers the last buffers it was bound
  *    to (it is re-bound on each call).
@@ -181,10 +182,14 @@ void brr_plan_destroy(brr_plan *plan);
 
 /* Plan knobs for the size-class mapping; brr_plan_create uses defaults that
  * brr_plan_set_mapping may replace before the first run. lane_max: shuffles
- * with n <= lane_max run one per lane; wave_max: n <= wave_max one per
- * wavefront; larger shuffles one per workgroup of wg_threads threads while
- * they fit in LDS, else with device scratch. use_graph: 1 = capture the
- * launch sequence once and replay it as a hip graph. */
+ * with n <= lane_max run one per lane, the sequential batched Fisher-Yates
+ * of Algorithm 4 on a byte permutation in LDS (at most 256; 0 = no lane
+ * tier);
+ * wave_max: n <= wave_max one per wavefront (at most 512); larger shuffles
+ * one per workgroup of wg_threads (= 1024) threads while they fit in LDS,
+ * else with device scratch. use_graph: 1 = capture the launch sequence once
+ * and replay it as a hip graph. Every mapping gives the same output; an
+ * out-of-range knob, or a call after the first run, is BRR_EINVAL. */
 typedef struct {
     uint32_t lane_max;
     uint32_t wave_max;

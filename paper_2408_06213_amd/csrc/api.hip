@@ -171,6 +171,10 @@ brr_status brr::ensure_device() { return device_ready(nullptr); }
 // Plans
 // ---------------------------------------------------------------------------
 
+namespace {
+constexpr int kTiers = 5; // lane, wavefront, workgroup, peel, device-wide
+}
+
 struct brr_plan {
     int device = -1;
     uint32_t eb = 4;
@@ -181,9 +185,9 @@ struct brr_plan {
     std::vector<uint64_t> h_off;
     // classification (made on first run, after the mapping is final)
     bool classified = false;
-    uint32_t n_wave = 0, n_wg = 0, n_peel = 0, n_big = 0;
-    uint32_t wave_max_n = 0, wg_max_n = 0;
-    uint32_t *d_items = nullptr; // [wave items | wg items | peel items]
+    uint32_t n_lane = 0, n_wave = 0, n_wg = 0, n_peel = 0, n_big = 0;
+    uint32_t lane_max_n = 0, wave_max_n = 0, wg_max_n = 0;
+    uint32_t *d_items = nullptr; // [lane items | wave items | wg items | peel items]
     // device-wide tier for the shuffles too large for LDS
     GItem *d_gitems = nullptr;
     SegTable *d_gsegs = nullptr;
@@ -192,6 +196,10 @@ struct brr_plan {
     uint64_t g_pos_tiles = 0;
     uint64_t g_npos = 0, g_npairs = 0;
     void *d_scratch = nullptr;
+    // size classes run side by side: each non-empty class but the last on a
+    // branch stream forked from and joined back to the caller's stream
+    hipStream_t branch[kTiers - 1] = {};
+    hipEvent_t fork = nullptr, join[kTiers - 1] = {};
     // graph of the launch sequence, bound to the buffers of the last run
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -205,6 +213,14 @@ namespace {
 
 void release(brr_plan *p)
 {
+    for (int t = 0; t < kTiers - 1; ++t) {
+        if (p->branch[t]) (void)hipStreamDestroy(p->branch[t]);
+        if (p->join[t]) (void)hipEventDestroy(p->join[t]);
+        p->branch[t] = nullptr;
+        p->join[t] = nullptr;
+    }
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    p->fork = nullptr;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
@@ -237,16 +253,20 @@ template <typename T> brr_status upload(T **dst, const std::vector<T> &src)
 
 brr_status classify(brr_plan *p)
 {
-    std::vector<uint32_t> wave, wg, peel;
+    std::vector<uint32_t> lane, wave, wg, peel;
     std::vector<GItem> gitems;
     std::vector<SegTable> gsegs;
     std::vector<uint64_t> pos_base(1, 0), pair_base(1, 0);
     const uint32_t wave_cap = std::min<uint32_t>(p->map.wave_max, wave_tier_max_n());
     const uint32_t wg_cap = lds_tier_max_n();
+    const uint32_t lane_cap = std::min<uint32_t>(p->map.lane_max, lane_tier_max_n());
     for (uint64_t q = 0; q < p->count; ++q) {
         const uint64_t n = p->h_off[q + 1] - p->h_off[q];
         if (n <= 1) continue;
-        if (n <= wave_cap) {
+        if (n <= lane_cap) {
+            lane.push_back((uint32_t)q);
+            p->lane_max_n = std::max<uint32_t>(p->lane_max_n, (uint32_t)n);
+        } else if (n <= wave_cap) {
             wave.push_back((uint32_t)q);
             p->wave_max_n = std::max<uint32_t>(p->wave_max_n, (uint32_t)n);
         } else if (n <= wg_cap) {
@@ -264,11 +284,17 @@ brr_status classify(brr_plan *p)
             pair_base.push_back(pair_base.back() + (st.S + 1) / 2);
         }
     }
+    // lanes of one block run in step when their sizes are close
+    std::stable_sort(lane.begin(), lane.end(), [&](uint32_t a, uint32_t b) {
+        return p->h_off[a + 1] - p->h_off[a] > p->h_off[b + 1] - p->h_off[b];
+    });
+    p->n_lane = (uint32_t)lane.size();
     p->n_wave = (uint32_t)wave.size();
     p->n_wg = (uint32_t)wg.size();
     p->n_peel = (uint32_t)peel.size();
     p->n_big = (uint32_t)gitems.size();
-    std::vector<uint32_t> items(wave);
+    std::vector<uint32_t> items(lane);
+    items.insert(items.end(), wave.begin(), wave.end());
     items.insert(items.end(), wg.begin(), wg.end());
     items.insert(items.end(), peel.begin(), peel.end());
     brr_status st = upload(&p->d_items, items);
@@ -298,22 +324,37 @@ brr_status classify(brr_plan *p)
         if (hipMalloc(&p->d_scratch, gtier_scratch_bytes(p->g_npos, p->eb)) != hipSuccess)
             return BRR_ENOMEM;
     }
+    if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess) return BRR_EHIP;
+    for (int t = 0; t < kTiers - 1; ++t) {
+        if (hipStreamCreateWithFlags(&p->branch[t], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->join[t], hipEventDisableTiming) != hipSuccess)
+            return BRR_EHIP;
+    }
     p->classified = true;
     return BRR_OK;
 }
 
-hipError_t enqueue(brr_plan *p, void *data, const uint64_t *offsets, uint64_t seed, uint64_t inst,
-                   hipStream_t s)
+hipError_t launch_tier(brr_plan *p, int tier, void *data, const uint64_t *offsets, uint64_t seed,
+                       uint64_t inst, hipStream_t s)
 {
-    hipError_t e = launch_batched_wave(data, offsets, p->d_items, p->n_wave, p->wave_max_n, p->eb,
-                                       p->ds, seed, inst, s);
-    if (e != hipSuccess) return e;
-    e = launch_batched_wg(data, offsets, p->d_items + p->n_wave, p->n_wg, p->wg_max_n, p->eb,
-                          p->ds, seed, inst, s);
-    if (e != hipSuccess) return e;
-    e = launch_batched_peel(data, offsets, p->d_items + p->n_wave + p->n_wg, p->n_peel, p->eb,
-                            p->ds, seed, inst, s);
-    if (e != hipSuccess || p->n_big == 0) return e;
+    const uint32_t *items = p->d_items;
+    switch (tier) {
+    case 0:
+        return launch_batched_lane(data, offsets, items, p->n_lane, p->lane_max_n, p->eb, p->ds,
+                                   seed, inst, s);
+    case 1:
+        return launch_batched_wave(data, offsets, items + p->n_lane, p->n_wave, p->wave_max_n,
+                                   p->eb, p->ds, seed, inst, s);
+    case 2:
+        return launch_batched_wg(data, offsets, items + p->n_lane + p->n_wave, p->n_wg,
+                                 p->wg_max_n, p->eb, p->ds, seed, inst, s);
+    case 3:
+        return launch_batched_peel(data, offsets, items + p->n_lane + p->n_wave + p->n_wg,
+                                   p->n_peel, p->eb, p->ds, seed, inst, s);
+    default:
+        break;
+    }
+    if (p->n_big == 0) return hipSuccess;
     GTierArgs a;
     std::memset(&a, 0, sizeof a);
     a.data = data;
@@ -331,6 +372,38 @@ hipError_t enqueue(brr_plan *p, void *data, const uint64_t *offsets, uint64_t se
     a.pair_tile = p->d_gtile + p->g_pos_tiles;
     a.scratch = p->d_scratch;
     return launch_gtier(a, s);
+}
+
+bool tier_used(const brr_plan *p, int tier)
+{
+    const uint32_t n[kTiers] = {p->n_lane, p->n_wave, p->n_wg, p->n_peel, p->n_big};
+    return n[tier] != 0;
+}
+
+// The size classes are independent (disjoint arrays): all but the last
+// non-empty one run on branch streams that fork from s and join back into it.
+hipError_t enqueue(brr_plan *p, void *data, const uint64_t *offsets, uint64_t seed, uint64_t inst,
+                   hipStream_t s)
+{
+    int used[kTiers], nu = 0;
+    for (int t = 0; t < kTiers; ++t)
+        if (tier_used(p, t)) used[nu++] = t;
+    if (nu == 0) return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (nu > 1) {
+        if ((e = hipEventRecord(p->fork, s)) != hipSuccess) return e;
+        for (int b = 0; b + 1 < nu; ++b) {
+            if ((e = hipStreamWaitEvent(p->branch[b], p->fork, 0)) != hipSuccess) return e;
+            if ((e = launch_tier(p, used[b], data, offsets, seed, inst, p->branch[b])) !=
+                hipSuccess)
+                return e;
+            if ((e = hipEventRecord(p->join[b], p->branch[b])) != hipSuccess) return e;
+        }
+    }
+    if ((e = launch_tier(p, used[nu - 1], data, offsets, seed, inst, s)) != hipSuccess) return e;
+    for (int b = 0; b + 1 < nu; ++b)
+        if ((e = hipStreamWaitEvent(s, p->join[b], 0)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 brr_status run_plan(brr_plan *p, void *data, const uint64_t *offsets, uint64_t seed, uint64_t inst,
@@ -426,7 +499,7 @@ brr_status brr_dice(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, u
 {
     if (k < 1 || k > 8) return BRR_EINVAL;
     if (count == 0) return BRR_OK;
-    if (!d_bounds || !d_out) return BRR_EINVAL;
+    if (!d_bounds || !d_out || misaligned(d_bounds, 4) || misaligned(d_out, 4)) return BRR_EINVAL;
     uint32_t *status = nullptr;
     const brr_status st = device_ready(&status);
     if (st != BRR_OK) return st;
@@ -439,7 +512,7 @@ brr_status brr_dice_const(uint32_t bound, uint32_t *d_out, uint64_t count, uint3
 {
     if (k < 1 || k > 8) return BRR_EINVAL;
     if (count == 0) return BRR_OK;
-    if (!d_out || bound == 0) return BRR_EINVAL;
+    if (!d_out || bound == 0 || misaligned(d_out, 4)) return BRR_EINVAL;
     const u128 two64 = (u128)1 << 64;
     u128 p_full = 1;
     for (uint32_t i = 0; i < k; ++i) p_full *= bound;
@@ -462,7 +535,7 @@ brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_
 {
     if (elem_bytes != 4 && elem_bytes != 8) return BRR_EINVAL;
     if (n <= 1) return BRR_OK;
-    if (!d_data || n > 0xFFFFFFFFull) return BRR_EINVAL;
+    if (!d_data || n > 0xFFFFFFFFull || misaligned(d_data, elem_bytes)) return BRR_EINVAL;
     const brr_schedule &sc = sched ? *sched : paper6();
     brr_status st = check_for(sc, n, n - 1);
     if (st != BRR_OK) return st;
@@ -479,6 +552,7 @@ brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_
     if (m > n) return BRR_EINVAL;
     if (m == 0) return BRR_OK;
     if (!d_data || !d_out || n > 0xFFFFFFFFull) return BRR_EINVAL;
+    if (misaligned(d_data, elem_bytes) || misaligned(d_out, elem_bytes)) return BRR_EINVAL;
     const brr_schedule &sc = sched ? *sched : paper6();
     const uint64_t steps = std::min<uint64_t>(m, n - 1);
     brr_status st = check_for(sc, n, steps);
@@ -520,7 +594,7 @@ brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t c
         p->count = count;
         p->sched = sc;
         p->ds = to_dev(sc);
-        p->map = brr_mapping{0, wave_tier_max_n(), 1024, 1};
+        p->map = brr_mapping{lane_tier_max_n(), wave_tier_max_n(), 1024, 1};
         p->h_off.assign(h_offsets, h_offsets + (count ? count + 1 : 0));
     } catch (...) {
         delete p;
@@ -548,7 +622,7 @@ brr_status brr_plan_set_mapping(brr_plan *plan, const brr_mapping *m)
 {
     if (!plan || !m) return BRR_EINVAL;
     if (plan->classified) return BRR_EINVAL; // the mapping is fixed by the first run
-    if (m->lane_max != 0) return BRR_EINVAL; // one-lane tier not offered by this build
+    if (m->lane_max > lane_tier_max_n()) return BRR_EINVAL;
     if (m->wave_max > wave_tier_max_n()) return BRR_EINVAL;
     if (m->wg_threads != 1024) return BRR_EINVAL;
     plan->map = *m;
@@ -561,7 +635,8 @@ brr_status brr_shuffle_batched(void *d_data, const uint64_t *d_offsets, uint64_t
 {
     if (elem_bytes != 4 && elem_bytes != 8) return BRR_EINVAL;
     if (count == 0) return BRR_OK;
-    if (!d_data || !d_offsets) return BRR_EINVAL;
+    if (!d_data || !d_offsets || misaligned(d_data, elem_bytes) || misaligned(d_offsets, 8))
+        return BRR_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (plan) {
         if (plan->eb != elem_bytes || plan->count != count) return BRR_EINVAL;

@@ -43,11 +43,13 @@ struct SegTable {
 // under schedule sc (steps = n - 1 for a full shuffle): while more than
 // thr[g] elements remain, batches of k[g] dice; a batch that would pass
 // `steps` keeps only the dice it needs; then, with a tail, one batch of
-// i - 1 dice. Requires thr[g] + 1 >= k[g] (checked on the host).
-__host__ __device__ inline void build_segments(uint32_t n, uint32_t steps, const DevSched &sc,
-                                               SegTable &t)
+// i - 1 dice. Calls f(Seg) for each run in order and returns the number of
+// batches. Requires thr[g] + 1 >= k[g] (checked on the host).
+template <typename F>
+__host__ __device__ inline uint32_t walk_segments(uint32_t n, uint32_t steps, const DevSched &sc,
+                                                  F &&f)
 {
-    uint32_t i = n, s = 0, done = 0, ns = 0;
+    uint32_t i = n, s = 0, done = 0;
     for (uint32_t g = 0; g < sc.nsteps && done < steps; ++g) {
         const uint32_t thr = sc.thr[g], k = sc.k[g];
         if (i <= thr) continue;
@@ -56,14 +58,14 @@ __host__ __device__ inline void build_segments(uint32_t n, uint32_t steps, const
         uint32_t nb = cnt;
         if ((uint64_t)nb * k > left) nb = left / k;
         if (nb) {
-            t.seg[ns++] = Seg{s, i, k, nb, sc.u[g]};
+            f(Seg{s, i, k, nb, sc.u[g]});
             s += nb;
             i -= nb * k;
             done += nb * k;
         }
         if (nb < cnt && done < steps) {
             const uint32_t kk = steps - done;
-            t.seg[ns++] = Seg{s, i, kk, 1, sc.u[g]};
+            f(Seg{s, i, kk, 1, sc.u[g]});
             s += 1;
             i -= kk;
             done += kk;
@@ -72,12 +74,26 @@ __host__ __device__ inline void build_segments(uint32_t n, uint32_t steps, const
     if (sc.tail && i > 1 && done < steps) {
         uint32_t kk = i - 1;
         if (kk > steps - done) kk = steps - done;
-        t.seg[ns++] = Seg{s, i, kk, 1, sc.u_tail};
+        f(Seg{s, i, kk, 1, sc.u_tail});
         s += 1;
         done += kk;
     }
+    return s;
+}
+
+// The runs of walk_segments as a table.
+__host__ __device__ inline void build_segments(uint32_t n, uint32_t steps, const DevSched &sc,
+                                               SegTable &t)
+{
+    uint32_t ns = 0;
+    t.S = walk_segments(n, steps, sc, [&](const Seg &g) { t.seg[ns++] = g; });
     t.nseg = ns;
-    t.S = s;
+}
+
+// Whether a device pointer is not aligned to its element size.
+inline bool misaligned(const void *p, uint32_t bytes)
+{
+    return (reinterpret_cast<uintptr_t>(p) & (uintptr_t)(bytes - 1)) != 0;
 }
 
 // Kernel launchers (dice.hip, shuffle.hip).
@@ -154,6 +170,12 @@ hipError_t launch_batched_wave(void *data, const uint64_t *offsets, const uint32
 hipError_t launch_batched_wg(void *data, const uint64_t *offsets, const uint32_t *items,
                              uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
                              uint64_t seed, uint64_t inst_base, hipStream_t stream);
+// Lane tier: one lane per in-place shuffle of 2 <= n <= lane_tier_max_n()
+// (items sorted by size for the plan), max_n = largest n among the items.
+uint32_t lane_tier_max_n();
+hipError_t launch_batched_lane(void *data, const uint64_t *offsets, const uint32_t *items,
+                               uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
+                               uint64_t seed, uint64_t inst_base, hipStream_t stream);
 // Peel tier: one workgroup per in-place shuffle of lds_tier_max_n() < n <=
 // peel_tier_max_n(), processed top-down in LDS-sized peels.
 uint32_t peel_tier_max_n();

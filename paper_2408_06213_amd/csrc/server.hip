@@ -255,6 +255,7 @@ brr_status brr_server_submit(brr_server *sv, const brr_request *req, uint64_t *i
     if (r.kind != BRR_REQ_SHUFFLE && r.kind != BRR_REQ_SAMPLE) return BRR_EINVAL;
     if ((r.elem_bytes != 4 && r.elem_bytes != 8) || r.n > 0xFFFFFFFFull) return BRR_EINVAL;
     if (r.n > 0 && !r.d_data) return BRR_EINVAL;
+    if (misaligned(r.d_data, r.elem_bytes) || misaligned(r.d_out, r.elem_bytes)) return BRR_EINVAL;
     if (r.session >= (1ull << 24)) return BRR_EINVAL;
     if (r.kind == BRR_REQ_SAMPLE && (r.m > r.n || (r.m && !r.d_out))) return BRR_EINVAL;
     Req q;

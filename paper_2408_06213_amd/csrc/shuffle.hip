@@ -260,6 +260,307 @@ __global__ __launch_bounds__(BLOCK) void k_lds_batched(Elem *data, const uint64_
                                  make_key(seed, inst_base + q), smem, wsum);
 }
 
+// ---------------------------------------------------------------------------
+// Lane tier: small shuffles, one lane each, the sequential batched
+// Fisher-Yates of Algorithm 4. A block of kLaneItems lanes owns kLaneItems
+// shuffles (the plan sorts them by size so lanes stay in step). Each lane
+// shuffles a byte permutation of its indices in LDS (n <= 256), so the
+// payload is not resident while the dice are rolled; the block then moves
+// the payload in chunks of whole arrays: the original elements of a chunk
+// into an LDS stage, then out[x] = stage[perm[x]] back to HBM.
+// ---------------------------------------------------------------------------
+
+constexpr int kLaneItems = 64;           // shuffles (lanes) per block
+constexpr uint32_t kLaneMaxN = 256;      // byte permutations
+constexpr uint32_t kLaneStageBytes = 8192;
+constexpr int kLaneU = 8;                // loads in flight per lane
+
+__device__ __forceinline__ uint32_t lane_div(uint32_t e, uint32_t n, float rcp)
+{
+    uint32_t t = (uint32_t)((float)e * rcp); // off by at most one for e < 2^16
+    if (t * n > e)
+        --t;
+    else if (e - t * n >= n)
+        ++t;
+    return t;
+}
+
+// LDS of a lane-tier block whose largest array has max_n elements:
+// offs u64[64] | pre u32[65] (+pad) | permutation rows u32[64 * row_words] |
+// stage Elem[stage_cap + 16 / eb] (16-byte aligned).
+struct LaneLds {
+    uint32_t row_words, stage_cap, perm_off, stage_off, bytes;
+};
+
+__host__ __device__ inline LaneLds lane_lds(uint32_t max_n, uint32_t eb)
+{
+    LaneLds L;
+    L.row_words = ((max_n + 3) / 4) | 1u; // odd: lanes' rows start in distinct banks
+    const uint32_t all = kLaneItems * max(max_n, 1u);
+    L.stage_cap = min(kLaneStageBytes / eb, all);
+    L.perm_off = 8 * kLaneItems + 4 * (kLaneItems + 4);
+    L.stage_off = (L.perm_off + 4 * kLaneItems * L.row_words + 15) & ~15u;
+    L.bytes = L.stage_off + (L.stage_cap + 16 / eb) * eb;
+    return L;
+}
+
+// One batch of K dice at i elements left on a lane's byte permutation a:
+// the dice come from one pass of the chain, all 2K bytes the batch touches
+// are read at once, the K sequential swaps are resolved in registers and
+// written back in order (a later write to a position wins, as in the
+// sequential algorithm). Position p_l = i-1-l is final after swap l, and a
+// later die never reaches it, so the value each swap moves is the original
+// byte unless an earlier die of the batch wrote that position.
+template <int K>
+__device__ __forceinline__ void lane_batch(uint8_t *a, uint32_t i, uint64_t u, uint64_t w,
+                                           uint32_t S, uint32_t s, const StreamKey &key)
+{
+    uint32_t j[K];
+    uint64_t r = w;
+#pragma unroll
+    for (int l = 0; l < K; ++l) j[l] = mul_roll(i - l, r);
+    if (u == 0 || r < u) { // not cleared by the guard: exact test, rerolls
+        r = accept_word(i, K, u, w, S, s, key);
+#pragma unroll
+        for (int l = 0; l < K; ++l) j[l] = mul_roll(i - l, r);
+    }
+    uint8_t vp[K], vj[K];
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+        vp[l] = a[i - 1 - l];
+        vj[l] = a[j[l]];
+    }
+    uint8_t to_j[K], to_p[K]; // what swap l writes at j_l and at p_l
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+        uint8_t bp = vp[l], bj = vj[l];
+#pragma unroll
+        for (int m = 0; m < l; ++m) {
+            if (j[m] == i - 1 - (uint32_t)l) bp = to_j[m];
+            if (j[m] == j[l]) bj = to_j[m];
+        }
+        to_j[l] = bp;
+        to_p[l] = bj;
+    }
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+        a[i - 1 - l] = to_p[l];
+        a[j[l]] = to_j[l];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void lane_segment(uint8_t *a, const Seg &g, uint32_t S,
+                                             const StreamKey &key, uint64_t &w_odd)
+{
+    for (uint32_t b = 0; b < g.cnt; ++b) {
+        const uint32_t s = g.s0 + b, i = g.i0 - b * g.k;
+        uint64_t w;
+        if ((s & 1) == 0)
+            word_pair(s >> 1, key, w, w_odd);
+        else
+            w = w_odd; // batches run in order: s - 1 made the pair
+        lane_batch<K>(a, i, g.u, w, S, s, key);
+    }
+}
+
+template <typename Elem>
+__global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const uint64_t *offsets,
+                                                            const uint32_t *items, uint32_t nitems,
+                                                            uint32_t max_n, DevSched sc,
+                                                            uint64_t seed, uint64_t inst_base)
+{
+    constexpr uint32_t V = 16 / sizeof(Elem); // elements per 16-byte vector
+    extern __shared__ __align__(16) char smem[];
+    const LaneLds L = lane_lds(max_n, sizeof(Elem));
+    const uint32_t C = L.stage_cap, RW = L.row_words;
+    uint64_t *offs = reinterpret_cast<uint64_t *>(smem);
+    uint32_t *pre = reinterpret_cast<uint32_t *>(smem + 8 * kLaneItems);
+    uint32_t *permw = reinterpret_cast<uint32_t *>(smem + L.perm_off);
+    Elem *stage = reinterpret_cast<Elem *>(smem + L.stage_off);
+    const uint8_t *perm_bytes = reinterpret_cast<const uint8_t *>(permw);
+    const uint32_t lane = threadIdx.x;
+    const uint32_t first = blockIdx.x * kLaneItems;
+    const uint32_t mine = min<uint32_t>(kLaneItems, nitems - first);
+    uint32_t my_n = 0, my_q = 0;
+    uint64_t my_off = 0;
+    if (lane < mine) {
+        my_q = items[first + lane];
+        my_off = offsets[my_q];
+        my_n = (uint32_t)(offsets[my_q + 1] - my_off);
+    }
+    pre[lane + 1] = wave_inclusive_scan(my_n);
+    if (lane == 0) pre[0] = 0;
+    offs[lane] = my_off;
+    // equal sizes stored back to back (the usual case after sorting): the
+    // block's arrays are one contiguous range
+    const uint32_t n0 = __shfl(my_n, 0);
+    const uint64_t off0 = __shfl(my_off, 0);
+    const bool uniform =
+        __all(lane >= mine || (my_n == n0 && my_off == off0 + (uint64_t)lane * n0));
+
+    // Uniform blocks move whole arrays in chunks of at most C elements:
+    // 16-byte vectors where they fit, single elements at the two ends, with
+    // stage[sh + e] holding chunk element e (sh aligns the vectors in LDS
+    // too). A chunk is loaded into registers while the previous one is being
+    // written out, the first one while the dice are rolled.
+    struct Chunk {
+        uint32_t t0, t1, E, head, sh, nv, tail0;
+    };
+    auto plan_chunk = [&](uint32_t t0) {
+        Chunk c;
+        c.t0 = t0;
+        c.t1 = min(mine, t0 + max(1u, C / max(n0, 1u)));
+        c.E = (c.t1 - t0) * n0;
+        const uintptr_t a = reinterpret_cast<uintptr_t>(data + off0 + (uint64_t)t0 * n0);
+        c.head = min<uint32_t>(c.E, (uint32_t)((16 - (a & 15)) & 15) / sizeof(Elem));
+        c.sh = (V - c.head % V) % V;
+        c.nv = (c.E - c.head) / V;
+        c.tail0 = c.head + c.nv * V;
+        return c;
+    };
+    u32x4 v[kLaneU];
+    Elem hv = 0, tv = 0;
+    auto issue = [&](const Chunk &c) {
+        const Elem *src = data + off0 + (uint64_t)c.t0 * n0;
+        if (lane < c.head) hv = src[lane];
+        if (c.tail0 + lane < c.E) tv = src[c.tail0 + lane];
+        const u32x4 *vs = reinterpret_cast<const u32x4 *>(src + c.head);
+#pragma unroll
+        for (int u = 0; u < kLaneU; ++u) {
+            const uint32_t i = u * kLaneItems + lane;
+            if (i < c.nv) v[u] = __builtin_nontemporal_load(vs + i);
+        }
+    };
+    auto park = [&](const Chunk &c) {
+        if (lane < c.head) stage[c.sh + lane] = hv;
+        if (c.tail0 + lane < c.E) stage[c.sh + c.tail0 + lane] = tv;
+        u32x4 *vstage = reinterpret_cast<u32x4 *>(stage + c.sh + c.head);
+#pragma unroll
+        for (int u = 0; u < kLaneU; ++u) {
+            const uint32_t i = u * kLaneItems + lane;
+            if (i < c.nv) vstage[i] = v[u];
+        }
+    };
+    Chunk cur{};
+    if (uniform) {
+        cur = plan_chunk(0);
+        issue(cur);
+    }
+
+    if (lane < mine && my_n > 1) {
+        uint32_t *row = permw + lane * RW;
+        for (uint32_t w = 0; w < (my_n + 3) / 4; ++w) // identity, four bytes a word
+            row[w] = (4 * w) * 0x01010101u + 0x03020100u;
+        uint8_t *a = reinterpret_cast<uint8_t *>(row);
+        const uint32_t n = my_n;
+        const StreamKey key = make_key(seed, inst_base + my_q);
+        const uint32_t S = walk_segments(n, n - 1, sc, [](const Seg &) {});
+        uint64_t w_odd = 0;
+        walk_segments(n, n - 1, sc, [&](const Seg &g) {
+            switch (g.k) {
+            case 1: lane_segment<1>(a, g, S, key, w_odd); break;
+            case 2: lane_segment<2>(a, g, S, key, w_odd); break;
+            case 3: lane_segment<3>(a, g, S, key, w_odd); break;
+            case 4: lane_segment<4>(a, g, S, key, w_odd); break;
+            case 5: lane_segment<5>(a, g, S, key, w_odd); break;
+            case 6: lane_segment<6>(a, g, S, key, w_odd); break;
+            case 7: lane_segment<7>(a, g, S, key, w_odd); break;
+            case 8: lane_segment<8>(a, g, S, key, w_odd); break;
+            default: // larger batches one swap at a time
+                for (uint32_t b = 0; b < g.cnt; ++b) {
+                    const uint32_t s = g.s0 + b, i = g.i0 - b * g.k;
+                    uint64_t w;
+                    if ((s & 1) == 0)
+                        word_pair(s >> 1, key, w, w_odd);
+                    else
+                        w = w_odd;
+                    uint64_t r = accept_word(i, g.k, g.u, w, S, s, key);
+                    for (uint32_t l = 0; l < g.k; ++l) {
+                        const uint32_t j = mul_roll(i - l, r), p = i - 1 - l;
+                        const uint8_t x = a[p];
+                        a[p] = a[j];
+                        a[j] = x;
+                    }
+                }
+            }
+        });
+    }
+    __syncthreads();
+
+    if (uniform) {
+        const float rcp = 1.0f / (float)max(n0, 1u);
+        for (;;) {
+            park(cur);
+            __syncthreads();
+            const bool more = cur.t1 < mine;
+            Chunk nxt{};
+            if (more) {
+                nxt = plan_chunk(cur.t1);
+                issue(nxt);
+            }
+            // chunk element e is x = e mod n0 of local array e / n0
+            Elem *dst = data + off0 + (uint64_t)cur.t0 * n0;
+            auto out = [&](uint32_t e) {
+                const uint32_t lt = lane_div(e, n0, rcp), x = e - lt * n0;
+                const uint32_t px = perm_bytes[(cur.t0 + lt) * RW * 4 + x];
+                return stage[cur.sh + lt * n0 + px];
+            };
+            if (lane < cur.head) dst[lane] = out(lane);
+            if (cur.tail0 + lane < cur.E) dst[cur.tail0 + lane] = out(cur.tail0 + lane);
+            u32x4 *vd = reinterpret_cast<u32x4 *>(dst + cur.head);
+            for (uint32_t i = lane; i < cur.nv; i += kLaneItems) {
+                Elem tmp[V];
+#pragma unroll
+                for (uint32_t j = 0; j < V; ++j) tmp[j] = out(cur.head + i * V + j);
+                u32x4 w;
+                __builtin_memcpy(&w, tmp, 16);
+                __builtin_nontemporal_store(w, vd + i);
+            }
+            __syncthreads();
+            if (!more) break;
+            cur = nxt;
+        }
+        return;
+    }
+
+    // arrays apart: element by element in chunks of whole arrays, each lane
+    // walking the array table forward as its positions grow
+    for (uint32_t t0 = 0; t0 < mine;) {
+        uint32_t t1 = t0 + 1;
+        while (t1 < mine && pre[t1 + 1] - pre[t0] <= C) ++t1;
+        const uint32_t E = pre[t1] - pre[t0];
+        const uint32_t base = pre[t0];
+        uint32_t t = t0;
+        for (uint32_t e0 = 0; e0 < E; e0 += kLaneU * kLaneItems) {
+            Elem x[kLaneU];
+#pragma unroll
+            for (int u = 0; u < kLaneU; ++u) {
+                const uint32_t e = e0 + u * kLaneItems + lane;
+                if (e < E) {
+                    while (pre[t + 1] - base <= e) ++t;
+                    x[u] = data[offs[t] + (e - (pre[t] - base))];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kLaneU; ++u) {
+                const uint32_t e = e0 + u * kLaneItems + lane;
+                if (e < E) stage[e] = x[u];
+            }
+        }
+        __syncthreads();
+        t = t0;
+        for (uint32_t e = lane; e < E; e += kLaneItems) {
+            while (pre[t + 1] - base <= e) ++t;
+            const uint32_t lo = pre[t] - base, xi = e - lo;
+            const uint32_t px = perm_bytes[t * RW * 4 + xi];
+            data[offs[t] + xi] = stage[lo + px];
+        }
+        __syncthreads();
+        t0 = t1;
+    }
+}
+
 constexpr uint32_t kPeel = 8192;       // positions per peel
 constexpr uint32_t kPeelHashBits = 12; // 4096 chains, load factor <= 2
 constexpr uint32_t kPeelTierMax = 1u << 20;
@@ -747,9 +1048,34 @@ hipError_t batched_peel_t(void *data, const uint64_t *offsets, const uint32_t *i
     return hipGetLastError();
 }
 
+template <typename Elem>
+hipError_t batched_lane_t(void *data, const uint64_t *offsets, const uint32_t *items,
+                          uint32_t nitems, uint32_t max_n, const DevSched &sc, uint64_t seed,
+                          uint64_t inst_base, hipStream_t stream)
+{
+    if (nitems == 0) return hipSuccess;
+    const uint32_t blocks = (nitems + kLaneItems - 1) / kLaneItems;
+    const LaneLds L = lane_lds(max_n, sizeof(Elem));
+    k_lane_batched<Elem><<<blocks, kLaneItems, L.bytes, stream>>>(
+        static_cast<Elem *>(data), offsets, items, nitems, max_n, sc, seed, inst_base);
+    return hipGetLastError();
+}
+
 } // namespace
 
 uint32_t lds_tier_max_n() { return kWgThreads * kWgP; }
+uint32_t lane_tier_max_n() { return kLaneMaxN; }
+
+hipError_t launch_batched_lane(void *data, const uint64_t *offsets, const uint32_t *items,
+                               uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
+                               uint64_t seed, uint64_t inst_base, hipStream_t stream)
+{
+    if (max_n > lane_tier_max_n()) return hipErrorInvalidValue;
+    return eb == 4 ? batched_lane_t<uint32_t>(data, offsets, items, nitems, max_n, sc, seed,
+                                              inst_base, stream)
+                   : batched_lane_t<uint64_t>(data, offsets, items, nitems, max_n, sc, seed,
+                                              inst_base, stream);
+}
 uint32_t peel_tier_max_n() { return kPeelTierMax; }
 
 hipError_t launch_batched_peel(void *data, const uint64_t *offsets, const uint32_t *items,

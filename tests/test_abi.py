@@ -89,3 +89,14 @@ def test_host_argument_errors_need_no_device():
     assert brr.lib.brr_shuffle(None, 1, 4, None, 1, 0, None) == brr.BRR_OK
     assert brr.lib.brr_sample(None, 5, 6, 4, None, None, 1, 0, None) == brr.BRR_EINVAL
     assert brr.lib.brr_sample(None, 5, 0, 4, None, None, 1, 0, None) == brr.BRR_OK
+    # element arrays not aligned to their element size (never dereferenced)
+    odd4, odd8 = 0x10002, 0x10004
+    assert brr.lib.brr_dice(odd4, 0x20000, 10, 4, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_dice(0x20000, odd4, 10, 4, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_dice_const(6, odd4, 10, 2, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_shuffle(odd4, 10, 4, None, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_shuffle(odd8, 10, 8, None, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_sample(odd8, 10, 2, 8, 0x20000, None, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_sample(0x20000, 10, 2, 8, odd8, None, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_shuffle_batched(odd4, 0x20000, 3, 4, None, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_shuffle_batched(0x20000, odd8, 3, 4, None, 1, 0, None) == brr.BRR_EINVAL

@@ -96,18 +96,20 @@ def test_sample_parity(gpu, orc, dtype):
         assert np.array_equal(to_host(d), data)  # input untouched
 
 
-def run_batched(gpu, sizes, dtype, seed, inst_base, plan=True, graph=True, reps=1):
+def run_batched(gpu, sizes, dtype, seed, inst_base, plan=True, graph=True, reps=1, sched=None,
+                **mapping):
     off = workloads.csr_offsets(sizes)
     data = workloads.iota_segments(sizes, dtype)
     d = to_dev(data)
     d_off = to_dev(off)
     p = None
     if plan:
-        p = gpu.Plan(off, data.itemsize)
-        if not graph:
-            m = p.mapping()
-            m.use_graph = 0
-            gpu.check(p.set_mapping(m), "set_mapping")
+        p = gpu.Plan(off, data.itemsize, sched)
+        m = p.mapping()
+        m.use_graph = int(graph)
+        for key, v in mapping.items():
+            setattr(m, key, v)
+        gpu.check(p.set_mapping(m), "set_mapping")
     results = []
     for _ in range(reps):
         d.copy_(to_dev(data))
@@ -143,12 +145,58 @@ def test_batched_without_plan(gpu, orc):
     assert np.array_equal(results[0], want)
 
 
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("max_k", [6, 2, 1, "costs", "wide", "deep"])
+def test_batched_lane_tier(gpu, orc, dtype, max_k):
+    """One lane per shuffle: every size up to the tier's limit, ragged and in
+    runs of equal sizes (both copy paths), with a partly filled last block of
+    lanes, under several schedules ("wide":
+    up to 8 dice with exact-product guards, so that about one batch in 2^8
+    is rejected at n = 256; "deep": batches of 9 and 10 dice)."""
+    cap = 256
+    rng = np.random.default_rng(21)
+    # runs of equal sizes give blocks of lanes whose arrays are contiguous
+    sizes = np.concatenate([np.arange(cap + 1), np.full(150, 37), rng.integers(0, cap + 1, size=131),
+                            np.full(70, cap), [cap + 1, 600]]).astype(np.uint64)
+    if max_k == "costs":
+        sg = gpu.brr_schedule_from_costs(6, 25.0, 40.0, pow2=False, smooth=True)
+        so = orc.Schedule.from_segments(sg.steps(), tail=bool(sg.tail), u_tail=sg.u_tail)
+    elif max_k in ("wide", "deep"):
+        steps = ([(305, 1, 0), (146, 7, 0), (8, 8, 0)] if max_k == "wide"
+                 else [(120, 1, 0), (40, 9, 0), (11, 10, 0)])
+        sg = gpu.brr_schedule.from_steps(steps, tail=True, u_tail=0)
+        so = orc.Schedule.from_segments(steps, tail=True, u_tail=0)
+    else:
+        sg, so = both_schedules(gpu, orc, max_k)
+    say("batched lane tier", np.dtype(dtype).name, max_k)
+    data, off, results = run_batched(gpu, sizes, dtype, seed=31, inst_base=11, reps=2, sched=sg,
+                                     lane_max=cap)
+    want = data.copy()
+    assert orc.shuffle_batched(want, off, so, 31, 11) == 0
+    for got in results:
+        assert np.array_equal(got, want)
+
+
+def test_lane_mapping_limits(gpu):
+    off = workloads.csr_offsets(np.array([3, 4], dtype=np.uint64))
+    for eb in (4, 8):
+        p = gpu.Plan(off, eb)
+        m = p.mapping()
+        m.lane_max = 257
+        assert p.set_mapping(m) == gpu.BRR_EINVAL
+        m.lane_max = 256
+        assert p.set_mapping(m) == 0
+        p.close()
+
+
 @pytest.mark.slow
-def test_batched_equal_size_full(gpu, orc):
+@pytest.mark.parametrize("lane_max", [0, 256])
+def test_batched_equal_size_full(gpu, orc, lane_max):
     """65,536 shuffles of n = 256 (values 0..255), seed 1, instance = id."""
     sizes = np.full(65536, 256, dtype=np.uint64)
-    say("batched 65536 x 256")
-    data, off, results = run_batched(gpu, sizes, np.uint32, seed=1, inst_base=0, reps=2)
+    say("batched 65536 x 256, lane_max", lane_max)
+    data, off, results = run_batched(gpu, sizes, np.uint32, seed=1, inst_base=0, reps=2,
+                                     lane_max=lane_max)
     want = data.copy()
     assert orc.shuffle_batched(want, off, orc.schedule_paper(6), 1, 0) == 0
     for got in results:
