@@ -172,7 +172,8 @@ brr_status brr::ensure_device() { return device_ready(nullptr); }
 // ---------------------------------------------------------------------------
 
 namespace {
-constexpr int kTiers = 5; // lane, wavefront, workgroup, peel, device-wide
+// lane, the LDS size classes, peel, device-wide
+constexpr int kTiers = 3 + kLdsClasses;
 }
 
 struct brr_plan {
@@ -185,9 +186,9 @@ struct brr_plan {
     std::vector<uint64_t> h_off;
     // classification (made on first run, after the mapping is final)
     bool classified = false;
-    uint32_t n_lane = 0, n_wave = 0, n_wg = 0, n_peel = 0, n_big = 0;
-    uint32_t lane_max_n = 0, wave_max_n = 0, wg_max_n = 0;
-    uint32_t *d_items = nullptr; // [lane items | wave items | wg items | peel items]
+    uint32_t n_lane = 0, n_peel = 0, n_big = 0, lane_max_n = 0;
+    uint32_t n_cls[kLdsClasses] = {}, max_cls[kLdsClasses] = {};
+    uint32_t *d_items = nullptr; // [lane items | LDS class 0, 1, ... items | peel items]
     // device-wide tier for the shuffles too large for LDS
     GItem *d_gitems = nullptr;
     SegTable *d_gsegs = nullptr;
@@ -253,12 +254,11 @@ template <typename T> brr_status upload(T **dst, const std::vector<T> &src)
 
 brr_status classify(brr_plan *p)
 {
-    std::vector<uint32_t> lane, wave, wg, peel;
+    std::vector<uint32_t> lane, cls[kLdsClasses], peel;
     std::vector<GItem> gitems;
     std::vector<SegTable> gsegs;
     std::vector<uint64_t> pos_base(1, 0), pair_base(1, 0);
     const uint32_t wave_cap = std::min<uint32_t>(p->map.wave_max, wave_tier_max_n());
-    const uint32_t wg_cap = lds_tier_max_n();
     const uint32_t lane_cap = std::min<uint32_t>(p->map.lane_max, lane_tier_max_n());
     for (uint64_t q = 0; q < p->count; ++q) {
         const uint64_t n = p->h_off[q + 1] - p->h_off[q];
@@ -266,12 +266,15 @@ brr_status classify(brr_plan *p)
         if (n <= lane_cap) {
             lane.push_back((uint32_t)q);
             p->lane_max_n = std::max<uint32_t>(p->lane_max_n, (uint32_t)n);
-        } else if (n <= wave_cap) {
-            wave.push_back((uint32_t)q);
-            p->wave_max_n = std::max<uint32_t>(p->wave_max_n, (uint32_t)n);
-        } else if (n <= wg_cap) {
-            wg.push_back((uint32_t)q);
-            p->wg_max_n = std::max<uint32_t>(p->wg_max_n, (uint32_t)n);
+        } else if (n <= lds_tier_max_n()) {
+            // the one-wavefront class up to wave_max, then the smallest
+            // workgroup that holds the array
+            int c = 0;
+            if (n > wave_cap)
+                for (c = 1; n > lds_class_max_n(c); ++c) {
+                }
+            cls[c].push_back((uint32_t)q);
+            p->max_cls[c] = std::max<uint32_t>(p->max_cls[c], (uint32_t)n);
         } else if (n <= peel_tier_max_n()) {
             peel.push_back((uint32_t)q);
         } else {
@@ -289,13 +292,13 @@ brr_status classify(brr_plan *p)
         return p->h_off[a + 1] - p->h_off[a] > p->h_off[b + 1] - p->h_off[b];
     });
     p->n_lane = (uint32_t)lane.size();
-    p->n_wave = (uint32_t)wave.size();
-    p->n_wg = (uint32_t)wg.size();
     p->n_peel = (uint32_t)peel.size();
     p->n_big = (uint32_t)gitems.size();
     std::vector<uint32_t> items(lane);
-    items.insert(items.end(), wave.begin(), wave.end());
-    items.insert(items.end(), wg.begin(), wg.end());
+    for (int c = 0; c < kLdsClasses; ++c) {
+        p->n_cls[c] = (uint32_t)cls[c].size();
+        items.insert(items.end(), cls[c].begin(), cls[c].end());
+    }
     items.insert(items.end(), peel.begin(), peel.end());
     brr_status st = upload(&p->d_items, items);
     if (st != BRR_OK) return st;
@@ -338,22 +341,18 @@ hipError_t launch_tier(brr_plan *p, int tier, void *data, const uint64_t *offset
                        uint64_t inst, hipStream_t s)
 {
     const uint32_t *items = p->d_items;
-    switch (tier) {
-    case 0:
+    if (tier == 0)
         return launch_batched_lane(data, offsets, items, p->n_lane, p->lane_max_n, p->eb, p->ds,
                                    seed, inst, s);
-    case 1:
-        return launch_batched_wave(data, offsets, items + p->n_lane, p->n_wave, p->wave_max_n,
-                                   p->eb, p->ds, seed, inst, s);
-    case 2:
-        return launch_batched_wg(data, offsets, items + p->n_lane + p->n_wave, p->n_wg,
-                                 p->wg_max_n, p->eb, p->ds, seed, inst, s);
-    case 3:
-        return launch_batched_peel(data, offsets, items + p->n_lane + p->n_wave + p->n_wg,
-                                   p->n_peel, p->eb, p->ds, seed, inst, s);
-    default:
-        break;
+    items += p->n_lane;
+    for (int c = 0; c < kLdsClasses; ++c) {
+        if (tier == 1 + c)
+            return launch_batched_lds(c, data, offsets, items, p->n_cls[c], p->max_cls[c], p->eb,
+                                      p->ds, seed, inst, s);
+        items += p->n_cls[c];
     }
+    if (tier == 1 + kLdsClasses)
+        return launch_batched_peel(data, offsets, items, p->n_peel, p->eb, p->ds, seed, inst, s);
     if (p->n_big == 0) return hipSuccess;
     GTierArgs a;
     std::memset(&a, 0, sizeof a);
@@ -376,8 +375,9 @@ hipError_t launch_tier(brr_plan *p, int tier, void *data, const uint64_t *offset
 
 bool tier_used(const brr_plan *p, int tier)
 {
-    const uint32_t n[kTiers] = {p->n_lane, p->n_wave, p->n_wg, p->n_peel, p->n_big};
-    return n[tier] != 0;
+    if (tier == 0) return p->n_lane != 0;
+    if (tier <= kLdsClasses) return p->n_cls[tier - 1] != 0;
+    return (tier == 1 + kLdsClasses ? p->n_peel : p->n_big) != 0;
 }
 
 // The size classes are independent (disjoint arrays): all but the last

@@ -160,16 +160,16 @@ hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, u
 uint32_t gtier_tile_shift(); // log2 of the indices per tile-table entry
 hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream);
 
-// Batched shuffles of one size class. items: device u32[nitems] of shuffle
-// indices into the CSR offsets. Wave tier: one wavefront per shuffle
-// (n <= wave_tier_max_n()); workgroup tier: one workgroup per shuffle with
-// LDS index arrays (n <= lds_tier_max_n()).
-hipError_t launch_batched_wave(void *data, const uint64_t *offsets, const uint32_t *items,
-                               uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
-                               uint64_t seed, uint64_t inst_base, hipStream_t stream);
-hipError_t launch_batched_wg(void *data, const uint64_t *offsets, const uint32_t *items,
-                             uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
-                             uint64_t seed, uint64_t inst_base, hipStream_t stream);
+// Batched shuffles of one LDS size class: one block per shuffle with its
+// index arrays in LDS, class c holding n <= lds_class_max_n(c) (0: one
+// wavefront, n <= wave_tier_max_n(); kLdsClasses - 1: 1024 threads,
+// n <= lds_tier_max_n()). items: device u32[nitems] of shuffle indices into
+// the CSR offsets; max_n: the largest n among them (sizes the LDS).
+constexpr int kLdsClasses = 5;
+uint32_t lds_class_max_n(int c);
+hipError_t launch_batched_lds(int c, void *data, const uint64_t *offsets, const uint32_t *items,
+                              uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
+                              uint64_t seed, uint64_t inst_base, hipStream_t stream);
 // Lane tier: one lane per in-place shuffle of 2 <= n <= lane_tier_max_n()
 // (items sorted by size for the plan), max_n = largest n among the items.
 uint32_t lane_tier_max_n();

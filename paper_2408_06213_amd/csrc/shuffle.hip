@@ -561,8 +561,8 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const u
     }
 }
 
-constexpr uint32_t kPeel = 8192;       // positions per peel
-constexpr uint32_t kPeelHashBits = 12; // 4096 chains, load factor <= 2
+constexpr uint32_t kPeel = 6144;       // positions per peel
+constexpr uint32_t kPeelHashBits = 12; // 4096 chains, load factor <= 1.5
 constexpr uint32_t kPeelTierMax = 1u << 20;
 
 __device__ __forceinline__ uint32_t peel_hash(uint32_t q)
@@ -571,59 +571,54 @@ __device__ __forceinline__ uint32_t peel_hash(uint32_t q)
 }
 
 struct PeelState {
-    const uint32_t *qof;  // target of the step at local position p' (= p - i_end)
-    const uint16_t *nxt;  // next entry of the same chain
+    const uint32_t *qof;   // target of the step at local position e (= p - i_end)
+    const uint16_t *nxt;   // next entry of the same hash chain
     const uint32_t *table; // chain heads (local positions)
     uint32_t i_end, H;
 };
 
-// Smallest step p'' (global position) targeting q with lo < p'' (kNone32 if
-// none), among the steps of the peel.
-__device__ __forceinline__ uint32_t peel_min_above(const PeelState &ps, uint32_t q, uint32_t lo)
+// One pass over the hash chain of q: the smallest step (global position)
+// of the peel above lo that targets q (kNone32 if none), and whether some
+// step below lo targets q.
+__device__ __forceinline__ uint32_t peel_query(const PeelState &ps, uint32_t q, uint32_t lo,
+                                               bool &below)
 {
-    uint32_t best = kNone32;
+    uint32_t above = kNone32;
+    below = false;
     uint32_t e = ps.table[peel_hash(q)];
     for (uint32_t guard = 0; e != kNone32 && guard < ps.H; ++guard) {
-        const uint32_t pg = ps.i_end + e;
-        if (ps.qof[e] == q && pg > lo && pg < best) best = pg;
+        if (ps.qof[e] == q) {
+            const uint32_t pg = ps.i_end + e;
+            if (pg > lo && pg < above) above = pg;
+            below |= pg < lo;
+        }
         const uint16_t nx = ps.nxt[e];
         e = (nx == kNone16) ? kNone32 : nx;
     }
-    return best;
+    return above;
 }
 
-// Whether some step of the peel below position p targets q.
-__device__ __forceinline__ bool peel_any_below(const PeelState &ps, uint32_t q, uint32_t p)
-{
-    uint32_t e = ps.table[peel_hash(q)];
-    for (uint32_t guard = 0; e != kNone32 && guard < ps.H; ++guard) {
-        if (ps.qof[e] == q && ps.i_end + e < p) return true;
-        const uint16_t nx = ps.nxt[e];
-        e = (nx == kNone16) ? kNone32 : nx;
-    }
-    return false;
-}
-
-// End of the head chain x -> min T_H(x) -> ... (x inside the peel).
-__device__ __forceinline__ uint32_t peel_walk(const PeelState &ps, uint32_t x)
-{
-    for (uint32_t guard = 0; guard < ps.H; ++guard) {
-        const uint32_t h = peel_min_above(ps, x, x);
-        if (h == kNone32) break;
-        x = h;
-    }
-    return x;
-}
-
+// Peel tier: one workgroup per shuffle, positions taken top-down in peels of
+// whole batches (at most kPeel positions); the array stays in HBM/L2. For a
+// peel [i_end, i_begin), with z the array after the peels above:
+//  - the head chain of a position x of the peel, x -> smallest step above x
+//    targeting x -> ..., ends at a position whose value is z at that
+//    position; root[] holds every chain's end;
+//  - step p with target q: the final value at p is the value at root(p) if
+//    q = p, else at root(succ) where succ is the next step above p that
+//    targets q, else z[q];
+//  - a target q below the peel receives, from the smallest step that targets
+//    it, the value at root of that step.
 template <typename Elem>
 __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const uint64_t *offsets,
                                                              const uint32_t *items, DevSched sc,
                                                              uint64_t seed, uint64_t inst_base)
 {
     constexpr uint32_t PEEL = kPeel;
-    constexpr int P = PEEL / kWgThreads;
+    constexpr int P = (PEEL + kWgThreads - 1) / kWgThreads;
     __shared__ uint32_t qof[kPeel];
     __shared__ uint16_t nxt[kPeel];
+    __shared__ uint16_t root[kPeel];
     __shared__ uint32_t table[1u << kPeelHashBits];
     __shared__ SegTable st;
     __shared__ uint32_t next_s, next_i;
@@ -680,7 +675,32 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
         }
         __syncthreads();
         const PeelState ps{qof, nxt, table, i_end, H};
-        // sources first (LDS only), then all gathers back to back
+        // one step up each head chain
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const uint32_t e = tid + r * kWgThreads;
+            if (e >= H) continue;
+            bool below;
+            const uint32_t up = peel_query(ps, i_end + e, i_end + e, below);
+            root[e] = (uint16_t)(up == kNone32 ? e : up - i_end);
+        }
+        __syncthreads();
+        // to the end of each chain; links only ever move up the same chain,
+        // so reading a link another thread has already advanced is harmless
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const uint32_t e = tid + r * kWgThreads;
+            if (e >= H) continue;
+            uint32_t x = e;
+            for (uint32_t guard = 0; guard < H; ++guard) {
+                const uint32_t y = root[x];
+                if (y == x) break;
+                x = y;
+            }
+            root[e] = (uint16_t)x;
+        }
+        __syncthreads();
+        // sources (LDS only), then all gathers back to back
         uint32_t src[P], ext_q[P], ext_src[P];
         uint32_t ext_mask = 0;
 #pragma unroll
@@ -688,17 +708,18 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             const uint32_t e = tid + r * kWgThreads;
             if (e >= H) continue;
             const uint32_t p = i_end + e, q = qof[e];
+            const uint32_t own = i_end + root[e];
             if (q == p) {
-                src[r] = peel_walk(ps, p);
+                src[r] = own;
             } else {
-                const uint32_t sc = peel_min_above(ps, q, p);
-                src[r] = (sc == kNone32) ? q : peel_walk(ps, sc);
-            }
-            // the smallest step into a target below the peel deposits V(p) there
-            if (q < i_end && !peel_any_below(ps, q, p)) {
-                ext_mask |= 1u << r;
-                ext_q[r] = q;
-                ext_src[r] = peel_walk(ps, p);
+                bool below;
+                const uint32_t succ = peel_query(ps, q, p, below);
+                src[r] = (succ == kNone32) ? q : i_end + root[succ - i_end];
+                if (q < i_end && !below) {
+                    ext_mask |= 1u << r;
+                    ext_q[r] = q;
+                    ext_src[r] = own;
+                }
             }
         }
         Elem val[P], ext_val[P];
@@ -1090,15 +1111,32 @@ hipError_t launch_batched_peel(void *data, const uint64_t *offsets, const uint32
 
 hipError_t prepare_shuffle_kernels()
 {
-    const int wg = (int)lds_bytes(kWgThreads * kWgP), wave = (int)lds_bytes(64 * kWaveP);
+    const int wg = (int)lds_bytes(kWgThreads * kWgP);
     const void *fns[] = {(const void *)k_lds_single<uint32_t, kWgThreads, kWgP>,
                          (const void *)k_lds_single<uint64_t, kWgThreads, kWgP>,
-                         (const void *)k_lds_batched<uint32_t, kWgThreads, kWgP>,
-                         (const void *)k_lds_batched<uint64_t, kWgThreads, kWgP>,
                          (const void *)k_lds_batched<uint32_t, 64, kWaveP>,
-                         (const void *)k_lds_batched<uint64_t, 64, kWaveP>};
-    const int bytes[] = {wg, wg, wg, wg, wave, wave};
-    for (int f = 0; f < 6; ++f) {
+                         (const void *)k_lds_batched<uint64_t, 64, kWaveP>,
+                         (const void *)k_lds_batched<uint32_t, 256, 8>,
+                         (const void *)k_lds_batched<uint64_t, 256, 8>,
+                         (const void *)k_lds_batched<uint32_t, 256, 16>,
+                         (const void *)k_lds_batched<uint64_t, 256, 16>,
+                         (const void *)k_lds_batched<uint32_t, 512, 16>,
+                         (const void *)k_lds_batched<uint64_t, 512, 16>,
+                         (const void *)k_lds_batched<uint32_t, kWgThreads, kWgP>,
+                         (const void *)k_lds_batched<uint64_t, kWgThreads, kWgP>};
+    const int bytes[] = {wg,
+                         wg,
+                         (int)lds_bytes(lds_class_max_n(0)),
+                         (int)lds_bytes(lds_class_max_n(0)),
+                         (int)lds_bytes(lds_class_max_n(1)),
+                         (int)lds_bytes(lds_class_max_n(1)),
+                         (int)lds_bytes(lds_class_max_n(2)),
+                         (int)lds_bytes(lds_class_max_n(2)),
+                         (int)lds_bytes(lds_class_max_n(3)),
+                         (int)lds_bytes(lds_class_max_n(3)),
+                         wg,
+                         wg};
+    for (int f = 0; f < (int)(sizeof(bytes) / sizeof(bytes[0])); ++f) {
         const hipError_t e =
             hipFuncSetAttribute(fns[f], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[f]);
         if (e != hipSuccess) return e;
@@ -1181,26 +1219,31 @@ hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream)
                      : gproblem_t<uint64_t>(P, a.data, a.seed, a.scratch, stream);
 }
 
-hipError_t launch_batched_wave(void *data, const uint64_t *offsets, const uint32_t *items,
-                               uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
-                               uint64_t seed, uint64_t inst_base, hipStream_t stream)
+uint32_t lds_class_max_n(int c)
 {
-    if (max_n > wave_tier_max_n()) return hipErrorInvalidValue;
-    return eb == 4 ? batched_lds_t<uint32_t, 64, kWaveP>(data, offsets, items, nitems, max_n, sc,
-                                                         seed, inst_base, stream)
-                   : batched_lds_t<uint64_t, 64, kWaveP>(data, offsets, items, nitems, max_n, sc,
-                                                         seed, inst_base, stream);
+    static const uint32_t cap[kLdsClasses] = {64 * kWaveP, 256 * 8, 256 * 16, 512 * 16,
+                                              kWgThreads * kWgP};
+    return (c >= 0 && c < kLdsClasses) ? cap[c] : 0;
 }
 
-hipError_t launch_batched_wg(void *data, const uint64_t *offsets, const uint32_t *items,
-                             uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
-                             uint64_t seed, uint64_t inst_base, hipStream_t stream)
+hipError_t launch_batched_lds(int c, void *data, const uint64_t *offsets, const uint32_t *items,
+                              uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
+                              uint64_t seed, uint64_t inst_base, hipStream_t stream)
 {
-    if (max_n > lds_tier_max_n()) return hipErrorInvalidValue;
-    return eb == 4 ? batched_lds_t<uint32_t, kWgThreads, kWgP>(data, offsets, items, nitems, max_n,
-                                                               sc, seed, inst_base, stream)
-                   : batched_lds_t<uint64_t, kWgThreads, kWgP>(data, offsets, items, nitems, max_n,
-                                                               sc, seed, inst_base, stream);
+    if (max_n > lds_class_max_n(c)) return hipErrorInvalidValue;
+#define BRR_LDS_CLASS(B, P)                                                                    \
+    return eb == 4 ? batched_lds_t<uint32_t, B, P>(data, offsets, items, nitems, max_n, sc, seed,  \
+                                                   inst_base, stream)                          \
+                   : batched_lds_t<uint64_t, B, P>(data, offsets, items, nitems, max_n, sc, seed,  \
+                                                   inst_base, stream)
+    switch (c) {
+    case 0: BRR_LDS_CLASS(64, kWaveP);
+    case 1: BRR_LDS_CLASS(256, 8);
+    case 2: BRR_LDS_CLASS(256, 16);
+    case 3: BRR_LDS_CLASS(512, 16);
+    default: BRR_LDS_CLASS(kWgThreads, kWgP);
+    }
+#undef BRR_LDS_CLASS
 }
 
 } // namespace brr

@@ -227,13 +227,17 @@ def test_shuffle_2_26(gpu, orc):
 
 
 @pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
-def test_batched_tier_boundaries(gpu, orc, dtype):
-    """Sizes on both sides of every size-class limit: wavefront (512),
-    workgroup (16384), peel (2^20) and device-wide tiers in one batch."""
-    sizes = np.array([512, 513, 16384, 16385, 16404, 32773, 65536, 100000, 1 << 20, (1 << 20) + 1,
-                      2, 70001], dtype=np.uint64)
-    say("batched tier boundaries", np.dtype(dtype).name)
-    data, off, results = run_batched(gpu, sizes, dtype, seed=12, inst_base=7, reps=2)
+@pytest.mark.parametrize("wave_max", [512, 100])
+def test_batched_tier_boundaries(gpu, orc, dtype, wave_max):
+    """Sizes on both sides of every size-class limit: lane (256), wavefront
+    (wave_max), the workgroup classes (2048, 4096, 8192, 16384), peel (2^20)
+    and device-wide tiers in one batch."""
+    sizes = np.array([256, 257, 100, 101, 512, 513, 2048, 2049, 4096, 4097, 8192, 8193, 16384,
+                      16385, 16404, 32773, 65536, 100000, 1 << 20, (1 << 20) + 1, 2, 70001],
+                     dtype=np.uint64)
+    say("batched tier boundaries", np.dtype(dtype).name, wave_max)
+    data, off, results = run_batched(gpu, sizes, dtype, seed=12, inst_base=7, reps=2,
+                                     wave_max=wave_max)
     want = data.copy()
     assert orc.shuffle_batched(want, off, orc.schedule_paper(6), 12, 7) == 0
     for got in results:
