@@ -2,12 +2,15 @@
 """Benchmark of the batched dice-roll hot path on one MI355X.
 
 The timed step is one pass of the flat dice stream: 2^28 u32 bounds uniform
-in [1, 2^16) (seed 7) rolled k = 4 per 64-bit word (brr_dice, Theorem 1 chain
-+ Algorithm 3 acceptance), inputs resident in HBM. The same stream at k = 1
-(the single-roll multiply-and-reject form) is timed beside it. Secondary
+in [1, 2^16) (seed 7) rolled k per 64-bit word (brr_dice, Theorem 1 chain +
+Algorithm 3 acceptance), inputs resident in HBM. k = 1..4 are all timed; the
+headline is the fastest batched k (2..4) unless --k fixes one, and k = 1
+(the single-roll multiply-and-reject form) is reported beside it. Secondary
 workloads report shuffled elements per second: 65,536 shuffles of 256
-elements, 20,000 ragged shuffles, one 10,000-element shuffle and one
-2^26-element shuffle, each batched (shuffle_6) and unbatched (k = 1).
+elements, 20,000 ragged shuffles (also autotuned, exhaustively and by the
+learned model), one 10,000-element shuffle and one 2^26-element shuffle,
+each batched (shuffle_6) and unbatched (k = 1), and the serving loop's
+latency under Poisson load.
 
 Prints one JSON line. Timing: HIP events recorded on the stream the kernels
 are launched on (torch's current stream), K steps after W warmup steps.

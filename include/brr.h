@@ -186,8 +186,11 @@ void brr_plan_destroy(brr_plan *plan);
  * of Algorithm 4 on a byte permutation in LDS (at most 256; 0 = no lane
  * tier);
  * wave_max: n <= wave_max one per wavefront (at most 512); larger shuffles
- * one per workgroup of wg_threads (= 1024) threads while they fit in LDS,
- * else with device scratch. use_graph: 1 = capture the launch sequence once
+ * one per workgroup with their index arrays in LDS, in classes of 256, 256,
+ * 512 and 1024 threads up to 2048, 4096, 8192 and 16384 elements, using
+ * classes up to wg_threads (256, 512 or 1024) threads; larger ones one per
+ * workgroup in peels of whole batches (up to 2^20 elements), else
+ * device-wide with device scratch. use_graph: 1 = capture the launch sequence once
  * and replay it as a hip graph. Every mapping gives the same output; an
  * out-of-range knob, or a call after the first run, is BRR_EINVAL. */
 typedef struct {

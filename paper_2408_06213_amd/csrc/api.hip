@@ -260,13 +260,17 @@ brr_status classify(brr_plan *p)
     std::vector<uint64_t> pos_base(1, 0), pair_base(1, 0);
     const uint32_t wave_cap = std::min<uint32_t>(p->map.wave_max, wave_tier_max_n());
     const uint32_t lane_cap = std::min<uint32_t>(p->map.lane_max, lane_tier_max_n());
+    // LDS classes up to workgroups of wg_threads; larger arrays take peels
+    const uint32_t lds_cap = lds_class_max_n(p->map.wg_threads == 256   ? 2
+                                             : p->map.wg_threads == 512 ? 3
+                                                                        : kLdsClasses - 1);
     for (uint64_t q = 0; q < p->count; ++q) {
         const uint64_t n = p->h_off[q + 1] - p->h_off[q];
         if (n <= 1) continue;
         if (n <= lane_cap) {
             lane.push_back((uint32_t)q);
             p->lane_max_n = std::max<uint32_t>(p->lane_max_n, (uint32_t)n);
-        } else if (n <= lds_tier_max_n()) {
+        } else if (n <= lds_cap) {
             // the one-wavefront class up to wave_max, then the smallest
             // workgroup that holds the array
             int c = 0;
@@ -624,7 +628,7 @@ brr_status brr_plan_set_mapping(brr_plan *plan, const brr_mapping *m)
     if (plan->classified) return BRR_EINVAL; // the mapping is fixed by the first run
     if (m->lane_max > lane_tier_max_n()) return BRR_EINVAL;
     if (m->wave_max > wave_tier_max_n()) return BRR_EINVAL;
-    if (m->wg_threads != 1024) return BRR_EINVAL;
+    if (m->wg_threads != 256 && m->wg_threads != 512 && m->wg_threads != 1024) return BRR_EINVAL;
     plan->map = *m;
     return BRR_OK;
 }

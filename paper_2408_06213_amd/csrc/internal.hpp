@@ -176,8 +176,9 @@ uint32_t lane_tier_max_n();
 hipError_t launch_batched_lane(void *data, const uint64_t *offsets, const uint32_t *items,
                                uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
                                uint64_t seed, uint64_t inst_base, hipStream_t stream);
-// Peel tier: one workgroup per in-place shuffle of lds_tier_max_n() < n <=
-// peel_tier_max_n(), processed top-down in LDS-sized peels.
+// Peel tier: one workgroup per in-place shuffle of 2 <= n <=
+// peel_tier_max_n(), processed top-down in LDS-sized peels (the plan sends
+// it the arrays too large for its LDS classes).
 uint32_t peel_tier_max_n();
 hipError_t launch_batched_peel(void *data, const uint64_t *offsets, const uint32_t *items,
                                uint32_t nitems, uint32_t eb, const DevSched &sc, uint64_t seed,

@@ -54,11 +54,11 @@ double cost_upper(uint64_t n, uint32_t k, uint32_t L, double c_rng, double c_div
     return ((c_rng + k) / (1.0 - p1) + (c_div + k - 1) * p1) / k;
 }
 
-// n_k: the last n of the run n = k, k+1, ... on which a batch of k costs
-// less per die than a batch of k - 1 (Table 2: "cheaper ... for all n up to
-// n_k, but not n_k + 1"). Sizes where the comparison cannot fail (the upper
-// bound of cost(k) below the smallest cost(k-1)) are skipped; the rest are
-// scanned one by one with the exact costs.
+// n_k (Table 2): the largest n such that a batch of k costs less per die
+// than a batch of k - 1 at every size from k up to n. Sizes where the
+// comparison cannot fail (the upper bound of cost(k) below the smallest
+// cost(k-1)) are skipped; the rest are scanned one by one with the exact
+// costs.
 uint64_t threshold_nk(uint32_t k, uint32_t L, double c_rng, double c_div)
 {
     const double floor_prev = (c_rng + (k - 1)) / (double)(k - 1);

@@ -603,7 +603,7 @@ __device__ __forceinline__ uint32_t peel_query(const PeelState &ps, uint32_t q, 
 // peel [i_end, i_begin), with z the array after the peels above:
 //  - the head chain of a position x of the peel, x -> smallest step above x
 //    targeting x -> ..., ends at a position whose value is z at that
-//    position; root[] holds every chain's end;
+//    position; root[] holds every chain's parent, then its end;
 //  - step p with target q: the final value at p is the value at root(p) if
 //    q = p, else at root(succ) where succ is the next step above p that
 //    targets q, else z[q];
@@ -618,7 +618,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
     constexpr int P = (PEEL + kWgThreads - 1) / kWgThreads;
     __shared__ uint32_t qof[kPeel];
     __shared__ uint16_t nxt[kPeel];
-    __shared__ uint16_t root[kPeel];
+    __shared__ uint32_t root[kPeel]; // head-chain parent, then chain end (local)
     __shared__ uint32_t table[1u << kPeelHashBits];
     __shared__ SegTable st;
     __shared__ uint32_t next_s, next_i;
@@ -649,6 +649,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             next_i = i;
         }
         for (uint32_t x = tid; x < (1u << kPeelHashBits); x += kWgThreads) table[x] = kNone32;
+        for (uint32_t x = tid; x < PEEL; x += kWgThreads) root[x] = kNone32;
         __syncthreads();
         const uint32_t s_end = next_s, i_end = next_i, H = i_begin - i_end;
         for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += kWgThreads) {
@@ -666,27 +667,22 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             }
         }
         __syncthreads();
+        // hash chains of the steps that move an element; the head-chain parent
+        // of a peel position (its smallest step above that targets it) by
+        // atomic minimum
         for (uint32_t e = tid; e < H; e += kWgThreads) {
             const uint32_t q = qof[e];
             if (q != i_end + e) {
                 const uint32_t old = atomicExch(&table[peel_hash(q)], e);
                 nxt[e] = (old == kNone32) ? kNone16 : (uint16_t)old;
+                if (q >= i_end) atomicMin(&root[q - i_end], e);
             }
         }
         __syncthreads();
         const PeelState ps{qof, nxt, table, i_end, H};
-        // one step up each head chain
-#pragma unroll
-        for (int r = 0; r < P; ++r) {
-            const uint32_t e = tid + r * kWgThreads;
-            if (e >= H) continue;
-            bool below;
-            const uint32_t up = peel_query(ps, i_end + e, i_end + e, below);
-            root[e] = (uint16_t)(up == kNone32 ? e : up - i_end);
-        }
-        __syncthreads();
-        // to the end of each chain; links only ever move up the same chain,
-        // so reading a link another thread has already advanced is harmless
+        // to the end of each chain (a position without a parent keeps
+        // kNone32); links only ever move up the same chain, so reading a link
+        // another thread has already advanced is harmless
 #pragma unroll
         for (int r = 0; r < P; ++r) {
             const uint32_t e = tid + r * kWgThreads;
@@ -694,10 +690,10 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             uint32_t x = e;
             for (uint32_t guard = 0; guard < H; ++guard) {
                 const uint32_t y = root[x];
-                if (y == x) break;
+                if (y == kNone32) break;
                 x = y;
             }
-            root[e] = (uint16_t)x;
+            if (x != e) root[e] = x;
         }
         __syncthreads();
         // sources (LDS only), then all gathers back to back
@@ -708,13 +704,19 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             const uint32_t e = tid + r * kWgThreads;
             if (e >= H) continue;
             const uint32_t p = i_end + e, q = qof[e];
-            const uint32_t own = i_end + root[e];
+            const uint32_t re = root[e];
+            const uint32_t own = i_end + (re == kNone32 ? e : re);
             if (q == p) {
                 src[r] = own;
             } else {
                 bool below;
                 const uint32_t succ = peel_query(ps, q, p, below);
-                src[r] = (succ == kNone32) ? q : i_end + root[succ - i_end];
+                if (succ == kNone32) {
+                    src[r] = q;
+                } else {
+                    const uint32_t rs = root[succ - i_end];
+                    src[r] = i_end + (rs == kNone32 ? succ - i_end : rs);
+                }
                 if (q < i_end && !below) {
                     ext_mask |= 1u << r;
                     ext_q[r] = q;
@@ -848,6 +850,8 @@ __global__ __launch_bounds__(256) void k_gp_init(uint32_t *cnt, uint64_t len)
         cnt[x] = 0;
 }
 
+constexpr uint32_t kFastK = 6; // batches up to this size keep their dice in registers
+
 __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t seed)
 {
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < P.npairs;
@@ -860,20 +864,51 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
         const StreamKey key = make_key(seed, ib + it.inst);
         uint64_t wd[2];
         word_pair(m, key, wd[0], wd[1]);
+        uint32_t i0[2] = {0, 0}, kk[2] = {0, 0};
+        uint64_t r[2] = {0, 0};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t s = 2 * m + h;
-            if (s >= st.S) break;
-            uint32_t i0, k;
+            if (s >= st.S) continue;
             uint64_t u;
-            batch_at(s, st.seg, st.nseg, i0, k, u);
-            uint64_t r = accept_word(i0, k, u, wd[h], st.S, s, key);
-            for (uint32_t l = 0; l < k; ++l) {
-                const uint32_t p = i0 - 1 - l;
-                const uint32_t a = mul_roll(i0 - l, r);
-                g.jj[it.pos_base + p] = a;
-                if (a < p) g.slot[it.pos_base + p] = atomicAdd(&g.cnt[it.pos_base + a], 1u);
-            }
+            batch_at(s, st.seg, st.nseg, i0[h], kk[h], u);
+            r[h] = accept_word(i0[h], kk[h], u, wd[h], st.S, s, key);
+        }
+        uint32_t *jj = g.jj + it.pos_base, *slot = g.slot + it.pos_base;
+        uint32_t *cnt = g.cnt + it.pos_base;
+        if (kk[0] <= kFastK && kk[1] <= kFastK) {
+            // every die of the pair first, then all counting atomics in
+            // flight together, then their slots
+            uint32_t a[2 * kFastK], sl[2 * kFastK];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (uint32_t l = 0; l < kFastK; ++l)
+                    if (l < kk[h]) {
+                        a[h * kFastK + l] = mul_roll(i0[h] - l, r[h]);
+                        jj[i0[h] - 1 - l] = a[h * kFastK + l];
+                    }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (uint32_t l = 0; l < kFastK; ++l)
+                    if (l < kk[h] && a[h * kFastK + l] < i0[h] - 1 - l)
+                        sl[h * kFastK + l] = atomicAdd(&cnt[a[h * kFastK + l]], 1u);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (uint32_t l = 0; l < kFastK; ++l)
+                    if (l < kk[h] && a[h * kFastK + l] < i0[h] - 1 - l)
+                        slot[i0[h] - 1 - l] = sl[h * kFastK + l];
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                for (uint32_t l = 0; l < kk[h]; ++l) {
+                    const uint32_t p = i0[h] - 1 - l;
+                    const uint32_t a = mul_roll(i0[h] - l, r[h]);
+                    jj[p] = a;
+                    if (a < p) slot[p] = atomicAdd(&cnt[a], 1u);
+                }
         }
     }
 }
