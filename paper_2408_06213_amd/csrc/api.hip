@@ -312,6 +312,7 @@ brr_status classify(brr_plan *p)
         if ((st = upload(&p->d_gitems, gitems)) != BRR_OK) return st;
         if ((st = upload(&p->d_gsegs, gsegs)) != BRR_OK) return st;
         if ((st = upload(&p->d_gbase, bases)) != BRR_OK) return st;
+        if (pos_base.back() > kMaxGtierPositions) return BRR_EINVAL;
         p->g_npos = pos_base.back();
         p->g_npairs = pair_base.back();
         // owner of the first index of every tile, positions then pairs

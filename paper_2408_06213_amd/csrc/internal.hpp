@@ -149,6 +149,8 @@ struct GTierArgs {
     void *scratch;           // gtier_scratch_bytes(npos, eb)
 };
 uint64_t gtier_scratch_bytes(uint64_t npos, uint32_t eb);
+// Positions (summed over items) one device-wide launch takes: indices are u32.
+constexpr uint64_t kMaxGtierPositions = 0xFFFFFFFFull;
 
 // One shuffle (out == nullptr) or sample through the LDS tier or, for
 // n > lds_tier_max_n(), the device-wide tier with stream-ordered scratch of

@@ -751,51 +751,63 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
 // Device-wide tier: any number of shuffles/samples ("items") too large for
 // LDS, processed together by grid-wide kernels. Item i owns positions
 // pos_base[i] .. pos_base[i+1]-1 of the concatenated index arrays and batch
-// pairs pair_base[i] .. pair_base[i+1]-1.
-//   dice:    jj[x] = j_p; slot[x] = rank of step p among the steps into j_p
-//   scan:    cnt = exclusive prefix of the per-target counts, over all items
-//            (item i's last target ends where item i+1's first begins)
-//   scatter: bucket[cnt[target] + slot] = p
-//   head:    one sequential pass over targets: head[x] = min of bucket(x),
-//            and for every step p in bucket(x) its successor there (stored
-//            in slot[], which is dead after the scatter)
+// pairs pair_base[i] .. pair_base[i+1]-1; a step's target as a global index
+// is pos_base[i] + j_p.
+//   init:    sort keys "none", sort values = own position, heads "none"
+//   dice:    jj[x] = j_p; sort key of step x = its global target (steps
+//            with j_p = p keep "none")
+//   sort:    stable LSD radix sort of (target, step) pairs, 8-bit digits;
+//            steps into one target end up adjacent and in increasing order
+//   links:   over the sorted pairs: head[t] = first step of t's run, and
+//            each step's successor is the next one in its run
 //   resolve: source of every output position, gathered from the input
 //   copy:    in-place shuffles copy the gathered values back
 // ---------------------------------------------------------------------------
 
+constexpr uint32_t kSortThreads = 256;
+constexpr uint32_t kSortItems = 8;
+constexpr uint32_t kSortTile = kSortThreads * kSortItems; // pairs per sort block
+constexpr uint32_t kSortNone = 0xFFFFFFFFu;               // sorts after every target
+
 struct GArrays {
-    uint32_t *jj, *slot, *cnt, *head, *bucket, *tiles;
-    void *tmp;
+    uint32_t *jj;              // j_p of every position (item-local)
+    uint32_t *key[2], *val[2]; // sort ping-pong: global target, global step
+    uint32_t *head;            // smallest step into each global target
+    uint32_t *succ;            // next larger step into the same target
+    uint32_t *hist;            // per-block digit counts, digit-major, then scanned
+    uint32_t *tiles;           // scan partial sums
+    void *tmp;                 // gathered values of in-place shuffles
 };
 
 __host__ __device__ inline uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
 __host__ __device__ inline uint64_t scan_tiles(uint64_t len) { return (len + kScanTile - 1) / kScanTile; }
 
+__host__ __device__ inline uint64_t sort_blocks(uint64_t npos)
+{
+    return (npos + kSortTile - 1) / kSortTile;
+}
+
 __host__ __device__ inline uint64_t garrays_bytes(uint64_t npos, uint32_t eb)
 {
-    const uint64_t w = align256(4 * npos);
-    return 4 * w + align256(4 * (npos + 1)) + align256(4 * scan_tiles(npos + 1)) +
-           align256(eb * npos);
+    const uint64_t w = align256(4 * npos), nh = 256 * sort_blocks(npos);
+    return 7 * w + align256(4 * nh) + align256(4 * scan_tiles(nh)) + align256(eb * npos);
 }
 
 __host__ __device__ inline GArrays garrays(void *base, uint64_t npos)
 {
     char *p = static_cast<char *>(base);
-    const uint64_t w = align256(4 * npos);
+    const uint64_t w = align256(4 * npos), nh = 256 * sort_blocks(npos);
     GArrays g;
-    g.jj = reinterpret_cast<uint32_t *>(p);
-    p += w;
-    g.slot = reinterpret_cast<uint32_t *>(p);
-    p += w;
-    g.cnt = reinterpret_cast<uint32_t *>(p);
-    p += align256(4 * (npos + 1));
-    g.head = reinterpret_cast<uint32_t *>(p);
-    p += w;
-    g.bucket = reinterpret_cast<uint32_t *>(p);
-    p += w;
+    uint32_t **arr[7] = {&g.jj, &g.key[0], &g.val[0], &g.key[1], &g.val[1], &g.head, &g.succ};
+    for (int a = 0; a < 7; ++a) {
+        *arr[a] = reinterpret_cast<uint32_t *>(p);
+        p += w;
+    }
+    g.hist = reinterpret_cast<uint32_t *>(p);
+    p += align256(4 * nh);
     g.tiles = reinterpret_cast<uint32_t *>(p);
-    p += align256(4 * scan_tiles(npos + 1));
+    p += align256(4 * scan_tiles(nh));
     g.tmp = p;
     return g;
 }
@@ -843,14 +855,15 @@ __device__ __forceinline__ uint32_t item_of_pos(const GProblem &P, uint64_t x)
     return P.items ? find_item(P.pos_tile, P.pos_base, P.nitems, x) : 0u;
 }
 
-__global__ __launch_bounds__(256) void k_gp_init(uint32_t *cnt, uint64_t len)
+__global__ __launch_bounds__(256) void k_gp_init(GArrays g, uint64_t npos)
 {
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < len;
-         x += (uint64_t)gridDim.x * blockDim.x)
-        cnt[x] = 0;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npos;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        g.key[0][x] = kSortNone;
+        g.val[0][x] = (uint32_t)x;
+        g.head[x] = kNone32;
+    }
 }
-
-constexpr uint32_t kFastK = 6; // batches up to this size keep their dice in registers
 
 __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t seed)
 {
@@ -864,52 +877,206 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
         const StreamKey key = make_key(seed, ib + it.inst);
         uint64_t wd[2];
         word_pair(m, key, wd[0], wd[1]);
-        uint32_t i0[2] = {0, 0}, kk[2] = {0, 0};
-        uint64_t r[2] = {0, 0};
+        uint32_t *jj = g.jj + it.pos_base, *sk = g.key[0] + it.pos_base;
+        const uint32_t tb = (uint32_t)it.pos_base;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t s = 2 * m + h;
             if (s >= st.S) continue;
+            uint32_t i0, k;
             uint64_t u;
-            batch_at(s, st.seg, st.nseg, i0[h], kk[h], u);
-            r[h] = accept_word(i0[h], kk[h], u, wd[h], st.S, s, key);
+            batch_at(s, st.seg, st.nseg, i0, k, u);
+            uint64_t r = accept_word(i0, k, u, wd[h], st.S, s, key);
+            for (uint32_t l = 0; l < k; ++l) {
+                const uint32_t p = i0 - 1 - l;
+                const uint32_t a = mul_roll(i0 - l, r);
+                jj[p] = a;
+                if (a < p) sk[p] = tb + a;
+            }
         }
-        uint32_t *jj = g.jj + it.pos_base, *slot = g.slot + it.pos_base;
-        uint32_t *cnt = g.cnt + it.pos_base;
-        if (kk[0] <= kFastK && kk[1] <= kFastK) {
-            // every die of the pair first, then all counting atomics in
-            // flight together, then their slots
-            uint32_t a[2 * kFastK], sl[2 * kFastK];
+    }
+}
+
+// Exclusive scan of one u64 per thread over a block of 256 (4 wavefronts),
+// in thread order; *total receives the block's sum. Ends with a barrier.
+__device__ __forceinline__ uint64_t sort_block_scan(uint64_t v, uint64_t *wsum, uint64_t &total)
+{
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t incl = v;
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t o = __shfl_up(incl, d, 64);
+        if (lane >= (uint32_t)d) incl += o;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    uint64_t before = 0;
+    for (uint32_t w = 0; w < wid; ++w) before += wsum[w];
+    total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    return before + incl - v;
+}
+
+// Radix sort, pass on bits sh .. sh+7: digit counts of every block's tile.
+__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *keys, uint64_t n,
+                                                          uint32_t sh, uint32_t *hist,
+                                                          uint32_t nblk)
+{
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
 #pragma unroll
-                for (uint32_t l = 0; l < kFastK; ++l)
-                    if (l < kk[h]) {
-                        a[h * kFastK + l] = mul_roll(i0[h] - l, r[h]);
-                        jj[i0[h] - 1 - l] = a[h * kFastK + l];
-                    }
+    for (uint32_t u = 0; u < kSortItems; ++u) {
+        const uint64_t i = base + u * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> sh) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Radix sort, pass on bits sh .. sh+7: the block sorts its tile by the digit
+// in LDS (four stable 2-bit splits), then writes each digit's run to its
+// place: the scanned count of that digit over all earlier digits and
+// blocks, plus the rank inside the tile's run.
+__global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin,
+                                                             const uint32_t *vin, uint32_t *kout,
+                                                             uint32_t *vout, uint64_t n,
+                                                             uint32_t sh, const uint32_t *hist,
+                                                             uint32_t nblk)
+{
+    __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+    __shared__ uint32_t first[256], dst[256];
+    __shared__ uint64_t wsum[kSortThreads / 64];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint32_t valid = (uint32_t)min<uint64_t>(kSortTile, n - base);
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+    for (uint32_t u = 0; u < kSortItems; ++u) { // coalesced; padding sorts last
+        const uint32_t i = u * kSortThreads + tid;
+        sk[i] = (i < valid) ? kin[base + i] : kSortNone;
+        sv[i] = (i < valid) ? vin[base + i] : 0u;
+    }
+    dst[tid] = hist[(uint64_t)tid * nblk + blockIdx.x];
+    __syncthreads();
+    uint32_t k[kSortItems], v[kSortItems];
 #pragma unroll
-                for (uint32_t l = 0; l < kFastK; ++l)
-                    if (l < kk[h] && a[h * kFastK + l] < i0[h] - 1 - l)
-                        sl[h * kFastK + l] = atomicAdd(&cnt[a[h * kFastK + l]], 1u);
+    for (uint32_t u = 0; u < kSortItems; ++u) { // thread tid: tile items 8*tid ..
+        k[u] = sk[tid * kSortItems + u];
+        v[u] = sv[tid * kSortItems + u];
+    }
+    __syncthreads();
+    for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t b = sh + 2 * r;
+        // per thread: running count of each 2-bit value in 16-bit fields
+        uint64_t run = 0;
+        uint32_t before[kSortItems];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (uint32_t l = 0; l < kFastK; ++l)
-                    if (l < kk[h] && a[h * kFastK + l] < i0[h] - 1 - l)
-                        slot[i0[h] - 1 - l] = sl[h * kFastK + l];
-        } else {
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-                for (uint32_t l = 0; l < kk[h]; ++l) {
-                    const uint32_t p = i0[h] - 1 - l;
-                    const uint32_t a = mul_roll(i0[h] - l, r[h]);
-                    jj[p] = a;
-                    if (a < p) slot[p] = atomicAdd(&cnt[a], 1u);
-                }
+        for (uint32_t u = 0; u < kSortItems; ++u) {
+            const uint32_t d = (k[u] >> b) & 3u;
+            before[u] = (uint32_t)(run >> (16 * d)) & 0xFFFFu;
+            run += 1ull << (16 * d);
         }
+        uint64_t total;
+        const uint64_t excl = sort_block_scan(run, wsum, total);
+        const uint32_t t0 = (uint32_t)total & 0xFFFFu, t1 = (uint32_t)(total >> 16) & 0xFFFFu,
+                       t2 = (uint32_t)(total >> 32) & 0xFFFFu;
+        const uint32_t start[4] = {0, t0, t0 + t1, t0 + t1 + t2};
+#pragma unroll
+        for (uint32_t u = 0; u < kSortItems; ++u) {
+            const uint32_t d = (k[u] >> b) & 3u;
+            const uint32_t pos = start[d] + ((uint32_t)(excl >> (16 * d)) & 0xFFFFu) + before[u];
+            sk[pos] = k[u];
+            sv[pos] = v[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t u = 0; u < kSortItems; ++u) {
+            k[u] = sk[tid * kSortItems + u];
+            v[u] = sv[tid * kSortItems + u];
+        }
+        __syncthreads();
+    }
+    // the tile is now in LDS sorted by digit; first index of each digit's run
+#pragma unroll
+    for (uint32_t u = 0; u < kSortItems; ++u) {
+        const uint32_t i = tid * kSortItems + u;
+        const uint32_t d = (k[u] >> sh) & 255u;
+        if (i == 0 || ((sk[i - 1] >> sh) & 255u) != d) first[d] = i;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t u = 0; u < kSortItems; ++u) {
+        const uint32_t i = u * kSortThreads + tid;
+        if (i < valid) {
+            const uint32_t key = sk[i], d = (key >> sh) & 255u;
+            const uint32_t o = dst[d] + (i - first[d]);
+            kout[o] = key;
+            vout[o] = sv[i];
+        }
+    }
+}
+
+// Over the sorted pairs: runs of equal targets give heads and successors.
+__global__ __launch_bounds__(256) void k_gp_links(GArrays g, const uint32_t *keys,
+                                                  const uint32_t *vals, uint64_t npos)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npos;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t t = keys[i];
+        if (t == kSortNone) continue;
+        const uint32_t x = vals[i];
+        if (i == 0 || keys[i - 1] != t) g.head[t] = x;
+        g.succ[x] = (i + 1 < npos && keys[i + 1] == t) ? vals[i + 1] : kNone32;
+    }
+}
+
+template <typename Elem>
+__global__ __launch_bounds__(256) void k_gp_resolve(GProblem P, GArrays g, const Elem *data)
+{
+    Elem *tmp = static_cast<Elem *>(g.tmp);
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const GItem &it = item_at(P, item_of_pos(P, x));
+        const uint32_t p = (uint32_t)(x - it.pos_base);
+        if (p < it.out_lo) continue;
+        const uint32_t lo = it.n - it.steps;
+        const uint32_t q = (p >= lo) ? g.jj[x] : p;
+        const uint32_t *head = g.head + it.pos_base;
+        uint32_t y = p, src;
+        bool walk = true;
+        if (p >= lo && q != p) {
+            const uint32_t sc = g.succ[x];
+            if (sc == kNone32) {
+                walk = false;
+                src = q;
+            } else {
+                y = sc - (uint32_t)it.pos_base;
+            }
+        }
+        if (walk) {
+            uint32_t h;
+            for (uint32_t guard = 0; guard < it.n && (h = head[y]) != kNone32; ++guard)
+                y = h - (uint32_t)it.pos_base;
+            src = y;
+        }
+        const Elem v = data[it.data_off + src];
+        if (it.out)
+            static_cast<Elem *>(it.out)[it.n - 1 - p] = v;
+        else
+            tmp[x] = v;
+    }
+}
+
+template <typename Elem>
+__global__ __launch_bounds__(256) void k_gp_copy(GProblem P, GArrays g, Elem *data)
+{
+    const Elem *tmp = static_cast<const Elem *>(g.tmp);
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const GItem &it = item_at(P, item_of_pos(P, x));
+        if (it.out) continue;
+        data[it.data_off + (x - it.pos_base)] = tmp[x];
     }
 }
 
@@ -952,92 +1119,6 @@ __global__ __launch_bounds__(1024) void k_gp_scan_apply(uint32_t *a, const uint3
     for (uint32_t x = threadIdx.x; x < n; x += 1024) a[b0 + x] = buf[x];
 }
 
-__global__ __launch_bounds__(256) void k_gp_scatter(GProblem P, GArrays g)
-{
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        const GItem &it = item_at(P, item_of_pos(P, x));
-        const uint32_t p = (uint32_t)(x - it.pos_base);
-        if (p < it.n - it.steps) continue;
-        const uint32_t q = g.jj[x];
-        if (q < p) g.bucket[g.cnt[it.pos_base + q] + g.slot[x]] = p;
-    }
-}
-
-// Targets in order: head of each bucket, and each step's successor among the
-// steps into the same target (kNone32 for the largest).
-__global__ __launch_bounds__(256) void k_gp_head(GProblem P, GArrays g)
-{
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t b0 = g.cnt[x], b1 = g.cnt[x + 1];
-        uint32_t h = kNone32;
-        for (uint32_t e = b0; e < b1; ++e) h = min(h, g.bucket[e]);
-        g.head[x] = h;
-        if (b1 > b0) {
-            const GItem &it = item_at(P, item_of_pos(P, x));
-            for (uint32_t e = b0; e < b1; ++e) {
-                const uint32_t v = g.bucket[e];
-                uint32_t sc = kNone32;
-                for (uint32_t f = b0; f < b1; ++f) {
-                    const uint32_t w2 = g.bucket[f];
-                    if (w2 > v && w2 < sc) sc = w2;
-                }
-                g.slot[it.pos_base + v] = sc;
-            }
-        }
-    }
-}
-
-template <typename Elem>
-__global__ __launch_bounds__(256) void k_gp_resolve(GProblem P, GArrays g, const Elem *data)
-{
-    Elem *tmp = static_cast<Elem *>(g.tmp);
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        const GItem &it = item_at(P, item_of_pos(P, x));
-        const uint32_t p = (uint32_t)(x - it.pos_base);
-        if (p < it.out_lo) continue;
-        const uint32_t lo = it.n - it.steps;
-        const uint32_t q = (p >= lo) ? g.jj[x] : p;
-        uint32_t y = p, src;
-        bool walk = true;
-        if (p >= lo && q != p) {
-            const uint32_t sc = g.slot[x];
-            if (sc == kNone32) {
-                walk = false;
-                src = q;
-            } else {
-                y = sc;
-            }
-        }
-        if (walk) {
-            uint32_t h;
-            for (uint32_t guard = 0; guard < it.n && (h = g.head[it.pos_base + y]) != kNone32;
-                 ++guard)
-                y = h;
-            src = y;
-        }
-        const Elem v = data[it.data_off + src];
-        if (it.out)
-            static_cast<Elem *>(it.out)[it.n - 1 - p] = v;
-        else
-            tmp[x] = v;
-    }
-}
-
-template <typename Elem>
-__global__ __launch_bounds__(256) void k_gp_copy(GProblem P, GArrays g, Elem *data)
-{
-    const Elem *tmp = static_cast<const Elem *>(g.tmp);
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        const GItem &it = item_at(P, item_of_pos(P, x));
-        if (it.out) continue;
-        data[it.data_off + (x - it.pos_base)] = tmp[x];
-    }
-}
-
 uint32_t grid_for(uint64_t work, uint32_t block)
 {
     uint64_t b = (work + block - 1) / block;
@@ -1046,20 +1127,34 @@ uint32_t grid_for(uint64_t work, uint32_t block)
     return (uint32_t)b;
 }
 
+void scan_exclusive(uint32_t *a, uint32_t *tiles, uint64_t len, hipStream_t stream)
+{
+    const uint64_t ntiles = scan_tiles(len);
+    k_gp_scan_tiles<<<(uint32_t)ntiles, 1024, 0, stream>>>(a, tiles, len);
+    k_gp_scan_sums<<<1, 1024, 0, stream>>>(tiles, (uint32_t)ntiles);
+    k_gp_scan_apply<<<(uint32_t)ntiles, 1024, 0, stream>>>(a, tiles, len);
+}
+
 template <typename Elem>
 hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratch,
                       hipStream_t stream)
 {
     const GArrays g = garrays(scratch, P.npos);
-    const uint64_t len = P.npos + 1;
-    const uint64_t ntiles = scan_tiles(len);
-    k_gp_init<<<grid_for(len, 256), 256, 0, stream>>>(g.cnt, len);
+    k_gp_init<<<grid_for(P.npos, 256), 256, 0, stream>>>(g, P.npos);
     k_gp_dice<<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
-    k_gp_scan_tiles<<<(uint32_t)ntiles, 1024, 0, stream>>>(g.cnt, g.tiles, len);
-    k_gp_scan_sums<<<1, 1024, 0, stream>>>(g.tiles, (uint32_t)ntiles);
-    k_gp_scan_apply<<<(uint32_t)ntiles, 1024, 0, stream>>>(g.cnt, g.tiles, len);
-    k_gp_scatter<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
-    k_gp_head<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
+    // targets are < npos, so bit_length(npos) bits order them all, and the
+    // "none" key (all ones) after them
+    uint32_t bits = 0;
+    while (bits < 32 && (P.npos >> bits) != 0) ++bits;
+    const uint32_t nblk = (uint32_t)sort_blocks(P.npos);
+    int cur = 0;
+    for (uint32_t sh = 0; sh < bits; sh += 8, cur ^= 1) {
+        k_rs_hist<<<nblk, kSortThreads, 0, stream>>>(g.key[cur], P.npos, sh, g.hist, nblk);
+        scan_exclusive(g.hist, g.tiles, (uint64_t)256 * nblk, stream);
+        k_rs_scatter<<<nblk, kSortThreads, 0, stream>>>(g.key[cur], g.val[cur], g.key[cur ^ 1],
+                                                        g.val[cur ^ 1], P.npos, sh, g.hist, nblk);
+    }
+    k_gp_links<<<grid_for(P.npos, 256), 256, 0, stream>>>(g, g.key[cur], g.val[cur], P.npos);
     k_gp_resolve<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,
                                                                   static_cast<const Elem *>(data));
     k_gp_copy<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, static_cast<Elem *>(data));
@@ -1232,6 +1327,7 @@ hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, u
 hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream)
 {
     if (a.nitems == 0) return hipSuccess;
+    if (a.npos > kMaxGtierPositions) return hipErrorInvalidValue;
     GProblem P;
     std::memset(&P, 0, sizeof P);
     P.nitems = a.nitems;
