@@ -753,6 +753,16 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
 // pos_base[i] .. pos_base[i+1]-1 of the concatenated index arrays and batch
 // pairs pair_base[i] .. pair_base[i+1]-1; a step's target as a global index
 // is pos_base[i] + j_p.
+// Steps are grouped by target in one of two ways:
+//  counting (up to kCountMaxPositions, where the counters stay in L2):
+//   dice:    jj[x] = j_p; slot[x] = rank of step x among the steps into its
+//            target (returning atomic add on cnt[target])
+//   scan:    cnt = exclusive prefix of the per-target counts
+//   scatter: bucket[cnt[target] + slot[x]] = x
+//   links:   per target: head[t] = smallest step of its bucket, and each
+//            step's successor = the next larger one there
+//  sorting (larger problems, where returning atomics on scattered counters
+//  cost more than sorting):
 //   init:    sort keys "none", sort values = own position, heads "none"
 //   dice:    jj[x] = j_p; sort key of step x = its global target (steps
 //            with j_p = p keep "none")
@@ -760,6 +770,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
 //            steps into one target end up adjacent and in increasing order
 //   links:   over the sorted pairs: head[t] = first step of t's run, and
 //            each step's successor is the next one in its run
+// then, either way (steps, heads and successors as global positions):
 //   resolve: source of every output position, gathered from the input
 //   copy:    in-place shuffles copy the gathered values back
 // ---------------------------------------------------------------------------
@@ -769,9 +780,13 @@ constexpr uint32_t kSortItems = 8;
 constexpr uint32_t kSortTile = kSortThreads * kSortItems; // pairs per sort block
 constexpr uint32_t kSortNone = 0xFFFFFFFFu;               // sorts after every target
 
+constexpr uint64_t kCountMaxPositions = 1ull << 21;
+
 struct GArrays {
     uint32_t *jj;              // j_p of every position (item-local)
     uint32_t *key[2], *val[2]; // sort ping-pong: global target, global step
+                               // (counting: slot = key[0], bucket = key[1])
+    uint32_t *cnt;             // counting: per-target counts, then offsets
     uint32_t *head;            // smallest step into each global target
     uint32_t *succ;            // next larger step into the same target
     uint32_t *hist;            // per-block digit counts, digit-major, then scanned
@@ -791,7 +806,9 @@ __host__ __device__ inline uint64_t sort_blocks(uint64_t npos)
 __host__ __device__ inline uint64_t garrays_bytes(uint64_t npos, uint32_t eb)
 {
     const uint64_t w = align256(4 * npos), nh = 256 * sort_blocks(npos);
-    return 7 * w + align256(4 * nh) + align256(4 * scan_tiles(nh)) + align256(eb * npos);
+    const uint64_t nt = scan_tiles(nh > npos + 1 ? nh : npos + 1);
+    return 7 * w + align256(4 * (npos + 1)) + align256(4 * nh) + align256(4 * nt) +
+           align256(eb * npos);
 }
 
 __host__ __device__ inline GArrays garrays(void *base, uint64_t npos)
@@ -804,10 +821,12 @@ __host__ __device__ inline GArrays garrays(void *base, uint64_t npos)
         *arr[a] = reinterpret_cast<uint32_t *>(p);
         p += w;
     }
+    g.cnt = reinterpret_cast<uint32_t *>(p);
+    p += align256(4 * (npos + 1));
     g.hist = reinterpret_cast<uint32_t *>(p);
     p += align256(4 * nh);
     g.tiles = reinterpret_cast<uint32_t *>(p);
-    p += align256(4 * scan_tiles(nh));
+    p += align256(4 * scan_tiles(nh > npos + 1 ? nh : npos + 1));
     g.tmp = p;
     return g;
 }
@@ -893,6 +912,111 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
                 jj[p] = a;
                 if (a < p) sk[p] = tb + a;
             }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gc_init(uint32_t *cnt, uint64_t len)
+{
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < len;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        cnt[x] = 0;
+}
+
+constexpr uint32_t kFastK = 6; // batches up to this size keep their dice in registers
+
+__global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t seed)
+{
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < P.npairs;
+         w += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = P.items ? find_item(P.pair_tile, P.pair_base, P.nitems, w) : 0u;
+        const GItem &it = item_at(P, i);
+        const SegTable &st = segs_at(P, i);
+        const uint32_t m = (uint32_t)(w - (P.items ? P.pair_base[i] : 0));
+        const uint64_t ib = P.inst_base + (P.inst_dev ? *P.inst_dev : 0);
+        const StreamKey key = make_key(seed, ib + it.inst);
+        uint64_t wd[2];
+        word_pair(m, key, wd[0], wd[1]);
+        uint32_t i0[2] = {0, 0}, kk[2] = {0, 0};
+        uint64_t r[2] = {0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t s = 2 * m + h;
+            if (s >= st.S) continue;
+            uint64_t u;
+            batch_at(s, st.seg, st.nseg, i0[h], kk[h], u);
+            r[h] = accept_word(i0[h], kk[h], u, wd[h], st.S, s, key);
+        }
+        uint32_t *jj = g.jj + it.pos_base, *slot = g.key[0] + it.pos_base;
+        uint32_t *cnt = g.cnt + it.pos_base;
+        if (kk[0] <= kFastK && kk[1] <= kFastK) {
+            // every die of the pair first, then all counting atomics in
+            // flight together, then their slots
+            uint32_t a[2 * kFastK], sl[2 * kFastK];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (uint32_t l = 0; l < kFastK; ++l)
+                    if (l < kk[h]) {
+                        a[h * kFastK + l] = mul_roll(i0[h] - l, r[h]);
+                        jj[i0[h] - 1 - l] = a[h * kFastK + l];
+                    }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (uint32_t l = 0; l < kFastK; ++l)
+                    if (l < kk[h] && a[h * kFastK + l] < i0[h] - 1 - l)
+                        sl[h * kFastK + l] = atomicAdd(&cnt[a[h * kFastK + l]], 1u);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (uint32_t l = 0; l < kFastK; ++l)
+                    if (l < kk[h] && a[h * kFastK + l] < i0[h] - 1 - l)
+                        slot[i0[h] - 1 - l] = sl[h * kFastK + l];
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                for (uint32_t l = 0; l < kk[h]; ++l) {
+                    const uint32_t p = i0[h] - 1 - l;
+                    const uint32_t a = mul_roll(i0[h] - l, r[h]);
+                    jj[p] = a;
+                    if (a < p) slot[p] = atomicAdd(&cnt[a], 1u);
+                }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gc_scatter(GProblem P, GArrays g)
+{
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const GItem &it = item_at(P, item_of_pos(P, x));
+        const uint32_t p = (uint32_t)(x - it.pos_base);
+        if (p < it.n - it.steps) continue;
+        const uint32_t q = g.jj[x];
+        if (q < p) g.key[1][g.cnt[it.pos_base + q] + g.key[0][x]] = (uint32_t)x;
+    }
+}
+
+// Targets in order: head of each bucket, and each step's successor among the
+// steps into the same target (kNone32 for the largest).
+__global__ __launch_bounds__(256) void k_gc_links(GArrays g, uint64_t npos)
+{
+    const uint32_t *bucket = g.key[1];
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npos;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t b0 = g.cnt[x], b1 = g.cnt[x + 1];
+        uint32_t h = kNone32;
+        for (uint32_t e = b0; e < b1; ++e) h = min(h, bucket[e]);
+        g.head[x] = h;
+        for (uint32_t e = b0; e < b1; ++e) {
+            const uint32_t v = bucket[e];
+            uint32_t sc = kNone32;
+            for (uint32_t f = b0; f < b1; ++f) {
+                const uint32_t w2 = bucket[f];
+                if (w2 > v && w2 < sc) sc = w2;
+            }
+            g.succ[v] = sc;
         }
     }
 }
@@ -1140,6 +1264,18 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
                       hipStream_t stream)
 {
     const GArrays g = garrays(scratch, P.npos);
+    if (P.npos <= kCountMaxPositions) {
+        k_gc_init<<<grid_for(P.npos + 1, 256), 256, 0, stream>>>(g.cnt, P.npos + 1);
+        k_gc_dice<<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
+        scan_exclusive(g.cnt, g.tiles, P.npos + 1, stream);
+        k_gc_scatter<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
+        k_gc_links<<<grid_for(P.npos, 256), 256, 0, stream>>>(g, P.npos);
+        k_gp_resolve<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(
+            P, g, static_cast<const Elem *>(data));
+        k_gp_copy<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,
+                                                                   static_cast<Elem *>(data));
+        return hipGetLastError();
+    }
     k_gp_init<<<grid_for(P.npos, 256), 256, 0, stream>>>(g, P.npos);
     k_gp_dice<<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
     // targets are < npos, so bit_length(npos) bits order them all, and the

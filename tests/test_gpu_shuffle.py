@@ -10,7 +10,8 @@ pytestmark = pytest.mark.gpu
 
 LDS_SIZES = [2, 3, 4, 5, 6, 7, 8, 13, 64, 100, 255, 256, 257, 511, 512, 513, 1000, 4096, 10000,
              16383, 16384]
-GLOBAL_SIZES = [16385, 20000, 65536, 100003, 1 << 20]
+# device-wide tier: counting up to 2^21 positions, radix sort above
+GLOBAL_SIZES = [16385, 20000, 65536, 100003, 1 << 20, 1 << 21, (1 << 21) + 5]
 
 
 def both_schedules(gpu, orc, max_k):
@@ -82,7 +83,8 @@ def test_sample_parity(gpu, orc, dtype):
     rng = np.random.default_rng(9)
     cases = [(2, 1), (2, 2), (5, 5), (5, 4), (10, 3), (256, 25), (1000, 1), (10000, 1000),
              (16384, 16384), (16384, 1638), (16385, 1638), (100003, 10000), (1 << 20, 104857),
-             (1 << 20, 1), (70000, 69999), (70000, 70000)]
+             (1 << 20, 1), (70000, 69999), (70000, 70000), (3000000, 300000),
+             ((1 << 21) + 1, 1)]
     for n, m in cases:
         say("sample", np.dtype(dtype).name, n, m)
         data = rng.integers(0, 2**31, size=n).astype(dtype)
