@@ -38,7 +38,8 @@ constexpr uint32_t kNone32 = 0xFFFFFFFFu;
 constexpr int kWaveP = 8;        // positions per lane in the wavefront tier
 constexpr int kWgThreads = 1024; // workgroup tier and single-workgroup global tier
 constexpr int kWgP = 16;         // positions per thread in the workgroup tier
-constexpr uint32_t kScanTile = 1024 * 16;
+constexpr uint32_t kScanThreads = 256;
+constexpr uint32_t kScanTile = kScanThreads * 16; // entries per block of the device-wide scan
 constexpr uint64_t kMaxAttempts = 1024;
 constexpr int kTileShift = 8; // 256 indices per tile of the item tables
 
@@ -998,26 +999,31 @@ __global__ __launch_bounds__(256) void k_gc_scatter(GProblem P, GArrays g)
     }
 }
 
-// Targets in order: head of each bucket, and each step's successor among the
-// steps into the same target (kNone32 for the largest).
-__global__ __launch_bounds__(256) void k_gc_links(GArrays g, uint64_t npos)
+// Position x as a target: the head of its bucket; as a step into q: its
+// successor, the next larger step in q's bucket (kNone32 for the largest).
+// One bucket scan each, so no thread pays for a whole bucket's pairs.
+__global__ __launch_bounds__(256) void k_gc_links(GProblem P, GArrays g)
 {
     const uint32_t *bucket = g.key[1];
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npos;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
          x += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t b0 = g.cnt[x], b1 = g.cnt[x + 1];
         uint32_t h = kNone32;
         for (uint32_t e = b0; e < b1; ++e) h = min(h, bucket[e]);
         g.head[x] = h;
-        for (uint32_t e = b0; e < b1; ++e) {
-            const uint32_t v = bucket[e];
-            uint32_t sc = kNone32;
-            for (uint32_t f = b0; f < b1; ++f) {
-                const uint32_t w2 = bucket[f];
-                if (w2 > v && w2 < sc) sc = w2;
-            }
-            g.succ[v] = sc;
+        const GItem &it = item_at(P, item_of_pos(P, x));
+        const uint32_t p = (uint32_t)(x - it.pos_base);
+        if (p < it.n - it.steps) continue;
+        const uint32_t q = g.jj[x];
+        if (q >= p) continue;
+        const uint64_t t = it.pos_base + q;
+        const uint32_t c0 = g.cnt[t], c1 = g.cnt[t + 1];
+        uint32_t sc = kNone32;
+        for (uint32_t f = c0; f < c1; ++f) {
+            const uint32_t w2 = bucket[f];
+            if (w2 > x && w2 < sc) sc = w2;
         }
+        g.succ[x] = sc;
     }
 }
 
@@ -1204,20 +1210,21 @@ __global__ __launch_bounds__(256) void k_gp_copy(GProblem P, GArrays g, Elem *da
     }
 }
 
-__global__ __launch_bounds__(1024) void k_gp_scan_tiles(const uint32_t *a, uint32_t *tiles,
-                                                        uint64_t len)
+__global__ __launch_bounds__(kScanThreads) void k_gp_scan_tiles(const uint32_t *a,
+                                                                 uint32_t *tiles, uint64_t len)
 {
-    __shared__ uint32_t wsum[16];
+    constexpr int NW = kScanThreads / 64;
+    __shared__ uint32_t wsum[NW];
     const uint64_t b0 = (uint64_t)blockIdx.x * kScanTile;
     const uint32_t n = (uint32_t)min((uint64_t)kScanTile, len - b0);
     uint32_t local = 0;
-    for (uint32_t x = threadIdx.x; x < n; x += 1024) local += a[b0 + x];
+    for (uint32_t x = threadIdx.x; x < n; x += kScanThreads) local += a[b0 + x];
     local = wave_inclusive_scan(local);
     if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = local;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t t = 0;
-        for (int w = 0; w < 16; ++w) t += wsum[w];
+        for (int w = 0; w < NW; ++w) t += wsum[w];
         tiles[blockIdx.x] = t;
     }
 }
@@ -1230,17 +1237,18 @@ __global__ __launch_bounds__(1024) void k_gp_scan_sums(uint32_t *tiles, uint32_t
 
 // Exclusive scan of one tile of kScanTile counts starting at the tile's
 // base: coalesced loads into LDS, an LDS scan, coalesced stores.
-__global__ __launch_bounds__(1024) void k_gp_scan_apply(uint32_t *a, const uint32_t *tiles,
-                                                        uint64_t len)
+__global__ __launch_bounds__(kScanThreads) void k_gp_scan_apply(uint32_t *a,
+                                                                 const uint32_t *tiles,
+                                                                 uint64_t len)
 {
     __shared__ uint32_t buf[kScanTile];
-    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t wsum[kScanThreads / 64];
     const uint64_t b0 = (uint64_t)blockIdx.x * kScanTile;
     const uint32_t n = (uint32_t)min((uint64_t)kScanTile, len - b0);
-    for (uint32_t x = threadIdx.x; x < n; x += 1024) buf[x] = a[b0 + x];
+    for (uint32_t x = threadIdx.x; x < n; x += kScanThreads) buf[x] = a[b0 + x];
     __syncthreads();
-    block_scan_array<1024>(buf, n, tiles[blockIdx.x], wsum);
-    for (uint32_t x = threadIdx.x; x < n; x += 1024) a[b0 + x] = buf[x];
+    block_scan_array<kScanThreads>(buf, n, tiles[blockIdx.x], wsum);
+    for (uint32_t x = threadIdx.x; x < n; x += kScanThreads) a[b0 + x] = buf[x];
 }
 
 uint32_t grid_for(uint64_t work, uint32_t block)
@@ -1254,9 +1262,9 @@ uint32_t grid_for(uint64_t work, uint32_t block)
 void scan_exclusive(uint32_t *a, uint32_t *tiles, uint64_t len, hipStream_t stream)
 {
     const uint64_t ntiles = scan_tiles(len);
-    k_gp_scan_tiles<<<(uint32_t)ntiles, 1024, 0, stream>>>(a, tiles, len);
+    k_gp_scan_tiles<<<(uint32_t)ntiles, kScanThreads, 0, stream>>>(a, tiles, len);
     k_gp_scan_sums<<<1, 1024, 0, stream>>>(tiles, (uint32_t)ntiles);
-    k_gp_scan_apply<<<(uint32_t)ntiles, 1024, 0, stream>>>(a, tiles, len);
+    k_gp_scan_apply<<<(uint32_t)ntiles, kScanThreads, 0, stream>>>(a, tiles, len);
 }
 
 template <typename Elem>
@@ -1269,7 +1277,7 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
         k_gc_dice<<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
         scan_exclusive(g.cnt, g.tiles, P.npos + 1, stream);
         k_gc_scatter<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
-        k_gc_links<<<grid_for(P.npos, 256), 256, 0, stream>>>(g, P.npos);
+        k_gc_links<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
         k_gp_resolve<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(
             P, g, static_cast<const Elem *>(data));
         k_gp_copy<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,
