@@ -68,11 +68,13 @@ def time_launches(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per step
 
 
-def serving(brr, workloads, up, rates=(1000, 4000, 16000), count=400):
+def serving(brr, workloads, up, rates=(1000, 4000, 16000), count=400, clients=64):
     """Poisson arrivals at each rate: requests (shuffle or sample, n
-    log-uniform in [2^4, 2^22], u64 payload, m <= n/10) are submitted at their
-    arrival times to a continuous-batching server; p50/p99 latency from
-    submission to completion, and the throughput achieved."""
+    log-uniform in [2^4, 2^22], u64 payload, m <= n/10) from `clients`
+    independent clients (request i belongs to session i mod clients; a
+    session's requests run in order) are submitted at their arrival times to
+    a continuous-batching server; p50/p99 latency from submission to
+    completion, and the throughput achieved."""
     import numpy as np
 
     out = []
@@ -86,15 +88,15 @@ def serving(brr, workloads, up, rates=(1000, 4000, 16000), count=400):
         torch_sync()
         srv = brr.Server(hbm_budget=8 << 30, max_inflight=64, nstreams=8, seed=11)
         t0 = time.perf_counter()
-        for r, (d, o) in zip(reqs, bufs):
+        for i, (r, (d, o)) in enumerate(zip(reqs, bufs)):
             while time.perf_counter() - t0 < r["t"]:
                 pass
             kind = brr.BRR_REQ_SAMPLE if r["kind"] == "sample" else brr.BRR_REQ_SHUFFLE
-            srv.submit(kind, d, r["n"], 8, session=0, m=r["m"], out=o)
+            srv.submit(kind, d, r["n"], 8, session=i % clients, m=r["m"], out=o)
         srv.drain()
         st = srv.stats()
         srv.close()
-        out.append({"offered_req_per_s": rate, "requests": count,
+        out.append({"offered_req_per_s": rate, "requests": count, "clients": clients,
                     "p50_us": st["p50_us"], "p99_us": st["p99_us"], "mean_us": st["mean_us"],
                     "req_per_s": st["requests_per_s"], "elems_per_s": st["elements_per_s"],
                     "peak_inflight": st["peak_inflight"]})

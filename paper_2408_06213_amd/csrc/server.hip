@@ -62,6 +62,7 @@ struct brr_server {
     std::vector<hipStream_t> streams;
     uint64_t *d_counters = nullptr; // [kMaxSessions]
     uint64_t *d_slots = nullptr;    // [max_inflight] instance of each in-flight request
+    std::vector<hipEvent_t> slot_events; // [max_inflight] completion of each slot's request
     std::map<uint64_t, uint32_t> session_index;
     std::mutex mu;
     std::condition_variable cv;
@@ -114,7 +115,7 @@ brr_status launch(brr_server *sv, Req &q)
                            slot, s);
     }
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? BRR_ENOMEM : BRR_EHIP;
-    if (hipEventCreateWithFlags(&q.ev, hipEventDisableTiming) != hipSuccess) return BRR_EHIP;
+    q.ev = sv->slot_events[q.slot];
     if (hipEventRecord(q.ev, s) != hipSuccess) return BRR_EHIP;
     return BRR_OK;
 }
@@ -123,7 +124,6 @@ void finish(brr_server *sv, Req &q, uint64_t id)
 {
     q.done = true;
     q.t_done = clock_t_::now();
-    if (q.ev) (void)hipEventDestroy(q.ev);
     q.ev = nullptr;
     if (q.slot >= 0) sv->free_slots.push_back(q.slot);
     q.slot = -1;
@@ -179,12 +179,14 @@ void worker_loop(brr_server *sv)
         if (progress) sv->cv.notify_all();
         if (sv->stop && sv->pending.empty() && sv->inflight.empty()) break;
         if (!progress) {
-            // nothing to do: wait for a submission, or poll the device shortly
-            if (sv->inflight.empty())
+            // nothing to do: wait for a submission, or keep polling the device
+            // (a timed sleep would add its own wake-up latency to every
+            // request)
+            if (sv->inflight.empty()) {
                 sv->cv.wait_for(lock, std::chrono::milliseconds(5));
-            else {
+            } else {
                 lock.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                std::this_thread::yield();
                 lock.lock();
             }
         }
@@ -237,6 +239,11 @@ brr_status brr_server_create(brr_server **out, const brr_server_config *cfg)
         hipStream_t s;
         ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
         if (ok) sv->streams.push_back(s);
+    }
+    for (uint32_t i = 0; ok && i < cfg->max_inflight; ++i) {
+        hipEvent_t ev;
+        ok = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        if (ok) sv->slot_events.push_back(ev);
     }
     if (!ok) {
         brr_server_destroy(sv);
@@ -376,6 +383,7 @@ void brr_server_destroy(brr_server *sv)
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
     }
+    for (hipEvent_t ev : sv->slot_events) (void)hipEventDestroy(ev);
     if (sv->d_counters) (void)hipFree(sv->d_counters);
     if (sv->d_slots) (void)hipFree(sv->d_slots);
     delete sv;
