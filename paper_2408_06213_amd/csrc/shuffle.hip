@@ -697,9 +697,11 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             if (x != e) root[e] = x;
         }
         __syncthreads();
-        // sources (LDS only), then all gathers back to back
-        uint32_t src[P], ext_q[P], ext_src[P];
+        // sources from LDS; each gather is issued as soon as its source is
+        // known, so it is in flight while the next position is worked out
+        uint32_t ext_q[P];
         uint32_t ext_mask = 0;
+        Elem val[P], ext_val[P];
 #pragma unroll
         for (int r = 0; r < P; ++r) {
             const uint32_t e = tid + r * kWgThreads;
@@ -707,29 +709,25 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             const uint32_t p = i_end + e, q = qof[e];
             const uint32_t re = root[e];
             const uint32_t own = i_end + (re == kNone32 ? e : re);
+            uint32_t src;
             if (q == p) {
-                src[r] = own;
+                src = own;
             } else {
                 bool below;
                 const uint32_t succ = peel_query(ps, q, p, below);
                 if (succ == kNone32) {
-                    src[r] = q;
+                    src = q;
                 } else {
                     const uint32_t rs = root[succ - i_end];
-                    src[r] = i_end + (rs == kNone32 ? succ - i_end : rs);
+                    src = i_end + (rs == kNone32 ? succ - i_end : rs);
                 }
                 if (q < i_end && !below) {
                     ext_mask |= 1u << r;
                     ext_q[r] = q;
-                    ext_src[r] = own;
+                    ext_val[r] = z[own];
                 }
             }
-        }
-        Elem val[P], ext_val[P];
-#pragma unroll
-        for (int r = 0; r < P; ++r) {
-            if (tid + r * kWgThreads < H) val[r] = z[src[r]];
-            if (ext_mask & (1u << r)) ext_val[r] = z[ext_src[r]];
+            val[r] = z[src];
         }
         // Every read of z precedes every write. Only this workgroup touches
         // its array, with plain loads and stores; its wavefronts share the
@@ -742,7 +740,10 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             z[i_end + e] = val[r];
             if (ext_mask & (1u << r)) z[ext_q[r]] = ext_val[r];
         }
-        __syncthreads(); // the next peel reads what this one wrote
+        // The next peel reads z only after several barriers (the first one
+        // follows its bounds and table clearing), which order these writes
+        // before its gathers; it writes LDS only after this peel's last LDS
+        // read, which precedes the barrier above.
         s_begin = s_end;
         i_begin = i_end;
     }
