@@ -291,10 +291,15 @@ brr_status classify(brr_plan *p)
             pair_base.push_back(pair_base.back() + (st.S + 1) / 2);
         }
     }
-    // lanes of one block run in step when their sizes are close
-    std::stable_sort(lane.begin(), lane.end(), [&](uint32_t a, uint32_t b) {
+    // largest first: lanes of one block run in step when their sizes are
+    // close, and for the block tiers the long blocks start first, so the
+    // short ones fill the tail of the launch
+    auto larger = [&](uint32_t a, uint32_t b) {
         return p->h_off[a + 1] - p->h_off[a] > p->h_off[b + 1] - p->h_off[b];
-    });
+    };
+    std::stable_sort(lane.begin(), lane.end(), larger);
+    for (int c = 0; c < kLdsClasses; ++c) std::stable_sort(cls[c].begin(), cls[c].end(), larger);
+    std::stable_sort(peel.begin(), peel.end(), larger);
     p->n_lane = (uint32_t)lane.size();
     p->n_peel = (uint32_t)peel.size();
     p->n_big = (uint32_t)gitems.size();

@@ -563,7 +563,7 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const u
 }
 
 constexpr uint32_t kPeel = 6144;       // positions per peel
-constexpr uint32_t kPeelHashBits = 12; // 4096 chains, load factor <= 1.5
+constexpr uint32_t kPeelHashBits = 13; // 8192 chains of u16 heads, load factor <= 0.75
 constexpr uint32_t kPeelTierMax = 1u << 20;
 
 __device__ __forceinline__ uint32_t peel_hash(uint32_t q)
@@ -574,7 +574,7 @@ __device__ __forceinline__ uint32_t peel_hash(uint32_t q)
 struct PeelState {
     const uint32_t *qof;   // target of the step at local position e (= p - i_end)
     const uint16_t *nxt;   // next entry of the same hash chain
-    const uint32_t *table; // chain heads (local positions)
+    const uint16_t *table; // chain heads (local positions)
     uint32_t i_end, H;
 };
 
@@ -587,14 +587,13 @@ __device__ __forceinline__ uint32_t peel_query(const PeelState &ps, uint32_t q, 
     uint32_t above = kNone32;
     below = false;
     uint32_t e = ps.table[peel_hash(q)];
-    for (uint32_t guard = 0; e != kNone32 && guard < ps.H; ++guard) {
+    for (uint32_t guard = 0; e != kNone16 && guard < ps.H; ++guard) {
         if (ps.qof[e] == q) {
             const uint32_t pg = ps.i_end + e;
             if (pg > lo && pg < above) above = pg;
             below |= pg < lo;
         }
-        const uint16_t nx = ps.nxt[e];
-        e = (nx == kNone16) ? kNone32 : nx;
+        e = ps.nxt[e];
     }
     return above;
 }
@@ -620,7 +619,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
     __shared__ uint32_t qof[kPeel];
     __shared__ uint16_t nxt[kPeel];
     __shared__ uint32_t root[kPeel]; // head-chain parent, then chain end (local)
-    __shared__ uint32_t table[1u << kPeelHashBits];
+    __shared__ uint16_t table[1u << kPeelHashBits]; // two heads per 32-bit word
     __shared__ SegTable st;
     __shared__ uint32_t next_s, next_i;
     const uint32_t tid = threadIdx.x;
@@ -649,7 +648,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             next_s = s;
             next_i = i;
         }
-        for (uint32_t x = tid; x < (1u << kPeelHashBits); x += kWgThreads) table[x] = kNone32;
+        for (uint32_t x = tid; x < (1u << kPeelHashBits); x += kWgThreads) table[x] = kNone16;
         for (uint32_t x = tid; x < PEEL; x += kWgThreads) root[x] = kNone32;
         __syncthreads();
         const uint32_t s_end = next_s, i_end = next_i, H = i_begin - i_end;
@@ -674,8 +673,16 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
         for (uint32_t e = tid; e < H; e += kWgThreads) {
             const uint32_t q = qof[e];
             if (q != i_end + e) {
-                const uint32_t old = atomicExch(&table[peel_hash(q)], e);
-                nxt[e] = (old == kNone32) ? kNone16 : (uint16_t)old;
+                // push e on its chain: a compare-and-swap on the word holding
+                // the chain's 16-bit head (each round lets one contender in)
+                const uint32_t bkt = peel_hash(q), sh = (bkt & 1u) * 16u;
+                uint32_t *word = reinterpret_cast<uint32_t *>(table) + (bkt >> 1);
+                uint32_t cur = *word, seen;
+                do {
+                    seen = cur;
+                    cur = atomicCAS(word, seen, (seen & ~(0xFFFFu << sh)) | (e << sh));
+                } while (cur != seen);
+                nxt[e] = (uint16_t)(seen >> sh);
                 if (q >= i_end) atomicMin(&root[q - i_end], e);
             }
         }
