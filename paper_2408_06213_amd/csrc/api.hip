@@ -552,7 +552,7 @@ brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_
     st = device_ready(nullptr);
     if (st != BRR_OK) return st;
     return hip_status(launch_one(d_data, (uint32_t)n, (uint32_t)(n - 1), 0, elem_bytes, nullptr,
-                                 to_dev(sc), seed, inst, nullptr, static_cast<hipStream_t>(stream)));
+                                 to_dev(sc), seed, inst, DevClaim{}, static_cast<hipStream_t>(stream)));
 }
 
 brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_bytes, void *d_out,
@@ -574,7 +574,7 @@ brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_
         return hip_status(hipMemcpyAsync(d_out, d_data, elem_bytes, hipMemcpyDeviceToDevice, s));
     void *data = const_cast<void *>(d_data); // only read when an output buffer is given
     return hip_status(launch_one(data, (uint32_t)n, (uint32_t)steps, (uint32_t)(n - m), elem_bytes,
-                                 d_out, to_dev(sc), seed, inst, nullptr, s));
+                                 d_out, to_dev(sc), seed, inst, DevClaim{}, s));
 }
 
 brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t count,

@@ -109,14 +109,23 @@ uint32_t wave_tier_max_n();
 // Raises the dynamic-LDS limit of the LDS-tier kernels (once per device).
 hipError_t prepare_shuffle_kernels();
 
+// A device-side instance claim. With counter set, the first kernel of a
+// launch takes c = *counter, stores c + 1 back and base + c into *slot (one
+// thread), and the launch's instance is inst + base + c. Claims on one
+// stream therefore follow stream order. counter == nullptr: no claim.
+struct DevClaim {
+    uint64_t *counter;
+    uint64_t *slot;
+    uint64_t base;
+};
+
 // One shuffle (steps = n - 1, out = nullptr, in place) or one sample
 // (out != nullptr: out[n-1-p] = final z[p] for out_lo <= p < n, the input
 // untouched) by one workgroup with its index arrays in LDS;
 // n <= lds_tier_max_n(), 1 <= steps < n, out_lo <= n - steps.
-// The stream instance is inst, plus *inst_dev when inst_dev is not null.
 hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
                              void *out, const DevSched &sc, uint64_t seed, uint64_t inst,
-                             const uint64_t *inst_dev, hipStream_t stream);
+                             const DevClaim &claim, hipStream_t stream);
 
 // One item of the device-wide tier: the array at element offset data_off of
 // the shared data pointer, n elements, the first `steps` Fisher-Yates steps
@@ -137,7 +146,7 @@ struct GTierArgs {
     uint32_t eb;
     uint64_t seed;
     uint64_t inst_base; // item q uses instance inst_base + items[q].inst
-    const uint64_t *inst_dev; // device; if set, *inst_dev is added to inst_base
+    DevClaim claim;     // if set, the claimed instance is added to inst_base
     uint32_t nitems;
     uint64_t npos, npairs;
     const GItem *items;      // device
@@ -158,7 +167,7 @@ constexpr uint64_t kMaxGtierPositions = 0xFFFFFFFFull;
 uint64_t one_scratch_bytes(uint64_t n, uint32_t eb);
 hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
                       void *out, const DevSched &ds, uint64_t seed, uint64_t inst,
-                      const uint64_t *inst_dev, hipStream_t s);
+                      const DevClaim &claim, hipStream_t s);
 uint32_t gtier_tile_shift(); // log2 of the indices per tile-table entry
 hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream);
 

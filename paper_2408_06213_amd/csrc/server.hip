@@ -98,21 +98,35 @@ brr_status launch(brr_server *sv, Req &q)
     q.stream = sidx % (uint32_t)sv->streams.size();
     hipStream_t s = sv->streams[q.stream];
     uint64_t *slot = sv->d_slots + q.slot;
-    k_claim<<<1, 1, 0, s>>>(sv->d_counters + sidx, slot, r.session);
-    if (hipGetLastError() != hipSuccess) return BRR_EHIP;
+    // the request's first kernel claims its instance; a request that runs no
+    // kernel still takes one, so every session's counter advances once per
+    // request in submission order
+    const DevClaim claim{sv->d_counters + sidx, slot, r.session << kSessionShift};
     const uint64_t n = r.n;
     hipError_t e = hipSuccess;
+    bool claimed = false;
     if (r.kind == BRR_REQ_SHUFFLE) {
-        if (n > 1)
+        if (n > 1) {
             e = launch_one(r.d_data, (uint32_t)n, (uint32_t)(n - 1), 0, r.elem_bytes, nullptr,
-                           sv->ds, sv->cfg.seed, 0, slot, s);
+                           sv->ds, sv->cfg.seed, 0, claim, s);
+            claimed = true;
+        }
     } else {
-        if (n == 1)
+        if (n == 1) {
             e = hipMemcpyAsync(r.d_out, r.d_data, r.elem_bytes, hipMemcpyDeviceToDevice, s);
-        else if (r.m > 0)
+        } else if (r.m > 0) {
             e = launch_one(r.d_data, (uint32_t)n, (uint32_t)std::min<uint64_t>(r.m, n - 1),
                            (uint32_t)(n - r.m), r.elem_bytes, r.d_out, sv->ds, sv->cfg.seed, 0,
-                           slot, s);
+                           claim, s);
+            claimed = true;
+        }
+    }
+    // a device-wide request whose scratch could not be allocated failed before
+    // its first kernel: its instance is still taken
+    if (!claimed || e == hipErrorOutOfMemory) {
+        k_claim<<<1, 1, 0, s>>>(sv->d_counters + sidx, slot, r.session);
+        const hipError_t f = hipGetLastError();
+        if (e == hipSuccess) e = f;
     }
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? BRR_ENOMEM : BRR_EHIP;
     q.ev = sv->slot_events[q.slot];

@@ -226,20 +226,31 @@ __device__ void lds_tier_run(Elem *z, uint32_t n, uint32_t steps, uint32_t out_l
     }
 }
 
-// inst_dev != nullptr: the instance is read from device memory (a counter
-// claimed on the same stream), added to the key's instance.
+// Takes one instance from a device counter on the stream (see DevClaim);
+// returns the claimed value to the calling thread.
+__device__ __forceinline__ uint64_t take_claim(const DevClaim &c)
+{
+    const uint64_t v = *c.counter;
+    *c.counter = v + 1;
+    const uint64_t inst = c.base + v;
+    *c.slot = inst;
+    return inst;
+}
+
 template <typename Elem, int BLOCK, int P>
 __global__ __launch_bounds__(BLOCK) void k_lds_single(Elem *z, uint32_t n, uint32_t steps,
                                                       uint32_t out_lo, Elem *out, SegTable st,
                                                       uint64_t seed, uint64_t inst,
-                                                      const uint64_t *inst_dev)
+                                                      DevClaim claim)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ Seg seg[kMaxSegs];
     __shared__ uint32_t wsum[BLOCK / 64];
+    __shared__ uint64_t claimed;
     if (threadIdx.x < st.nseg) seg[threadIdx.x] = st.seg[threadIdx.x];
+    if (threadIdx.x == 0) claimed = claim.counter ? take_claim(claim) : 0;
     __syncthreads();
-    const StreamKey key = make_key(seed, inst + (inst_dev ? *inst_dev : 0));
+    const StreamKey key = make_key(seed, inst + claimed);
     lds_tier_run<Elem, BLOCK, P>(z, n, steps, out_lo, out, seg, st.nseg, st.S, key, smem, wsum);
 }
 
@@ -852,7 +863,7 @@ struct GProblem {
     uint32_t nitems;
     uint64_t npos, npairs;
     uint64_t inst_base;       // added to every item's instance
-    const uint64_t *inst_dev; // if set, *inst_dev is added as well
+    DevClaim claim;           // if set, the claimed instance is added as well
     GItem one;
     SegTable one_seg;
 };
@@ -883,8 +894,9 @@ __device__ __forceinline__ uint32_t item_of_pos(const GProblem &P, uint64_t x)
     return P.items ? find_item(P.pos_tile, P.pos_base, P.nitems, x) : 0u;
 }
 
-__global__ __launch_bounds__(256) void k_gp_init(GArrays g, uint64_t npos)
+__global__ __launch_bounds__(256) void k_gp_init(GProblem P, GArrays g, uint64_t npos)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && P.claim.counter) (void)take_claim(P.claim);
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npos;
          x += (uint64_t)gridDim.x * blockDim.x) {
         g.key[0][x] = kSortNone;
@@ -901,7 +913,7 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
         const GItem &it = item_at(P, i);
         const SegTable &st = segs_at(P, i);
         const uint32_t m = (uint32_t)(w - (P.items ? P.pair_base[i] : 0));
-        const uint64_t ib = P.inst_base + (P.inst_dev ? *P.inst_dev : 0);
+        const uint64_t ib = P.inst_base + (P.claim.counter ? *P.claim.slot : 0);
         const StreamKey key = make_key(seed, ib + it.inst);
         uint64_t wd[2];
         word_pair(m, key, wd[0], wd[1]);
@@ -925,8 +937,9 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
     }
 }
 
-__global__ __launch_bounds__(256) void k_gc_init(uint32_t *cnt, uint64_t len)
+__global__ __launch_bounds__(256) void k_gc_init(GProblem P, uint32_t *cnt, uint64_t len)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && P.claim.counter) (void)take_claim(P.claim);
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < len;
          x += (uint64_t)gridDim.x * blockDim.x)
         cnt[x] = 0;
@@ -942,7 +955,7 @@ __global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t
         const GItem &it = item_at(P, i);
         const SegTable &st = segs_at(P, i);
         const uint32_t m = (uint32_t)(w - (P.items ? P.pair_base[i] : 0));
-        const uint64_t ib = P.inst_base + (P.inst_dev ? *P.inst_dev : 0);
+        const uint64_t ib = P.inst_base + (P.claim.counter ? *P.claim.slot : 0);
         const StreamKey key = make_key(seed, ib + it.inst);
         uint64_t wd[2];
         word_pair(m, key, wd[0], wd[1]);
@@ -1281,7 +1294,7 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
 {
     const GArrays g = garrays(scratch, P.npos);
     if (P.npos <= kCountMaxPositions) {
-        k_gc_init<<<grid_for(P.npos + 1, 256), 256, 0, stream>>>(g.cnt, P.npos + 1);
+        k_gc_init<<<grid_for(P.npos + 1, 256), 256, 0, stream>>>(P, g.cnt, P.npos + 1);
         k_gc_dice<<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
         scan_exclusive(g.cnt, g.tiles, P.npos + 1, stream);
         k_gc_scatter<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
@@ -1292,7 +1305,7 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
                                                                    static_cast<Elem *>(data));
         return hipGetLastError();
     }
-    k_gp_init<<<grid_for(P.npos, 256), 256, 0, stream>>>(g, P.npos);
+    k_gp_init<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, P.npos);
     k_gp_dice<<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
     // targets are < npos, so bit_length(npos) bits order them all, and the
     // "none" key (all ones) after them
@@ -1315,7 +1328,7 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
 
 template <typename Elem>
 hipError_t lds_single_t(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, void *out,
-                        const DevSched &sc, uint64_t seed, uint64_t inst, const uint64_t *inst_dev,
+                        const DevSched &sc, uint64_t seed, uint64_t inst, const DevClaim &claim,
                         hipStream_t stream)
 {
     SegTable st;
@@ -1323,7 +1336,7 @@ hipError_t lds_single_t(void *data, uint32_t n, uint32_t steps, uint32_t out_lo,
     const uint32_t bytes = lds_bytes(n);
     k_lds_single<Elem, kWgThreads, kWgP><<<1, kWgThreads, bytes, stream>>>(
         static_cast<Elem *>(data), n, steps, out_lo, static_cast<Elem *>(out), st, seed, inst,
-        inst_dev);
+        claim);
     return hipGetLastError();
 }
 
@@ -1432,13 +1445,13 @@ uint32_t gtier_tile_shift() { return kTileShift; }
 
 hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
                              void *out, const DevSched &sc, uint64_t seed, uint64_t inst,
-                             const uint64_t *inst_dev, hipStream_t stream)
+                             const DevClaim &claim, hipStream_t stream)
 {
     if (n > lds_tier_max_n() || steps == 0 || steps >= n || out_lo > n - steps)
         return hipErrorInvalidValue;
-    return eb == 4 ? lds_single_t<uint32_t>(data, n, steps, out_lo, out, sc, seed, inst, inst_dev,
+    return eb == 4 ? lds_single_t<uint32_t>(data, n, steps, out_lo, out, sc, seed, inst, claim,
                                             stream)
-                   : lds_single_t<uint64_t>(data, n, steps, out_lo, out, sc, seed, inst, inst_dev,
+                   : lds_single_t<uint64_t>(data, n, steps, out_lo, out, sc, seed, inst, claim,
                                             stream);
 }
 
@@ -1449,10 +1462,10 @@ uint64_t one_scratch_bytes(uint64_t n, uint32_t eb)
 
 hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
                       void *out, const DevSched &ds, uint64_t seed, uint64_t inst,
-                      const uint64_t *inst_dev, hipStream_t s)
+                      const DevClaim &claim, hipStream_t s)
 {
     if (n <= lds_tier_max_n())
-        return launch_lds_single(data, n, steps, out_lo, eb, out, ds, seed, inst, inst_dev, s);
+        return launch_lds_single(data, n, steps, out_lo, eb, out, ds, seed, inst, claim, s);
     SegTable st;
     build_segments(n, steps, ds, st);
     const GItem it{0, 0, inst, n, steps, out_lo, 0, out};
@@ -1461,7 +1474,7 @@ hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, u
     a.data = data;
     a.eb = eb;
     a.seed = seed;
-    a.inst_dev = inst_dev;
+    a.claim = claim;
     a.nitems = 1;
     a.npos = n;
     a.npairs = (st.S + 1) / 2;
@@ -1486,7 +1499,7 @@ hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream)
     P.npos = a.npos;
     P.npairs = a.npairs;
     P.inst_base = a.inst_base;
-    P.inst_dev = a.inst_dev;
+    P.claim = a.claim;
     if (a.nitems == 1 && a.one_item) {
         P.one = *a.one_item;
         P.one_seg = *a.one_seg;

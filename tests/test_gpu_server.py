@@ -21,6 +21,13 @@ def make_requests(seed, count):
         dtype = np.uint64 if rng.random() < 0.7 else np.uint32
         data = rng.integers(0, 2**31, size=n).astype(dtype)
         reqs.append(dict(kind=kind, n=n, m=m, data=data, session=int(rng.integers(0, 5))))
+    # requests that run no shuffle kernel still take their instance, and one
+    # large enough for the sorting path of the device-wide tier
+    big = (1 << 21) + 7
+    reqs[3] = dict(kind="shuffle", n=1, m=1, data=np.array([5], np.uint64), session=reqs[3]["session"])
+    reqs[7] = dict(kind="sample", n=1, m=1, data=np.array([9], np.uint32), session=reqs[7]["session"])
+    reqs[11] = dict(kind="shuffle", n=big, m=big, data=rng.integers(0, 2**31, size=big).astype(np.uint32),
+                    session=reqs[11]["session"])
     return reqs
 
 
@@ -55,7 +62,9 @@ def expected(orc, reqs, order, seed):
         j = seen.get(r["session"], 0)
         seen[r["session"]] = j + 1
         inst = (r["session"] << SESSION_SHIFT) + j
-        if r["kind"] == "sample":
+        if r["kind"] == "sample" and r["n"] == 1:
+            err, out = 0, r["data"].copy()
+        elif r["kind"] == "sample":
             err, out = orc.sample(r["data"], r["m"], s6, seed, inst)
         else:
             out = r["data"].copy()
