@@ -1334,9 +1334,23 @@ hipError_t lds_single_t(void *data, uint32_t n, uint32_t steps, uint32_t out_lo,
     SegTable st;
     build_segments(n, steps, sc, st);
     const uint32_t bytes = lds_bytes(n);
-    k_lds_single<Elem, kWgThreads, kWgP><<<1, kWgThreads, bytes, stream>>>(
-        static_cast<Elem *>(data), n, steps, out_lo, static_cast<Elem *>(out), st, seed, inst,
-        claim);
+    Elem *z = static_cast<Elem *>(data), *o = static_cast<Elem *>(out);
+    // the smallest block of the size classes that holds the array
+    if (n <= lds_class_max_n(0))
+        k_lds_single<Elem, 64, kWaveP><<<1, 64, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
+                                                                 inst, claim);
+    else if (n <= lds_class_max_n(1))
+        k_lds_single<Elem, 256, 8><<<1, 256, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
+                                                              inst, claim);
+    else if (n <= lds_class_max_n(2))
+        k_lds_single<Elem, 256, 16><<<1, 256, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
+                                                               inst, claim);
+    else if (n <= lds_class_max_n(3))
+        k_lds_single<Elem, 512, 16><<<1, 512, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
+                                                               inst, claim);
+    else
+        k_lds_single<Elem, kWgThreads, kWgP><<<1, kWgThreads, bytes, stream>>>(
+            z, n, steps, out_lo, o, st, seed, inst, claim);
     return hipGetLastError();
 }
 
@@ -1409,6 +1423,8 @@ hipError_t prepare_shuffle_kernels()
     const int wg = (int)lds_bytes(kWgThreads * kWgP);
     const void *fns[] = {(const void *)k_lds_single<uint32_t, kWgThreads, kWgP>,
                          (const void *)k_lds_single<uint64_t, kWgThreads, kWgP>,
+                         (const void *)k_lds_single<uint32_t, 512, 16>,
+                         (const void *)k_lds_single<uint64_t, 512, 16>,
                          (const void *)k_lds_batched<uint32_t, 64, kWaveP>,
                          (const void *)k_lds_batched<uint64_t, 64, kWaveP>,
                          (const void *)k_lds_batched<uint32_t, 256, 8>,
@@ -1421,6 +1437,8 @@ hipError_t prepare_shuffle_kernels()
                          (const void *)k_lds_batched<uint64_t, kWgThreads, kWgP>};
     const int bytes[] = {wg,
                          wg,
+                         (int)lds_bytes(lds_class_max_n(3)),
+                         (int)lds_bytes(lds_class_max_n(3)),
                          (int)lds_bytes(lds_class_max_n(0)),
                          (int)lds_bytes(lds_class_max_n(0)),
                          (int)lds_bytes(lds_class_max_n(1)),
