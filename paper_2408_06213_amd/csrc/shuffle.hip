@@ -798,6 +798,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
 constexpr uint32_t kSortThreads = 256;
 constexpr uint32_t kSortItems = 8;
 constexpr uint32_t kSortTile = kSortThreads * kSortItems; // pairs per sort block
+static_assert(kSortThreads % 64 == 0 && kSortTile < 65536, "16-bit split counters");
 constexpr uint32_t kSortNone = 0xFFFFFFFFu;               // sorts after every target
 
 constexpr uint64_t kCountMaxPositions = 1ull << 21;
@@ -1048,10 +1049,11 @@ __global__ __launch_bounds__(256) void k_gc_links(GProblem P, GArrays g)
     }
 }
 
-// Exclusive scan of one u64 per thread over a block of 256 (4 wavefronts),
-// in thread order; *total receives the block's sum. Ends with a barrier.
+// Exclusive scan of one u64 per thread over a block of kSortThreads, in
+// thread order; *total receives the block's sum. Ends with a barrier.
 __device__ __forceinline__ uint64_t sort_block_scan(uint64_t v, uint64_t *wsum, uint64_t &total)
 {
+    constexpr uint32_t NW = kSortThreads / 64;
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint64_t incl = v;
 #pragma unroll
@@ -1061,9 +1063,13 @@ __device__ __forceinline__ uint64_t sort_block_scan(uint64_t v, uint64_t *wsum, 
     }
     if (lane == 63) wsum[wid] = incl;
     __syncthreads();
-    uint64_t before = 0;
-    for (uint32_t w = 0; w < wid; ++w) before += wsum[w];
-    total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    uint64_t before = 0, all = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < NW; ++w) {
+        before += (w < wid) ? wsum[w] : 0;
+        all += wsum[w];
+    }
+    total = all;
     __syncthreads();
     return before + incl - v;
 }
@@ -1074,7 +1080,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *keys, 
                                                           uint32_t nblk)
 {
     __shared__ uint32_t cnt[256];
-    cnt[threadIdx.x] = 0;
+    for (uint32_t d = threadIdx.x; d < 256; d += kSortThreads) cnt[d] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
 #pragma unroll
@@ -1083,7 +1089,8 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *keys, 
         if (i < n) atomicAdd(&cnt[(keys[i] >> sh) & 255u], 1u);
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = cnt[threadIdx.x];
+    for (uint32_t d = threadIdx.x; d < 256; d += kSortThreads)
+        hist[(uint64_t)d * nblk + blockIdx.x] = cnt[d];
 }
 
 // Radix sort, pass on bits sh .. sh+7: the block sorts its tile by the digit
@@ -1108,7 +1115,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
         sk[i] = (i < valid) ? kin[base + i] : kSortNone;
         sv[i] = (i < valid) ? vin[base + i] : 0u;
     }
-    dst[tid] = hist[(uint64_t)tid * nblk + blockIdx.x];
+    for (uint32_t d = tid; d < 256; d += kSortThreads) dst[d] = hist[(uint64_t)d * nblk + blockIdx.x];
     __syncthreads();
     uint32_t k[kSortItems], v[kSortItems];
 #pragma unroll
