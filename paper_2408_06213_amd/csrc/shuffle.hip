@@ -895,14 +895,19 @@ __device__ __forceinline__ uint32_t item_of_pos(const GProblem &P, uint64_t x)
     return P.items ? find_item(P.pos_tile, P.pos_base, P.nitems, x) : 0u;
 }
 
+// Heads start empty; positions that take no step (below n - steps) get their
+// sort pair here, every other one from the dice.
 __global__ __launch_bounds__(256) void k_gp_init(GProblem P, GArrays g, uint64_t npos)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0 && P.claim.counter) (void)take_claim(P.claim);
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npos;
          x += (uint64_t)gridDim.x * blockDim.x) {
-        g.key[0][x] = kSortNone;
-        g.val[0][x] = (uint32_t)x;
         g.head[x] = kNone32;
+        const GItem &it = item_at(P, item_of_pos(P, x));
+        if (x - it.pos_base < it.n - it.steps) {
+            g.key[0][x] = kSortNone;
+            g.val[0][x] = (uint32_t)x;
+        }
     }
 }
 
@@ -919,6 +924,7 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
         uint64_t wd[2];
         word_pair(m, key, wd[0], wd[1]);
         uint32_t *jj = g.jj + it.pos_base, *sk = g.key[0] + it.pos_base;
+        uint32_t *sv = g.val[0] + it.pos_base;
         const uint32_t tb = (uint32_t)it.pos_base;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -932,7 +938,8 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
                 const uint32_t p = i0 - 1 - l;
                 const uint32_t a = mul_roll(i0 - l, r);
                 jj[p] = a;
-                if (a < p) sk[p] = tb + a;
+                sk[p] = (a < p) ? tb + a : kSortNone;
+                sv[p] = tb + p;
             }
         }
     }
