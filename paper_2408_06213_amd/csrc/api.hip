@@ -199,6 +199,7 @@ struct brr_plan {
     void *d_scratch = nullptr;
     // size classes run side by side: each non-empty class but the last on a
     // branch stream forked from and joined back to the caller's stream
+    bool fork_classes = true; // off for one-shot plans: streams cost more than they save
     hipStream_t branch[kTiers - 1] = {};
     hipEvent_t fork = nullptr, join[kTiers - 1] = {};
     // graph of the launch sequence, bound to the buffers of the last run
@@ -337,11 +338,14 @@ brr_status classify(brr_plan *p)
         if (hipMalloc(&p->d_scratch, gtier_scratch_bytes(p->g_npos, p->eb)) != hipSuccess)
             return BRR_ENOMEM;
     }
-    if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess) return BRR_EHIP;
-    for (int t = 0; t < kTiers - 1; ++t) {
-        if (hipStreamCreateWithFlags(&p->branch[t], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&p->join[t], hipEventDisableTiming) != hipSuccess)
+    if (p->fork_classes) {
+        if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess)
             return BRR_EHIP;
+        for (int t = 0; t < kTiers - 1; ++t) {
+            if (hipStreamCreateWithFlags(&p->branch[t], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&p->join[t], hipEventDisableTiming) != hipSuccess)
+                return BRR_EHIP;
+        }
     }
     p->classified = true;
     return BRR_OK;
@@ -400,6 +404,11 @@ hipError_t enqueue(brr_plan *p, void *data, const uint64_t *offsets, uint64_t se
         if (tier_used(p, t)) used[nu++] = t;
     if (nu == 0) return hipSuccess;
     hipError_t e = hipSuccess;
+    if (!p->fork_classes) {
+        for (int b = 0; b < nu; ++b)
+            if ((e = launch_tier(p, used[b], data, offsets, seed, inst, s)) != hipSuccess) return e;
+        return hipSuccess;
+    }
     if (nu > 1) {
         if ((e = hipEventRecord(p->fork, s)) != hipSuccess) return e;
         for (int b = 0; b + 1 < nu; ++b) {
@@ -674,6 +683,7 @@ brr_status brr_shuffle_batched(void *d_data, const uint64_t *d_offsets, uint64_t
     brr_status st = brr_plan_create(&tmp, h.data(), count, elem_bytes, nullptr);
     if (st != BRR_OK) return st;
     tmp->map.use_graph = 0;
+    tmp->fork_classes = false;
     try {
         st = run_plan(tmp, d_data, d_offsets, seed, inst_base, s);
     } catch (...) {
