@@ -75,38 +75,39 @@ __device__ __forceinline__ uint64_t accept_word(uint32_t i, uint32_t k, uint64_t
     return r;
 }
 
-// Exclusive prefix sums of a[0..len) in place, by the whole block (contiguous
-// chunks per thread); returns the total. Ends with a barrier.
+// Exclusive prefix sums of a[0..len) in place, offset by base, by the whole
+// block; returns the total (without base). Each wavefront owns a contiguous
+// run of 64-entry rows and walks it row by row (lane l touches entry 64r + l,
+// so LDS accesses are conflict-free and global ones coalesced): a first pass
+// sums the run, the runs' sums are scanned across wavefronts, and a second
+// pass writes the prefix sums with a running carry. Ends with a barrier.
 template <int BLOCK>
 __device__ uint32_t block_scan_array(uint32_t *a, uint32_t len, uint32_t base, uint32_t *wsum)
 {
-    constexpr int NW = BLOCK / 64;
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const uint32_t chunk = (len + BLOCK - 1) / BLOCK;
-    const uint32_t b0 = min(len, tid * chunk), b1 = min(len, b0 + chunk);
-    uint32_t local = 0;
-    for (uint32_t x = b0; x < b1; ++x) local += a[x];
-    uint32_t incl = wave_inclusive_scan(local);
-    uint32_t total;
-    if (NW > 1) {
-        if (lane == 63) wsum[wid] = incl;
-        __syncthreads();
-        if (wid == 0) {
-            uint32_t w = (lane < (uint32_t)NW) ? wsum[lane] : 0u;
-            w = wave_inclusive_scan(w);
-            if (lane < (uint32_t)NW) wsum[lane] = w;
-        }
-        __syncthreads();
-        if (wid > 0) incl += wsum[wid - 1];
-        total = wsum[NW - 1];
-    } else {
-        total = __shfl(incl, 63, 64);
+    constexpr uint32_t NW = BLOCK / 64;
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t nrows = (len + 63) / 64, R = (nrows + NW - 1) / NW;
+    const uint32_t r0 = min(nrows, wid * R), r1 = min(nrows, r0 + R);
+    uint32_t sum = 0;
+    for (uint32_t r = r0; r < r1; ++r) {
+        const uint32_t x = r * 64 + lane;
+        sum += (x < len) ? a[x] : 0u;
     }
-    uint32_t run = base + incl - local;
-    for (uint32_t x = b0; x < b1; ++x) {
-        const uint32_t v = a[x];
-        a[x] = run;
-        run += v;
+    sum = __shfl(wave_inclusive_scan(sum), 63, 64);
+    if (lane == 0) wsum[wid] = sum;
+    __syncthreads();
+    uint32_t carry = base, total = 0;
+    for (uint32_t w = 0; w < NW; ++w) {
+        const uint32_t v = wsum[w];
+        carry += (w < wid) ? v : 0u;
+        total += v;
+    }
+    for (uint32_t r = r0; r < r1; ++r) {
+        const uint32_t x = r * 64 + lane;
+        const uint32_t v = (x < len) ? a[x] : 0u;
+        const uint32_t incl = wave_inclusive_scan(v);
+        if (x < len) a[x] = carry + incl - v;
+        carry += __shfl(incl, 63, 64);
     }
     __syncthreads();
     return total;
@@ -1081,6 +1082,8 @@ __device__ __forceinline__ uint64_t sort_block_scan(uint64_t v, uint64_t *wsum, 
     return before + incl - v;
 }
 
+__device__ __forceinline__ uint32_t sort_pad(uint32_t i) { return i + (i >> 3); }
+
 // Radix sort, pass on bits sh .. sh+7: digit counts of every block's tile.
 __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *keys, uint64_t n,
                                                           uint32_t sh, uint32_t *hist,
@@ -1110,7 +1113,9 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
                                                              uint32_t sh, const uint32_t *hist,
                                                              uint32_t nblk)
 {
-    __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+    // tile index i lives at i + i/8: a thread's eight consecutive items then
+    // fall in distinct banks
+    __shared__ uint32_t sk[kSortTile + kSortTile / 8], sv[kSortTile + kSortTile / 8];
     __shared__ uint32_t first[256], dst[256];
     __shared__ uint64_t wsum[kSortThreads / 64];
     const uint32_t tid = threadIdx.x;
@@ -1119,16 +1124,16 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
 #pragma unroll
     for (uint32_t u = 0; u < kSortItems; ++u) { // coalesced; padding sorts last
         const uint32_t i = u * kSortThreads + tid;
-        sk[i] = (i < valid) ? kin[base + i] : kSortNone;
-        sv[i] = (i < valid) ? vin[base + i] : 0u;
+        sk[sort_pad(i)] = (i < valid) ? kin[base + i] : kSortNone;
+        sv[sort_pad(i)] = (i < valid) ? vin[base + i] : 0u;
     }
     for (uint32_t d = tid; d < 256; d += kSortThreads) dst[d] = hist[(uint64_t)d * nblk + blockIdx.x];
     __syncthreads();
     uint32_t k[kSortItems], v[kSortItems];
 #pragma unroll
     for (uint32_t u = 0; u < kSortItems; ++u) { // thread tid: tile items 8*tid ..
-        k[u] = sk[tid * kSortItems + u];
-        v[u] = sv[tid * kSortItems + u];
+        k[u] = sk[sort_pad(tid * kSortItems + u)];
+        v[u] = sv[sort_pad(tid * kSortItems + u)];
     }
     __syncthreads();
     for (uint32_t r = 0; r < 4; ++r) {
@@ -1151,14 +1156,14 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
         for (uint32_t u = 0; u < kSortItems; ++u) {
             const uint32_t d = (k[u] >> b) & 3u;
             const uint32_t pos = start[d] + ((uint32_t)(excl >> (16 * d)) & 0xFFFFu) + before[u];
-            sk[pos] = k[u];
-            sv[pos] = v[u];
+            sk[sort_pad(pos)] = k[u];
+            sv[sort_pad(pos)] = v[u];
         }
         __syncthreads();
 #pragma unroll
         for (uint32_t u = 0; u < kSortItems; ++u) {
-            k[u] = sk[tid * kSortItems + u];
-            v[u] = sv[tid * kSortItems + u];
+            k[u] = sk[sort_pad(tid * kSortItems + u)];
+            v[u] = sv[sort_pad(tid * kSortItems + u)];
         }
         __syncthreads();
     }
@@ -1167,17 +1172,17 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
     for (uint32_t u = 0; u < kSortItems; ++u) {
         const uint32_t i = tid * kSortItems + u;
         const uint32_t d = (k[u] >> sh) & 255u;
-        if (i == 0 || ((sk[i - 1] >> sh) & 255u) != d) first[d] = i;
+        if (i == 0 || ((sk[sort_pad(i - 1)] >> sh) & 255u) != d) first[d] = i;
     }
     __syncthreads();
 #pragma unroll
     for (uint32_t u = 0; u < kSortItems; ++u) {
         const uint32_t i = u * kSortThreads + tid;
         if (i < valid) {
-            const uint32_t key = sk[i], d = (key >> sh) & 255u;
+            const uint32_t key = sk[sort_pad(i)], d = (key >> sh) & 255u;
             const uint32_t o = dst[d] + (i - first[d]);
             kout[o] = key;
-            vout[o] = sv[i];
+            vout[o] = sv[sort_pad(i)];
         }
     }
 }
