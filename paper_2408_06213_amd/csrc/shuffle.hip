@@ -275,7 +275,7 @@ __global__ __launch_bounds__(BLOCK) void k_lds_batched(Elem *data, const uint64_
 
 // ---------------------------------------------------------------------------
 // Lane tier: small shuffles, one lane each, the sequential batched
-// Fisher-Yates of Algorithm 4. A block of kLaneItems lanes owns kLaneItems
+// Fisher-Yates of Algorithm 4. A block of kLaneItems lanes owns up to 64
 // shuffles (the plan sorts them by size so lanes stay in step). Each lane
 // shuffles a byte permutation of its indices in LDS (n <= 256), so the
 // payload is not resident while the dice are rolled; the block then moves
@@ -283,7 +283,15 @@ __global__ __launch_bounds__(BLOCK) void k_lds_batched(Elem *data, const uint64_
 // into an LDS stage, then out[x] = stage[perm[x]] back to HBM.
 // ---------------------------------------------------------------------------
 
-constexpr int kLaneItems = 64;           // shuffles (lanes) per block
+constexpr int kLaneItems = 64;           // threads (one wavefront) per block
+// Shuffles per block (lanes 0 .. A-1 roll dice, all 64 move data): 64, or
+// 32 for the largest arrays, whose dice phase is long enough that two
+// blocks per SIMD overlap one's dice with the other's data movement.
+constexpr uint32_t kLaneHalfAbove = 192;
+__host__ __device__ inline uint32_t lane_arrays(uint32_t max_n)
+{
+    return max_n > kLaneHalfAbove ? 32u : 64u;
+}
 constexpr uint32_t kLaneMaxN = 256;      // byte permutations
 constexpr uint32_t kLaneStageBytes = 8192;
 constexpr int kLaneU = 8;                // loads in flight per lane
@@ -307,12 +315,13 @@ struct LaneLds {
 
 __host__ __device__ inline LaneLds lane_lds(uint32_t max_n, uint32_t eb)
 {
+    const uint32_t arrays = lane_arrays(max_n);
     LaneLds L;
     L.row_words = ((max_n + 3) / 4) | 1u; // odd: lanes' rows start in distinct banks
-    const uint32_t all = kLaneItems * max(max_n, 1u);
+    const uint32_t all = arrays * max(max_n, 1u);
     L.stage_cap = min(kLaneStageBytes / eb, all);
     L.perm_off = 8 * kLaneItems + 4 * (kLaneItems + 4);
-    L.stage_off = (L.perm_off + 4 * kLaneItems * L.row_words + 15) & ~15u;
+    L.stage_off = (L.perm_off + 4 * arrays * L.row_words + 15) & ~15u;
     L.bytes = L.stage_off + (L.stage_cap + 16 / eb) * eb;
     return L;
 }
@@ -393,8 +402,9 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const u
     Elem *stage = reinterpret_cast<Elem *>(smem + L.stage_off);
     const uint8_t *perm_bytes = reinterpret_cast<const uint8_t *>(permw);
     const uint32_t lane = threadIdx.x;
-    const uint32_t first = blockIdx.x * kLaneItems;
-    const uint32_t mine = min<uint32_t>(kLaneItems, nitems - first);
+    const uint32_t arrays = lane_arrays(max_n);
+    const uint32_t first = blockIdx.x * arrays;
+    const uint32_t mine = min<uint32_t>(arrays, nitems - first);
     uint32_t my_n = 0, my_q = 0;
     uint64_t my_off = 0;
     if (lane < mine) {
@@ -1403,7 +1413,8 @@ hipError_t batched_lane_t(void *data, const uint64_t *offsets, const uint32_t *i
                           uint64_t inst_base, hipStream_t stream)
 {
     if (nitems == 0) return hipSuccess;
-    const uint32_t blocks = (nitems + kLaneItems - 1) / kLaneItems;
+    const uint32_t arrays = lane_arrays(max_n);
+    const uint32_t blocks = (nitems + arrays - 1) / arrays;
     const LaneLds L = lane_lds(max_n, sizeof(Elem));
     k_lane_batched<Elem><<<blocks, kLaneItems, L.bytes, stream>>>(
         static_cast<Elem *>(data), offsets, items, nitems, max_n, sc, seed, inst_base);
