@@ -371,6 +371,18 @@ void brr_server_destroy(brr_server *server);
 /* ------------------------------------------------------------------------ */
 /* Status                                                                   */
 /* ------------------------------------------------------------------------ */
+/* Diagnostics                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Measures how many dice per second the device's vector ALUs can chain: one
+ * Theorem 1 step (two 32x32+64 -> 64-bit multiply-adds, Sec. 4) per die, in
+ * independent chains on every compute unit, `iters` steps per chain, with no
+ * memory traffic and no word generation. It is the VALU ceiling of a dice
+ * stream, for the roofline. Runs two launches on the null stream and
+ * synchronizes it; *dice_per_s receives the rate of the second. */
+brr_status brr_probe_chain_rate(uint32_t iters, double *dice_per_s);
+
+/* ------------------------------------------------------------------------ */
 
 /* Waits for `stream`, then returns and clears the first device-detected
  * error of the current device (BRR_OK if none). */

@@ -30,7 +30,7 @@ EXPORTS = (
     "brr_server_destroy", "brr_mlp_create", "brr_mlp_destroy", "brr_mlp_num_params",
     "brr_mlp_get_params", "brr_mlp_set_params", "brr_mlp_get_grads", "brr_mlp_forward",
     "brr_mlp_backward", "brr_mlp_adam_step", "brr_mlp_train", "brr_plan_features",
-    "brr_plan_autotune_learned",
+    "brr_plan_autotune_learned", "brr_probe_chain_rate",
 )
 BRR_PLAN_FEATURES = 16
 BRR_REQ_SHUFFLE, BRR_REQ_SAMPLE = 1, 2
@@ -149,6 +149,7 @@ def _load():
         "brr_plan_features": (st, [p, u64, u32, sched_p, u32, p]),
         "brr_plan_autotune_learned": (st, [p, p, u32, p, p, u64, u64, p,
                                            ctypes.POINTER(brr_tune_report)]),
+        "brr_probe_chain_rate": (st, [u32, ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -460,3 +461,10 @@ def brr_plan_autotune_learned(plan: Plan, model: MLP, top: int, data, d_offsets,
 
 def brr_sync_status(stream=None) -> int:
     return lib.brr_sync_status(_stream(stream))
+
+
+def brr_probe_chain_rate(iters: int = 4096) -> float:
+    """Dice per second the vector ALUs can chain (no memory, no word generation)."""
+    out = ctypes.c_double()
+    check(lib.brr_probe_chain_rate(iters, ctypes.byref(out)), "brr_probe_chain_rate")
+    return out.value

@@ -100,3 +100,4 @@ def test_host_argument_errors_need_no_device():
     assert brr.lib.brr_sample(0x20000, 10, 2, 8, odd8, None, 1, 0, None) == brr.BRR_EINVAL
     assert brr.lib.brr_shuffle_batched(odd4, 0x20000, 3, 4, None, 1, 0, None) == brr.BRR_EINVAL
     assert brr.lib.brr_shuffle_batched(0x20000, odd8, 3, 4, None, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_probe_chain_rate(0, None) == brr.BRR_EINVAL
