@@ -82,6 +82,10 @@ def lib():
         L.orc_dice.restype = ctypes.c_int
         L.orc_dice_group.argtypes = [p, ctypes.c_uint, u64, u64, u64, u64, p]
         L.orc_dice_group.restype = ctypes.c_int
+        L.orc_dice32.argtypes = [p, p, u64, ctypes.c_uint, u64, u64]
+        L.orc_dice32.restype = ctypes.c_int
+        L.orc_word32.argtypes = [u64, u64, u64]
+        L.orc_word32.restype = ctypes.c_uint32
         L.orc_dice_const.argtypes = [u32, p, u64, ctypes.c_uint, u64, u64]
         L.orc_dice_const.restype = ctypes.c_int
         L.orc_schedule_paper.argtypes = [ctypes.c_int, ctypes.POINTER(Schedule)]
@@ -142,6 +146,18 @@ def dice(bounds: np.ndarray, k: int, seed: int, inst: int = 0):
     out = np.zeros(bounds.size, dtype=np.uint32)
     err = lib().orc_dice(_ptr(bounds), _ptr(out), bounds.size, k, seed, inst)
     return err, out
+
+
+def dice32(bounds: np.ndarray, k: int, seed: int, inst: int = 0):
+    """The dice stream at word width 32 (32-bit halves of the 64-bit words)."""
+    bounds = np.ascontiguousarray(bounds, dtype=np.uint32)
+    out = np.zeros(bounds.size, dtype=np.uint32)
+    err = lib().orc_dice32(_ptr(bounds), _ptr(out), bounds.size, k, seed, inst)
+    return err, out
+
+
+def word32(seed: int, inst: int, c: int) -> int:
+    return int(lib().orc_word32(seed, inst, c))
 
 
 def dice_group(group_bounds, S: int, s: int, seed: int, inst: int = 0):

@@ -10,7 +10,8 @@
  * written with unsigned __int128 so that every full-width product is exact:
  *   - full-width multiply b (x) r = (x, y), 2^L x + y = b r      (Sec. 1.1)
  *   - Theorem 1 chain + Lemire's criterion on the leftover       (Sec. 4)
- *   - Algorithm 2 (known threshold) and Algorithm 3 (unknown)    (Sec. 5)
+ *   - Algorithm 2 (known threshold) and Algorithm 3 (unknown)    (Sec. 5),
+ *     at word width 64 and, for dice streams, 32
  *   - Algorithm 4 (batched partial shuffle with carried bound u) (Sec. 6)
  *   - the full-shuffle procedure with batch sizes growing as the
  *     array shrinks, and one last batch at the end              (Sec. 6, 6.1)
@@ -192,6 +193,63 @@ int orc_dice_group(const uint32_t *group_bounds, unsigned kk, uint64_t S, uint64
     if (err) return err;
     for (unsigned i = 0; i < kk; ++i) out[i] = (uint32_t)a[i];
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Dice streams at word width L = 32                                   */
+/* ------------------------------------------------------------------ */
+
+/* Word c of the 32-bit stream: the 32-bit half c mod 2 (low half first) of
+ * 64-bit word c/2, i.e. x[c mod 4] of Philox block c/4. */
+uint32_t orc_word32(uint64_t seed, uint64_t inst, uint64_t c)
+{
+    const uint64_t w = orc_word(seed, inst, c / 2);
+    return (c % 2 == 0) ? (uint32_t)w : (uint32_t)(w >> 32);
+}
+
+/* Algorithm 3 for one group at L = 32: the chain on 32-bit words, the
+ * product of the bounds at most 2^32, the threshold 2^32 mod product. Same
+ * attempt addressing as at L = 64 (attempt a of group s reads word a*S + s
+ * of the 32-bit stream). */
+static int roll_group32(const uint64_t *b, unsigned k, uint64_t seed, uint64_t inst, uint64_t S,
+                        uint64_t s, uint64_t *a)
+{
+    u128 prod;
+    const int err = bound_product(32, b, k, &prod);
+    if (err) return err;
+    uint64_t attempt = 0;
+    uint64_t r = orc_chain(32, b, k, orc_word32(seed, inst, s), a);
+    if ((u128)r < prod) {
+        const uint64_t t = (uint64_t)((((u128)1) << 32) % prod);
+        while (r < t) {
+            ++attempt;
+            r = orc_chain(32, b, k, orc_word32(seed, inst, attempt * S + s), a);
+        }
+    }
+    return ORC_OK;
+}
+
+/* The dice stream of orc_dice at L = 32 (groups of k bounds, the last group
+ * keeping count mod k). */
+int orc_dice32(const uint32_t *bounds, uint32_t *out, uint64_t count, unsigned k, uint64_t seed,
+               uint64_t inst)
+{
+    if (k == 0 || k > 32) return ORC_EINVAL;
+    const uint64_t S = ceil_div(count, k);
+    int status = ORC_OK;
+    for (uint64_t s = 0; s < S; ++s) {
+        const uint64_t first = s * k;
+        const unsigned kk = (unsigned)((count - first < k) ? count - first : k);
+        uint64_t b[32], a[32];
+        for (unsigned i = 0; i < kk; ++i) b[i] = bounds[first + i];
+        const int err = roll_group32(b, kk, seed, inst, S, s, a);
+        if (err) {
+            if (!status) status = err;
+            continue;
+        }
+        for (unsigned i = 0; i < kk; ++i) out[first + i] = (uint32_t)a[i];
+    }
+    return status;
 }
 
 /* Sampling with replacement from [0, bound): Algorithm 2, with the threshold

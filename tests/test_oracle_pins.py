@@ -234,6 +234,102 @@ def test_dice_uniform_chi2(orc):
 
 
 # ---------------------------------------------------------------------------
+# Dice streams at word width 32
+# ---------------------------------------------------------------------------
+
+TWO32 = 1 << 32
+
+
+def _stream_words32(orc, seed, inst, S, g):
+    a = 0
+    while True:
+        yield orc.word32(seed, inst, a * S + g)
+        a += 1
+
+
+def test_word32_is_halves_of_word64(orc):
+    """The 32-bit stream reads each 64-bit word low half first."""
+    for c in (0, 1, 2, 3, 10, 2**33 + 5):
+        w = orc.word(21, 4, c)
+        assert orc.word32(21, 4, 2 * c) == w & 0xFFFFFFFF
+        assert orc.word32(21, 4, 2 * c + 1) == w >> 32
+
+
+def test_chain_equals_one_shot_product_L32(orc):
+    """Theorem 1's one-shot form at L = 32: (prod b) (x) r0 = (a, r_k)."""
+    rng = np.random.default_rng(32)
+    for _ in range(400):
+        k = int(rng.integers(1, 9))
+        bounds = [int(x) for x in rng.integers(1, 1 << int(rng.integers(1, 17)), size=k)]
+        if math.prod(bounds) > TWO32:
+            continue
+        r0 = int(rng.integers(0, TWO32))
+        a, rk = orc.chain(32, bounds, r0)
+        value, low = divmod(math.prod(bounds) * r0, TWO32)
+        assert rk == low and ref.digits(value, bounds) == a
+
+
+def test_k1_dice32_is_lemire(orc):
+    """One die per 32-bit word is Lemire's method at L = 32 (Sec. 2)."""
+    rng = np.random.default_rng(6)
+    bounds = np.concatenate([rng.integers(1, 1 << 32, size=300, dtype=np.uint64),
+                             rng.integers(1, 7, size=100, dtype=np.uint64),
+                             np.array([1, 2, 2**31, 2**31 + 1, 2**32 - 1], dtype=np.uint64)]
+                            ).astype(np.uint32)
+    err, out = orc.dice32(bounds, 1, seed=99, inst=3)
+    assert err == 0
+    S = bounds.size
+    for g, b in enumerate(bounds):
+        x, _ = ref.lemire(32, int(b), _stream_words32(orc, 99, 3, S, g))
+        assert out[g] == x
+
+
+@pytest.mark.parametrize("k,bits", [(2, 16), (3, 10), (4, 8), (8, 4)])
+def test_dice32_groups_follow_theorem1(orc, k, bits):
+    """Every group of an L = 32 stream is the Theorem 1 chain on the first
+    accepted 32-bit word of its attempt sequence; at these widths products
+    come near 2^32, so rejections are frequent."""
+    rng = np.random.default_rng(100 + k)
+    count = 1000 + k - 1
+    bounds = rng.integers((1 << bits) // 2, 1 << bits, size=count, dtype=np.uint64).astype(np.uint32)
+    err, out = orc.dice32(bounds, k, seed=7, inst=11)
+    assert err == 0
+    S = -(-count // k)
+    rerolled = 0
+    for g in range(S):
+        b = [int(x) for x in bounds[g * k:(g + 1) * k]]
+        for att, r0 in enumerate(_stream_words32(orc, 7, 11, S, g)):
+            a, rk = ref.chain(32, b, r0)
+            if ref.accept(32, b, rk):
+                break
+        rerolled += att > 0
+        assert list(out[g * k:g * k + len(b)]) == a
+    assert np.all(out < bounds)
+    if k == 2:
+        assert rerolled > S // 20
+
+
+def test_dice32_edge_cases(orc):
+    # product exactly 2^32: threshold 0, the first word always accepted
+    err, out = orc.dice32(np.array([2**16, 2**16], dtype=np.uint32), 2, seed=3, inst=0)
+    assert err == 0 and list(out) == ref.chain(32, [2**16, 2**16], orc.word32(3, 0, 0))[0]
+    assert orc.dice32(np.array([2**16 + 1, 2**16], dtype=np.uint32), 2, 1, 0)[0] == 2
+    assert orc.dice32(np.array([5, 0], dtype=np.uint32), 2, 1, 0)[0] == 1
+    err, out = orc.dice32(np.zeros(0, dtype=np.uint32), 4, 1, 0)
+    assert err == 0 and out.size == 0
+
+
+def test_dice32_uniform_chi2(orc):
+    """Digits of a k = 4 stream of 6-sided dice at L = 32 are uniform."""
+    count = 200_000
+    err, out = orc.dice32(np.full(count, 6, dtype=np.uint32), 4, seed=17, inst=0)
+    assert err == 0
+    hist = np.bincount(out, minlength=6)
+    stat = float(((hist - count / 6) ** 2 / (count / 6)).sum())
+    assert stat < chi2.ppf(1 - 1e-3, 5)
+
+
+# ---------------------------------------------------------------------------
 # Shuffles (Algorithm 4 under the paper's schedules)
 # ---------------------------------------------------------------------------
 
