@@ -155,6 +155,17 @@ brr_status brr_dice(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, u
 brr_status brr_dice_const(uint32_t bound, uint32_t *d_out, uint64_t count, uint32_t k,
                           uint64_t seed, uint64_t inst, void *stream);
 
+/* The dice stream of brr_dice at word width L = 32 (Theorem 1 holds for any
+ * L, Sec. 4): each group is rolled from one 32-bit word with one 32x32 ->
+ * 64-bit multiply per die, and accepted when the leftover is at least
+ * 2^32 mod P (Algorithm 3). Word c of the 32-bit stream is the 32-bit half
+ * c mod 2, low half first, of 64-bit word c/2 (so four dice groups share one
+ * Philox block); attempt a of group s reads word a*S + s. The bound product
+ * of a group must not exceed 2^32 (else BRR_EOVERFLOW through
+ * brr_sync_status). Arguments, grouping and errors as brr_dice. */
+brr_status brr_dice32(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
+                      uint64_t seed, uint64_t inst, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Shuffles (Algorithm 1 driven by Algorithm 4 batches)                     */
 /* ------------------------------------------------------------------------ */

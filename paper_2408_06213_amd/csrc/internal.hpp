@@ -101,6 +101,9 @@ hipError_t launch_dice(const uint32_t *bounds, uint32_t *out, uint64_t count, ui
                        StreamKey key, uint32_t *status, hipStream_t stream);
 hipError_t launch_dice_const(uint32_t bound, uint32_t *out, uint64_t count, uint32_t k,
                              StreamKey key, uint64_t t_full, uint64_t t_last, hipStream_t stream);
+// The dice stream at word width 32 (dice32.hip).
+hipError_t launch_dice32(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
+                         StreamKey key, uint32_t *status, hipStream_t stream);
 
 // Largest n that one workgroup shuffles with its index arrays in LDS.
 uint32_t lds_tier_max_n();

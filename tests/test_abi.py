@@ -12,7 +12,7 @@ from conftest import ROOT, golden_rows
 def declared_symbols():
     text = open(os.path.join(ROOT, "include", "brr.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(brr_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(brr_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():

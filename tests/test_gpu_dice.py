@@ -121,3 +121,63 @@ def test_dice_full_size_sampled(gpu, orc, k):
         err, want = orc.dice_group(bounds[lo:hi], S, int(g), 7, 0)
         assert err == 0
         assert np.array_equal(got[lo:hi], want), (k, int(g))
+
+
+# ---------------------------------------------------------------------------
+# Word width 32 (brr_dice32)
+# ---------------------------------------------------------------------------
+
+# bound width per k so that a group's product stays <= 2^32
+BITS32 = {1: 32, 2: 16, 3: 10, 4: 8, 5: 6, 6: 5, 7: 4, 8: 4}
+
+
+def run_dice32(gpu, bounds_np, k, seed, inst, offset=0):
+    n = bounds_np.size
+    b = to_dev(np.concatenate([np.zeros(offset, np.uint32), bounds_np]))
+    out = to_dev(np.zeros(n + offset, np.uint32))
+    gpu.check(gpu.brr_dice32(b.data_ptr() + 4 * offset, out.data_ptr() + 4 * offset, n, k, seed,
+                             inst), "brr_dice32")
+    st = gpu.brr_sync_status()
+    return st, to_host(out)[offset:]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_dice32_parity_ragged_counts(gpu, orc, k):
+    """Bounds in the upper half of their width: products come near 2^32, so
+    a good share of groups reroll (several times for some)."""
+    rng = np.random.default_rng(300 + k)
+    hi = 1 << BITS32[k]
+    for count in (1, 3, 4 * k - 1, 4 * k + 1, 256 * k + 5, 1000 + 7, 65536 + 3, 300001):
+        say("dice32", k, count)
+        bounds = rng.integers(max(1, hi // 2), hi, size=count, dtype=np.uint64).astype(np.uint32)
+        st, got = run_dice32(gpu, bounds, k, seed=13, inst=5)
+        err, want = orc.dice32(bounds, k, 13, 5)
+        assert st == 0 and err == 0
+        assert np.array_equal(got, want), (k, count)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_dice32_unaligned_buffers(gpu, orc, k):
+    rng = np.random.default_rng(400 + k)
+    bounds = rng.integers(1, 1 << BITS32[k], size=5003, dtype=np.uint64).astype(np.uint32)
+    say("dice32 unaligned", k)
+    st, got = run_dice32(gpu, bounds, k, seed=5, inst=0, offset=1)
+    assert st == 0
+    assert np.array_equal(got, orc.dice32(bounds, k, 5, 0)[1])
+
+
+def test_dice32_edge_cases(gpu, orc):
+    # product exactly 2^32 (threshold 0)
+    b = np.tile(np.array([2**16, 2**16], np.uint32), 999)
+    st, got = run_dice32(gpu, b, 2, seed=3, inst=0)
+    assert st == 0 and np.array_equal(got, orc.dice32(b, 2, 3, 0)[1])
+    # the C2 stream's bounds at two dice per 32-bit word
+    b = workloads.dice_bounds(100003, seed=7)
+    st, got = run_dice32(gpu, b, 2, seed=7, inst=0)
+    assert st == 0 and np.array_equal(got, orc.dice32(b, 2, 7, 0)[1])
+    # errors reach the status word
+    st, _ = run_dice32(gpu, np.array([2**16 + 1, 2**16] * 5, np.uint32), 2, 1, 0)
+    assert st == gpu.BRR_EOVERFLOW
+    st, _ = run_dice32(gpu, np.array([5, 0, 3, 4], np.uint32), 2, 1, 0)
+    assert st == gpu.BRR_EINVAL
+    assert gpu.brr_sync_status() == 0  # reading the status clears it
