@@ -289,6 +289,18 @@ def main():
         return lambda: brr.check(brr.brr_dice(bounds, out, COUNT, k, 7, 0), "brr_dice")
 
     ms_k = {k: time_launches(step(k), args.steps, args.warmup) for k in (1, 2, 3, 4)}
+    # the same stream on 32-bit words (two dice per word fit: every bound
+    # is below 2^16); and a stream of bounds below 2^12, under the L = 32
+    # threshold n_2 = 20724 of Table 2, at both widths
+    ms_32 = {k: time_launches(lambda k=k: brr.check(brr.brr_dice32(bounds, out, COUNT, k, 7, 0),
+                                                    "brr_dice32"), args.steps, args.warmup)
+             for k in (1, 2)}
+    small = up(workloads.dice_bounds(COUNT, seed=8, high=1 << 12))
+    ms_small = {f"L{L}_k{k}": time_launches(
+        lambda L=L, k=k: brr.check((brr.brr_dice32 if L == 32 else brr.brr_dice)(
+            small, out, COUNT, k, 8, 0), "dice"), args.steps, args.warmup)
+        for L, k in ((64, 1), (64, 2), (32, 1), (32, 2))}
+    del small
     brr.check(brr.brr_sync_status(), "device status")
     k_head = min((2, 3, 4), key=lambda k: ms_k[k]) if args.k == "best" else int(args.k)
     ms = ms_k[k_head]
@@ -328,6 +340,11 @@ def main():
                              "hbm_frac": BYTES_PER_ROLL * COUNT / (v * 1e-3) / 1e9 / PEAK_HBM_GBS}
                     for k, v in ms_k.items()},
         "speedup_vs_k1": ms_k[1] / ms,
+        "l32_sweep": {str(k): {"ms": v, "rolls_per_s": COUNT / (v * 1e-3),
+                               "hbm_frac": BYTES_PER_ROLL * COUNT / (v * 1e-3) / 1e9 / PEAK_HBM_GBS}
+                      for k, v in ms_32.items()},
+        "bounds_below_2p12": {key: {"ms": v, "rolls_per_s": COUNT / (v * 1e-3)}
+                              for key, v in ms_small.items()},
         "ceilings": ceilings(brr, torch),
     }
     del out, bounds

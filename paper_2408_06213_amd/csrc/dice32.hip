@@ -23,39 +23,49 @@ namespace {
 constexpr uint64_t kMaxAttempts32 = 1024;
 constexpr int kGroups32 = 4; // groups per lane = lanes per quad
 
-// Value of lane (q + m) mod 4 of this lane's quad (q = lane mod 4).
-template <int M> __device__ __forceinline__ uint32_t from_quad_lane(uint32_t v)
+// Value of lane L ^ M within this lane's quad (M = 1: quad_perm [1,0,3,2];
+// M = 2: quad_perm [2,3,0,1]).
+template <int M> __device__ __forceinline__ uint32_t from_quad_xor(uint32_t v)
 {
-    constexpr int ctrl = (M == 1) ? 0x39 : (M == 2) ? 0x4E : 0x93; // quad_perm rotations
+    constexpr int ctrl = (M == 1) ? 0xB1 : 0x4E;
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xF, 0xF, false);
 }
 
-__device__ __forceinline__ uint32_t pick4(const uint32_t (&x)[4], uint32_t i)
-{
-    return i == 0 ? x[0] : i == 1 ? x[1] : i == 2 ? x[2] : x[3];
-}
-
 // First-attempt words of this lane's groups g0 + 64j + lane, j = 0..3.
+//
+// Lane q of a quad (q = lane mod 4) computes the Philox block of slot j = q,
+// i.e. the words of the quad's four groups g0 + 64q + (lane & ~3) + m; word
+// m belongs to quad lane m. As a matrix M[row = computing lane][column =
+// receiving lane] this is a 4x4 transpose, done as two exchange stages
+// (partner q ^ 1, then q ^ 2) with selects on the lane bits only: no
+// dynamically indexed register array, which the compiler would put in
+// scratch memory.
 __device__ __forceinline__ void tile_words32(uint64_t g0, uint32_t lane, const StreamKey &key,
                                              uint32_t (&r)[4])
 {
-    const uint32_t q = lane & 3;
-    // the block of slot j = q for the quad's groups g0 + 64q + (lane & ~3) + 0..3
+    const bool o1 = lane & 1, o2 = lane & 2;
     uint64_t we, wo;
-    word_pair((g0 + 64 * q + (lane & ~3u)) >> 2, key, we, wo);
-    const uint32_t x[4] = {(uint32_t)we, (uint32_t)(we >> 32), (uint32_t)wo, (uint32_t)(wo >> 32)};
-    // round m: lane q receives from lane (q + m) mod 4 (which computed slot
-    // (q + m) mod 4) its word x[q]; that lane sends x[(its q - m) mod 4]
-    const uint32_t v0 = x[q];
-    const uint32_t v1 = from_quad_lane<1>(pick4(x, (q - 1) & 3));
-    const uint32_t v2 = from_quad_lane<2>(pick4(x, (q - 2) & 3));
-    const uint32_t v3 = from_quad_lane<3>(pick4(x, (q - 3) & 3));
-    // slot j arrived in round m = (j - q) mod 4
-#pragma unroll
-    for (uint32_t j = 0; j < 4; ++j) {
-        const uint32_t m = (j - q) & 3;
-        r[j] = m == 0 ? v0 : m == 1 ? v1 : m == 2 ? v2 : v3;
-    }
+    word_pair((g0 + 64 * (lane & 3) + (lane & ~3u)) >> 2, key, we, wo);
+    const uint32_t x0 = (uint32_t)we, x1 = (uint32_t)(we >> 32), x2 = (uint32_t)wo,
+                   x3 = (uint32_t)(wo >> 32);
+    // stage 1: keep the columns of this lane's parity, swap the others with
+    // lane q ^ 1; afterwards this lane holds rows q and q ^ 1 of columns
+    // c0 = q & 1 and c1 = c0 + 2
+    const uint32_t k0 = o1 ? x1 : x0, k1 = o1 ? x3 : x2;
+    const uint32_t r0 = from_quad_xor<1>(o1 ? x0 : x1);
+    const uint32_t r1 = from_quad_xor<1>(o1 ? x2 : x3);
+    // stage 2: keep column q, swap the other with lane q ^ 2
+    const uint32_t u0 = o2 ? k1 : k0; // M[q][q]
+    const uint32_t u1 = o2 ? r1 : r0; // M[q ^ 1][q]
+    const uint32_t w0 = from_quad_xor<2>(o2 ? k0 : k1); // M[q ^ 2][q]
+    const uint32_t w1 = from_quad_xor<2>(o2 ? r0 : r1); // M[q ^ 3][q]
+    // order by row: rows q, q ^ 1 share bit 1 with q, rows q ^ 2, q ^ 3 not
+    const uint32_t ue = o1 ? u1 : u0, uo = o1 ? u0 : u1; // even, odd row of {q, q ^ 1}
+    const uint32_t we_ = o1 ? w1 : w0, wo_ = o1 ? w0 : w1;
+    r[0] = o2 ? we_ : ue;
+    r[1] = o2 ? wo_ : uo;
+    r[2] = o2 ? ue : we_;
+    r[3] = o2 ? uo : wo_;
 }
 
 __device__ __forceinline__ uint32_t word32_at(uint64_t c, const StreamKey &key)
