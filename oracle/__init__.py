@@ -32,10 +32,14 @@ def build() -> str:
     return LIB
 
 
+FORM_MULTIPLY, FORM_DIVISION = 0, 1
+
+
 class Schedule(ctypes.Structure):
     """A batch-size schedule: while more than thr[g] elements remain, roll
-    batches of k[g] dice with upper bound u[g] (0 = exact product); then, if
-    ``tail``, one last batch of i-1 dice bounded by ``u_tail``."""
+    batches of k[g] dice with upper bound u[g] (0 = exact product), their
+    dice from Theorem 1 (form 0) or the division form of Sec. 2.1 (form 1);
+    then, if ``tail``, one last batch of i-1 dice bounded by ``u_tail``."""
 
     _fields_ = [
         ("nseg", ctypes.c_uint32),
@@ -44,20 +48,33 @@ class Schedule(ctypes.Structure):
         ("k", ctypes.c_uint32 * 16),
         ("u", ctypes.c_uint64 * 16),
         ("u_tail", ctypes.c_uint64),
+        ("form", ctypes.c_uint32 * 16),
     ]
 
     def segments(self):
         return [(int(self.thr[g]), int(self.k[g]), int(self.u[g])) for g in range(self.nseg)]
 
+    def forms(self):
+        return [int(self.form[g]) for g in range(self.nseg)]
+
     @classmethod
-    def from_segments(cls, segs, tail=True, u_tail=720):
+    def from_segments(cls, segs, tail=True, u_tail=720, forms=None):
         s = cls()
         s.nseg = len(segs)
         for g, (thr, k, u) in enumerate(segs):
             s.thr[g], s.k[g], s.u[g] = thr, k, u
+            s.form[g] = forms[g] if forms else FORM_MULTIPLY
         s.tail = 1 if tail else 0
         s.u_tail = u_tail
         return s
+
+
+def schedule_naive2() -> Schedule:
+    """The division-based comparison shuffle of Appendix A: one die per
+    batch above 2^32 elements, then batches of two dice in the division form
+    while more than one element remains (no separate last batch)."""
+    return Schedule.from_segments([(1 << 32, 1, 0), (1, 2, 0)], tail=False,
+                                  forms=[FORM_DIVISION, FORM_DIVISION])
 
 
 _lib = None
@@ -82,6 +99,10 @@ def lib():
         L.orc_dice.restype = ctypes.c_int
         L.orc_dice_group.argtypes = [p, ctypes.c_uint, u64, u64, u64, u64, p]
         L.orc_dice_group.restype = ctypes.c_int
+        L.orc_dice_div.argtypes = [p, p, u64, ctypes.c_uint, u64, u64]
+        L.orc_dice_div.restype = ctypes.c_int
+        L.orc_dice_div_group.argtypes = [p, ctypes.c_uint, u64, u64, u64, u64, p]
+        L.orc_dice_div_group.restype = ctypes.c_int
         L.orc_dice32.argtypes = [p, p, u64, ctypes.c_uint, u64, u64]
         L.orc_dice32.restype = ctypes.c_int
         L.orc_word32.argtypes = [u64, u64, u64]
@@ -145,6 +166,22 @@ def dice(bounds: np.ndarray, k: int, seed: int, inst: int = 0):
     bounds = np.ascontiguousarray(bounds, dtype=np.uint32)
     out = np.zeros(bounds.size, dtype=np.uint32)
     err = lib().orc_dice(_ptr(bounds), _ptr(out), bounds.size, k, seed, inst)
+    return err, out
+
+
+def dice_div(bounds: np.ndarray, k: int, seed: int, inst: int = 0):
+    """The dice stream in the division form (Sec. 2.1): per group one value
+    below the product of its bounds, digits as successive remainders."""
+    bounds = np.ascontiguousarray(bounds, dtype=np.uint32)
+    out = np.zeros(bounds.size, dtype=np.uint32)
+    err = lib().orc_dice_div(_ptr(bounds), _ptr(out), bounds.size, k, seed, inst)
+    return err, out
+
+
+def dice_div_group(group_bounds, S: int, s: int, seed: int, inst: int = 0):
+    b = np.ascontiguousarray(group_bounds, dtype=np.uint32)
+    out = np.zeros(b.size, dtype=np.uint32)
+    err = lib().orc_dice_div_group(_ptr(b), b.size, S, s, seed, inst, _ptr(out))
     return err, out
 
 

@@ -13,6 +13,9 @@
  *   - Algorithm 2 (known threshold) and Algorithm 3 (unknown)    (Sec. 5),
  *     at word width 64 and, for dice streams, 32
  *   - Algorithm 4 (batched partial shuffle with carried bound u) (Sec. 6)
+ *   - the division form of batched dice: one roll of the product of the
+ *     bounds, digits as successive remainders of quotients  (Sec. 2.1,
+ *     and the naive batched shuffle of Appendix A)
  *   - the full-shuffle procedure with batch sizes growing as the
  *     array shrinks, and one last batch at the end              (Sec. 6, 6.1)
  *
@@ -196,6 +199,79 @@ int orc_dice_group(const uint32_t *group_bounds, unsigned kk, uint64_t S, uint64
 }
 
 /* ------------------------------------------------------------------ */
+/* The division form of batched dice (Sec. 2.1)                        */
+/* ------------------------------------------------------------------ */
+
+/* Digits of V in [0, b_1 ... b_k) as successive remainders of quotients:
+ * a_1 = V mod b_1, then V <- V div b_1, a_2 = V mod b_2, and so on (the
+ * first die is the remainder on dividing by b_1). */
+static void division_digits(u128 V, const uint64_t *b, unsigned k, uint64_t *a)
+{
+    for (unsigned i = 0; i < k; ++i) {
+        a[i] = (uint64_t)(V % b[i]);
+        V /= b[i];
+    }
+}
+
+/* Lemire's method (Sec. 2) for one value in [0, prod), prod <= 2^64, on
+ * the words of attempts 0, 1, ... of batch s: (V, y) = prod (x) r, accept
+ * when y >= 2^64 mod prod, which is only computed once y < prod. */
+static u128 lemire_value(u128 prod, uint64_t seed, uint64_t inst, uint64_t S, uint64_t s)
+{
+    uint64_t attempt = 0;
+    u128 x = prod * orc_word(seed, inst, s);
+    if ((u128)(uint64_t)x < prod) {
+        const u128 t = (((u128)1) << 64) % prod;
+        while ((u128)(uint64_t)x < t) {
+            ++attempt;
+            x = prod * orc_word(seed, inst, attempt * S + s);
+        }
+    }
+    return x >> 64;
+}
+
+/* The dice stream of orc_dice (same groups, same word addressing) with the
+ * division form in place of Theorem 1: each group rolls one value below the
+ * product of its bounds and splits it into digits. */
+int orc_dice_div(const uint32_t *bounds, uint32_t *out, uint64_t count, unsigned k, uint64_t seed,
+                 uint64_t inst)
+{
+    if (k == 0 || k > 64) return ORC_EINVAL;
+    const uint64_t S = ceil_div(count, k);
+    int status = ORC_OK;
+    for (uint64_t s = 0; s < S; ++s) {
+        const uint64_t first = s * k;
+        const unsigned kk = (unsigned)((count - first < k) ? count - first : k);
+        uint64_t b[64], a[64];
+        for (unsigned i = 0; i < kk; ++i) b[i] = bounds[first + i];
+        u128 prod;
+        const int err = bound_product(64, b, kk, &prod);
+        if (err) {
+            if (!status) status = err;
+            continue;
+        }
+        division_digits(lemire_value(prod, seed, inst, S, s), b, kk, a);
+        for (unsigned i = 0; i < kk; ++i) out[first + i] = (uint32_t)a[i];
+    }
+    return status;
+}
+
+/* Group s alone of a division-form stream with S groups. */
+int orc_dice_div_group(const uint32_t *group_bounds, unsigned kk, uint64_t S, uint64_t s,
+                       uint64_t seed, uint64_t inst, uint32_t *out)
+{
+    if (kk == 0 || kk > 64) return ORC_EINVAL;
+    uint64_t b[64], a[64];
+    for (unsigned i = 0; i < kk; ++i) b[i] = group_bounds[i];
+    u128 prod;
+    const int err = bound_product(64, b, kk, &prod);
+    if (err) return err;
+    division_digits(lemire_value(prod, seed, inst, S, s), b, kk, a);
+    for (unsigned i = 0; i < kk; ++i) out[i] = (uint32_t)a[i];
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Dice streams at word width L = 32                                   */
 /* ------------------------------------------------------------------ */
 
@@ -290,8 +366,12 @@ int orc_dice_const(uint32_t bound, uint32_t *out, uint64_t count, unsigned k, ui
 /* A schedule lists segments in order: while the number i of elements still
  * to shuffle exceeds thr[s], roll batches of k[s] dice with the upper bound
  * starting at u[s] (u[s] = 0: the exact falling factorial is the bound).
+ * form[s] = 0 takes the dice of a batch from Theorem 1's chain (Alg. 4),
+ * form[s] = 1 from the division form of Sec. 2.1 (one value below the
+ * falling product by Lemire's method, digits as successive remainders of
+ * quotients: the naive batched shuffle of Appendix A; u is not used).
  * If `tail` is set and i > 1 afterwards, one last batch of i-1 dice with
- * bound u_tail finishes the shuffle. */
+ * bound u_tail finishes the shuffle (Theorem 1 form). */
 typedef struct {
     uint32_t nseg;
     uint32_t tail;
@@ -299,6 +379,7 @@ typedef struct {
     uint32_t k[16];
     uint64_t u[16];
     uint64_t u_tail;
+    uint32_t form[16];
 } orc_schedule;
 
 /* The paper's schedules: max_k = 6 is shuffle_6 (one die above 2^30
@@ -407,6 +488,29 @@ static u128 partial_shuffle(uint8_t *z, uint64_t n, unsigned k, u128 u, unsigned
     return u;
 }
 
+/* Batch s at size n with k dice in the division form: V below the falling
+ * product n (n-1) ... (n-k+1) by Lemire's method on the batch's words, the
+ * die for bound n - i + 1 the i-th remainder of the successive quotients,
+ * and the swaps in the order of Algorithm 4 (z[n-1] first). */
+static void partial_shuffle_div(uint8_t *z, uint64_t n, unsigned k, unsigned eb, word_src *w,
+                                uint64_t s)
+{
+    uint64_t bounds[64], a[64];
+    for (unsigned i = 1; i <= k; ++i) bounds[i - 1] = n + 1 - i;
+    const u128 prod = falling(n, k);
+    uint64_t attempt = 0;
+    u128 x = prod * next_word(w, attempt, s);
+    if ((u128)(uint64_t)x < prod) {
+        const u128 t = (((u128)1) << 64) % prod;
+        while ((u128)(uint64_t)x < t && !w->exhausted) {
+            ++attempt;
+            x = prod * next_word(w, attempt, s);
+        }
+    }
+    division_digits(x >> 64, bounds, k, a);
+    for (unsigned i = 1; i <= k; ++i) swap_elems(z, a[i - 1], n - i, eb);
+}
+
 enum { RUN_COUNT = 0, RUN_CHECK = 1, RUN_EXEC = 2 };
 
 /* Walks the batches of an n-element shuffle that performs `steps`
@@ -432,7 +536,9 @@ static uint64_t run_schedule(int mode, uint8_t *z, uint64_t n, uint64_t steps, u
                 if (p > two64) { *err = ORC_EOVERFLOW; return ~(uint64_t)0; }
                 if (u0 && u < p) { *err = ORC_EINVAL; return ~(uint64_t)0; }
             }
-            if (mode == RUN_EXEC) {
+            if (mode == RUN_EXEC && sch->form[g] == 1) {
+                partial_shuffle_div(z, i, k, eb, w, s);
+            } else if (mode == RUN_EXEC) {
                 const u128 next_u = partial_shuffle(z, i, k, u, eb, w, s);
                 if (u0) u = next_u; /* carry the bound only when one was given */
             }
@@ -464,6 +570,7 @@ static int check_segments(const orc_schedule *sch)
     if (sch->nseg == 0 || sch->nseg > 16) return ORC_EINVAL;
     for (uint32_t g = 0; g < sch->nseg; ++g) {
         if (sch->k[g] == 0 || sch->k[g] > 64) return ORC_EINVAL;
+        if (sch->form[g] > 1) return ORC_EINVAL;
         if (sch->thr[g] + 1 < sch->k[g]) return ORC_EINVAL;
         if (g > 0 && sch->thr[g] > sch->thr[g - 1]) return ORC_EINVAL;
     }

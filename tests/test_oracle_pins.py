@@ -527,3 +527,135 @@ def test_dice_group_equals_stream(orc):
         for g in range(S):
             e, got = orc.dice_group(bounds[g * k:(g + 1) * k], S, g, 9, 2)
             assert e == 0 and np.array_equal(got, out[g * k:(g + 1) * k])
+
+
+# ---------------------------------------------------------------------------
+# The division form (Sec. 2.1; the naive batched shuffle of Appendix A)
+# ---------------------------------------------------------------------------
+
+def test_k1_division_dice_is_lemire(orc):
+    """One die per group: the division form is Lemire's method (Sec. 2)."""
+    rng = np.random.default_rng(6)
+    bounds = np.concatenate([rng.integers(1, 1 << 32, size=200, dtype=np.uint64),
+                             np.array([1, 2, 2**31 + 1, 2**32 - 1], dtype=np.uint64)]).astype(np.uint32)
+    err, out = orc.dice_div(bounds, 1, seed=21, inst=5)
+    assert err == 0
+    S = bounds.size
+    for g, b in enumerate(bounds):
+        assert out[g] == ref.lemire(64, int(b), _stream_words(orc, 21, 5, S, g))[0]
+
+
+@pytest.mark.parametrize("k,bits", [(2, 32), (2, 16), (3, 21), (4, 16), (6, 10)])
+def test_division_and_multiply_forms_share_the_value(orc, k, bits):
+    """Both forms accept by Lemire's criterion on the same word (the chain's
+    leftover is the low half of prod(b) * r, pinned above), so a group reads
+    the same words in both and rolls the same value V below prod(b). The
+    multiply form writes V with b_1's digit most significant, the division
+    form with b_1's digit least significant (V mod b_1 first)."""
+    rng = np.random.default_rng(100 + k)
+    count = 600 * k + k - 1
+    bounds = rng.integers(1, 1 << bits, size=count, dtype=np.uint64).astype(np.uint32)
+    if bits == 32:  # rejection-heavy pairs as well
+        bounds[: 200] = np.tile(np.array([2**31 + 1, 2**32 - 1], dtype=np.uint32), 100)
+    e1, mul = orc.dice(bounds, k, seed=3, inst=9)
+    e2, div = orc.dice_div(bounds, k, seed=3, inst=9)
+    assert e1 == e2 == 0
+    assert np.all(div < bounds)
+    for g in range(-(-count // k)):
+        b = [int(x) for x in bounds[g * k:(g + 1) * k]]
+        a = [int(x) for x in mul[g * k:(g + 1) * k]]
+        d = [int(x) for x in div[g * k:(g + 1) * k]]
+        assert ref.mixed_radix(a, b) == ref.mixed_radix(d[::-1], b[::-1])
+    if k >= 2:  # the forms differ as tuples
+        assert not np.array_equal(mul, div)
+
+
+def test_division_form_product_2_64(orc):
+    """Four bounds of 2^16: the product is 2^64, every word is accepted and
+    V is the word itself, so the dice are its 16-bit fields, least
+    significant first."""
+    bounds = np.full(8, 1 << 16, dtype=np.uint32)
+    err, out = orc.dice_div(bounds, 4, seed=12, inst=1)
+    assert err == 0
+    for g in range(2):
+        w = orc.word(12, 1, g)
+        assert [int(x) for x in out[4 * g:4 * g + 4]] == [(w >> (16 * i)) & 0xFFFF for i in range(4)]
+
+
+def test_division_form_two_dice_example(orc):
+    """Sec. 2.1 with b_1 = b_2 = 6: the pair is the remainder and the
+    quotient of one roll of a 36-sided die (all 36 pairs, uniform)."""
+    count = 360_000
+    err, out = orc.dice_div(np.full(count, 6, dtype=np.uint32), 2, seed=2, inst=0)
+    assert err == 0
+    pairs = out[0::2].astype(np.int64) + 6 * out[1::2].astype(np.int64)
+    e36, big = orc.dice(np.full(count // 2, 36, dtype=np.uint32), 1, seed=2, inst=0)
+    assert e36 == 0 and np.array_equal(pairs, big.astype(np.int64))
+    hist = np.bincount(pairs, minlength=36)
+    stat = float(((hist - count / 72) ** 2 / (count / 72)).sum())
+    assert stat < chi2.ppf(1 - 1e-3, 35)
+
+
+def test_division_edge_cases(orc):
+    assert orc.dice_div(np.array([2**32 - 1] * 3, dtype=np.uint32), 3, 1, 0)[0] == 2
+    assert orc.dice_div(np.array([5, 0, 7, 9], dtype=np.uint32), 2, 1, 0)[0] == 1
+    err, out = orc.dice_div(np.zeros(0, dtype=np.uint32), 3, 1, 0)
+    assert err == 0 and out.size == 0
+    rng = np.random.default_rng(4)
+    bounds = rng.integers(1, 1 << 16, size=1003, dtype=np.uint32)
+    err, out = orc.dice_div(bounds, 4, 9, 2)
+    S = -(-bounds.size // 4)
+    for g in range(S):
+        e, got = orc.dice_div_group(bounds[4 * g:4 * g + 4], S, g, 9, 2)
+        assert e == 0 and np.array_equal(got, out[4 * g:4 * g + 4])
+
+
+def _division_dice_for_shuffle(orc, n, seed, inst):
+    """Dice of the naive batched shuffle from big integers: batch s at size
+    i rolls V below i (i - 1) by Lemire's method on words a*S + s; the die
+    for step i-1 is V mod i and the die for step i-2 is V div i (a batch at
+    i = 2 keeps one die)."""
+    batches = []
+    i = n
+    while i > 1:
+        batches.append((i, min(2, i - 1)))
+        i -= 2
+    S = len(batches)
+    js = []
+    for s, (i, k) in enumerate(batches):
+        bound = i * (i - 1) if k == 2 else i
+        V = ref.lemire(64, bound, _stream_words(orc, seed, inst, S, s))[0]
+        js.extend([V % i, V // i] if k == 2 else [V])
+    return js
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 9, 100, 5001])
+def test_naive2_shuffle_is_fisher_yates(orc, n):
+    sched = orc.schedule_naive2()
+    assert orc.count_batches(n, n - 1, sched) == n // 2
+    z = np.arange(n, dtype=np.uint64)
+    assert orc.shuffle(z, sched, seed=23, inst=n) == 0
+    assert list(z) == ref.fisher_yates(range(n), _division_dice_for_shuffle(orc, n, 23, n))
+
+
+def test_naive2_chi2_all_24_permutations(orc):
+    trials = 2_000_000
+    data = np.tile(np.arange(4, dtype=np.uint32), trials)
+    offsets = np.arange(0, 4 * trials + 1, 4, dtype=np.uint64)
+    assert orc.shuffle_batched(data, offsets, orc.schedule_naive2(), seed=43) == 0
+    hist = np.bincount(_perm_index4(data.reshape(trials, 4)), minlength=24)
+    assert hist.size == 24 and hist.min() > 0
+    stat = float(((hist - trials / 24) ** 2 / (trials / 24)).sum())
+    assert stat < chi2.ppf(1 - 1e-3, 23), stat
+
+
+def test_mixed_form_schedule_and_bad_form(orc):
+    """Forms may change from segment to segment; an unknown form is an
+    invalid schedule."""
+    mixed = orc.Schedule.from_segments([(500, 1, 0), (100, 2, 0), (6, 3, 2**57)], tail=True,
+                                       u_tail=720, forms=[0, 1, 0])
+    z = np.arange(3000, dtype=np.uint32)
+    assert orc.shuffle(z, mixed, 1, 0) == 0
+    assert np.array_equal(np.sort(z), np.arange(3000, dtype=np.uint32))
+    bad = orc.Schedule.from_segments([(1, 2, 0)], tail=False, forms=[2])
+    assert orc.shuffle(np.arange(10, dtype=np.uint32), bad, 1, 0) == 1
