@@ -59,21 +59,33 @@ typedef enum {
 #define BRR_MAX_STEPS 16
 #define BRR_MAX_K 20 /* 21 dice never fit: 21! > 2^64 */
 
+/* How a batch turns its word into dice:
+ * BRR_FORM_MULTIPLY -- the multiply chain of Theorem 1 (Algorithm 4);
+ * BRR_FORM_DIVISION -- the division form of Sec. 2.1, the comparison of the
+ *   paper's experiments (its naive batched shuffle): one value V below the
+ *   falling product i (i-1) ... (i-k+1) by Lemire's method (Sec. 2) on the
+ *   batch's words, the die for bound i - l being the l-th successive
+ *   remainder (V mod i first, then V div i continues); u0 is not used. */
+#define BRR_FORM_MULTIPLY 0u
+#define BRR_FORM_DIVISION 1u
+
 /* While more than n_above elements remain to be shuffled, roll batches of k
- * dice; u0 is the initial upper bound on the batch's bound product (Algorithm
- * 4's u; 0 = none known, compare against the exact product). A schedule's
- * upper bounds only decide how often the exact product is formed; they never
- * change an output. */
+ * dice in the given form; u0 is the initial upper bound on the batch's bound
+ * product (Algorithm 4's u; 0 = none known, compare against the exact
+ * product). A schedule's upper bounds only decide how often the exact
+ * product is formed; they never change an output. Both forms read the same
+ * words (the acceptance test is the same), so they differ only in the digits. */
 typedef struct {
     uint64_t n_above;
     uint32_t k;
-    uint32_t reserved;
+    uint32_t form; /* BRR_FORM_* (any other value: BRR_EINVAL) */
     uint64_t u0;
 } brr_step;
 
 /* Steps run in order with non-increasing n_above. With tail = 1, when more
  * than one element remains after the last step, one batch of (i - 1) dice
- * bounded by u_tail finishes the shuffle (the last batch of Sec. 6). */
+ * bounded by u_tail finishes the shuffle (the last batch of Sec. 6; always
+ * in the multiply form). */
 typedef struct {
     uint32_t nsteps;
     uint32_t tail;
@@ -91,6 +103,13 @@ typedef struct {
  * max_k = 1: the unbatched shuffle, one die per word.
  * Returns BRR_EINVAL for any other max_k or a null out. */
 brr_status brr_schedule_paper(int max_k, brr_schedule *out);
+
+/* Fills *out with the division-based comparison shuffle of the paper's
+ * experiments (Sec. 7, Appendix A): one die per batch above 2^32 elements
+ * (never reached: n < 2^32 here), then batches of two dice in the division
+ * form while more than one element remains; no tail (a last batch at two
+ * elements keeps one die). BRR_EINVAL for a null out. */
+brr_status brr_schedule_naive2(brr_schedule *out);
 
 /* Number of batches (= words on first attempts) of an n-element shuffle that
  * performs `steps` Fisher-Yates steps (steps = n - 1 for a full shuffle).
@@ -154,6 +173,18 @@ brr_status brr_dice(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, u
  * 1 <= k <= 8, bound^k <= 2^64 (else BRR_EOVERFLOW). */
 brr_status brr_dice_const(uint32_t bound, uint32_t *d_out, uint64_t count, uint32_t k,
                           uint64_t seed, uint64_t inst, void *stream);
+
+/* The division-based form of batched dice (Sec. 2.1, the comparison that the
+ * paper's method replaces): each group rolls one value V uniform in
+ * [0, b_1 ... b_k) by Lemire's method (Sec. 2) on the same words as brr_dice
+ * (attempt a of group s reads word a*S + s; the acceptance test is the same,
+ * so both forms read the same words), then takes its dice as successive
+ * remainders of quotients: a_1 = V mod b_1, V <- V div b_1, a_2 = V mod b_2,
+ * and so on (k - 1 integer divisions per group). Per group, brr_dice and
+ * this form write the same V in mixed radix, most and least significant
+ * digit first respectively. Arguments, grouping and errors as brr_dice. */
+brr_status brr_dice_div(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
+                        uint64_t seed, uint64_t inst, void *stream);
 
 /* The dice stream of brr_dice at word width L = 32 (Theorem 1 holds for any
  * L, Sec. 4): each group is rolled from one 32-bit word with one 32x32 ->

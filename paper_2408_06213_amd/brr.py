@@ -30,7 +30,8 @@ EXPORTS = (
     "brr_server_destroy", "brr_mlp_create", "brr_mlp_destroy", "brr_mlp_num_params",
     "brr_mlp_get_params", "brr_mlp_set_params", "brr_mlp_get_grads", "brr_mlp_forward",
     "brr_mlp_backward", "brr_mlp_adam_step", "brr_mlp_train", "brr_plan_features",
-    "brr_plan_autotune_learned", "brr_probe_chain_rate", "brr_dice32",
+    "brr_plan_autotune_learned", "brr_probe_chain_rate", "brr_dice32", "brr_dice_div",
+    "brr_schedule_naive2",
 )
 BRR_PLAN_FEATURES = 16
 BRR_REQ_SHUFFLE, BRR_REQ_SAMPLE = 1, 2
@@ -42,9 +43,12 @@ class BrrError(RuntimeError):
         super().__init__(f"{what}: {brr_strerror(status)} (status {status})")
 
 
+BRR_FORM_MULTIPLY, BRR_FORM_DIVISION = 0, 1
+
+
 class brr_step(ctypes.Structure):
     _fields_ = [("n_above", ctypes.c_uint64), ("k", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("u0", ctypes.c_uint64)]
+                ("form", ctypes.c_uint32), ("u0", ctypes.c_uint64)]
 
 
 class brr_schedule(ctypes.Structure):
@@ -54,12 +58,16 @@ class brr_schedule(ctypes.Structure):
     def steps(self):
         return [(int(s.n_above), int(s.k), int(s.u0)) for s in self.step[: self.nsteps]]
 
+    def forms(self):
+        return [int(s.form) for s in self.step[: self.nsteps]]
+
     @classmethod
-    def from_steps(cls, steps, tail=True, u_tail=720):
+    def from_steps(cls, steps, tail=True, u_tail=720, forms=None):
         s = cls()
         s.nsteps = len(steps)
         for g, (above, k, u0) in enumerate(steps):
             s.step[g].n_above, s.step[g].k, s.step[g].u0 = above, k, u0
+            s.step[g].form = forms[g] if forms else BRR_FORM_MULTIPLY
         s.tail = 1 if tail else 0
         s.u_tail = u_tail
         return s
@@ -108,11 +116,13 @@ def _load():
     sched_p = ctypes.POINTER(brr_schedule)
     sig = {
         "brr_schedule_paper": (st, [ctypes.c_int, sched_p]),
+        "brr_schedule_naive2": (st, [sched_p]),
         "brr_schedule_batches": (u64, [sched_p, u64, u64]),
         "brr_schedule_check": (st, [sched_p, u64]),
         "brr_dice": (st, [p, p, u64, u32, u64, u64, p]),
         "brr_dice_const": (st, [u32, p, u64, u32, u64, u64, p]),
         "brr_dice32": (st, [p, p, u64, u32, u64, u64, p]),
+        "brr_dice_div": (st, [p, p, u64, u32, u64, u64, p]),
         "brr_shuffle": (st, [p, u64, u32, sched_p, u64, u64, p]),
         "brr_plan_create": (st, [ctypes.POINTER(p), p, u64, u32, sched_p]),
         "brr_plan_destroy": (None, [p]),
@@ -200,6 +210,12 @@ def brr_schedule_paper(max_k: int) -> brr_schedule:
     return s
 
 
+def brr_schedule_naive2() -> brr_schedule:
+    s = brr_schedule()
+    check(lib.brr_schedule_naive2(ctypes.byref(s)), "brr_schedule_naive2")
+    return s
+
+
 def brr_schedule_batches(sched: brr_schedule, n: int, steps: int) -> int:
     return int(lib.brr_schedule_batches(ctypes.byref(sched), n, steps))
 
@@ -236,6 +252,10 @@ def brr_dice(bounds, out, count: int, k: int, seed: int, inst: int = 0, stream=N
 
 def brr_dice32(bounds, out, count: int, k: int, seed: int, inst: int = 0, stream=None) -> int:
     return lib.brr_dice32(_addr(bounds), _addr(out), count, k, seed, inst, _stream(stream))
+
+
+def brr_dice_div(bounds, out, count: int, k: int, seed: int, inst: int = 0, stream=None) -> int:
+    return lib.brr_dice_div(_addr(bounds), _addr(out), count, k, seed, inst, _stream(stream))
 
 
 def brr_dice_const(bound: int, out, count: int, k: int, seed: int, inst: int = 0,

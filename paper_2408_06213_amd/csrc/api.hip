@@ -132,6 +132,7 @@ brr_status check_structure(const brr_schedule &sc)
     for (uint32_t g = 0; g < sc.nsteps; ++g) {
         const brr_step &st = sc.step[g];
         if (st.k == 0 || st.k > BRR_MAX_K) return BRR_EINVAL;
+        if (st.form != BRR_FORM_MULTIPLY && st.form != BRR_FORM_DIVISION) return BRR_EINVAL;
         if (st.n_above + 1 < st.k) return BRR_EINVAL;
         if (g > 0 && st.n_above > sc.step[g - 1].n_above) return BRR_EINVAL;
     }
@@ -148,20 +149,7 @@ brr_status check_for(const brr_schedule &sc, uint64_t n, uint64_t steps)
     return e;
 }
 
-DevSched to_dev(const brr_schedule &sc)
-{
-    DevSched d;
-    std::memset(&d, 0, sizeof d);
-    d.nsteps = sc.nsteps;
-    d.tail = sc.tail;
-    for (uint32_t g = 0; g < sc.nsteps; ++g) {
-        d.thr[g] = (uint32_t)std::min<uint64_t>(sc.step[g].n_above, 0xFFFFFFFFull);
-        d.k[g] = sc.step[g].k;
-        d.u[g] = sc.step[g].u0;
-    }
-    d.u_tail = sc.u_tail;
-    return d;
-}
+DevSched to_dev(const brr_schedule &sc) { return dev_schedule(sc); }
 
 } // namespace
 
@@ -500,6 +488,19 @@ brr_status brr_schedule_paper(int max_k, brr_schedule *out)
     return BRR_OK;
 }
 
+brr_status brr_schedule_naive2(brr_schedule *out)
+{
+    if (!out) return BRR_EINVAL;
+    brr_schedule s;
+    std::memset(&s, 0, sizeof s);
+    s.nsteps = 2;
+    s.step[0] = brr_step{1ull << 32, 1, BRR_FORM_DIVISION, 0};
+    s.step[1] = brr_step{1, 2, BRR_FORM_DIVISION, 0};
+    s.tail = 0;
+    *out = s;
+    return BRR_OK;
+}
+
 uint64_t brr_schedule_batches(const brr_schedule *sched, uint64_t n, uint64_t steps)
 {
     if (!sched || check_structure(*sched) != BRR_OK) return 0;
@@ -524,6 +525,19 @@ brr_status brr_dice(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, u
     if (st != BRR_OK) return st;
     return hip_status(launch_dice(d_bounds, d_out, count, k, make_key(seed, inst), status,
                                   static_cast<hipStream_t>(stream)));
+}
+
+brr_status brr_dice_div(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
+                        uint64_t seed, uint64_t inst, void *stream)
+{
+    if (k < 1 || k > 8) return BRR_EINVAL;
+    if (count == 0) return BRR_OK;
+    if (!d_bounds || !d_out || misaligned(d_bounds, 4) || misaligned(d_out, 4)) return BRR_EINVAL;
+    uint32_t *status = nullptr;
+    const brr_status st = device_ready(&status);
+    if (st != BRR_OK) return st;
+    return hip_status(launch_dice_div(d_bounds, d_out, count, k, make_key(seed, inst), status,
+                                      static_cast<hipStream_t>(stream)));
 }
 
 brr_status brr_dice32(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,

@@ -103,6 +103,18 @@ __host__ __device__ __forceinline__ uint64_t pow2_64_mod(uint64_t B)
     return t;
 }
 
+// The division form of batched dice (Sec. 2.1): the next die of the value V
+// below the remaining bound product is V mod b, and V continues as V div b.
+// One 64-by-32-bit division (the compiler's expansion; the form exists as the
+// division-based comparison, so it keeps the plain operation).
+__host__ __device__ __forceinline__ uint32_t div_digit(uint32_t b, uint64_t &V)
+{
+    const uint64_t q = V / b;
+    const uint32_t d = (uint32_t)(V - q * b);
+    V = q;
+    return d;
+}
+
 // Exact product of u32 bounds as long as it is at most 2^64.
 // p holds the product modulo 2^64; e64 marks a product of exactly 2^64
 // (then p == 0); over marks a product above 2^64; zero marks a zero bound.

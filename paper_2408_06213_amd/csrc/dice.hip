@@ -173,6 +173,88 @@ __global__ __launch_bounds__(256) void dice_kernel(const uint32_t *__restrict__ 
     if (err) atomicOr(status, err);
 }
 
+// The division form (Sec. 2.1), the comparison for the kernel above: group
+// g rolls one value V below the product P of its bounds by Lemire's method
+// (Sec. 2) on the same words (attempt a reads word a*S + g), accepting when
+// the low half of P*r is at least 2^64 mod P, and splits V into dice by
+// successive division: a_1 = V mod b_1, V <- V div b_1, ... (the last die is
+// what remains). Same tiling and word sharing as dice_kernel.
+template <int K>
+__device__ __forceinline__ void div_group(const uint32_t *b, int kk, uint32_t *a, uint64_t r,
+                                          uint64_t S, uint64_t g, const StreamKey &key,
+                                          uint32_t &err)
+{
+    BoundProduct P;
+    P.init(b[0]);
+#pragma unroll
+    for (int i = 1; i < K; ++i)
+        if (i < kk) P.mul(b[i]);
+    if (P.zero) {
+        err |= kDevZeroBound;
+        return;
+    }
+    if (P.over) {
+        err |= kDevOverflow;
+        return;
+    }
+    uint64_t V = r; // P = 2^64: every word is accepted and V is the word
+    if (!P.e64) {
+        V = __umul64hi(P.p, r);
+        uint64_t y = P.p * r;
+        if (y < P.p) {
+            const uint64_t t = pow2_64_mod(P.p);
+            // each attempt is rejected with probability t / 2^64 < 1/2; the
+            // cap only bounds the loop against corrupted inputs
+            for (uint64_t attempt = 1; y < t && attempt <= kMaxAttempts; ++attempt) {
+                const uint64_t w = word_at(attempt * S + g, key);
+                V = __umul64hi(P.p, w);
+                y = P.p * w;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < kk) a[i] = (i + 1 < kk) ? div_digit(b[i], V) : (uint32_t)V;
+}
+
+template <int K, int G, bool VEC>
+__global__ __launch_bounds__(256) void dice_div_kernel(const uint32_t *__restrict__ bounds,
+                                                       uint32_t *__restrict__ out, uint64_t count,
+                                                       uint64_t S, uint64_t full, StreamKey key,
+                                                       uint32_t *status)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t g0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * G);
+    if (g0 >= S) return;
+    uint64_t r[G];
+    tile_words<G>(g0, lane, key, r);
+    uint32_t b[G][K], a[G][K];
+    uint32_t err = 0;
+    if (g0 + 64 * G <= full) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) load_group<K, VEC>(bounds + K * (g0 + 64 * j + lane), b[j]);
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            div_group<K>(b[j], K, a[j], r[j], S, g0 + 64 * j + lane, key, err);
+#pragma unroll
+        for (int j = 0; j < G; ++j) store_group<K, VEC>(out + K * (g0 + 64 * j + lane), a[j]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const uint64_t g = g0 + 64 * j + lane;
+            const int kk = (g < full) ? K : (g < S ? (int)(count - K * g) : 0);
+            if (kk == 0) continue;
+#pragma unroll
+            for (int i = 0; i < K; ++i) b[j][i] = (i < kk) ? bounds[K * g + i] : 1u;
+            div_group<K>(b[j], kk, a[j], r[j], S, g, key, err);
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (i < kk) out[K * g + i] = a[j][i];
+        }
+    }
+    if (err) atomicOr(status, err);
+}
+
 // Constant bound (Algorithm 2): t_full is 2^64 mod bound^K, t_last the same
 // for the short last group.
 template <int K, int G, bool VEC>
@@ -235,6 +317,22 @@ hipError_t launch_dice_k(const uint32_t *bounds, uint32_t *out, uint64_t count, 
 }
 
 template <int K>
+hipError_t launch_dice_div_k(const uint32_t *bounds, uint32_t *out, uint64_t count, StreamKey key,
+                             uint32_t *status, hipStream_t stream)
+{
+    const uint64_t S = (count + K - 1) / K;
+    const uint64_t full = count / K;
+    const bool vec = ((((uintptr_t)bounds) | ((uintptr_t)out)) & 15) == 0;
+    if (vec)
+        dice_div_kernel<K, kGroupsPerLane, true><<<tile_blocks(S), 256, 0, stream>>>(
+            bounds, out, count, S, full, key, status);
+    else
+        dice_div_kernel<K, kGroupsPerLane, false><<<tile_blocks(S), 256, 0, stream>>>(
+            bounds, out, count, S, full, key, status);
+    return hipGetLastError();
+}
+
+template <int K>
 hipError_t launch_dice_const_k(uint32_t bound, uint32_t *out, uint64_t count, StreamKey key,
                                uint64_t t_full, uint64_t t_last, hipStream_t stream)
 {
@@ -264,6 +362,22 @@ hipError_t launch_dice(const uint32_t *bounds, uint32_t *out, uint64_t count, ui
     case 6: return launch_dice_k<6>(bounds, out, count, key, status, stream);
     case 7: return launch_dice_k<7>(bounds, out, count, key, status, stream);
     case 8: return launch_dice_k<8>(bounds, out, count, key, status, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_dice_div(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
+                           StreamKey key, uint32_t *status, hipStream_t stream)
+{
+    switch (k) {
+    case 1: return launch_dice_div_k<1>(bounds, out, count, key, status, stream);
+    case 2: return launch_dice_div_k<2>(bounds, out, count, key, status, stream);
+    case 3: return launch_dice_div_k<3>(bounds, out, count, key, status, stream);
+    case 4: return launch_dice_div_k<4>(bounds, out, count, key, status, stream);
+    case 5: return launch_dice_div_k<5>(bounds, out, count, key, status, stream);
+    case 6: return launch_dice_div_k<6>(bounds, out, count, key, status, stream);
+    case 7: return launch_dice_div_k<7>(bounds, out, count, key, status, stream);
+    case 8: return launch_dice_div_k<8>(bounds, out, count, key, status, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -21,14 +21,33 @@ struct DevSched {
     uint32_t k[16];
     uint64_t u[16];
     uint64_t u_tail;
+    uint32_t form[16]; // BRR_FORM_* of each step (the tail batch multiplies)
 };
+
+// The kernels' form of a schedule that brr_schedule_check accepted.
+inline DevSched dev_schedule(const brr_schedule &sc)
+{
+    DevSched d{};
+    d.nsteps = sc.nsteps;
+    d.tail = sc.tail;
+    for (uint32_t g = 0; g < sc.nsteps; ++g) {
+        d.thr[g] = sc.step[g].n_above < 0xFFFFFFFFull ? (uint32_t)sc.step[g].n_above : 0xFFFFFFFFu;
+        d.k[g] = sc.step[g].k;
+        d.u[g] = sc.step[g].u0;
+        d.form[g] = sc.step[g].form;
+    }
+    d.u_tail = sc.u_tail;
+    return d;
+}
 
 // A run of cnt consecutive batches (batch indices s0 .. s0+cnt-1) of k dice
 // each; the first starts with i0 elements left, each next one k fewer. u is
-// the guard of Algorithm 4 (0 = compare against the exact product).
+// the guard of Algorithm 4 (0 = compare against the exact product); form is
+// how the batches take their dice (BRR_FORM_*).
 struct Seg {
     uint32_t s0, i0, k, cnt;
     uint64_t u;
+    uint32_t form, pad;
 };
 
 constexpr int kMaxSegs = 18; // 16 steps + one truncated batch + the last batch
@@ -58,14 +77,14 @@ __host__ __device__ inline uint32_t walk_segments(uint32_t n, uint32_t steps, co
         uint32_t nb = cnt;
         if ((uint64_t)nb * k > left) nb = left / k;
         if (nb) {
-            f(Seg{s, i, k, nb, sc.u[g]});
+            f(Seg{s, i, k, nb, sc.u[g], sc.form[g], 0});
             s += nb;
             i -= nb * k;
             done += nb * k;
         }
         if (nb < cnt && done < steps) {
             const uint32_t kk = steps - done;
-            f(Seg{s, i, kk, 1, sc.u[g]});
+            f(Seg{s, i, kk, 1, sc.u[g], sc.form[g], 0});
             s += 1;
             i -= kk;
             done += kk;
@@ -74,7 +93,7 @@ __host__ __device__ inline uint32_t walk_segments(uint32_t n, uint32_t steps, co
     if (sc.tail && i > 1 && done < steps) {
         uint32_t kk = i - 1;
         if (kk > steps - done) kk = steps - done;
-        f(Seg{s, i, kk, 1, sc.u_tail});
+        f(Seg{s, i, kk, 1, sc.u_tail, BRR_FORM_MULTIPLY, 0});
         s += 1;
         done += kk;
     }
@@ -101,6 +120,9 @@ hipError_t launch_dice(const uint32_t *bounds, uint32_t *out, uint64_t count, ui
                        StreamKey key, uint32_t *status, hipStream_t stream);
 hipError_t launch_dice_const(uint32_t bound, uint32_t *out, uint64_t count, uint32_t k,
                              StreamKey key, uint64_t t_full, uint64_t t_last, hipStream_t stream);
+// The dice stream in the division form (dice.hip).
+hipError_t launch_dice_div(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
+                           StreamKey key, uint32_t *status, hipStream_t stream);
 // The dice stream at word width 32 (dice32.hip).
 hipError_t launch_dice32(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
                          StreamKey key, uint32_t *status, hipStream_t stream);

@@ -236,15 +236,7 @@ brr_status brr_server_create(brr_server **out, const brr_server_config *cfg)
     sv->cfg.schedule = nullptr;
     (void)hipGetDevice(&sv->device);
     // DevSched from the checked schedule
-    std::memset(&sv->ds, 0, sizeof sv->ds);
-    sv->ds.nsteps = sc.nsteps;
-    sv->ds.tail = sc.tail;
-    sv->ds.u_tail = sc.u_tail;
-    for (uint32_t g = 0; g < sc.nsteps; ++g) {
-        sv->ds.thr[g] = (uint32_t)std::min<uint64_t>(sc.step[g].n_above, 0xFFFFFFFFull);
-        sv->ds.k[g] = sc.step[g].k;
-        sv->ds.u[g] = sc.step[g].u0;
-    }
+    sv->ds = dev_schedule(sc);
     bool ok = hipMalloc(reinterpret_cast<void **>(&sv->d_counters), kMaxSessions * 8) == hipSuccess &&
               hipMalloc(reinterpret_cast<void **>(&sv->d_slots), cfg->max_inflight * 8ull) == hipSuccess &&
               hipMemset(sv->d_counters, 0, kMaxSessions * 8) == hipSuccess &&

@@ -44,13 +44,14 @@ constexpr uint64_t kMaxAttempts = 1024;
 constexpr int kTileShift = 8; // 256 indices per tile of the item tables
 
 __device__ __forceinline__ void batch_at(uint32_t s, const Seg *seg, uint32_t nseg, uint32_t &i,
-                                         uint32_t &k, uint64_t &u)
+                                         uint32_t &k, uint64_t &u, uint32_t &form)
 {
     uint32_t g = 0;
     while (g + 1 < nseg && s >= seg[g + 1].s0) ++g;
     i = seg[g].i0 - (s - seg[g].s0) * seg[g].k;
     k = seg[g].k;
     u = seg[g].u;
+    form = seg[g].form;
 }
 
 // The accepted word of batch s (k dice at size i, guard u) whose first
@@ -73,6 +74,44 @@ __device__ __forceinline__ uint64_t accept_word(uint32_t i, uint32_t k, uint64_t
         }
     }
     return r;
+}
+
+// The division form (Sec. 2.1) of batch s: the value V below the exact
+// falling product B = i (i-1) ... (i-k+1) (below 2^64: checked on the host)
+// by Lemire's method on the batch's words; div_digit then takes its dice.
+// Same words as the multiply form: both accept when the low half of B*r is
+// at least 2^64 mod B.
+__device__ uint64_t accept_div(uint32_t i, uint32_t k, uint64_t w, uint32_t S, uint32_t s,
+                               const StreamKey &key)
+{
+    uint64_t B = i;
+    for (uint32_t l = 1; l < k; ++l) B *= (uint64_t)(i - l);
+    uint64_t V = __umul64hi(B, w), y = B * w;
+    if (y < B) {
+        const uint64_t t = pow2_64_mod(B);
+        for (uint64_t attempt = 1; y < t && attempt <= kMaxAttempts; ++attempt) {
+            const uint64_t r = word_at(attempt * S + s, key);
+            V = __umul64hi(B, r);
+            y = B * r;
+        }
+    }
+    return V;
+}
+
+// The state a batch's dice are drawn from, given its first word: the
+// accepted word (multiply form) or the value V (division form).
+__device__ __forceinline__ uint64_t batch_state(uint32_t form, uint32_t i, uint32_t k, uint64_t u,
+                                                uint64_t w, uint32_t S, uint32_t s,
+                                                const StreamKey &key)
+{
+    return form == BRR_FORM_DIVISION ? accept_div(i, k, w, S, s, key)
+                                     : accept_word(i, k, u, w, S, s, key);
+}
+
+// The next die of a batch, for bound b = i - l (l = 0, 1, ... in order).
+__device__ __forceinline__ uint32_t next_die(uint32_t form, uint32_t b, uint64_t &r)
+{
+    return form == BRR_FORM_DIVISION ? div_digit(b, r) : mul_roll(b, r);
 }
 
 // Exclusive prefix sums of a[0..len) in place, offset by base, by the whole
@@ -145,11 +184,11 @@ __device__ void lds_tier_run(Elem *z, uint32_t n, uint32_t steps, uint32_t out_l
         for (int h = 0; h < 2; ++h) {
             const uint32_t s = 2 * m + h;
             if (s < S) {
-                uint32_t i, k;
+                uint32_t i, k, f;
                 uint64_t u;
-                batch_at(s, seg, nseg, i, k, u);
-                uint64_t r = accept_word(i, k, u, w[h], S, s, key);
-                for (uint32_t l = 0; l < k; ++l) jb[i - 1 - l] = (uint16_t)mul_roll(i - l, r);
+                batch_at(s, seg, nseg, i, k, u, f);
+                uint64_t r = batch_state(f, i, k, u, w[h], S, s, key);
+                for (uint32_t l = 0; l < k; ++l) jb[i - 1 - l] = (uint16_t)next_die(f, i - l, r);
             }
         }
     }
@@ -481,7 +520,8 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const u
         const uint32_t S = walk_segments(n, n - 1, sc, [](const Seg &) {});
         uint64_t w_odd = 0;
         walk_segments(n, n - 1, sc, [&](const Seg &g) {
-            switch (g.k) {
+            // the division form takes the general path
+            switch (g.form == BRR_FORM_DIVISION ? 0u : g.k) {
             case 1: lane_segment<1>(a, g, S, key, w_odd); break;
             case 2: lane_segment<2>(a, g, S, key, w_odd); break;
             case 3: lane_segment<3>(a, g, S, key, w_odd); break;
@@ -498,9 +538,9 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const u
                         word_pair(s >> 1, key, w, w_odd);
                     else
                         w = w_odd;
-                    uint64_t r = accept_word(i, g.k, g.u, w, S, s, key);
+                    uint64_t r = batch_state(g.form, i, g.k, g.u, w, S, s, key);
                     for (uint32_t l = 0; l < g.k; ++l) {
-                        const uint32_t j = mul_roll(i - l, r), p = i - 1 - l;
+                        const uint32_t j = next_die(g.form, i - l, r), p = i - 1 - l;
                         const uint8_t x = a[p];
                         a[p] = a[j];
                         a[j] = x;
@@ -681,11 +721,11 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             for (int h = 0; h < 2; ++h) {
                 const uint32_t s = 2 * m + h;
                 if (s < s_begin || s >= s_end) continue;
-                uint32_t i, k;
+                uint32_t i, k, f;
                 uint64_t u;
-                batch_at(s, st.seg, st.nseg, i, k, u);
-                uint64_t r = accept_word(i, k, u, w[h], st.S, s, key);
-                for (uint32_t l = 0; l < k; ++l) qof[i - 1 - l - i_end] = mul_roll(i - l, r);
+                batch_at(s, st.seg, st.nseg, i, k, u, f);
+                uint64_t r = batch_state(f, i, k, u, w[h], st.S, s, key);
+                for (uint32_t l = 0; l < k; ++l) qof[i - 1 - l - i_end] = next_die(f, i - l, r);
             }
         }
         __syncthreads();
@@ -941,13 +981,13 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
         for (int h = 0; h < 2; ++h) {
             const uint32_t s = 2 * m + h;
             if (s >= st.S) continue;
-            uint32_t i0, k;
+            uint32_t i0, k, f;
             uint64_t u;
-            batch_at(s, st.seg, st.nseg, i0, k, u);
-            uint64_t r = accept_word(i0, k, u, wd[h], st.S, s, key);
+            batch_at(s, st.seg, st.nseg, i0, k, u, f);
+            uint64_t r = batch_state(f, i0, k, u, wd[h], st.S, s, key);
             for (uint32_t l = 0; l < k; ++l) {
                 const uint32_t p = i0 - 1 - l;
-                const uint32_t a = mul_roll(i0 - l, r);
+                const uint32_t a = next_die(f, i0 - l, r);
                 jj[p] = a;
                 sk[p] = (a < p) ? tb + a : kSortNone;
                 sv[p] = tb + p;
@@ -978,15 +1018,15 @@ __global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t
         const StreamKey key = make_key(seed, ib + it.inst);
         uint64_t wd[2];
         word_pair(m, key, wd[0], wd[1]);
-        uint32_t i0[2] = {0, 0}, kk[2] = {0, 0};
+        uint32_t i0[2] = {0, 0}, kk[2] = {0, 0}, f[2] = {0, 0};
         uint64_t r[2] = {0, 0};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t s = 2 * m + h;
             if (s >= st.S) continue;
             uint64_t u;
-            batch_at(s, st.seg, st.nseg, i0[h], kk[h], u);
-            r[h] = accept_word(i0[h], kk[h], u, wd[h], st.S, s, key);
+            batch_at(s, st.seg, st.nseg, i0[h], kk[h], u, f[h]);
+            r[h] = batch_state(f[h], i0[h], kk[h], u, wd[h], st.S, s, key);
         }
         uint32_t *jj = g.jj + it.pos_base, *slot = g.key[0] + it.pos_base;
         uint32_t *cnt = g.cnt + it.pos_base;
@@ -999,7 +1039,7 @@ __global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t
 #pragma unroll
                 for (uint32_t l = 0; l < kFastK; ++l)
                     if (l < kk[h]) {
-                        a[h * kFastK + l] = mul_roll(i0[h] - l, r[h]);
+                        a[h * kFastK + l] = next_die(f[h], i0[h] - l, r[h]);
                         jj[i0[h] - 1 - l] = a[h * kFastK + l];
                     }
 #pragma unroll
@@ -1019,7 +1059,7 @@ __global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t
             for (int h = 0; h < 2; ++h)
                 for (uint32_t l = 0; l < kk[h]; ++l) {
                     const uint32_t p = i0[h] - 1 - l;
-                    const uint32_t a = mul_roll(i0[h] - l, r[h]);
+                    const uint32_t a = next_die(f[h], i0[h] - l, r[h]);
                     jj[p] = a;
                     if (a < p) slot[p] = atomicAdd(&cnt[a], 1u);
                 }

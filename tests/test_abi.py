@@ -58,6 +58,21 @@ def test_host_batch_counts_match_oracle(orc, max_k):
             assert brr.brr_schedule_batches(s, n, steps) == orc.count_batches(n, steps, o), (n, steps)
 
 
+def test_naive2_schedule_host(orc):
+    """The division-form comparison schedule: same steps, forms and batch
+    counts on the host side as the oracle's; unknown forms are rejected."""
+    from paper_2408_06213_amd import brr
+
+    s, o = brr.brr_schedule_naive2(), orc.schedule_naive2()
+    assert s.steps() == o.segments() and s.forms() == o.forms() == [1, 1] and s.tail == 0
+    for n in list(range(2, 40)) + [257, 10001, 2**20 + 7, 2**32 - 1]:
+        assert brr.brr_schedule_check(s, n) == brr.BRR_OK
+        for steps in {n - 1, max(1, n // 3), 1}:
+            assert brr.brr_schedule_batches(s, n, steps) == orc.count_batches(n, steps, o)
+    bad = brr.brr_schedule.from_steps([(1, 2, 0)], tail=False, forms=[2])
+    assert brr.brr_schedule_check(bad, 100) == brr.BRR_EINVAL
+
+
 def test_schedule_check_host():
     from paper_2408_06213_amd import brr
 

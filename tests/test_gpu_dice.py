@@ -181,3 +181,67 @@ def test_dice32_edge_cases(gpu, orc):
     st, _ = run_dice32(gpu, np.array([5, 0, 3, 4], np.uint32), 2, 1, 0)
     assert st == gpu.BRR_EINVAL
     assert gpu.brr_sync_status() == 0  # reading the status clears it
+
+
+# ---------------------------------------------------------------------------
+# The division form (brr_dice_div)
+# ---------------------------------------------------------------------------
+
+# bound width per k so that a group's product stays <= 2^64
+BITS64 = {1: 32, 2: 32, 3: 21, 4: 16, 5: 12, 6: 10, 7: 9, 8: 8}
+
+
+def run_dice_div(gpu, bounds_np, k, seed, inst, offset=0):
+    n = bounds_np.size
+    b = to_dev(np.concatenate([np.zeros(offset, np.uint32), bounds_np]))
+    out = to_dev(np.zeros(n + offset, np.uint32))
+    gpu.check(gpu.brr_dice_div(b.data_ptr() + 4 * offset, out.data_ptr() + 4 * offset, n, k, seed,
+                               inst), "brr_dice_div")
+    st = gpu.brr_sync_status()
+    return st, to_host(out)[offset:]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_dice_div_parity_ragged_counts(gpu, orc, k):
+    """Bounds in the upper half of their width, so products come near 2^64
+    and groups reroll."""
+    rng = np.random.default_rng(500 + k)
+    hi = 1 << BITS64[k]
+    for count in (1, 3, 4 * k - 1, 256 * k + 5, 1000 + 7, 65536 + 3, 300001):
+        say("dice_div", k, count)
+        bounds = rng.integers(max(1, hi // 2), hi, size=count, dtype=np.uint64).astype(np.uint32)
+        st, got = run_dice_div(gpu, bounds, k, seed=17, inst=6)
+        err, want = orc.dice_div(bounds, k, 17, 6)
+        assert st == 0 and err == 0
+        assert np.array_equal(got, want), (k, count)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_dice_div_unaligned_buffers(gpu, orc, k):
+    rng = np.random.default_rng(600 + k)
+    bounds = rng.integers(1, 1 << BITS64[k], size=5003, dtype=np.uint64).astype(np.uint32)
+    say("dice_div unaligned", k)
+    st, got = run_dice_div(gpu, bounds, k, seed=5, inst=0, offset=1)
+    assert st == 0
+    assert np.array_equal(got, orc.dice_div(bounds, k, 5, 0)[1])
+
+
+def test_dice_div_edge_cases(gpu, orc):
+    # product exactly 2^64: V is the word itself
+    b = np.full(4 * 999, 1 << 16, np.uint32)
+    st, got = run_dice_div(gpu, b, 4, seed=3, inst=0)
+    assert st == 0 and np.array_equal(got, orc.dice_div(b, 4, 3, 0)[1])
+    # rejection-heavy pairs (product 2^63 + 2^31 - 1)
+    b = np.tile(np.array([2**31 + 1, 2**32 - 1], np.uint32), 5000)
+    st, got = run_dice_div(gpu, b, 2, seed=4, inst=1)
+    assert st == 0 and np.array_equal(got, orc.dice_div(b, 2, 4, 1)[1])
+    # the 2^28 stream's bounds (uniform below 2^16) at k = 2..4
+    b = workloads.dice_bounds(100003, seed=7)
+    for k in (2, 3, 4):
+        st, got = run_dice_div(gpu, b, k, seed=7, inst=0)
+        assert st == 0 and np.array_equal(got, orc.dice_div(b, k, 7, 0)[1]), k
+    st, _ = run_dice_div(gpu, np.array([2**32 - 1] * 6, np.uint32), 3, 1, 0)
+    assert st == gpu.BRR_EOVERFLOW
+    st, _ = run_dice_div(gpu, np.array([5, 0, 3, 4], np.uint32), 2, 1, 0)
+    assert st == gpu.BRR_EINVAL
+    assert gpu.brr_sync_status() == 0

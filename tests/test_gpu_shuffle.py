@@ -244,3 +244,74 @@ def test_batched_tier_boundaries(gpu, orc, dtype, wave_max):
     assert orc.shuffle_batched(want, off, orc.schedule_paper(6), 12, 7) == 0
     for got in results:
         assert np.array_equal(got, want)
+
+
+# ---------------------------------------------------------------------------
+# The division form (BRR_FORM_DIVISION steps; the naive two-dice shuffle)
+# ---------------------------------------------------------------------------
+
+def naive2_schedules(gpu, orc):
+    return gpu.brr_schedule_naive2(), orc.schedule_naive2()
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("tier", ["lds", "global"])
+def test_naive2_shuffle_parity(gpu, orc, dtype, tier):
+    gs, os_ = naive2_schedules(gpu, orc)
+    assert gs.forms() == os_.forms() == [1, 1] and gs.steps() == os_.segments()
+    sizes = LDS_SIZES if tier == "lds" else GLOBAL_SIZES
+    for n in sizes:
+        say("naive2 shuffle", tier, np.dtype(dtype).name, n)
+        a = np.arange(n, dtype=dtype) * 5 + 2
+        got = gpu_shuffle(gpu, a, gs, seed=4321, inst=n)
+        want = a.copy()
+        assert orc.shuffle(want, os_, 4321, n) == 0
+        assert np.array_equal(got, want), (tier, n)
+
+
+def test_mixed_form_schedule(gpu, orc):
+    """Forms change from step to step: multiply, division, multiply with a
+    guard, then the (multiply) tail batch."""
+    steps = [(5000, 1, 0), (300, 2, 0), (6, 3, 2**57)]
+    forms = [0, 1, 0]
+    gs = gpu.brr_schedule.from_steps(steps, tail=True, u_tail=720, forms=forms)
+    os_ = orc.Schedule.from_segments(steps, tail=True, u_tail=720, forms=forms)
+    for n in (7, 301, 4000, 16384, 70000):
+        say("mixed forms", n)
+        a = np.arange(n, dtype=np.uint32)
+        got = gpu_shuffle(gpu, a, gs, seed=9, inst=2)
+        want = a.copy()
+        assert orc.shuffle(want, os_, 9, 2) == 0
+        assert np.array_equal(got, want), n
+    bad = gpu.brr_schedule.from_steps([(1, 2, 0)], tail=False, forms=[2])
+    assert gpu.brr_schedule_check(bad, 100) == gpu.BRR_EINVAL
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_naive2_batched_every_tier(gpu, orc, dtype):
+    """Lane tier (every n up to 256), the wavefront and workgroup classes,
+    peel and device-wide arrays, under the division-form schedule."""
+    gs, os_ = naive2_schedules(gpu, orc)
+    sizes = np.concatenate([np.arange(258), [511, 512, 513, 2049, 4097, 8193, 16384, 16385, 40000,
+                                             (1 << 20), (1 << 20) + 1]]).astype(np.uint64)
+    say("naive2 batched", np.dtype(dtype).name)
+    data, off, results = run_batched(gpu, sizes, dtype, seed=19, inst_base=3, reps=2, sched=gs,
+                                     lane_max=256)
+    want = data.copy()
+    assert orc.shuffle_batched(want, off, os_, 19, 3) == 0
+    for got in results:
+        assert np.array_equal(got, want)
+
+
+def test_naive2_sample_parity(gpu, orc):
+    gs, os_ = naive2_schedules(gpu, orc)
+    rng = np.random.default_rng(10)
+    for n, m in ((5, 5), (1000, 100), (16384, 1638), (100003, 10000), ((1 << 21) + 1, 1000)):
+        say("naive2 sample", n, m)
+        data = rng.integers(0, 2**31, size=n).astype(np.uint64)
+        d = to_dev(data)
+        out = to_dev(np.zeros(m, np.uint64))
+        gpu.check(gpu.brr_sample(d, n, m, 8, out, gs, 33, n), "brr_sample")
+        assert gpu.brr_sync_status() == 0
+        err, want = orc.sample(data, m, os_, 33, n)
+        assert err == 0 and np.array_equal(to_host(out), want), (n, m)
