@@ -5,12 +5,15 @@ The timed step is one pass of the flat dice stream: 2^28 u32 bounds uniform
 in [1, 2^16) (seed 7) rolled k per 64-bit word (brr_dice, Theorem 1 chain +
 Algorithm 3 acceptance), inputs resident in HBM. k = 1..4 are all timed; the
 headline is the fastest batched k (2..4) unless --k fixes one, and k = 1
-(the single-roll multiply-and-reject form) is reported beside it. Secondary
-workloads report shuffled elements per second: 65,536 shuffles of 256
-elements, 20,000 ragged shuffles (also autotuned, exhaustively and by the
-learned model), one 10,000-element shuffle and one 2^26-element shuffle,
-each batched (shuffle_6) and unbatched (k = 1), and the serving loop's
-latency under Poisson load.
+(the single-roll multiply-and-reject form) is reported beside it, with the
+same stream at word width 32, in the division form of Sec. 2.1 (one roll of
+the bound product, dice by successive remainders) and with bounds below
+2^12. Secondary workloads report shuffled elements per second: 65,536
+shuffles of 256 elements, 20,000 ragged shuffles (also autotuned,
+exhaustively and by the learned model), one 10,000-element shuffle and one
+2^26-element shuffle, each batched (shuffle_6), unbatched (k = 1) and with
+the division-based pairs of the paper's comparison (naive shuffle_2), and
+the serving loop's latency under Poisson load.
 
 Prints one JSON line. Timing: HIP events recorded on the stream the kernels
 are launched on (torch's current stream), K steps after W warmup steps.
@@ -192,6 +195,8 @@ def secondary(brr, workloads, up, steps, only=None):
     out = {}
     s6 = brr.brr_schedule_paper(6)
     s1 = brr.brr_schedule_paper(1)
+    # the paper's comparisons: unbatched (k1) and two dice by division (naive2)
+    scheds = (("k6", s6), ("k1", s1), ("naive2", brr.brr_schedule_naive2()))
 
     def batched(sizes, tag):
         off = workloads.csr_offsets(sizes)
@@ -201,7 +206,7 @@ def secondary(brr, workloads, up, steps, only=None):
         sets = min(8, max(1, -(-(512 << 20) // data.nbytes)))
         ds, d_off = [up(data) for _ in range(sets)], up(off)
         res = {"buffer_sets": sets}
-        for name, sched in (("k6", s6), ("k1", s1)):
+        for name, sched in scheds:
             plans = [brr.Plan(off, 4, sched) for _ in range(sets)]
             turn = [0]
 
@@ -215,6 +220,7 @@ def secondary(brr, workloads, up, steps, only=None):
             for plan in plans:
                 plan.close()
         res["speedup_k6_vs_k1"] = res["k1"]["ms"] / res["k6"]["ms"]
+        res["speedup_k6_vs_naive2"] = res["naive2"]["ms"] / res["k6"]["ms"]
         res["hbm_frac_k6"] = 2 * 4 * data.size / (res["k6"]["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS
         out[tag] = res
 
@@ -229,11 +235,12 @@ def secondary(brr, workloads, up, steps, only=None):
             continue
         a = up(np.arange(n, dtype=np.uint32))
         res = {}
-        for name, sched in (("k6", s6), ("k1", s1)):
+        for name, sched in scheds:
             f = lambda: brr.check(brr.brr_shuffle(a, n, 4, sched, 42, 0))
             ms = time_launches(f, max(3, steps // 2), 1)
             res[name] = {"ms": ms, "elems_per_s": n / (ms * 1e-3)}
         res["speedup_k6_vs_k1"] = res["k1"]["ms"] / res["k6"]["ms"]
+        res["speedup_k6_vs_naive2"] = res["naive2"]["ms"] / res["k6"]["ms"]
         out[tag] = res
     if only in (None, "tuned"):
         out["ragged_20000_u32_tuned"] = tuned_ragged(brr, workloads, up, steps)
@@ -288,6 +295,15 @@ def main():
     def step(k):
         return lambda: brr.check(brr.brr_dice(bounds, out, COUNT, k, 7, 0), "brr_dice")
 
+    # steady state before any timing: without it the first kernel timed runs
+    # while clocks and the memory system are still ramping (k = 1 read about
+    # 20% slow when it was timed first)
+    t_end = time.perf_counter() + 0.5
+    while time.perf_counter() < t_end:
+        for _ in range(10):
+            step(2)()
+        torch.cuda.synchronize()
+
     ms_k = {k: time_launches(step(k), args.steps, args.warmup) for k in (1, 2, 3, 4)}
     # the same stream on 32-bit words (two dice per word fit: every bound
     # is below 2^16); and a stream of bounds below 2^12, under the L = 32
@@ -295,6 +311,11 @@ def main():
     ms_32 = {k: time_launches(lambda k=k: brr.check(brr.brr_dice32(bounds, out, COUNT, k, 7, 0),
                                                     "brr_dice32"), args.steps, args.warmup)
              for k in (1, 2)}
+    # the division form of Sec. 2.1 on the same stream (same words, dice by
+    # successive remainders)
+    ms_div = {k: time_launches(lambda k=k: brr.check(brr.brr_dice_div(bounds, out, COUNT, k, 7, 0),
+                                                     "brr_dice_div"), args.steps, args.warmup)
+              for k in (1, 2, 3, 4)}
     small = up(workloads.dice_bounds(COUNT, seed=8, high=1 << 12))
     ms_small = {f"L{L}_k{k}": time_launches(
         lambda L=L, k=k: brr.check((brr.brr_dice32 if L == 32 else brr.brr_dice)(
@@ -345,6 +366,9 @@ def main():
                       for k, v in ms_32.items()},
         "bounds_below_2p12": {key: {"ms": v, "rolls_per_s": COUNT / (v * 1e-3)}
                               for key, v in ms_small.items()},
+        "division_form_sweep": {str(k): {"ms": v, "rolls_per_s": COUNT / (v * 1e-3),
+                                         "multiply_form_speedup": v / ms_k[k]}
+                                for k, v in ms_div.items()},
         "ceilings": ceilings(brr, torch),
     }
     del out, bounds

@@ -103,6 +103,14 @@ def lib():
         L.orc_dice_div.restype = ctypes.c_int
         L.orc_dice_div_group.argtypes = [p, ctypes.c_uint, u64, u64, u64, u64, p]
         L.orc_dice_div_group.restype = ctypes.c_int
+        L.orc_chacha_quarter.argtypes = [p, p, p, p]
+        L.orc_chacha_quarter.restype = None
+        L.orc_chacha_block.argtypes = [p, ctypes.c_uint, p]
+        L.orc_chacha_block.restype = None
+        L.orc_word_chacha.argtypes = [u64, u64, u64]
+        L.orc_word_chacha.restype = u64
+        L.orc_dice_chacha.argtypes = [p, p, u64, ctypes.c_uint, u64, u64]
+        L.orc_dice_chacha.restype = ctypes.c_int
         L.orc_dice32.argtypes = [p, p, u64, ctypes.c_uint, u64, u64]
         L.orc_dice32.restype = ctypes.c_int
         L.orc_word32.argtypes = [u64, u64, u64]
@@ -182,6 +190,31 @@ def dice_div_group(group_bounds, S: int, s: int, seed: int, inst: int = 0):
     b = np.ascontiguousarray(group_bounds, dtype=np.uint32)
     out = np.zeros(b.size, dtype=np.uint32)
     err = lib().orc_dice_div_group(_ptr(b), b.size, S, s, seed, inst, _ptr(out))
+    return err, out
+
+
+def chacha_quarter(a: int, b: int, c: int, d: int):
+    v = [np.array([x], dtype=np.uint32) for x in (a, b, c, d)]
+    lib().orc_chacha_quarter(*[_ptr(x) for x in v])
+    return [int(x[0]) for x in v]
+
+
+def chacha_block(state, rounds: int = 20):
+    st = np.ascontiguousarray(state, dtype=np.uint32)
+    out = np.zeros(16, dtype=np.uint32)
+    lib().orc_chacha_block(_ptr(st), rounds, _ptr(out))
+    return [int(x) for x in out]
+
+
+def word_chacha(seed: int, inst: int, c: int) -> int:
+    return int(lib().orc_word_chacha(seed, inst, c))
+
+
+def dice_chacha(bounds: np.ndarray, k: int, seed: int, inst: int = 0):
+    """The dice stream with ChaCha20 words (counter mode) in place of Philox."""
+    bounds = np.ascontiguousarray(bounds, dtype=np.uint32)
+    out = np.zeros(bounds.size, dtype=np.uint32)
+    err = lib().orc_dice_chacha(_ptr(bounds), _ptr(out), bounds.size, k, seed, inst)
     return err, out
 
 

@@ -13,6 +13,8 @@
  *   - Algorithm 2 (known threshold) and Algorithm 3 (unknown)    (Sec. 5),
  *     at word width 64 and, for dice streams, 32
  *   - Algorithm 4 (batched partial shuffle with carried bound u) (Sec. 6)
+ *   - a second word source for dice streams: ChaCha20 in counter mode
+ *     (Bernstein 2008), the slow generator of the paper's experiments
  *   - the division form of batched dice: one roll of the product of the
  *     bounds, digits as successive remainders of quotients  (Sec. 2.1,
  *     and the naive batched shuffle of Appendix A)
@@ -91,6 +93,60 @@ uint64_t orc_word(uint64_t seed, uint64_t inst, uint64_t c)
 }
 
 /* ------------------------------------------------------------------ */
+/* Second word source: ChaCha in counter mode (Bernstein 2008), the     */
+/* paper's slow cryptographic generator                                */
+/* ------------------------------------------------------------------ */
+
+static uint32_t rotl32(uint32_t x, unsigned n) { return (x << n) | (x >> (32 - n)); }
+
+/* One quarter round on four state words: add, xor, rotate by 16, 12, 8, 7. */
+void orc_chacha_quarter(uint32_t *a, uint32_t *b, uint32_t *c, uint32_t *d)
+{
+    *a += *b; *d ^= *a; *d = rotl32(*d, 16);
+    *c += *d; *b ^= *c; *b = rotl32(*b, 12);
+    *a += *b; *d ^= *a; *d = rotl32(*d, 8);
+    *c += *d; *b ^= *c; *b = rotl32(*b, 7);
+}
+
+/* The block function on a full 16-word input state: `rounds` rounds (an
+ * even number; column rounds and diagonal rounds alternate), then the input
+ * added word by word. */
+void orc_chacha_block(const uint32_t in[16], unsigned rounds, uint32_t out[16])
+{
+    uint32_t x[16];
+    memcpy(x, in, sizeof x);
+    for (unsigned r = 0; r < rounds; r += 2) {
+        orc_chacha_quarter(&x[0], &x[4], &x[8], &x[12]);
+        orc_chacha_quarter(&x[1], &x[5], &x[9], &x[13]);
+        orc_chacha_quarter(&x[2], &x[6], &x[10], &x[14]);
+        orc_chacha_quarter(&x[3], &x[7], &x[11], &x[15]);
+        orc_chacha_quarter(&x[0], &x[5], &x[10], &x[15]);
+        orc_chacha_quarter(&x[1], &x[6], &x[11], &x[12]);
+        orc_chacha_quarter(&x[2], &x[7], &x[8], &x[13]);
+        orc_chacha_quarter(&x[3], &x[4], &x[9], &x[14]);
+    }
+    for (int i = 0; i < 16; ++i) out[i] = x[i] + in[i];
+}
+
+/* Word c of instance `inst` under `seed` from ChaCha20: input state = the
+ * four constant words of a 256-bit key ("expand 32-byte k"), key words
+ * (lo32 seed, hi32 seed, 0, 0, 0, 0, 0, 0), a 64-bit block counter c/8 in
+ * words 12-13 and a 64-bit nonce inst in words 14-15 (the original layout);
+ * the word is output words 2m and 2m+1 (low half first), m = c mod 8. */
+uint64_t orc_word_chacha(uint64_t seed, uint64_t inst, uint64_t c)
+{
+    const uint64_t blk = c / 8;
+    const unsigned m = (unsigned)(c % 8);
+    const uint32_t in[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u,
+                             (uint32_t)seed, (uint32_t)(seed >> 32), 0, 0, 0, 0, 0, 0,
+                             (uint32_t)blk, (uint32_t)(blk >> 32), (uint32_t)inst,
+                             (uint32_t)(inst >> 32)};
+    uint32_t out[16];
+    orc_chacha_block(in, 20, out);
+    return (uint64_t)out[2 * m] | ((uint64_t)out[2 * m + 1] << 32);
+}
+
+/* ------------------------------------------------------------------ */
 /* Theorem 1 at word width L (1..64)                                   */
 /* ------------------------------------------------------------------ */
 
@@ -158,6 +214,48 @@ static int roll_group_alg3(const uint64_t *b, unsigned k, uint64_t seed, uint64_
         }
     }
     return ORC_OK;
+}
+
+/* Algorithm 3 for one group with the ChaCha20 words (orc_word_chacha). */
+static int roll_group_chacha(const uint64_t *b, unsigned k, uint64_t seed, uint64_t inst,
+                             uint64_t S, uint64_t s, uint64_t *a)
+{
+    u128 prod;
+    const int err = bound_product(64, b, k, &prod);
+    if (err) return err;
+    uint64_t attempt = 0;
+    uint64_t r = orc_chain(64, b, k, orc_word_chacha(seed, inst, s), a);
+    if ((u128)r < prod) {
+        const uint64_t t = (uint64_t)((((u128)1) << 64) % prod);
+        while (r < t) {
+            ++attempt;
+            r = orc_chain(64, b, k, orc_word_chacha(seed, inst, attempt * S + s), a);
+        }
+    }
+    return ORC_OK;
+}
+
+/* The dice stream of orc_dice with ChaCha20 words in place of Philox (same
+ * groups, same attempt addressing). */
+int orc_dice_chacha(const uint32_t *bounds, uint32_t *out, uint64_t count, unsigned k,
+                    uint64_t seed, uint64_t inst)
+{
+    if (k == 0 || k > 64) return ORC_EINVAL;
+    const uint64_t S = ceil_div(count, k);
+    int status = ORC_OK;
+    for (uint64_t s = 0; s < S; ++s) {
+        const uint64_t first = s * k;
+        const unsigned kk = (unsigned)((count - first < k) ? count - first : k);
+        uint64_t b[64], a[64];
+        for (unsigned i = 0; i < kk; ++i) b[i] = bounds[first + i];
+        const int err = roll_group_chacha(b, kk, seed, inst, S, s, a);
+        if (err) {
+            if (!status) status = err;
+            continue;
+        }
+        for (unsigned i = 0; i < kk; ++i) out[first + i] = (uint32_t)a[i];
+    }
+    return status;
 }
 
 /* Group g holds bounds[g*k .. g*k+k-1]; the last group keeps count mod k

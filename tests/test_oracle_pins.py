@@ -659,3 +659,68 @@ def test_mixed_form_schedule_and_bad_form(orc):
     assert np.array_equal(np.sort(z), np.arange(3000, dtype=np.uint32))
     bad = orc.Schedule.from_segments([(1, 2, 0)], tail=False, forms=[2])
     assert orc.shuffle(np.arange(10, dtype=np.uint32), bad, 1, 0) == 1
+
+
+# ---------------------------------------------------------------------------
+# ChaCha20 words (counter mode), the paper's slow generator
+# ---------------------------------------------------------------------------
+
+def test_chacha_known_answers(orc):
+    """RFC 8439 Sec. 2.1.1 (quarter round) and Sec. 2.3.2 (block function)."""
+    for row in golden_rows("chacha20_rfc8439.txt"):
+        kind, rest = row.split(None, 1)
+        inp, outp = [[int(x, 16) for x in part.split()] for part in rest.split("|")]
+        if kind == "quarter":
+            assert orc.chacha_quarter(*inp) == outp
+        else:
+            assert orc.chacha_block(inp, 20) == outp
+
+
+def test_chacha_word_layout(orc):
+    """Word c is output words 2(c mod 8), 2(c mod 8)+1 of block c/8 of the
+    state (constants, key = seed, 64-bit counter, 64-bit nonce = inst)."""
+    seed, inst = 0x0123456789ABCDEF, 0xFEDCBA9876543210
+    for blk in (0, 1, 2**32 + 5):
+        st = [0x61707865, 0x3320646e, 0x79622d32, 0x6b206574, seed & 0xFFFFFFFF, seed >> 32,
+              0, 0, 0, 0, 0, 0, blk & 0xFFFFFFFF, blk >> 32, inst & 0xFFFFFFFF, inst >> 32]
+        out = orc.chacha_block(st, 20)
+        for m in range(8):
+            assert orc.word_chacha(seed, inst, 8 * blk + m) == out[2 * m] | (out[2 * m + 1] << 32)
+
+
+def _chacha_words(orc, seed, inst, S, g):
+    a = 0
+    while True:
+        yield orc.word_chacha(seed, inst, a * S + g)
+        a += 1
+
+
+def test_k1_chacha_dice_is_lemire(orc):
+    rng = np.random.default_rng(8)
+    bounds = np.concatenate([rng.integers(1, 1 << 32, size=200, dtype=np.uint64),
+                             np.array([1, 2, 2**31 + 1, 2**32 - 1], dtype=np.uint64)]).astype(np.uint32)
+    err, out = orc.dice_chacha(bounds, 1, seed=31, inst=2)
+    assert err == 0
+    for g, b in enumerate(bounds):
+        assert out[g] == ref.lemire(64, int(b), _chacha_words(orc, 31, 2, bounds.size, g))[0]
+
+
+@pytest.mark.parametrize("k,bits", [(2, 32), (3, 21), (4, 16)])
+def test_chacha_dice_follow_theorem1(orc, k, bits):
+    rng = np.random.default_rng(40 + k)
+    count = 500 * k + k - 1
+    bounds = rng.integers(1 << (bits - 1), 1 << bits, size=count, dtype=np.uint64).astype(np.uint32)
+    err, out = orc.dice_chacha(bounds, k, seed=5, inst=8)
+    assert err == 0
+    S = -(-count // k)
+    rerolled = 0
+    for g in range(S):
+        b = [int(x) for x in bounds[g * k:(g + 1) * k]]
+        for att, r0 in enumerate(_chacha_words(orc, 5, 8, S, g)):
+            a, rk = ref.chain(64, b, r0)
+            if ref.accept(64, b, rk):
+                break
+        rerolled += att > 0
+        assert list(out[g * k:g * k + len(b)]) == a
+    if bits == 32:
+        assert rerolled > 0
