@@ -316,11 +316,19 @@ def main():
     ms_div = {k: time_launches(lambda k=k: brr.check(brr.brr_dice_div(bounds, out, COUNT, k, 7, 0),
                                                      "brr_dice_div"), args.steps, args.warmup)
               for k in (1, 2, 3, 4)}
+    # ChaCha20 words (the paper's slow generator): batching saves words
+    ms_cc = {k: time_launches(lambda k=k: brr.check(brr.brr_dice_chacha(bounds, out, COUNT, k, 7, 0),
+                                                    "brr_dice_chacha"), args.steps, args.warmup)
+             for k in (1, 2, 3, 4)}
     small = up(workloads.dice_bounds(COUNT, seed=8, high=1 << 12))
     ms_small = {f"L{L}_k{k}": time_launches(
         lambda L=L, k=k: brr.check((brr.brr_dice32 if L == 32 else brr.brr_dice)(
             small, out, COUNT, k, 8, 0), "dice"), args.steps, args.warmup)
         for L, k in ((64, 1), (64, 2), (32, 1), (32, 2))}
+    # ChaCha20 words on these bounds: k = 4 rarely rerolls here
+    ms_small.update({f"chacha20_k{k}": time_launches(
+        lambda k=k: brr.check(brr.brr_dice_chacha(small, out, COUNT, k, 8, 0), "brr_dice_chacha"),
+        args.steps, args.warmup) for k in (1, 2, 3, 4)})
     del small
     brr.check(brr.brr_sync_status(), "device status")
     k_head = min((2, 3, 4), key=lambda k: ms_k[k]) if args.k == "best" else int(args.k)
@@ -366,6 +374,10 @@ def main():
                       for k, v in ms_32.items()},
         "bounds_below_2p12": {key: {"ms": v, "rolls_per_s": COUNT / (v * 1e-3)}
                               for key, v in ms_small.items()},
+        "chacha20_sweep": {str(k): {"ms": v, "rolls_per_s": COUNT / (v * 1e-3),
+                                    "speedup_vs_k1": ms_cc[1] / v,
+                                    "hbm_frac": BYTES_PER_ROLL * COUNT / (v * 1e-3) / 1e9 / PEAK_HBM_GBS}
+                           for k, v in ms_cc.items()},
         "division_form_sweep": {str(k): {"ms": v, "rolls_per_s": COUNT / (v * 1e-3),
                                          "multiply_form_speedup": v / ms_k[k]}
                                 for k, v in ms_div.items()},

@@ -186,6 +186,18 @@ brr_status brr_dice_const(uint32_t bound, uint32_t *d_out, uint64_t count, uint3
 brr_status brr_dice_div(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
                         uint64_t seed, uint64_t inst, void *stream);
 
+/* The dice stream of brr_dice with a second word source: ChaCha20
+ * (Bernstein 2008) in counter mode, the slow cryptographic generator of the
+ * paper's experiments (Sec. 7). Word c of instance `inst` under `seed` is
+ * output words 2m, 2m+1 (low half first, m = c mod 8) of ChaCha20 block c/8,
+ * whose input state holds the four constant words, key words
+ * (lo32 seed, hi32 seed, 0, 0, 0, 0, 0, 0), the 64-bit block counter c/8 in
+ * words 12-13 and the 64-bit nonce inst in words 14-15. Dice, acceptance,
+ * attempt addressing (attempt a of group s reads word a*S + s), arguments
+ * and errors as brr_dice. */
+brr_status brr_dice_chacha(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
+                           uint64_t seed, uint64_t inst, void *stream);
+
 /* The dice stream of brr_dice at word width L = 32 (Theorem 1 holds for any
  * L, Sec. 4): each group is rolled from one 32-bit word with one 32x32 ->
  * 64-bit multiply per die, and accepted when the leftover is at least

@@ -31,7 +31,7 @@ EXPORTS = (
     "brr_mlp_get_params", "brr_mlp_set_params", "brr_mlp_get_grads", "brr_mlp_forward",
     "brr_mlp_backward", "brr_mlp_adam_step", "brr_mlp_train", "brr_plan_features",
     "brr_plan_autotune_learned", "brr_probe_chain_rate", "brr_dice32", "brr_dice_div",
-    "brr_schedule_naive2",
+    "brr_schedule_naive2", "brr_dice_chacha",
 )
 BRR_PLAN_FEATURES = 16
 BRR_REQ_SHUFFLE, BRR_REQ_SAMPLE = 1, 2
@@ -123,6 +123,7 @@ def _load():
         "brr_dice_const": (st, [u32, p, u64, u32, u64, u64, p]),
         "brr_dice32": (st, [p, p, u64, u32, u64, u64, p]),
         "brr_dice_div": (st, [p, p, u64, u32, u64, u64, p]),
+        "brr_dice_chacha": (st, [p, p, u64, u32, u64, u64, p]),
         "brr_shuffle": (st, [p, u64, u32, sched_p, u64, u64, p]),
         "brr_plan_create": (st, [ctypes.POINTER(p), p, u64, u32, sched_p]),
         "brr_plan_destroy": (None, [p]),
@@ -256,6 +257,10 @@ def brr_dice32(bounds, out, count: int, k: int, seed: int, inst: int = 0, stream
 
 def brr_dice_div(bounds, out, count: int, k: int, seed: int, inst: int = 0, stream=None) -> int:
     return lib.brr_dice_div(_addr(bounds), _addr(out), count, k, seed, inst, _stream(stream))
+
+
+def brr_dice_chacha(bounds, out, count: int, k: int, seed: int, inst: int = 0, stream=None) -> int:
+    return lib.brr_dice_chacha(_addr(bounds), _addr(out), count, k, seed, inst, _stream(stream))
 
 
 def brr_dice_const(bound: int, out, count: int, k: int, seed: int, inst: int = 0,

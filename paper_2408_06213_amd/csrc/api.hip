@@ -540,6 +540,19 @@ brr_status brr_dice_div(const uint32_t *d_bounds, uint32_t *d_out, uint64_t coun
                                       static_cast<hipStream_t>(stream)));
 }
 
+brr_status brr_dice_chacha(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
+                           uint64_t seed, uint64_t inst, void *stream)
+{
+    if (k < 1 || k > 8) return BRR_EINVAL;
+    if (count == 0) return BRR_OK;
+    if (!d_bounds || !d_out || misaligned(d_bounds, 4) || misaligned(d_out, 4)) return BRR_EINVAL;
+    uint32_t *status = nullptr;
+    const brr_status st = device_ready(&status);
+    if (st != BRR_OK) return st;
+    return hip_status(launch_dice_chacha(d_bounds, d_out, count, k, make_key(seed, inst), status,
+                                         static_cast<hipStream_t>(stream)));
+}
+
 brr_status brr_dice32(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
                       uint64_t seed, uint64_t inst, void *stream)
 {

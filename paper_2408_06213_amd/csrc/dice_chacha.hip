@@ -1,0 +1,337 @@
+// Dice streams with ChaCha20 words (Bernstein 2008, counter mode): the slow
+// cryptographic generator of the paper's experiments (Sec. 7), where one
+// word costs far more than the dice drawn from it, so batching k dice per
+// word approaches a k-fold saving. The dice themselves follow Theorem 1 and
+// Algorithm 3 exactly as in brr_dice; only the word source differs.
+//
+// Word c of instance `inst` under `seed`: block c/8 of ChaCha20 with key
+// words (lo32 seed, hi32 seed, 0, 0, 0, 0, 0, 0), the 64-bit block counter
+// in state words 12-13 and the 64-bit nonce inst in words 14-15; the word is
+// output words 2m, 2m+1 (low half first), m = c mod 8. Attempt a of group s
+// reads word a*S + s.
+//
+// Work mapping, as for the Philox stream: a wavefront owns a tile of 64 x 8
+// groups and lane L takes groups g0 + 64j + L (j < 8), so that every load
+// and store instruction covers one contiguous span. The eight lanes of an
+// octet hold eight consecutive groups per j, which share one ChaCha block:
+// lane q of the octet computes the block of slot j = q, and an 8 x 8
+// transpose in registers (three exchange stages, partners q ^ 1, q ^ 2,
+// q ^ 4) hands every lane its word of all eight blocks. Rerolls are
+// compacted: each pass computes one block per lane, for the lowest group of
+// that lane still rejected, so a pass costs one block however many of the
+// lane's groups are pending.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace brr {
+
+namespace {
+
+constexpr uint64_t kMaxAttemptsChaCha = 1024;
+constexpr int kWordsPerBlock = 8;
+
+__device__ __forceinline__ uint32_t rotl32(uint32_t x, int n)
+{
+    return __builtin_amdgcn_alignbit(x, x, 32 - n); // rotate right by 32 - n
+}
+
+__device__ __forceinline__ void quarter(uint32_t &a, uint32_t &b, uint32_t &c, uint32_t &d)
+{
+    a += b;
+    d = rotl32(d ^ a, 16);
+    c += d;
+    b = rotl32(b ^ c, 12);
+    a += b;
+    d = rotl32(d ^ a, 8);
+    c += d;
+    b = rotl32(b ^ c, 7);
+}
+
+// The 16 output words of block `blk` (20 rounds: ten column/diagonal pairs,
+// then the input state added back).
+__device__ __forceinline__ void chacha20_block(const StreamKey &key, uint64_t blk,
+                                               uint32_t (&x)[16])
+{
+    const uint32_t in[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u,
+                             key.seed_lo, key.seed_hi, 0u, 0u, 0u, 0u, 0u, 0u,
+                             (uint32_t)blk, (uint32_t)(blk >> 32), key.inst_lo, key.inst_hi};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = in[i];
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        quarter(x[0], x[4], x[8], x[12]);
+        quarter(x[1], x[5], x[9], x[13]);
+        quarter(x[2], x[6], x[10], x[14]);
+        quarter(x[3], x[7], x[11], x[15]);
+        quarter(x[0], x[5], x[10], x[15]);
+        quarter(x[1], x[6], x[11], x[12]);
+        quarter(x[2], x[7], x[8], x[13]);
+        quarter(x[3], x[4], x[9], x[14]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] += in[i];
+}
+
+// Word c alone (rerolls only; kept out of line so that each kernel holds one
+// copy of the rounds for it).
+__device__ __noinline__ uint64_t chacha_word_at(uint64_t c, StreamKey key)
+{
+    uint32_t x[16];
+    chacha20_block(key, c / kWordsPerBlock, x);
+    const uint32_t m = (uint32_t)(c % kWordsPerBlock);
+    uint64_t w = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kWordsPerBlock; ++j)
+        if (j == m) w = (uint64_t)x[2 * j] | ((uint64_t)x[2 * j + 1] << 32);
+    return w;
+}
+
+// Value of lane L ^ D (D = 1, 2: quad DPP; D = 4: through the LDS crossbar).
+template <int D> __device__ __forceinline__ uint32_t from_lane_xor(uint32_t v)
+{
+    if (D == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    if (D == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    return (uint32_t)__shfl_xor((int)v, D, 64);
+}
+
+// One exchange stage of the octet transpose: for each index pair (i, i + D)
+// (bit D of i clear), a lane keeps the element whose index bit D equals its
+// lane bit D and swaps the other with lane L ^ D.
+template <int D> __device__ __forceinline__ void exchange(uint32_t (&lo)[8], uint32_t (&hi)[8],
+                                                          bool bit)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (i & D) continue;
+        const uint32_t rlo = from_lane_xor<D>(bit ? lo[i] : lo[i + D]);
+        const uint32_t rhi = from_lane_xor<D>(bit ? hi[i] : hi[i + D]);
+        if (bit) {
+            lo[i] = rlo;
+            hi[i] = rhi;
+        } else {
+            lo[i + D] = rlo;
+            hi[i + D] = rhi;
+        }
+    }
+}
+
+// First-attempt words of this lane's groups g0 + 64j + lane, j = 0..7.
+__device__ __forceinline__ void tile_words_chacha(uint64_t g0, uint32_t lane, const StreamKey &key,
+                                                  uint64_t (&r)[8])
+{
+    const uint32_t q = lane & 7, o = lane >> 3;
+    // block of slot j = q for groups g0 + 64q + 8o + m, m = 0..7
+    uint32_t x[16];
+    chacha20_block(key, g0 / kWordsPerBlock + 8 * q + o, x);
+    uint32_t lo[8], hi[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        lo[m] = x[2 * m];
+        hi[m] = x[2 * m + 1];
+    }
+    exchange<1>(lo, hi, lane & 1);
+    exchange<2>(lo, hi, lane & 2);
+    exchange<4>(lo, hi, lane & 4);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = (uint64_t)lo[j] | ((uint64_t)hi[j] << 32);
+}
+
+template <int K, bool VEC>
+__device__ __forceinline__ void load_group(const uint32_t *__restrict__ p, uint32_t *b)
+{
+    if (VEC && K == 4) {
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        b[0] = v.x;
+        b[1] = v.y;
+        b[2] = v.z;
+        b[3] = v.w;
+    } else if (VEC && K == 2) {
+        const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+        b[0] = v.x;
+        b[1] = v.y;
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) b[i] = __builtin_nontemporal_load(p + i);
+    }
+}
+
+template <int K, bool VEC>
+__device__ __forceinline__ void store_group(uint32_t *__restrict__ p, const uint32_t *a)
+{
+    if (VEC && K == 4) {
+        const u32x4 v = {a[0], a[1], a[2], a[3]};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+    } else if (VEC && K == 2) {
+        const u32x2 v = {a[0], a[1]};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(p));
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) __builtin_nontemporal_store(a[i], p + i);
+    }
+}
+
+// The chain on word r for one group: dice into a, returns the leftover.
+template <int K>
+__device__ __forceinline__ uint64_t chain(const uint32_t *b, int kk, uint32_t *a, uint64_t r)
+{
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < kk) a[i] = mul_roll(b[i], r);
+    return r;
+}
+
+// Lemire's threshold of the group's product, or 0 when the leftover rr
+// already accepts (r >= P > t, or P = 2^64); flags bad groups in err.
+template <int K>
+__device__ __forceinline__ uint64_t group_threshold(const uint32_t *b, int kk, uint64_t rr,
+                                                    uint32_t &err)
+{
+    BoundProduct P;
+    P.init(b[0]);
+#pragma unroll
+    for (int i = 1; i < K; ++i)
+        if (i < kk) P.mul(b[i]);
+    if (P.zero) {
+        err |= kDevZeroBound;
+        return 0;
+    }
+    if (P.over) {
+        err |= kDevOverflow;
+        return 0;
+    }
+    if (P.e64 || rr >= P.p) return 0;
+    return pow2_64_mod(P.p);
+}
+
+// Dice count of group g (K, the short last group's count, or 0 past it).
+template <int K>
+__device__ __forceinline__ int group_dice(uint64_t g, uint64_t full, uint64_t S, uint64_t count)
+{
+    return (g < full) ? K : (g < S ? (int)(count - (uint64_t)K * g) : 0);
+}
+
+template <int K, bool VEC>
+__device__ __forceinline__ void load_bounds(const uint32_t *__restrict__ bounds, uint64_t g, int kk,
+                                            bool whole, uint32_t *b)
+{
+    if (whole) {
+        load_group<K, VEC>(bounds + (uint64_t)K * g, b);
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) b[i] = (i < kk) ? bounds[(uint64_t)K * g + i] : 1u;
+    }
+}
+
+template <int K, bool VEC>
+__device__ __forceinline__ void store_dice(uint32_t *__restrict__ out, uint64_t g, int kk,
+                                           bool whole, const uint32_t *a)
+{
+    if (whole) {
+        store_group<K, VEC>(out + (uint64_t)K * g, a);
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (i < kk) out[(uint64_t)K * g + i] = a[i];
+    }
+}
+
+// Registers: the eight words (16) stay live from the transpose to the last
+// group; each group's bounds are loaded after the rounds, when it is rolled
+// (holding all 8K bounds through the rounds cost more in resident
+// wavefronts than it saved in latency: k = 2 took 0.76 ms that way, 0.57 ms
+// this way). A rejected group is left for the reroll passes, which reload
+// its bounds.
+template <int K, bool VEC>
+__global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__restrict__ bounds,
+                                                          uint32_t *__restrict__ out,
+                                                          uint64_t count, uint64_t S,
+                                                          uint64_t full, StreamKey key,
+                                                          uint32_t *status)
+{
+    constexpr int G = 8; // groups per lane
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t g0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * G);
+    if (g0 >= S) return; // the whole wavefront leaves together
+    const bool whole = g0 + 64 * G <= full; // every group of the tile has K dice
+    uint64_t r[G];
+    tile_words_chacha(g0, lane, key, r);
+    uint32_t err = 0, pending = 0;
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+        const uint64_t g = g0 + 64 * j + lane;
+        const int kk = group_dice<K>(g, full, S, count);
+        if (kk == 0) continue;
+        uint32_t b[K], a[K];
+        load_bounds<K, VEC>(bounds, g, kk, whole, b);
+        const uint64_t rr = chain<K>(b, kk, a, r[j]);
+        if (rr < group_threshold<K>(b, kk, rr, err))
+            pending |= 1u << j;
+        else
+            store_dice<K, VEC>(out, g, kk, whole, a);
+    }
+    // rerolls, compacted: a lane works on its lowest pending group; each
+    // attempt is rejected with probability t / 2^64 < 1/2 and the cap only
+    // bounds the loop against corrupted inputs
+    uint64_t attempt = 1;
+    while (__any(pending != 0)) {
+        if (pending) {
+            const int m = __builtin_ctz(pending);
+            const uint64_t g = g0 + 64 * (uint64_t)m + lane;
+            const int kk = group_dice<K>(g, full, S, count);
+            uint32_t b[K], a[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) b[i] = (i < kk) ? bounds[(uint64_t)K * g + i] : 1u;
+            const uint64_t rr = chain<K>(b, kk, a, chacha_word_at(attempt * S + g, key));
+            uint32_t e = 0;
+            if (rr >= group_threshold<K>(b, kk, rr, e) || attempt >= kMaxAttemptsChaCha) {
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+                    if (i < kk) out[(uint64_t)K * g + i] = a[i];
+                pending &= pending - 1;
+                attempt = 1;
+            } else {
+                ++attempt;
+            }
+        }
+    }
+    if (err) atomicOr(status, err);
+}
+
+template <int K>
+hipError_t launch_dice_chacha_k(const uint32_t *bounds, uint32_t *out, uint64_t count,
+                                StreamKey key, uint32_t *status, hipStream_t stream)
+{
+    const uint64_t S = (count + K - 1) / K;
+    const uint64_t full = count / K;
+    const uint64_t waves = (S + 64 * 8 - 1) / (64 * 8); // 8 groups per lane
+    const uint64_t blocks = (waves + 3) / 4;           // 4 wavefronts per block
+    if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    const bool vec = ((((uintptr_t)bounds) | ((uintptr_t)out)) & 15) == 0;
+    if (vec)
+        dice_chacha_kernel<K, true><<<(uint32_t)blocks, 256, 0, stream>>>(bounds, out, count, S,
+                                                                          full, key, status);
+    else
+        dice_chacha_kernel<K, false><<<(uint32_t)blocks, 256, 0, stream>>>(bounds, out, count, S,
+                                                                           full, key, status);
+    return hipGetLastError();
+}
+
+} // namespace
+
+hipError_t launch_dice_chacha(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
+                              StreamKey key, uint32_t *status, hipStream_t stream)
+{
+    switch (k) {
+    case 1: return launch_dice_chacha_k<1>(bounds, out, count, key, status, stream);
+    case 2: return launch_dice_chacha_k<2>(bounds, out, count, key, status, stream);
+    case 3: return launch_dice_chacha_k<3>(bounds, out, count, key, status, stream);
+    case 4: return launch_dice_chacha_k<4>(bounds, out, count, key, status, stream);
+    case 5: return launch_dice_chacha_k<5>(bounds, out, count, key, status, stream);
+    case 6: return launch_dice_chacha_k<6>(bounds, out, count, key, status, stream);
+    case 7: return launch_dice_chacha_k<7>(bounds, out, count, key, status, stream);
+    case 8: return launch_dice_chacha_k<8>(bounds, out, count, key, status, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+} // namespace brr

@@ -123,6 +123,9 @@ hipError_t launch_dice_const(uint32_t bound, uint32_t *out, uint64_t count, uint
 // The dice stream in the division form (dice.hip).
 hipError_t launch_dice_div(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
                            StreamKey key, uint32_t *status, hipStream_t stream);
+// The dice stream with ChaCha20 words (dice_chacha.hip).
+hipError_t launch_dice_chacha(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
+                              StreamKey key, uint32_t *status, hipStream_t stream);
 // The dice stream at word width 32 (dice32.hip).
 hipError_t launch_dice32(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
                          StreamKey key, uint32_t *status, hipStream_t stream);

@@ -245,3 +245,60 @@ def test_dice_div_edge_cases(gpu, orc):
     st, _ = run_dice_div(gpu, np.array([5, 0, 3, 4], np.uint32), 2, 1, 0)
     assert st == gpu.BRR_EINVAL
     assert gpu.brr_sync_status() == 0
+
+
+# ---------------------------------------------------------------------------
+# ChaCha20 words (brr_dice_chacha)
+# ---------------------------------------------------------------------------
+
+def run_dice_chacha(gpu, bounds_np, k, seed, inst, offset=0):
+    n = bounds_np.size
+    b = to_dev(np.concatenate([np.zeros(offset, np.uint32), bounds_np]))
+    out = to_dev(np.zeros(n + offset, np.uint32))
+    gpu.check(gpu.brr_dice_chacha(b.data_ptr() + 4 * offset, out.data_ptr() + 4 * offset, n, k,
+                                  seed, inst), "brr_dice_chacha")
+    st = gpu.brr_sync_status()
+    return st, to_host(out)[offset:]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_dice_chacha_parity_ragged_counts(gpu, orc, k):
+    """Bounds in the upper half of their width (rerolls); counts around the
+    8-group lane tiles and the 256-lane blocks, short last groups."""
+    rng = np.random.default_rng(700 + k)
+    hi = 1 << BITS64[k]
+    for count in (1, 3, 8 * k - 1, 8 * k + 1, 2048 * k + 5, 1000 + 7, 65536 + 3, 300001):
+        say("dice_chacha", k, count)
+        bounds = rng.integers(max(1, hi // 2), hi, size=count, dtype=np.uint64).astype(np.uint32)
+        st, got = run_dice_chacha(gpu, bounds, k, seed=23, inst=4)
+        err, want = orc.dice_chacha(bounds, k, 23, 4)
+        assert st == 0 and err == 0
+        assert np.array_equal(got, want), (k, count)
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_dice_chacha_unaligned_buffers(gpu, orc, k):
+    rng = np.random.default_rng(800 + k)
+    bounds = rng.integers(1, 1 << BITS64[k], size=5003, dtype=np.uint64).astype(np.uint32)
+    say("dice_chacha unaligned", k)
+    st, got = run_dice_chacha(gpu, bounds, k, seed=6, inst=1, offset=1)
+    assert st == 0
+    assert np.array_equal(got, orc.dice_chacha(bounds, k, 6, 1)[1])
+
+
+def test_dice_chacha_edge_cases(gpu, orc):
+    b = np.full(4 * 999, 1 << 16, np.uint32)  # product 2^64
+    st, got = run_dice_chacha(gpu, b, 4, seed=3, inst=0)
+    assert st == 0 and np.array_equal(got, orc.dice_chacha(b, 4, 3, 0)[1])
+    b = np.tile(np.array([2**31 + 1, 2**32 - 1], np.uint32), 5000)  # about half rejected
+    st, got = run_dice_chacha(gpu, b, 2, seed=4, inst=1)
+    assert st == 0 and np.array_equal(got, orc.dice_chacha(b, 2, 4, 1)[1])
+    b = workloads.dice_bounds(100003, seed=7)
+    for k in (1, 2, 3, 4):
+        st, got = run_dice_chacha(gpu, b, k, seed=7, inst=0)
+        assert st == 0 and np.array_equal(got, orc.dice_chacha(b, k, 7, 0)[1]), k
+    st, _ = run_dice_chacha(gpu, np.array([2**32 - 1] * 6, np.uint32), 3, 1, 0)
+    assert st == gpu.BRR_EOVERFLOW
+    st, _ = run_dice_chacha(gpu, np.array([5, 0, 3, 4], np.uint32), 2, 1, 0)
+    assert st == gpu.BRR_EINVAL
+    assert gpu.brr_sync_status() == 0
