@@ -117,6 +117,10 @@ def lib():
         L.orc_word32.restype = ctypes.c_uint32
         L.orc_dice_const.argtypes = [u32, p, u64, ctypes.c_uint, u64, u64]
         L.orc_dice_const.restype = ctypes.c_int
+        L.orc_schedule_kmax.argtypes = [ctypes.c_uint, ctypes.POINTER(Schedule)]
+        L.orc_schedule_kmax.restype = ctypes.c_int
+        L.orc_dice_tuple.argtypes = [p, ctypes.c_uint, p, u64, u64, u64]
+        L.orc_dice_tuple.restype = ctypes.c_int
         L.orc_schedule_paper.argtypes = [ctypes.c_int, ctypes.POINTER(Schedule)]
         L.orc_schedule_paper.restype = ctypes.c_int
         L.orc_count_batches.argtypes = [u64, u64, ctypes.POINTER(Schedule)]
@@ -250,6 +254,22 @@ def schedule_paper(max_k: int) -> Schedule:
     if err:
         raise ValueError(f"no paper schedule for max_k={max_k}")
     return s
+
+
+def schedule_kmax(kcap: int) -> Schedule:
+    """The greedy largest-batch schedule with at most kcap dice per batch."""
+    s = Schedule()
+    if lib().orc_schedule_kmax(kcap, ctypes.byref(s)):
+        raise ValueError(f"no KMAX schedule for kcap={kcap}")
+    return s
+
+
+def dice_tuple(tuple_bounds, count: int, seed: int, inst: int = 0):
+    """Algorithm 2 for a fixed tuple of bounds: out[j] in [0, tuple[j mod k])."""
+    t = np.ascontiguousarray(tuple_bounds, dtype=np.uint32)
+    out = np.zeros(count, dtype=np.uint32)
+    err = lib().orc_dice_tuple(_ptr(t), t.size, _ptr(out), count, seed, inst)
+    return err, out
 
 
 def count_batches(n: int, steps: int, sched: Schedule) -> int:

@@ -457,6 +457,39 @@ int orc_dice_const(uint32_t bound, uint32_t *out, uint64_t count, unsigned k, ui
     return ORC_OK;
 }
 
+/* Algorithm 2 for a fixed tuple of k bounds known ahead of time: the
+ * threshold t = 2^64 mod (b_1 ... b_k) is computed once (and once more for
+ * a short last group holding the first count mod k bounds of the tuple);
+ * each group repeats the chain on its next word until the leftover is at
+ * least t. out[j] is the die rolled against tuple[j mod k]. */
+int orc_dice_tuple(const uint32_t *tuple, unsigned k, uint32_t *out, uint64_t count,
+                   uint64_t seed, uint64_t inst)
+{
+    if (k == 0 || k > 64) return ORC_EINVAL;
+    uint64_t b[64], a[64];
+    for (unsigned i = 0; i < k; ++i) b[i] = tuple[i];
+    uint64_t t_full = 0, t_last = 0;
+    int err = orc_threshold(64, b, k, &t_full);
+    if (err) return err;
+    const uint64_t S = ceil_div(count, k);
+    const unsigned k_last = (unsigned)(count - (S ? (S - 1) * k : 0));
+    if (S) {
+        err = orc_threshold(64, b, k_last, &t_last);
+        if (err) return err;
+    }
+    for (uint64_t s = 0; s < S; ++s) {
+        const unsigned kk = (s + 1 == S) ? k_last : k;
+        const uint64_t t = (s + 1 == S) ? t_last : t_full;
+        uint64_t attempt = 0, r;
+        do {
+            r = orc_chain(64, b, kk, orc_word(seed, inst, attempt * S + s), a);
+            ++attempt;
+        } while (r < t);
+        for (unsigned i = 0; i < kk; ++i) out[s * k + i] = (uint32_t)a[i];
+    }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* Shuffles: Algorithm 4 batches under a batch-size schedule           */
 /* ------------------------------------------------------------------ */
@@ -532,6 +565,41 @@ static u128 falling(uint64_t n, unsigned k)
         if (p > cap) return cap;
     }
     return p;
+}
+
+/* The greedy largest-batch schedule (KMAX): while i elements remain, roll
+ * the largest k <= kcap whose batch product i (i-1) ... (i-k+1) fits in one
+ * 64-bit word (Theorem 1 needs the product at most 2^64). With N_k the
+ * largest n whose k-th falling power is at most 2^64, that is k dice while
+ * N_{k+1} < i <= N_k; each segment is guarded by the product at its top,
+ * N_k^(falling k). Batches of kcap dice run while more than kcap - 1
+ * elements remain and a last batch of i - 1 dice ends the shuffle. Each N_k
+ * comes from a bisection on the exact falling power. */
+int orc_schedule_kmax(unsigned kcap, orc_schedule *out)
+{
+    if (kcap < 1 || kcap > 16) return ORC_EINVAL;
+    memset(out, 0, sizeof *out);
+    const u128 two64 = (u128)1 << 64;
+    uint64_t N[18] = {0};
+    for (unsigned k = 2; k <= kcap + 1 && k <= 17; ++k) {
+        uint64_t lo = k, hi = (uint64_t)1 << 33; /* falling(lo) <= 2^64 < falling(hi) */
+        while (hi - lo > 1) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (falling(mid, k) <= two64) lo = mid; else hi = mid;
+        }
+        N[k] = lo;
+    }
+    unsigned g = 0;
+    for (unsigned k = 1; k <= kcap; ++k) {
+        out->k[g] = k;
+        out->thr[g] = (k < kcap) ? N[k + 1] : kcap - 1;
+        out->u[g] = (k == 1) ? 0 : (uint64_t)falling(N[k], k);
+        ++g;
+    }
+    out->nseg = g;
+    out->tail = 1;
+    out->u_tail = 0;
+    return ORC_OK;
 }
 
 typedef struct {

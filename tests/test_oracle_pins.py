@@ -724,3 +724,77 @@ def test_chacha_dice_follow_theorem1(orc, k, bits):
         assert list(out[g * k:g * k + len(b)]) == a
     if bits == 32:
         assert rerolled > 0
+
+
+# ---------------------------------------------------------------------------
+# Known-threshold specialisations (Algorithm 2) and the KMAX schedule
+# ---------------------------------------------------------------------------
+
+def _falling(n, k):
+    return math.prod(range(n - k + 1, n + 1))
+
+
+@pytest.mark.parametrize("kcap", [2, 4, 6, 8])
+def test_kmax_schedule_thresholds(orc, kcap):
+    """N_k is the largest n whose k-th falling power fits in 2^64 (checked
+    with exact integers); k dice run while N_{k+1} < i <= N_k, each segment
+    guarded by N_k^(falling k)."""
+    s = orc.schedule_kmax(kcap)
+    segs = s.segments()
+    assert [k for _, k, _ in segs] == list(range(1, kcap + 1)) and s.tail == 1
+    for idx, (thr, k, u) in enumerate(segs[:-1]):
+        n = thr  # N_{k+1}
+        assert _falling(n, k + 1) <= TWO64 < _falling(n + 1, k + 1), (k + 1, n)
+        if k > 1:
+            top = segs[idx - 1][0]  # N_k
+            assert u == _falling(top, k)
+    assert segs[-1][0] == kcap - 1
+
+
+@pytest.mark.parametrize("kcap", [3, 8])
+def test_kmax_batches_are_maximal(orc, kcap):
+    """Walking the schedule: every batch fits (product <= 2^64) and, above
+    the last segment, one more die would not fit or k is at its cap."""
+    s = orc.schedule_kmax(kcap)
+    segs = s.segments()
+    for n in (5, 8, 9, 259, 260, 567, 568, 569, 1627, 1628, 7133, 7134, 65537, 65538, 100000):
+        i = n
+        for thr, k, _ in segs:
+            while i > thr:
+                assert _falling(i, k) <= TWO64
+                assert k == kcap or _falling(i, k + 1) > TWO64, (n, i, k)
+                i -= k
+        assert i <= kcap - 1
+
+
+@pytest.mark.parametrize("n", [2, 9, 300, 2000, 70000])
+def test_kmax_shuffle_is_fisher_yates(orc, n):
+    sched = orc.schedule_kmax(8)
+    z = np.arange(n, dtype=np.uint32)
+    assert orc.shuffle(z, sched, seed=29, inst=n) == 0
+    assert list(z) == ref.fisher_yates(range(n), _dice_for_shuffle(orc, n, sched, 29, n))
+
+
+def test_dice_tuple_is_alg3_on_the_tiled_bounds(orc):
+    """A fixed tuple (threshold known, Algorithm 2) rolls what Algorithm 3
+    rolls on the same bounds written out group by group, short last group
+    included."""
+    for tup, count in (([4, 6, 8, 20], 4001), ([2**31 + 1, 2**32 - 1], 999), ([6], 500),
+                       ([3, 5, 7, 11, 13, 17, 19], 7 * 300 + 3)):
+        err, got = orc.dice_tuple(tup, count, seed=14, inst=3)
+        tiled = np.resize(np.array(tup, dtype=np.uint32), count)
+        e2, want = orc.dice(tiled, len(tup), 14, 3)
+        assert err == e2 == 0 and np.array_equal(got, want), tup
+        assert np.all(got < tiled)
+
+
+def test_dice_tuple_product_2_64_and_errors(orc):
+    """Four bounds of 2^16: threshold 0 and the dice are the word's 16-bit
+    fields, most significant first (Theorem 1's digit order)."""
+    err, out = orc.dice_tuple([1 << 16] * 4, 8, seed=12, inst=1)
+    assert err == 0
+    for g in range(2):
+        w = orc.word(12, 1, g)
+        assert [int(x) for x in out[4 * g:4 * g + 4]] == [(w >> (48 - 16 * i)) & 0xFFFF for i in range(4)]
+    assert orc.dice_tuple([2**32 - 1] * 3, 10, 1, 0)[0] == 2
+    assert orc.dice_tuple([5, 0, 3], 10, 1, 0)[0] == 1
