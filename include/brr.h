@@ -104,6 +104,19 @@ typedef struct {
  * Returns BRR_EINVAL for any other max_k or a null out. */
 brr_status brr_schedule_paper(int max_k, brr_schedule *out);
 
+/* Fills *out with the greedy largest-batch schedule (KMAX): while i elements
+ * remain, batches of the largest k <= kcap whose product i (i-1) ... (i-k+1)
+ * is at most 2^64 (the limit of Theorem 1 for 64-bit words). With N_k the
+ * largest n whose k-th falling power is at most 2^64 (N_2 = 2^32,
+ * N_3 = 2642246, N_4 = 65537, N_5 = 7133, N_6 = 1627, N_7 = 568, N_8 = 259),
+ * step k runs while more than N_{k+1} elements remain, guarded by
+ * N_k^(falling k); batches of kcap dice run while more than kcap - 1
+ * elements remain, and a last batch (exact product) ends the shuffle. Large
+ * batches reject more often (up to half the words near the top of a step);
+ * the schedule is for comparison with the cost-model schedules.
+ * 1 <= kcap <= 16, else BRR_EINVAL. */
+brr_status brr_schedule_kmax(uint32_t kcap, brr_schedule *out);
+
 /* Fills *out with the division-based comparison shuffle of the paper's
  * experiments (Sec. 7, Appendix A): one die per batch above 2^32 elements
  * (never reached: n < 2^32 here), then batches of two dice in the division
@@ -172,6 +185,17 @@ brr_status brr_dice(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, u
  * exactly what brr_dice produces for a constant bounds array. bound >= 1,
  * 1 <= k <= 8, bound^k <= 2^64 (else BRR_EOVERFLOW). */
 brr_status brr_dice_const(uint32_t bound, uint32_t *d_out, uint64_t count, uint32_t k,
+                          uint64_t seed, uint64_t inst, void *stream);
+
+/* Algorithm 2 for any tuple of bounds known ahead of time (the
+ * known-threshold case of Sec. 5): group g rolls h_bounds[0..k) from one
+ * word, out[g*k + i] uniform in [0, h_bounds[i]); the threshold 2^64 mod
+ * (b_1 ... b_k) is computed once on the host (and once more for a short last
+ * group, which holds the first count mod k bounds of the tuple). Produces
+ * exactly what brr_dice produces for the tuple repeated over count bounds.
+ * h_bounds: host u32[k], read during the call; 1 <= k <= 8; a zero bound is
+ * BRR_EINVAL, a product above 2^64 BRR_EOVERFLOW. */
+brr_status brr_dice_tuple(const uint32_t *h_bounds, uint32_t k, uint32_t *d_out, uint64_t count,
                           uint64_t seed, uint64_t inst, void *stream);
 
 /* The division-based form of batched dice (Sec. 2.1, the comparison that the

@@ -31,7 +31,7 @@ EXPORTS = (
     "brr_mlp_get_params", "brr_mlp_set_params", "brr_mlp_get_grads", "brr_mlp_forward",
     "brr_mlp_backward", "brr_mlp_adam_step", "brr_mlp_train", "brr_plan_features",
     "brr_plan_autotune_learned", "brr_probe_chain_rate", "brr_dice32", "brr_dice_div",
-    "brr_schedule_naive2", "brr_dice_chacha",
+    "brr_schedule_naive2", "brr_dice_chacha", "brr_dice_tuple", "brr_schedule_kmax",
 )
 BRR_PLAN_FEATURES = 16
 BRR_REQ_SHUFFLE, BRR_REQ_SAMPLE = 1, 2
@@ -117,6 +117,8 @@ def _load():
     sig = {
         "brr_schedule_paper": (st, [ctypes.c_int, sched_p]),
         "brr_schedule_naive2": (st, [sched_p]),
+        "brr_schedule_kmax": (st, [u32, sched_p]),
+        "brr_dice_tuple": (st, [p, u32, p, u64, u64, u64, p]),
         "brr_schedule_batches": (u64, [sched_p, u64, u64]),
         "brr_schedule_check": (st, [sched_p, u64]),
         "brr_dice": (st, [p, p, u64, u32, u64, u64, p]),
@@ -209,6 +211,17 @@ def brr_schedule_paper(max_k: int) -> brr_schedule:
     s = brr_schedule()
     check(lib.brr_schedule_paper(max_k, ctypes.byref(s)), "brr_schedule_paper")
     return s
+
+
+def brr_schedule_kmax(kcap: int) -> brr_schedule:
+    s = brr_schedule()
+    check(lib.brr_schedule_kmax(kcap, ctypes.byref(s)), "brr_schedule_kmax")
+    return s
+
+
+def brr_dice_tuple(bounds_tuple, out, count: int, seed: int, inst: int = 0, stream=None) -> int:
+    t = (ctypes.c_uint32 * len(bounds_tuple))(*[int(x) for x in bounds_tuple])
+    return lib.brr_dice_tuple(t, len(bounds_tuple), _addr(out), count, seed, inst, _stream(stream))
 
 
 def brr_schedule_naive2() -> brr_schedule:

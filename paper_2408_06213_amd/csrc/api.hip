@@ -488,6 +488,34 @@ brr_status brr_schedule_paper(int max_k, brr_schedule *out)
     return BRR_OK;
 }
 
+brr_status brr_schedule_kmax(uint32_t kcap, brr_schedule *out)
+{
+    if (!out || kcap < 1 || kcap > BRR_MAX_STEPS) return BRR_EINVAL;
+    const u128 two64 = (u128)1 << 64;
+    // N[k]: the largest n with n (n-1) ... (n-k+1) <= 2^64, by bisection
+    uint64_t N[BRR_MAX_STEPS + 2] = {};
+    for (uint32_t k = 2; k <= kcap + 1; ++k) {
+        uint64_t lo = k, hi = 1ull << 33; // falling(lo, k) <= 2^64 < falling(hi, k)
+        while (hi - lo > 1) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            (falling(mid, k) <= two64 ? lo : hi) = mid;
+        }
+        N[k] = lo;
+    }
+    brr_schedule s;
+    std::memset(&s, 0, sizeof s);
+    s.nsteps = kcap;
+    for (uint32_t k = 1; k <= kcap; ++k) {
+        const uint64_t above = (k < kcap) ? N[k + 1] : kcap - 1;
+        const uint64_t guard = (k == 1) ? 0 : (uint64_t)falling(N[k], k);
+        s.step[k - 1] = brr_step{above, k, BRR_FORM_MULTIPLY, guard};
+    }
+    s.tail = 1;
+    s.u_tail = 0;
+    *out = s;
+    return BRR_OK;
+}
+
 brr_status brr_schedule_naive2(brr_schedule *out)
 {
     if (!out) return BRR_EINVAL;
@@ -566,27 +594,57 @@ brr_status brr_dice32(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count,
                                     static_cast<hipStream_t>(stream)));
 }
 
+namespace {
+// Algorithm 2 with the thresholds of a full group and of the short last
+// group computed here, once.
+brr_status dice_known(const BoundTuple &tb, uint32_t *d_out, uint64_t count, uint32_t k,
+                      uint64_t seed, uint64_t inst, void *stream)
+{
+    const u128 two64 = (u128)1 << 64;
+    const uint64_t S = (count + k - 1) / k;
+    const uint64_t k_last = count - (S - 1) * k;
+    // products capped just above 2^64 so that eight 32-bit factors never wrap
+    u128 p_full = 1, p_last = 1;
+    for (uint32_t i = 0; i < k; ++i) {
+        p_full *= tb.b[i];
+        if (i < k_last) p_last *= tb.b[i];
+        if (p_full > two64) p_full = two64 + 1; // stays above 2^64 (bounds >= 1)
+        if (p_last > two64) p_last = two64 + 1;
+    }
+    if (p_full > two64 && count >= k) return BRR_EOVERFLOW;
+    if (p_last > two64) return BRR_EOVERFLOW;
+    const uint64_t t_full = p_full > two64 ? 0 : (uint64_t)(two64 % p_full);
+    const uint64_t t_last = (uint64_t)(two64 % p_last);
+    const brr_status st = device_ready(nullptr);
+    if (st != BRR_OK) return st;
+    return hip_status(launch_dice_const(tb, d_out, count, k, make_key(seed, inst), t_full, t_last,
+                                        static_cast<hipStream_t>(stream)));
+}
+} // namespace
+
 brr_status brr_dice_const(uint32_t bound, uint32_t *d_out, uint64_t count, uint32_t k,
                           uint64_t seed, uint64_t inst, void *stream)
 {
     if (k < 1 || k > 8) return BRR_EINVAL;
     if (count == 0) return BRR_OK;
     if (!d_out || bound == 0 || misaligned(d_out, 4)) return BRR_EINVAL;
-    const u128 two64 = (u128)1 << 64;
-    u128 p_full = 1;
-    for (uint32_t i = 0; i < k; ++i) p_full *= bound;
-    if (p_full > two64 && count >= k) return BRR_EOVERFLOW;
-    const uint64_t S = (count + k - 1) / k;
-    const uint64_t k_last = count - (S - 1) * k;
-    u128 p_last = 1;
-    for (uint64_t i = 0; i < k_last; ++i) p_last *= bound;
-    if (p_last > two64) return BRR_EOVERFLOW;
-    const uint64_t t_full = p_full > two64 ? 0 : (uint64_t)(two64 % p_full);
-    const uint64_t t_last = (uint64_t)(two64 % p_last);
-    const brr_status st = device_ready(nullptr);
-    if (st != BRR_OK) return st;
-    return hip_status(launch_dice_const(bound, d_out, count, k, make_key(seed, inst), t_full,
-                                        t_last, static_cast<hipStream_t>(stream)));
+    BoundTuple tb{};
+    for (uint32_t i = 0; i < 8; ++i) tb.b[i] = bound;
+    return dice_known(tb, d_out, count, k, seed, inst, stream);
+}
+
+brr_status brr_dice_tuple(const uint32_t *h_bounds, uint32_t k, uint32_t *d_out, uint64_t count,
+                          uint64_t seed, uint64_t inst, void *stream)
+{
+    if (k < 1 || k > 8 || !h_bounds) return BRR_EINVAL;
+    BoundTuple tb{};
+    for (uint32_t i = 0; i < k; ++i) {
+        if (h_bounds[i] == 0) return BRR_EINVAL;
+        tb.b[i] = h_bounds[i];
+    }
+    if (count == 0) return BRR_OK;
+    if (!d_out || misaligned(d_out, 4)) return BRR_EINVAL;
+    return dice_known(tb, d_out, count, k, seed, inst, stream);
 }
 
 brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_schedule *sched,

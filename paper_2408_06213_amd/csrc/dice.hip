@@ -255,10 +255,12 @@ __global__ __launch_bounds__(256) void dice_div_kernel(const uint32_t *__restric
     if (err) atomicOr(status, err);
 }
 
-// Constant bound (Algorithm 2): t_full is 2^64 mod bound^K, t_last the same
-// for the short last group.
+// Known bounds (Algorithm 2): every group rolls the same tuple tb.b[0..K),
+// t_full is 2^64 mod their product, t_last the same for the short last group
+// (the tuple's first count mod K bounds). A constant bound is the tuple of K
+// equal bounds.
 template <int K, int G, bool VEC>
-__global__ __launch_bounds__(256) void dice_const_kernel(uint32_t bound, uint32_t *__restrict__ out,
+__global__ __launch_bounds__(256) void dice_const_kernel(BoundTuple tb, uint32_t *__restrict__ out,
                                                          uint64_t count, uint64_t S, uint64_t full,
                                                          StreamKey key, uint64_t t_full,
                                                          uint64_t t_last)
@@ -278,12 +280,12 @@ __global__ __launch_bounds__(256) void dice_const_kernel(uint32_t bound, uint32_
         uint64_t rr = r[j];
 #pragma unroll
         for (int i = 0; i < K; ++i)
-            if (i < kk) a[i] = mul_roll(bound, rr);
+            if (i < kk) a[i] = mul_roll(tb.b[i], rr);
         for (uint64_t attempt = 1; rr < t && attempt <= kMaxAttempts; ++attempt) {
             rr = word_at(attempt * S + g, key);
 #pragma unroll
             for (int i = 0; i < K; ++i)
-                if (i < kk) a[i] = mul_roll(bound, rr);
+                if (i < kk) a[i] = mul_roll(tb.b[i], rr);
         }
         if (kk == K)
             store_group<K, VEC>(out + K * g, a);
@@ -333,7 +335,7 @@ hipError_t launch_dice_div_k(const uint32_t *bounds, uint32_t *out, uint64_t cou
 }
 
 template <int K>
-hipError_t launch_dice_const_k(uint32_t bound, uint32_t *out, uint64_t count, StreamKey key,
+hipError_t launch_dice_const_k(const BoundTuple &tb, uint32_t *out, uint64_t count, StreamKey key,
                                uint64_t t_full, uint64_t t_last, hipStream_t stream)
 {
     const uint64_t S = (count + K - 1) / K;
@@ -341,10 +343,10 @@ hipError_t launch_dice_const_k(uint32_t bound, uint32_t *out, uint64_t count, St
     const bool vec = (((uintptr_t)out) & 15) == 0;
     if (vec)
         dice_const_kernel<K, kGroupsPerLane, true><<<tile_blocks(S), 256, 0, stream>>>(
-            bound, out, count, S, full, key, t_full, t_last);
+            tb, out, count, S, full, key, t_full, t_last);
     else
         dice_const_kernel<K, kGroupsPerLane, false><<<tile_blocks(S), 256, 0, stream>>>(
-            bound, out, count, S, full, key, t_full, t_last);
+            tb, out, count, S, full, key, t_full, t_last);
     return hipGetLastError();
 }
 
@@ -382,18 +384,18 @@ hipError_t launch_dice_div(const uint32_t *bounds, uint32_t *out, uint64_t count
     }
 }
 
-hipError_t launch_dice_const(uint32_t bound, uint32_t *out, uint64_t count, uint32_t k,
+hipError_t launch_dice_const(const BoundTuple &tb, uint32_t *out, uint64_t count, uint32_t k,
                              StreamKey key, uint64_t t_full, uint64_t t_last, hipStream_t stream)
 {
     switch (k) {
-    case 1: return launch_dice_const_k<1>(bound, out, count, key, t_full, t_last, stream);
-    case 2: return launch_dice_const_k<2>(bound, out, count, key, t_full, t_last, stream);
-    case 3: return launch_dice_const_k<3>(bound, out, count, key, t_full, t_last, stream);
-    case 4: return launch_dice_const_k<4>(bound, out, count, key, t_full, t_last, stream);
-    case 5: return launch_dice_const_k<5>(bound, out, count, key, t_full, t_last, stream);
-    case 6: return launch_dice_const_k<6>(bound, out, count, key, t_full, t_last, stream);
-    case 7: return launch_dice_const_k<7>(bound, out, count, key, t_full, t_last, stream);
-    case 8: return launch_dice_const_k<8>(bound, out, count, key, t_full, t_last, stream);
+    case 1: return launch_dice_const_k<1>(tb, out, count, key, t_full, t_last, stream);
+    case 2: return launch_dice_const_k<2>(tb, out, count, key, t_full, t_last, stream);
+    case 3: return launch_dice_const_k<3>(tb, out, count, key, t_full, t_last, stream);
+    case 4: return launch_dice_const_k<4>(tb, out, count, key, t_full, t_last, stream);
+    case 5: return launch_dice_const_k<5>(tb, out, count, key, t_full, t_last, stream);
+    case 6: return launch_dice_const_k<6>(tb, out, count, key, t_full, t_last, stream);
+    case 7: return launch_dice_const_k<7>(tb, out, count, key, t_full, t_last, stream);
+    case 8: return launch_dice_const_k<8>(tb, out, count, key, t_full, t_last, stream);
     default: return hipErrorInvalidValue;
     }
 }

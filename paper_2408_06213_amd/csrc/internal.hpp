@@ -118,7 +118,11 @@ inline bool misaligned(const void *p, uint32_t bytes)
 // Kernel launchers (dice.hip, shuffle.hip).
 hipError_t launch_dice(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
                        StreamKey key, uint32_t *status, hipStream_t stream);
-hipError_t launch_dice_const(uint32_t bound, uint32_t *out, uint64_t count, uint32_t k,
+// Known bounds of a dice stream (Algorithm 2): group g rolls b[0..k).
+struct BoundTuple {
+    uint32_t b[8];
+};
+hipError_t launch_dice_const(const BoundTuple &tb, uint32_t *out, uint64_t count, uint32_t k,
                              StreamKey key, uint64_t t_full, uint64_t t_last, hipStream_t stream);
 // The dice stream in the division form (dice.hip).
 hipError_t launch_dice_div(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,

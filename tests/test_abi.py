@@ -1,6 +1,7 @@
 """The C ABI library loads and exports every declared symbol; host-side
 schedule logic agrees with the paper's fixtures and with the oracle (two
 independent implementations). No GPU work is launched here."""
+import ctypes
 import os
 import re
 
@@ -56,6 +57,22 @@ def test_host_batch_counts_match_oracle(orc, max_k):
     for n in list(range(2, 80)) + [255, 256, 257, 4097, 10000, 65536, 100003, 2**20 + 7]:
         for steps in {n - 1, max(1, n // 3), 1}:
             assert brr.brr_schedule_batches(s, n, steps) == orc.count_batches(n, steps, o), (n, steps)
+
+
+@pytest.mark.parametrize("kcap", [1, 2, 5, 8, 16])
+def test_kmax_schedule_host(orc, kcap):
+    """The library's KMAX schedule is the oracle's (each found by its own
+    bisection) and passes the schedule check at every size."""
+    from paper_2408_06213_amd import brr
+
+    s, o = brr.brr_schedule_kmax(kcap), orc.schedule_kmax(kcap)
+    assert s.steps() == o.segments() and s.tail == o.tail == 1 and s.u_tail == o.u_tail
+    for n in (2, 3, kcap + 1, 260, 7134, 65538, 2642247, 2**32 - 1):
+        assert brr.brr_schedule_check(s, n) == brr.BRR_OK
+        if n < 2**30:
+            assert brr.brr_schedule_batches(s, n, n - 1) == orc.count_batches(n, n - 1, o)
+    with pytest.raises(brr.BrrError):
+        brr.brr_schedule_kmax(17)
 
 
 def test_naive2_schedule_host(orc):
@@ -116,3 +133,16 @@ def test_host_argument_errors_need_no_device():
     assert brr.lib.brr_shuffle_batched(odd4, 0x20000, 3, 4, None, 1, 0, None) == brr.BRR_EINVAL
     assert brr.lib.brr_shuffle_batched(0x20000, odd8, 3, 4, None, 1, 0, None) == brr.BRR_EINVAL
     assert brr.lib.brr_probe_chain_rate(0, None) == brr.BRR_EINVAL
+    # known bounds: products checked on the host (eight 32-bit factors
+    # would wrap a 128-bit product if it were not capped)
+    assert brr.lib.brr_dice_const(2**32 - 1, 0x20000, 10, 5, 1, 0, None) == brr.BRR_EOVERFLOW
+    assert brr.lib.brr_dice_const(2**32 - 1, 0x20000, 16, 8, 1, 0, None) == brr.BRR_EOVERFLOW
+    big = (ctypes.c_uint32 * 8)(*([2**32 - 1] * 8))
+    assert brr.lib.brr_dice_tuple(big, 8, 0x20000, 16, 1, 0, None) == brr.BRR_EOVERFLOW
+    zero = (ctypes.c_uint32 * 3)(5, 0, 7)
+    assert brr.lib.brr_dice_tuple(zero, 3, 0x20000, 9, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_dice_tuple(big, 9, 0x20000, 9, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_dice_tuple(None, 2, 0x20000, 9, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_dice_tuple(zero, 1, odd4, 9, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_dice_div(None, None, 10, 9, 1, 0, None) == brr.BRR_EINVAL
+    assert brr.lib.brr_dice_chacha(odd4, 0x20000, 10, 2, 1, 0, None) == brr.BRR_EINVAL

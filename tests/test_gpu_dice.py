@@ -302,3 +302,34 @@ def test_dice_chacha_edge_cases(gpu, orc):
     st, _ = run_dice_chacha(gpu, np.array([5, 0, 3, 4], np.uint32), 2, 1, 0)
     assert st == gpu.BRR_EINVAL
     assert gpu.brr_sync_status() == 0
+
+
+# ---------------------------------------------------------------------------
+# Known bounds (brr_dice_tuple, Algorithm 2)
+# ---------------------------------------------------------------------------
+
+def test_dice_tuple_parity(gpu, orc):
+    cases = [([4, 6, 8, 20], 4001), ([2**31 + 1, 2**32 - 1], 100001), ([6], 777),
+             ([3, 5, 7, 11, 13, 17, 19, 23], 8 * 4096 + 5), ([1 << 16] * 4, 4 * 3000),
+             ([2**21 - 1, 2**21 - 3, 2**21 - 5], 3 * 70000 + 2), ([1, 1, 2], 1000)]
+    for tup, count in cases:
+        for offset in (0, 1):
+            say("dice_tuple", tup, count, offset)
+            out = to_dev(np.zeros(count + offset, np.uint32))
+            gpu.check(gpu.brr_dice_tuple(tup, out.data_ptr() + 4 * offset, count, 21, 2),
+                      "brr_dice_tuple")
+            assert gpu.brr_sync_status() == 0
+            err, want = orc.dice_tuple(tup, count, 21, 2)
+            assert err == 0 and np.array_equal(to_host(out)[offset:], want), (tup, count)
+
+
+def test_dice_tuple_equals_dice_on_tiled_bounds(gpu):
+    """The known-threshold path and the general path agree on the device."""
+    tup, count = [10, 12, 1000, 77], 50003
+    tiled = to_dev(np.resize(np.array(tup, np.uint32), count))
+    a = to_dev(np.zeros(count, np.uint32))
+    b = to_dev(np.zeros(count, np.uint32))
+    gpu.check(gpu.brr_dice_tuple(tup, a, count, 5, 9), "brr_dice_tuple")
+    gpu.check(gpu.brr_dice(tiled, b, count, len(tup), 5, 9), "brr_dice")
+    assert gpu.brr_sync_status() == 0
+    assert np.array_equal(to_host(a), to_host(b))

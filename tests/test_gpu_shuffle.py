@@ -315,3 +315,34 @@ def test_naive2_sample_parity(gpu, orc):
         assert gpu.brr_sync_status() == 0
         err, want = orc.sample(data, m, os_, 33, n)
         assert err == 0 and np.array_equal(to_host(out), want), (n, m)
+
+
+# ---------------------------------------------------------------------------
+# The greedy largest-batch schedule (brr_schedule_kmax)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kcap", [4, 8])
+def test_kmax_shuffle_parity(gpu, orc, kcap):
+    gs, os_ = gpu.brr_schedule_kmax(kcap), orc.schedule_kmax(kcap)
+    assert gs.steps() == os_.segments()
+    for n in LDS_SIZES + [16385, 65538, 100003, (1 << 21) + 5, 2642247]:
+        say("kmax shuffle", kcap, n)
+        a = np.arange(n, dtype=np.uint32) * 7 + 3
+        got = gpu_shuffle(gpu, a, gs, seed=555, inst=n)
+        want = a.copy()
+        assert orc.shuffle(want, os_, 555, n) == 0
+        assert np.array_equal(got, want), (kcap, n)
+
+
+def test_kmax_batched_every_tier(gpu, orc):
+    gs, os_ = gpu.brr_schedule_kmax(8), orc.schedule_kmax(8)
+    sizes = np.concatenate([np.arange(2, 258), [259, 260, 568, 569, 1627, 1628, 4097, 7133, 7134,
+                                                16384, 16385, 65537, 65538, (1 << 20) + 1]])
+    sizes = sizes.astype(np.uint64)
+    say("kmax batched")
+    data, off, results = run_batched(gpu, sizes, np.uint64, seed=41, inst_base=9, reps=2, sched=gs,
+                                     lane_max=256)
+    want = data.copy()
+    assert orc.shuffle_batched(want, off, os_, 41, 9) == 0
+    for got in results:
+        assert np.array_equal(got, want)
