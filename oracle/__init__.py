@@ -33,6 +33,7 @@ def build() -> str:
 
 
 FORM_MULTIPLY, FORM_DIVISION = 0, 1
+WORDS_PHILOX64, WORDS_PHILOX32, WORDS_CHACHA20 = 0, 1, 2
 
 
 class Schedule(ctypes.Structure):
@@ -49,6 +50,7 @@ class Schedule(ctypes.Structure):
         ("u", ctypes.c_uint64 * 16),
         ("u_tail", ctypes.c_uint64),
         ("form", ctypes.c_uint32 * 16),
+        ("words", ctypes.c_uint32),
     ]
 
     def segments(self):
@@ -58,8 +60,9 @@ class Schedule(ctypes.Structure):
         return [int(self.form[g]) for g in range(self.nseg)]
 
     @classmethod
-    def from_segments(cls, segs, tail=True, u_tail=720, forms=None):
+    def from_segments(cls, segs, tail=True, u_tail=720, forms=None, words=WORDS_PHILOX64):
         s = cls()
+        s.words = words
         s.nseg = len(segs)
         for g, (thr, k, u) in enumerate(segs):
             s.thr[g], s.k[g], s.u[g] = thr, k, u

@@ -13,8 +13,9 @@
  *   - Algorithm 2 (known threshold) and Algorithm 3 (unknown)    (Sec. 5),
  *     at word width 64 and, for dice streams, 32
  *   - Algorithm 4 (batched partial shuffle with carried bound u) (Sec. 6)
- *   - a second word source for dice streams: ChaCha20 in counter mode
- *     (Bernstein 2008), the slow generator of the paper's experiments
+ *   - a second word source: ChaCha20 in counter mode (Bernstein 2008), the
+ *     slow generator of the paper's experiments; shuffles also take the
+ *     32-bit halves of the Philox words (L = 32)
  *   - the division form of batched dice: one roll of the product of the
  *     bounds, digits as successive remainders of quotients  (Sec. 2.1,
  *     and the naive batched shuffle of Appendix A)
@@ -502,7 +503,11 @@ int orc_dice_tuple(const uint32_t *tuple, unsigned k, uint32_t *out, uint64_t co
  * falling product by Lemire's method, digits as successive remainders of
  * quotients: the naive batched shuffle of Appendix A; u is not used).
  * If `tail` is set and i > 1 afterwards, one last batch of i-1 dice with
- * bound u_tail finishes the shuffle (Theorem 1 form). */
+ * bound u_tail finishes the shuffle (Theorem 1 form).
+ * words selects the word stream of every batch: 0 = Philox 64-bit words
+ * (orc_word), 1 = their 32-bit halves with the chain and the threshold at
+ * L = 32 (orc_word32; every product at most 2^32; multiply form only),
+ * 2 = ChaCha20 64-bit words (orc_word_chacha). */
 typedef struct {
     uint32_t nseg;
     uint32_t tail;
@@ -511,7 +516,10 @@ typedef struct {
     uint64_t u[16];
     uint64_t u_tail;
     uint32_t form[16];
+    uint32_t words;
 } orc_schedule;
+
+enum { WORDS_PHILOX64 = 0, WORDS_PHILOX32 = 1, WORDS_CHACHA20 = 2 };
 
 /* The paper's schedules: max_k = 6 is shuffle_6 (one die above 2^30
  * elements, then 2/3/4/5/6 dice at or below 2^30/2^19/2^14/2^11/2^9, with
@@ -603,13 +611,17 @@ int orc_schedule_kmax(unsigned kcap, orc_schedule *out)
 }
 
 typedef struct {
-    /* word source: Philox (words == NULL) or an explicit attempt-major list */
+    /* word source: the schedule's stream (words == NULL) or an explicit
+     * attempt-major list */
     uint64_t seed, inst;
     const uint64_t *words;
     uint64_t nwords;
     uint64_t S; /* batches in this instance */
     int exhausted;
+    unsigned source; /* WORDS_* */
 } word_src;
+
+static unsigned word_bits(const word_src *w) { return w->source == WORDS_PHILOX32 ? 32 : 64; }
 
 static uint64_t next_word(word_src *w, uint64_t attempt, uint64_t s)
 {
@@ -621,6 +633,8 @@ static uint64_t next_word(word_src *w, uint64_t attempt, uint64_t s)
         }
         return w->words[c];
     }
+    if (w->source == WORDS_PHILOX32) return orc_word32(w->seed, w->inst, c);
+    if (w->source == WORDS_CHACHA20) return orc_word_chacha(w->seed, w->inst, c);
     return orc_word(w->seed, w->inst, c);
 }
 
@@ -638,16 +652,17 @@ static void swap_elems(uint8_t *z, uint64_t p, uint64_t q, unsigned eb)
 static u128 partial_shuffle(uint8_t *z, uint64_t n, unsigned k, u128 u, unsigned eb, word_src *w,
                             uint64_t s)
 {
+    const unsigned L = word_bits(w);
     uint64_t bounds[64], a[64];
     for (unsigned i = 1; i <= k; ++i) bounds[i - 1] = n + 1 - i;
     uint64_t attempt = 0;
-    uint64_t r = orc_chain(64, bounds, k, next_word(w, attempt, s), a);
+    uint64_t r = orc_chain(L, bounds, k, next_word(w, attempt, s), a);
     if (u == 0 || (u128)r < u) {
         u = falling(n, k);
-        const uint64_t t = (uint64_t)((((u128)1) << 64) % u);
+        const uint64_t t = (uint64_t)((((u128)1) << L) % u);
         while (r < t && !w->exhausted) {
             ++attempt;
-            r = orc_chain(64, bounds, k, next_word(w, attempt, s), a);
+            r = orc_chain(L, bounds, k, next_word(w, attempt, s), a);
         }
     }
     for (unsigned i = 1; i <= k; ++i) swap_elems(z, a[i - 1], n - i, eb);
@@ -689,7 +704,7 @@ enum { RUN_COUNT = 0, RUN_CHECK = 1, RUN_EXEC = 2 };
 static uint64_t run_schedule(int mode, uint8_t *z, uint64_t n, uint64_t steps, unsigned eb,
                              const orc_schedule *sch, word_src *w, int *err)
 {
-    const u128 two64 = (u128)1 << 64;
+    const u128 two64 = (u128)1 << (sch->words == WORDS_PHILOX32 ? 32 : 64); /* 2^L */
     uint64_t i = n, s = 0, done = 0;
     for (uint32_t g = 0; g < sch->nseg && done < steps; ++g) {
         const u128 u0 = sch->u[g];
@@ -734,9 +749,11 @@ static uint64_t run_schedule(int mode, uint8_t *z, uint64_t n, uint64_t steps, u
 static int check_segments(const orc_schedule *sch)
 {
     if (sch->nseg == 0 || sch->nseg > 16) return ORC_EINVAL;
+    if (sch->words > WORDS_CHACHA20) return ORC_EINVAL;
     for (uint32_t g = 0; g < sch->nseg; ++g) {
         if (sch->k[g] == 0 || sch->k[g] > 64) return ORC_EINVAL;
         if (sch->form[g] > 1) return ORC_EINVAL;
+        if (sch->form[g] == 1 && sch->words == WORDS_PHILOX32) return ORC_EINVAL;
         if (sch->thr[g] + 1 < sch->k[g]) return ORC_EINVAL;
         if (g > 0 && sch->thr[g] > sch->thr[g - 1]) return ORC_EINVAL;
     }
@@ -758,6 +775,7 @@ static int shuffle_impl(void *data, uint64_t n, uint64_t steps, unsigned eb,
     if (n > 0xFFFFFFFFull) return ORC_EINVAL;
     int err = check_segments(sch);
     if (err) return err;
+    w->source = sch->words;
     if (run_schedule(RUN_CHECK, NULL, n, steps, eb, sch, w, &err) == ~(uint64_t)0) return err;
     w->S = run_schedule(RUN_COUNT, NULL, n, steps, eb, sch, w, &err);
     run_schedule(RUN_EXEC, (uint8_t *)data, n, steps, eb, sch, w, &err);
@@ -767,7 +785,7 @@ static int shuffle_impl(void *data, uint64_t n, uint64_t steps, unsigned eb,
 int orc_shuffle(void *data, uint64_t n, unsigned eb, const orc_schedule *sch, uint64_t seed,
                 uint64_t inst)
 {
-    word_src w = {seed, inst, NULL, 0, 0, 0};
+    word_src w = {seed, inst, NULL, 0, 0, 0, 0};
     return shuffle_impl(data, n, n ? n - 1 : 0, eb, sch, &w);
 }
 
@@ -776,7 +794,7 @@ int orc_shuffle(void *data, uint64_t n, unsigned eb, const orc_schedule *sch, ui
 int orc_shuffle_words(void *data, uint64_t n, unsigned eb, const orc_schedule *sch,
                       const uint64_t *words, uint64_t nwords)
 {
-    word_src w = {0, 0, words, nwords, 0, 0};
+    word_src w = {0, 0, words, nwords, 0, 0, 0};
     return shuffle_impl(data, n, n ? n - 1 : 0, eb, sch, &w);
 }
 
@@ -800,7 +818,7 @@ int orc_partial_shuffle(void *data, uint64_t n, uint64_t m, unsigned eb, const o
                         uint64_t seed, uint64_t inst)
 {
     if (m > n) return ORC_EINVAL;
-    word_src w = {seed, inst, NULL, 0, 0, 0};
+    word_src w = {seed, inst, NULL, 0, 0, 0, 0};
     const uint64_t steps = (m < n) ? m : n - 1;
     return shuffle_impl(data, n, steps, eb, sch, &w);
 }

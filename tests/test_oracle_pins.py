@@ -798,3 +798,106 @@ def test_dice_tuple_product_2_64_and_errors(orc):
         assert [int(x) for x in out[4 * g:4 * g + 4]] == [(w >> (48 - 16 * i)) & 0xFFFF for i in range(4)]
     assert orc.dice_tuple([2**32 - 1] * 3, 10, 1, 0)[0] == 2
     assert orc.dice_tuple([5, 0, 3], 10, 1, 0)[0] == 1
+
+
+# ---------------------------------------------------------------------------
+# Shuffles on other word streams: 32-bit halves (L = 32) and ChaCha20
+# ---------------------------------------------------------------------------
+
+# batch sizes of Table 2's L = 32 column (n_2, n_3, n_4), exact guards
+L32_STEPS = [(20724, 1, 0), (581, 2, 0), (109, 3, 0), (4, 4, 0)]
+
+
+def _dice_for_shuffle_words(orc, n, sched, L, word):
+    """Dice of a scheduled shuffle on the word stream word(c) at width L,
+    by the big-integer chain and Lemire's criterion at L."""
+    batches = []
+    i = n
+    for thr, k, _ in sched.segments():
+        while i > thr:
+            batches.append((i, k))
+            i -= k
+    if sched.tail and i > 1:
+        batches.append((i, i - 1))
+    S = len(batches)
+    js = []
+    for s, (i, k) in enumerate(batches):
+        bounds = [i - l for l in range(k)]
+        att = 0
+        while True:
+            a, rk = ref.chain(L, bounds, word(att * S + s))
+            if ref.accept(L, bounds, rk):
+                break
+            att += 1
+        js.extend(a)
+    return js
+
+
+@pytest.mark.parametrize("n", [2, 5, 110, 600, 3000, 25000])
+def test_l32_shuffle_is_fisher_yates(orc, n):
+    sched = orc.Schedule.from_segments(L32_STEPS, tail=True, u_tail=0, words=orc.WORDS_PHILOX32)
+    z = np.arange(n, dtype=np.uint32)
+    assert orc.shuffle(z, sched, seed=37, inst=n) == 0
+    js = _dice_for_shuffle_words(orc, n, sched, 32, lambda c: orc.word32(37, n, c))
+    assert list(z) == ref.fisher_yates(range(n), js)
+
+
+def test_l32_k1_shuffle_is_lemire_at_32(orc):
+    n = 300
+    sched = orc.Schedule.from_segments([(1, 1, 0)], tail=False, words=orc.WORDS_PHILOX32)
+    z = np.arange(n, dtype=np.uint64)
+    assert orc.shuffle(z, sched, seed=3, inst=7) == 0
+    S = n - 1
+
+    def words(s):
+        a = 0
+        while True:
+            yield orc.word32(3, 7, a * S + s)
+            a += 1
+    js = [ref.lemire(32, i + 1, words(s))[0] for s, i in enumerate(range(n - 1, 0, -1))]
+    assert list(z) == ref.fisher_yates(range(n), js)
+
+
+@pytest.mark.parametrize("n", [3, 300, 20000])
+def test_chacha_shuffle_is_fisher_yates(orc, n):
+    s6 = orc.schedule_paper(6)
+    sched = orc.Schedule.from_segments(s6.segments(), tail=True, u_tail=720, words=orc.WORDS_CHACHA20)
+    z = np.arange(n, dtype=np.uint32)
+    assert orc.shuffle(z, sched, seed=38, inst=n) == 0
+    js = _dice_for_shuffle_words(orc, n, sched, 64, lambda c: orc.word_chacha(38, n, c))
+    assert list(z) == ref.fisher_yates(range(n), js)
+
+
+def test_word_stream_schedule_checks(orc):
+    z = np.arange(30000, dtype=np.uint32)
+    # at L = 32 a pair at 30000 elements (product about 9e8) fits, a triple does not
+    ok = orc.Schedule.from_segments([(1, 2, 0)], tail=False, words=orc.WORDS_PHILOX32)
+    assert orc.shuffle(z.copy(), ok, 1, 0) == 0
+    over = orc.Schedule.from_segments([(2, 3, 0)], tail=True, u_tail=0, words=orc.WORDS_PHILOX32)
+    assert orc.shuffle(z.copy(), over, 1, 0) == 2
+    # the division form needs 64-bit words; unknown streams are invalid
+    div32 = orc.Schedule.from_segments([(1, 2, 0)], tail=False, forms=[1], words=orc.WORDS_PHILOX32)
+    assert orc.shuffle(z.copy(), div32, 1, 0) == 1
+    bad = orc.Schedule.from_segments([(1, 1, 0)], tail=False, words=3)
+    assert orc.shuffle(z.copy(), bad, 1, 0) == 1
+    # ChaCha words with the division form are fine
+    divcc = orc.Schedule.from_segments([(1, 2, 0)], tail=False, forms=[1], words=orc.WORDS_CHACHA20)
+    zz = z.copy()
+    assert orc.shuffle(zz, divcc, 1, 0) == 0 and np.array_equal(np.sort(zz), z)
+
+
+@pytest.mark.parametrize("words", ["l32", "chacha"])
+def test_word_stream_chi2_all_24_permutations(orc, words):
+    if words == "l32":
+        sched = orc.Schedule.from_segments(L32_STEPS, tail=True, u_tail=0, words=orc.WORDS_PHILOX32)
+    else:
+        sched = orc.Schedule.from_segments(orc.schedule_paper(6).segments(), tail=True, u_tail=720,
+                                           words=orc.WORDS_CHACHA20)
+    trials = 1_000_000
+    data = np.tile(np.arange(4, dtype=np.uint32), trials)
+    offsets = np.arange(0, 4 * trials + 1, 4, dtype=np.uint64)
+    assert orc.shuffle_batched(data, offsets, sched, seed=47) == 0
+    hist = np.bincount(_perm_index4(data.reshape(trials, 4)), minlength=24)
+    assert hist.size == 24 and hist.min() > 0
+    stat = float(((hist - trials / 24) ** 2 / (trials / 24)).sum())
+    assert stat < chi2.ppf(1 - 1e-3, 23), stat
