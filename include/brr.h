@@ -82,15 +82,31 @@ typedef struct {
     uint64_t u0;
 } brr_step;
 
+/* The word stream every batch of a schedule reads (word c of instance inst):
+ * BRR_WORDS_PHILOX64 -- the 64-bit Philox words of brr_dice;
+ * BRR_WORDS_PHILOX32 -- their 32-bit halves, word c = half c mod 2 (low
+ *   first) of 64-bit word c/2, with the chain and Lemire's threshold at
+ *   L = 32 (Theorem 1 holds for any L, Sec. 4): every batch product at most
+ *   2^32, multiply form only (the batch sizes of Table 2's L = 32 column);
+ * BRR_WORDS_CHACHA20 -- the ChaCha20 words of brr_dice_chacha (the paper's
+ *   slow generator, Sec. 7). */
+#define BRR_WORDS_PHILOX64 0u
+#define BRR_WORDS_PHILOX32 1u
+#define BRR_WORDS_CHACHA20 2u
+
 /* Steps run in order with non-increasing n_above. With tail = 1, when more
  * than one element remains after the last step, one batch of (i - 1) dice
  * bounded by u_tail finishes the shuffle (the last batch of Sec. 6; always
- * in the multiply form). */
+ * in the multiply form). words: BRR_WORDS_* (0 = Philox 64-bit words, what
+ * every schedule-filling function sets unless stated otherwise); reserved
+ * must be 0. */
 typedef struct {
     uint32_t nsteps;
     uint32_t tail;
     uint64_t u_tail;
     brr_step step[BRR_MAX_STEPS];
+    uint32_t words;
+    uint32_t reserved;
 } brr_schedule;
 
 /* Fills *out with one of the paper's schedules (Sec. 7, Appendix A):
@@ -130,8 +146,10 @@ brr_status brr_schedule_naive2(brr_schedule *out);
 uint64_t brr_schedule_batches(const brr_schedule *sched, uint64_t n, uint64_t steps);
 
 /* Checks a schedule for an n-element shuffle: every batch's bound product at
- * most 2^64, every non-zero upper bound at least the product it guards, no
- * element left unshuffled. BRR_OK, BRR_EINVAL or BRR_EOVERFLOW. */
+ * most 2^L (L = 32 for BRR_WORDS_PHILOX32, else 64), every non-zero upper
+ * bound at least the product it guards, no element left unshuffled, a known
+ * word stream (division steps need 64-bit words), reserved = 0. BRR_OK,
+ * BRR_EINVAL or BRR_EOVERFLOW. */
 brr_status brr_schedule_check(const brr_schedule *sched, uint64_t n);
 
 /* ------------------------------------------------------------------------ */
@@ -153,7 +171,8 @@ double brr_cost_per_die(uint64_t n, uint32_t k, uint32_t L, double c_rng, double
 brr_status brr_cost_thresholds(uint32_t L, uint32_t kmax, double c_rng, double c_div,
                                uint64_t *out_nk);
 
-/* A schedule from the cost model (64-bit words): one die above n_2, then k
+/* A schedule from the cost model (64-bit words unless BRR_COSTS_L32): one
+ * die above n_2, then k
  * dice while more than n_{k+1} elements remain (k up to kmax), guards
  * u_k = n_k^k, and a last batch of at most kmax - 1 dice. Flags:
  * BRR_COSTS_POW2 rounds each n_k down to a power of two first, as the paper
@@ -163,6 +182,7 @@ brr_status brr_cost_thresholds(uint32_t L, uint32_t kmax, double c_rng, double c
  * first-crossing scan of brr_cost_thresholds (seconds for k = 2). */
 #define BRR_COSTS_POW2 1
 #define BRR_COSTS_SMOOTH 2
+#define BRR_COSTS_L32 4 /* the cost model at L = 32; the schedule reads BRR_WORDS_PHILOX32 */
 brr_status brr_schedule_from_costs(uint32_t kmax, double c_rng, double c_div, int flags,
                                    brr_schedule *out);
 

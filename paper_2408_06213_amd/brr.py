@@ -44,6 +44,7 @@ class BrrError(RuntimeError):
 
 
 BRR_FORM_MULTIPLY, BRR_FORM_DIVISION = 0, 1
+BRR_WORDS_PHILOX64, BRR_WORDS_PHILOX32, BRR_WORDS_CHACHA20 = 0, 1, 2
 
 
 class brr_step(ctypes.Structure):
@@ -53,7 +54,8 @@ class brr_step(ctypes.Structure):
 
 class brr_schedule(ctypes.Structure):
     _fields_ = [("nsteps", ctypes.c_uint32), ("tail", ctypes.c_uint32),
-                ("u_tail", ctypes.c_uint64), ("step", brr_step * BRR_MAX_STEPS)]
+                ("u_tail", ctypes.c_uint64), ("step", brr_step * BRR_MAX_STEPS),
+                ("words", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
     def steps(self):
         return [(int(s.n_above), int(s.k), int(s.u0)) for s in self.step[: self.nsteps]]
@@ -62,8 +64,9 @@ class brr_schedule(ctypes.Structure):
         return [int(s.form) for s in self.step[: self.nsteps]]
 
     @classmethod
-    def from_steps(cls, steps, tail=True, u_tail=720, forms=None):
+    def from_steps(cls, steps, tail=True, u_tail=720, forms=None, words=0):
         s = cls()
+        s.words = words
         s.nsteps = len(steps)
         for g, (above, k, u0) in enumerate(steps):
             s.step[g].n_above, s.step[g].k, s.step[g].u0 = above, k, u0
@@ -248,13 +251,15 @@ def brr_cost_thresholds(L: int, kmax: int, c_rng: float = 2.0, c_div: float = 16
     return {k: int(out[k]) for k in range(2, kmax + 1)}
 
 
-BRR_COSTS_POW2, BRR_COSTS_SMOOTH = 1, 2
+BRR_COSTS_POW2, BRR_COSTS_SMOOTH, BRR_COSTS_L32 = 1, 2, 4
 
 
 def brr_schedule_from_costs(kmax: int, c_rng: float = 2.0, c_div: float = 16.0,
-                            pow2: bool = True, smooth: bool = False) -> brr_schedule:
+                            pow2: bool = True, smooth: bool = False,
+                            l32: bool = False) -> brr_schedule:
     s = brr_schedule()
-    flags = (BRR_COSTS_POW2 if pow2 else 0) | (BRR_COSTS_SMOOTH if smooth else 0)
+    flags = ((BRR_COSTS_POW2 if pow2 else 0) | (BRR_COSTS_SMOOTH if smooth else 0)
+             | (BRR_COSTS_L32 if l32 else 0))
     check(lib.brr_schedule_from_costs(kmax, c_rng, c_div, flags, ctypes.byref(s)),
           "brr_schedule_from_costs")
     return s

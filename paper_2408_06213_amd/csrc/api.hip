@@ -87,7 +87,7 @@ const brr_schedule &paper6()
 uint64_t walk_schedule(const brr_schedule &sc, uint64_t n, uint64_t steps, bool check,
                        brr_status *err)
 {
-    const u128 two64 = (u128)1 << 64;
+    const u128 two64 = (u128)1 << (sc.words == BRR_WORDS_PHILOX32 ? 32 : 64); // 2^L
     uint64_t i = n, s = 0, done = 0;
     for (uint32_t g = 0; g < sc.nsteps && done < steps; ++g) {
         const uint64_t thr = sc.step[g].n_above, k = sc.step[g].k;
@@ -129,10 +129,12 @@ uint64_t walk_schedule(const brr_schedule &sc, uint64_t n, uint64_t steps, bool 
 brr_status check_structure(const brr_schedule &sc)
 {
     if (sc.nsteps == 0 || sc.nsteps > BRR_MAX_STEPS) return BRR_EINVAL;
+    if (sc.words > BRR_WORDS_CHACHA20 || sc.reserved != 0) return BRR_EINVAL;
     for (uint32_t g = 0; g < sc.nsteps; ++g) {
         const brr_step &st = sc.step[g];
         if (st.k == 0 || st.k > BRR_MAX_K) return BRR_EINVAL;
         if (st.form != BRR_FORM_MULTIPLY && st.form != BRR_FORM_DIVISION) return BRR_EINVAL;
+        if (st.form == BRR_FORM_DIVISION && sc.words == BRR_WORDS_PHILOX32) return BRR_EINVAL;
         if (st.n_above + 1 < st.k) return BRR_EINVAL;
         if (g > 0 && st.n_above > sc.step[g - 1].n_above) return BRR_EINVAL;
     }
@@ -359,6 +361,7 @@ hipError_t launch_tier(brr_plan *p, int tier, void *data, const uint64_t *offset
     GTierArgs a;
     std::memset(&a, 0, sizeof a);
     a.data = data;
+    a.words = p->ds.words;
     a.eb = p->eb;
     a.seed = seed;
     a.inst_base = inst;
@@ -857,9 +860,11 @@ std::map<std::pair<int, int>, uint32_t> g_dice_k; // (bit length, log2 count) ->
 
 bool same_steps(const brr_schedule &a, const brr_schedule &b)
 {
-    if (a.nsteps != b.nsteps || a.tail != b.tail) return false;
+    if (a.nsteps != b.nsteps || a.tail != b.tail || a.words != b.words) return false;
     for (uint32_t g = 0; g < a.nsteps; ++g)
-        if (a.step[g].n_above != b.step[g].n_above || a.step[g].k != b.step[g].k) return false;
+        if (a.step[g].n_above != b.step[g].n_above || a.step[g].k != b.step[g].k ||
+            a.step[g].form != b.step[g].form)
+            return false;
     return true;
 }
 
@@ -920,7 +925,12 @@ struct Candidate {
 std::vector<Candidate> candidates(const brr_plan *plan, uint64_t max_n)
 {
     std::vector<brr_schedule> scheds{plan->sched};
-    auto add = [&](const brr_schedule &c) {
+    // every candidate reads the plan's word stream: the stream is the
+    // caller's choice, only batch sizes and the mapping are tuned
+    const uint32_t words = plan->sched.words;
+    const int lflag = (words == BRR_WORDS_PHILOX32) ? BRR_COSTS_L32 : 0;
+    auto add = [&](brr_schedule c) {
+        c.words = words;
         if (check_for(c, max_n, max_n ? max_n - 1 : 0) != BRR_OK) return;
         for (const brr_schedule &o : scheds)
             if (same_steps(o, c)) return;
@@ -934,8 +944,8 @@ std::vector<Candidate> candidates(const brr_plan *plan, uint64_t max_n)
     for (uint32_t kmax = 3; kmax <= 8; ++kmax)
         for (const auto &r : ratios) {
             brr_schedule c;
-            if (brr_schedule_from_costs(kmax, r[0], r[1], BRR_COSTS_POW2 | BRR_COSTS_SMOOTH, &c) ==
-                BRR_OK)
+            if (brr_schedule_from_costs(kmax, r[0], r[1],
+                                        BRR_COSTS_POW2 | BRR_COSTS_SMOOTH | lflag, &c) == BRR_OK)
                 add(c);
         }
     std::vector<Candidate> out;

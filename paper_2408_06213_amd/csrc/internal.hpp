@@ -22,6 +22,7 @@ struct DevSched {
     uint64_t u[16];
     uint64_t u_tail;
     uint32_t form[16]; // BRR_FORM_* of each step (the tail batch multiplies)
+    uint32_t words;    // BRR_WORDS_*
 };
 
 // The kernels' form of a schedule that brr_schedule_check accepted.
@@ -37,6 +38,7 @@ inline DevSched dev_schedule(const brr_schedule &sc)
         d.form[g] = sc.step[g].form;
     }
     d.u_tail = sc.u_tail;
+    d.words = sc.words;
     return d;
 }
 
@@ -55,7 +57,8 @@ constexpr int kMaxSegs = 18; // 16 steps + one truncated batch + the last batch
 struct SegTable {
     Seg seg[kMaxSegs];
     uint32_t nseg;
-    uint32_t S; // batches in total
+    uint32_t S;     // batches in total
+    uint32_t words; // BRR_WORDS_* of the schedule
 };
 
 // Batches of the first `steps` Fisher-Yates steps of an n-element shuffle
@@ -107,6 +110,7 @@ __host__ __device__ inline void build_segments(uint32_t n, uint32_t steps, const
     uint32_t ns = 0;
     t.S = walk_segments(n, steps, sc, [&](const Seg &g) { t.seg[ns++] = g; });
     t.nseg = ns;
+    t.words = sc.words;
 }
 
 // Whether a device pointer is not aligned to its element size.
@@ -188,6 +192,7 @@ struct GTierArgs {
     const GItem *one_item;   // host, nitems == 1
     const SegTable *one_seg; // host, nitems == 1
     void *scratch;           // gtier_scratch_bytes(npos, eb)
+    uint32_t words;          // BRR_WORDS_* of the items' schedule
 };
 uint64_t gtier_scratch_bytes(uint64_t npos, uint32_t eb);
 // Positions (summed over items) one device-wide launch takes: indices are u32.

@@ -161,12 +161,17 @@ brr_status brr_schedule_from_costs(uint32_t kmax, double c_rng, double c_div, in
     if (!out || kmax < 1 || kmax > BRR_MAX_K) return BRR_EINVAL;
     brr_schedule s;
     std::memset(&s, 0, sizeof s);
-    if (kmax == 1) return brr_schedule_paper(1, out);
+    const uint32_t L = (pow2 & BRR_COSTS_L32) ? 32 : 64;
+    if (kmax == 1) {
+        const brr_status st = brr_schedule_paper(1, out);
+        if (L == 32) out->words = BRR_WORDS_PHILOX32;
+        return st;
+    }
     uint64_t nk[BRR_MAX_K + 1];
     if (pow2 & BRR_COSTS_SMOOTH) {
-        for (uint32_t k = 2; k <= kmax; ++k) nk[k] = threshold_nk_smooth(k, 64, c_rng, c_div);
+        for (uint32_t k = 2; k <= kmax; ++k) nk[k] = threshold_nk_smooth(k, L, c_rng, c_div);
     } else {
-        const brr_status st = brr_cost_thresholds(64, kmax, c_rng, c_div, nk);
+        const brr_status st = brr_cost_thresholds(L, kmax, c_rng, c_div, nk);
         if (st != BRR_OK) return st;
     }
     // one die while more than n_2 elements remain, then k dice while more than
@@ -185,7 +190,7 @@ brr_status brr_schedule_from_costs(uint32_t kmax, double c_rng, double c_div, in
         const uint64_t top = above[k];
         u128 u = 1;
         for (uint32_t l = 0; l < k; ++l) u *= top;
-        const uint64_t u0 = (u >= ((u128)1 << 64)) ? 0 : (uint64_t)u; // 0: exact product
+        const uint64_t u0 = (u >= ((u128)1 << L)) ? 0 : (uint64_t)u; // 0: exact product
         s.step[s.nsteps++] = brr_step{std::max<uint64_t>(lim, k - 1), k, 0, u0};
     }
     s.tail = 1;
@@ -193,6 +198,7 @@ brr_status brr_schedule_from_costs(uint32_t kmax, double c_rng, double c_div, in
     u128 tail = 1;
     for (uint32_t v = 2; v <= kmax; ++v) tail *= v;
     s.u_tail = (uint64_t)tail;
+    s.words = (L == 32) ? BRR_WORDS_PHILOX32 : BRR_WORDS_PHILOX64;
     *out = s;
     return BRR_OK;
 }

@@ -26,6 +26,7 @@
 // positions into the output (the input is untouched).
 #include <cstring>
 
+#include "chacha.hpp"
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -54,10 +55,73 @@ __device__ __forceinline__ void batch_at(uint32_t s, const Seg *seg, uint32_t ns
     form = seg[g].form;
 }
 
+// Word c of a schedule's stream (BRR_WORDS_*); the 32-bit stream's word is
+// returned zero-extended.
+__device__ uint64_t stream_word(uint32_t src, uint64_t c, const StreamKey &key)
+{
+    if (src == BRR_WORDS_CHACHA20) return chacha_word_at(c, key);
+    if (src == BRR_WORDS_PHILOX32) {
+        const uint64_t w = word_at(c >> 1, key);
+        return (c & 1) ? (w >> 32) : (uint64_t)(uint32_t)w;
+    }
+    return word_at(c, key);
+}
+
+// Words 2m and 2m + 1 of a schedule's stream (the first attempts of batches
+// 2m and 2m + 1): one Philox block, one 64-bit Philox word (its halves), or
+// one ChaCha20 block.
+__device__ __forceinline__ void first_pair(uint32_t src, uint64_t m, const StreamKey &key,
+                                           uint64_t &w0, uint64_t &w1)
+{
+    if (src == BRR_WORDS_PHILOX64) {
+        word_pair(m, key, w0, w1);
+    } else if (src == BRR_WORDS_PHILOX32) {
+        const uint64_t w = word_at(m, key);
+        w0 = (uint32_t)w;
+        w1 = w >> 32;
+    } else {
+        const WordPair p = chacha_pair_at(m, key);
+        w0 = p.w0;
+        w1 = p.w1;
+    }
+}
+
+// (a, r) <- b (x) r at L = 32 (r holds a 32-bit word).
+__device__ __forceinline__ uint32_t mul_roll32(uint32_t b, uint64_t &r)
+{
+    const uint64_t x = (uint64_t)b * (uint32_t)r;
+    r = (uint32_t)x;
+    return (uint32_t)(x >> 32);
+}
+
 // The accepted word of batch s (k dice at size i, guard u) whose first
-// attempt reads r.
+// attempt reads r, at L = 32: the chain on 32-bit words and Lemire's
+// threshold 2^32 mod B of the product B <= 2^32 (checked on the host).
+__device__ uint64_t accept_word32(uint32_t i, uint32_t k, uint64_t u, uint64_t r, uint32_t S,
+                                  uint32_t s, const StreamKey &key)
+{
+    uint64_t rr = r;
+    for (uint32_t l = 0; l < k; ++l) (void)mul_roll32(i - l, rr);
+    if (u == 0 || rr < u) {
+        uint64_t B = i;
+        for (uint32_t l = 1; l < k; ++l) B *= (uint64_t)(i - l);
+        const uint64_t t = (1ull << 32) % B;
+        // each attempt is rejected with probability t / 2^32 < 1/2; the cap
+        // only bounds the loop against corrupted inputs
+        for (uint64_t attempt = 1; rr < t && attempt <= kMaxAttempts; ++attempt) {
+            r = stream_word(BRR_WORDS_PHILOX32, attempt * S + s, key);
+            rr = r;
+            for (uint32_t l = 0; l < k; ++l) (void)mul_roll32(i - l, rr);
+        }
+    }
+    return r;
+}
+
+// The accepted word of batch s (k dice at size i, guard u) whose first
+// attempt reads r, on a 64-bit stream (rerolls read stream src).
 __device__ __forceinline__ uint64_t accept_word(uint32_t i, uint32_t k, uint64_t u, uint64_t r,
-                                                uint32_t S, uint32_t s, const StreamKey &key)
+                                                uint32_t S, uint32_t s, const StreamKey &key,
+                                                uint32_t src = BRR_WORDS_PHILOX64)
 {
     uint64_t rr = r;
     for (uint32_t l = 0; l < k; ++l) (void)mul_roll(i - l, rr);
@@ -68,7 +132,8 @@ __device__ __forceinline__ uint64_t accept_word(uint32_t i, uint32_t k, uint64_t
         // each attempt is rejected with probability t / 2^64 < 1/2; the cap
         // only bounds the loop against corrupted inputs
         for (uint64_t attempt = 1; rr < t && attempt <= kMaxAttempts; ++attempt) {
-            r = word_at(attempt * S + s, key);
+            r = (src == BRR_WORDS_PHILOX64) ? word_at(attempt * S + s, key)
+                                            : stream_word(src, attempt * S + s, key);
             rr = r;
             for (uint32_t l = 0; l < k; ++l) (void)mul_roll(i - l, rr);
         }
@@ -82,7 +147,7 @@ __device__ __forceinline__ uint64_t accept_word(uint32_t i, uint32_t k, uint64_t
 // Same words as the multiply form: both accept when the low half of B*r is
 // at least 2^64 mod B.
 __device__ uint64_t accept_div(uint32_t i, uint32_t k, uint64_t w, uint32_t S, uint32_t s,
-                               const StreamKey &key)
+                               const StreamKey &key, uint32_t src)
 {
     uint64_t B = i;
     for (uint32_t l = 1; l < k; ++l) B *= (uint64_t)(i - l);
@@ -90,7 +155,7 @@ __device__ uint64_t accept_div(uint32_t i, uint32_t k, uint64_t w, uint32_t S, u
     if (y < B) {
         const uint64_t t = pow2_64_mod(B);
         for (uint64_t attempt = 1; y < t && attempt <= kMaxAttempts; ++attempt) {
-            const uint64_t r = word_at(attempt * S + s, key);
+            const uint64_t r = stream_word(src, attempt * S + s, key);
             V = __umul64hi(B, r);
             y = B * r;
         }
@@ -98,19 +163,22 @@ __device__ uint64_t accept_div(uint32_t i, uint32_t k, uint64_t w, uint32_t S, u
     return V;
 }
 
-// The state a batch's dice are drawn from, given its first word: the
-// accepted word (multiply form) or the value V (division form).
-__device__ __forceinline__ uint64_t batch_state(uint32_t form, uint32_t i, uint32_t k, uint64_t u,
-                                                uint64_t w, uint32_t S, uint32_t s,
+// The state a batch's dice are drawn from, given its first word w of stream
+// src: the accepted word (multiply form, at L = 32 for the 32-bit stream) or
+// the value V (division form).
+__device__ __forceinline__ uint64_t batch_state(uint32_t src, uint32_t form, uint32_t i, uint32_t k,
+                                                uint64_t u, uint64_t w, uint32_t S, uint32_t s,
                                                 const StreamKey &key)
 {
-    return form == BRR_FORM_DIVISION ? accept_div(i, k, w, S, s, key)
-                                     : accept_word(i, k, u, w, S, s, key);
+    if (src == BRR_WORDS_PHILOX32) return accept_word32(i, k, u, w, S, s, key);
+    return form == BRR_FORM_DIVISION ? accept_div(i, k, w, S, s, key, src)
+                                     : accept_word(i, k, u, w, S, s, key, src);
 }
 
 // The next die of a batch, for bound b = i - l (l = 0, 1, ... in order).
-__device__ __forceinline__ uint32_t next_die(uint32_t form, uint32_t b, uint64_t &r)
+__device__ __forceinline__ uint32_t next_die(uint32_t src, uint32_t form, uint32_t b, uint64_t &r)
 {
+    if (src == BRR_WORDS_PHILOX32) return mul_roll32(b, r);
     return form == BRR_FORM_DIVISION ? div_digit(b, r) : mul_roll(b, r);
 }
 
@@ -163,11 +231,15 @@ __host__ __device__ inline uint32_t lds_bytes(uint32_t n)
     return ((2u * n + 3u) & ~3u) + 4u * (n + 1u) + ((2u * n + 3u) & ~3u);
 }
 
-template <typename Elem, int BLOCK, int P>
+// W: the schedule may read a stream other than the 64-bit Philox words (a
+// separate instantiation, so that the Philox-only kernels carry none of that
+// code); the same holds for every kernel below that takes W.
+template <typename Elem, int BLOCK, int P, bool W>
 __device__ void lds_tier_run(Elem *z, uint32_t n, uint32_t steps, uint32_t out_lo, Elem *out,
-                             const Seg *seg, uint32_t nseg, uint32_t S, const StreamKey &key,
-                             char *smem, uint32_t *wsum)
+                             const Seg *seg, uint32_t nseg, uint32_t S, uint32_t words,
+                             const StreamKey &key, char *smem, uint32_t *wsum)
 {
+    const uint32_t src = W ? words : BRR_WORDS_PHILOX64;
     const uint32_t tid = threadIdx.x;
     const uint32_t lo = n - steps; // positions lo..n-1 take a step
     uint16_t *jb = reinterpret_cast<uint16_t *>(smem);
@@ -179,7 +251,7 @@ __device__ void lds_tier_run(Elem *z, uint32_t n, uint32_t steps, uint32_t out_l
     // dice: thread takes batch pairs (2m, 2m+1), which share Philox block m
     for (uint32_t m = tid; 2 * m < S; m += BLOCK) {
         uint64_t w[2];
-        word_pair(m, key, w[0], w[1]);
+        first_pair(src, m, key, w[0], w[1]);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t s = 2 * m + h;
@@ -187,8 +259,9 @@ __device__ void lds_tier_run(Elem *z, uint32_t n, uint32_t steps, uint32_t out_l
                 uint32_t i, k, f;
                 uint64_t u;
                 batch_at(s, seg, nseg, i, k, u, f);
-                uint64_t r = batch_state(f, i, k, u, w[h], S, s, key);
-                for (uint32_t l = 0; l < k; ++l) jb[i - 1 - l] = (uint16_t)next_die(f, i - l, r);
+                uint64_t r = batch_state(src, f, i, k, u, w[h], S, s, key);
+                for (uint32_t l = 0; l < k; ++l)
+                    jb[i - 1 - l] = (uint16_t)next_die(src, f, i - l, r);
             }
         }
     }
@@ -277,7 +350,7 @@ __device__ __forceinline__ uint64_t take_claim(const DevClaim &c)
     return inst;
 }
 
-template <typename Elem, int BLOCK, int P>
+template <typename Elem, int BLOCK, int P, bool W>
 __global__ __launch_bounds__(BLOCK) void k_lds_single(Elem *z, uint32_t n, uint32_t steps,
                                                       uint32_t out_lo, Elem *out, SegTable st,
                                                       uint64_t seed, uint64_t inst,
@@ -291,10 +364,11 @@ __global__ __launch_bounds__(BLOCK) void k_lds_single(Elem *z, uint32_t n, uint3
     if (threadIdx.x == 0) claimed = claim.counter ? take_claim(claim) : 0;
     __syncthreads();
     const StreamKey key = make_key(seed, inst + claimed);
-    lds_tier_run<Elem, BLOCK, P>(z, n, steps, out_lo, out, seg, st.nseg, st.S, key, smem, wsum);
+    lds_tier_run<Elem, BLOCK, P, W>(z, n, steps, out_lo, out, seg, st.nseg, st.S, st.words, key,
+                                    smem, wsum);
 }
 
-template <typename Elem, int BLOCK, int P>
+template <typename Elem, int BLOCK, int P, bool W>
 __global__ __launch_bounds__(BLOCK) void k_lds_batched(Elem *data, const uint64_t *offsets,
                                                        const uint32_t *items, DevSched sc,
                                                        uint64_t seed, uint64_t inst_base)
@@ -308,8 +382,8 @@ __global__ __launch_bounds__(BLOCK) void k_lds_batched(Elem *data, const uint64_
     if (n <= 1) return; // the whole block leaves together
     if (threadIdx.x == 0) build_segments(n, n - 1, sc, st);
     __syncthreads();
-    lds_tier_run<Elem, BLOCK, P>(data + off, n, n - 1, 0, nullptr, st.seg, st.nseg, st.S,
-                                 make_key(seed, inst_base + q), smem, wsum);
+    lds_tier_run<Elem, BLOCK, P, W>(data + off, n, n - 1, 0, nullptr, st.seg, st.nseg, st.S,
+                                    st.words, make_key(seed, inst_base + q), smem, wsum);
 }
 
 // ---------------------------------------------------------------------------
@@ -425,13 +499,14 @@ __device__ __forceinline__ void lane_segment(uint8_t *a, const Seg &g, uint32_t 
     }
 }
 
-template <typename Elem>
+template <typename Elem, bool W>
 __global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const uint64_t *offsets,
                                                             const uint32_t *items, uint32_t nitems,
                                                             uint32_t max_n, DevSched sc,
                                                             uint64_t seed, uint64_t inst_base)
 {
     constexpr uint32_t V = 16 / sizeof(Elem); // elements per 16-byte vector
+    const uint32_t src = W ? sc.words : BRR_WORDS_PHILOX64;
     extern __shared__ __align__(16) char smem[];
     const LaneLds L = lane_lds(max_n, sizeof(Elem));
     const uint32_t C = L.stage_cap, RW = L.row_words;
@@ -520,8 +595,8 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const u
         const uint32_t S = walk_segments(n, n - 1, sc, [](const Seg &) {});
         uint64_t w_odd = 0;
         walk_segments(n, n - 1, sc, [&](const Seg &g) {
-            // the division form takes the general path
-            switch (g.form == BRR_FORM_DIVISION ? 0u : g.k) {
+            // the division form and the other word streams take the general path
+            switch ((g.form == BRR_FORM_DIVISION || src != BRR_WORDS_PHILOX64) ? 0u : g.k) {
             case 1: lane_segment<1>(a, g, S, key, w_odd); break;
             case 2: lane_segment<2>(a, g, S, key, w_odd); break;
             case 3: lane_segment<3>(a, g, S, key, w_odd); break;
@@ -535,12 +610,12 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const u
                     const uint32_t s = g.s0 + b, i = g.i0 - b * g.k;
                     uint64_t w;
                     if ((s & 1) == 0)
-                        word_pair(s >> 1, key, w, w_odd);
+                        first_pair(src, s >> 1, key, w, w_odd);
                     else
                         w = w_odd;
-                    uint64_t r = batch_state(g.form, i, g.k, g.u, w, S, s, key);
+                    uint64_t r = batch_state(src, g.form, i, g.k, g.u, w, S, s, key);
                     for (uint32_t l = 0; l < g.k; ++l) {
-                        const uint32_t j = next_die(g.form, i - l, r), p = i - 1 - l;
+                        const uint32_t j = next_die(src, g.form, i - l, r), p = i - 1 - l;
                         const uint8_t x = a[p];
                         a[p] = a[j];
                         a[j] = x;
@@ -671,7 +746,7 @@ __device__ __forceinline__ uint32_t peel_query(const PeelState &ps, uint32_t q, 
 //    targets q, else z[q];
 //  - a target q below the peel receives, from the smallest step that targets
 //    it, the value at root of that step.
-template <typename Elem>
+template <typename Elem, bool W>
 __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const uint64_t *offsets,
                                                              const uint32_t *items, DevSched sc,
                                                              uint64_t seed, uint64_t inst_base)
@@ -716,7 +791,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
         const uint32_t s_end = next_s, i_end = next_i, H = i_begin - i_end;
         for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += kWgThreads) {
             uint64_t w[2];
-            word_pair(m, key, w[0], w[1]);
+            first_pair((W ? st.words : BRR_WORDS_PHILOX64), m, key, w[0], w[1]);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const uint32_t s = 2 * m + h;
@@ -724,8 +799,9 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
                 uint32_t i, k, f;
                 uint64_t u;
                 batch_at(s, st.seg, st.nseg, i, k, u, f);
-                uint64_t r = batch_state(f, i, k, u, w[h], st.S, s, key);
-                for (uint32_t l = 0; l < k; ++l) qof[i - 1 - l - i_end] = next_die(f, i - l, r);
+                uint64_t r = batch_state((W ? st.words : BRR_WORDS_PHILOX64), f, i, k, u, w[h], st.S, s, key);
+                for (uint32_t l = 0; l < k; ++l)
+                    qof[i - 1 - l - i_end] = next_die((W ? st.words : BRR_WORDS_PHILOX64), f, i - l, r);
             }
         }
         __syncthreads();
@@ -962,6 +1038,7 @@ __global__ __launch_bounds__(256) void k_gp_init(GProblem P, GArrays g, uint64_t
     }
 }
 
+template <bool W>
 __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t seed)
 {
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < P.npairs;
@@ -969,11 +1046,12 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
         const uint32_t i = P.items ? find_item(P.pair_tile, P.pair_base, P.nitems, w) : 0u;
         const GItem &it = item_at(P, i);
         const SegTable &st = segs_at(P, i);
+        const uint32_t src = W ? st.words : BRR_WORDS_PHILOX64;
         const uint32_t m = (uint32_t)(w - (P.items ? P.pair_base[i] : 0));
         const uint64_t ib = P.inst_base + (P.claim.counter ? *P.claim.slot : 0);
         const StreamKey key = make_key(seed, ib + it.inst);
         uint64_t wd[2];
-        word_pair(m, key, wd[0], wd[1]);
+        first_pair(src, m, key, wd[0], wd[1]);
         uint32_t *jj = g.jj + it.pos_base, *sk = g.key[0] + it.pos_base;
         uint32_t *sv = g.val[0] + it.pos_base;
         const uint32_t tb = (uint32_t)it.pos_base;
@@ -984,10 +1062,10 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
             uint32_t i0, k, f;
             uint64_t u;
             batch_at(s, st.seg, st.nseg, i0, k, u, f);
-            uint64_t r = batch_state(f, i0, k, u, wd[h], st.S, s, key);
+            uint64_t r = batch_state(src, f, i0, k, u, wd[h], st.S, s, key);
             for (uint32_t l = 0; l < k; ++l) {
                 const uint32_t p = i0 - 1 - l;
-                const uint32_t a = next_die(f, i0 - l, r);
+                const uint32_t a = next_die(src, f, i0 - l, r);
                 jj[p] = a;
                 sk[p] = (a < p) ? tb + a : kSortNone;
                 sv[p] = tb + p;
@@ -1006,6 +1084,7 @@ __global__ __launch_bounds__(256) void k_gc_init(GProblem P, uint32_t *cnt, uint
 
 constexpr uint32_t kFastK = 6; // batches up to this size keep their dice in registers
 
+template <bool W>
 __global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t seed)
 {
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < P.npairs;
@@ -1013,11 +1092,12 @@ __global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t
         const uint32_t i = P.items ? find_item(P.pair_tile, P.pair_base, P.nitems, w) : 0u;
         const GItem &it = item_at(P, i);
         const SegTable &st = segs_at(P, i);
+        const uint32_t src = W ? st.words : BRR_WORDS_PHILOX64;
         const uint32_t m = (uint32_t)(w - (P.items ? P.pair_base[i] : 0));
         const uint64_t ib = P.inst_base + (P.claim.counter ? *P.claim.slot : 0);
         const StreamKey key = make_key(seed, ib + it.inst);
         uint64_t wd[2];
-        word_pair(m, key, wd[0], wd[1]);
+        first_pair(src, m, key, wd[0], wd[1]);
         uint32_t i0[2] = {0, 0}, kk[2] = {0, 0}, f[2] = {0, 0};
         uint64_t r[2] = {0, 0};
 #pragma unroll
@@ -1026,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t
             if (s >= st.S) continue;
             uint64_t u;
             batch_at(s, st.seg, st.nseg, i0[h], kk[h], u, f[h]);
-            r[h] = batch_state(f[h], i0[h], kk[h], u, wd[h], st.S, s, key);
+            r[h] = batch_state(src, f[h], i0[h], kk[h], u, wd[h], st.S, s, key);
         }
         uint32_t *jj = g.jj + it.pos_base, *slot = g.key[0] + it.pos_base;
         uint32_t *cnt = g.cnt + it.pos_base;
@@ -1039,7 +1119,7 @@ __global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t
 #pragma unroll
                 for (uint32_t l = 0; l < kFastK; ++l)
                     if (l < kk[h]) {
-                        a[h * kFastK + l] = next_die(f[h], i0[h] - l, r[h]);
+                        a[h * kFastK + l] = next_die(src, f[h], i0[h] - l, r[h]);
                         jj[i0[h] - 1 - l] = a[h * kFastK + l];
                     }
 #pragma unroll
@@ -1059,7 +1139,7 @@ __global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t
             for (int h = 0; h < 2; ++h)
                 for (uint32_t l = 0; l < kk[h]; ++l) {
                     const uint32_t p = i0[h] - 1 - l;
-                    const uint32_t a = next_die(f[h], i0[h] - l, r[h]);
+                    const uint32_t a = next_die(src, f[h], i0[h] - l, r[h]);
                     jj[p] = a;
                     if (a < p) slot[p] = atomicAdd(&cnt[a], 1u);
                 }
@@ -1357,14 +1437,14 @@ void scan_exclusive(uint32_t *a, uint32_t *tiles, uint64_t len, hipStream_t stre
     k_gp_scan_apply<<<(uint32_t)ntiles, kScanThreads, 0, stream>>>(a, tiles, len);
 }
 
-template <typename Elem>
+template <typename Elem, bool W>
 hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratch,
                       hipStream_t stream)
 {
     const GArrays g = garrays(scratch, P.npos);
     if (P.npos <= kCountMaxPositions) {
         k_gc_init<<<grid_for(P.npos + 1, 256), 256, 0, stream>>>(P, g.cnt, P.npos + 1);
-        k_gc_dice<<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
+        k_gc_dice<W><<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
         scan_exclusive(g.cnt, g.tiles, P.npos + 1, stream);
         k_gc_scatter<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
         k_gc_links<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
@@ -1375,7 +1455,7 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
         return hipGetLastError();
     }
     k_gp_init<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, P.npos);
-    k_gp_dice<<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
+    k_gp_dice<W><<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
     // targets are < npos, so bit_length(npos) bits order them all, and the
     // "none" key (all ones) after them
     uint32_t bits = 0;
@@ -1395,7 +1475,7 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
     return hipGetLastError();
 }
 
-template <typename Elem>
+template <typename Elem, bool W>
 hipError_t lds_single_t(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, void *out,
                         const DevSched &sc, uint64_t seed, uint64_t inst, const DevClaim &claim,
                         hipStream_t stream)
@@ -1406,48 +1486,48 @@ hipError_t lds_single_t(void *data, uint32_t n, uint32_t steps, uint32_t out_lo,
     Elem *z = static_cast<Elem *>(data), *o = static_cast<Elem *>(out);
     // the smallest block of the size classes that holds the array
     if (n <= lds_class_max_n(0))
-        k_lds_single<Elem, 64, kWaveP><<<1, 64, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
+        k_lds_single<Elem, 64, kWaveP, W><<<1, 64, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
                                                                  inst, claim);
     else if (n <= lds_class_max_n(1))
-        k_lds_single<Elem, 256, 8><<<1, 256, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
+        k_lds_single<Elem, 256, 8, W><<<1, 256, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
                                                               inst, claim);
     else if (n <= lds_class_max_n(2))
-        k_lds_single<Elem, 256, 16><<<1, 256, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
+        k_lds_single<Elem, 256, 16, W><<<1, 256, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
                                                                inst, claim);
     else if (n <= lds_class_max_n(3))
-        k_lds_single<Elem, 512, 16><<<1, 512, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
+        k_lds_single<Elem, 512, 16, W><<<1, 512, bytes, stream>>>(z, n, steps, out_lo, o, st, seed,
                                                                inst, claim);
     else
-        k_lds_single<Elem, kWgThreads, kWgP><<<1, kWgThreads, bytes, stream>>>(
+        k_lds_single<Elem, kWgThreads, kWgP, W><<<1, kWgThreads, bytes, stream>>>(
             z, n, steps, out_lo, o, st, seed, inst, claim);
     return hipGetLastError();
 }
 
-template <typename Elem, int BLOCK, int P>
+template <typename Elem, int BLOCK, int P, bool W>
 hipError_t batched_lds_t(void *data, const uint64_t *offsets, const uint32_t *items,
                          uint32_t nitems, uint32_t max_n, const DevSched &sc, uint64_t seed,
                          uint64_t inst_base, hipStream_t stream)
 {
     if (nitems == 0) return hipSuccess;
     const uint32_t bytes = lds_bytes(max_n);
-    k_lds_batched<Elem, BLOCK, P><<<nitems, BLOCK, bytes, stream>>>(static_cast<Elem *>(data),
+    k_lds_batched<Elem, BLOCK, P, W><<<nitems, BLOCK, bytes, stream>>>(static_cast<Elem *>(data),
                                                                   offsets, items, sc, seed,
                                                                   inst_base);
     return hipGetLastError();
 }
 
-template <typename Elem>
+template <typename Elem, bool W>
 hipError_t batched_peel_t(void *data, const uint64_t *offsets, const uint32_t *items,
                           uint32_t nitems, const DevSched &sc, uint64_t seed, uint64_t inst_base,
                           hipStream_t stream)
 {
     if (nitems == 0) return hipSuccess;
-    k_peel_batched<Elem><<<nitems, kWgThreads, 0, stream>>>(static_cast<Elem *>(data), offsets,
+    k_peel_batched<Elem, W><<<nitems, kWgThreads, 0, stream>>>(static_cast<Elem *>(data), offsets,
                                                            items, sc, seed, inst_base);
     return hipGetLastError();
 }
 
-template <typename Elem>
+template <typename Elem, bool W>
 hipError_t batched_lane_t(void *data, const uint64_t *offsets, const uint32_t *items,
                           uint32_t nitems, uint32_t max_n, const DevSched &sc, uint64_t seed,
                           uint64_t inst_base, hipStream_t stream)
@@ -1456,7 +1536,7 @@ hipError_t batched_lane_t(void *data, const uint64_t *offsets, const uint32_t *i
     const uint32_t arrays = lane_arrays(max_n);
     const uint32_t blocks = (nitems + arrays - 1) / arrays;
     const LaneLds L = lane_lds(max_n, sizeof(Elem));
-    k_lane_batched<Elem><<<blocks, kLaneItems, L.bytes, stream>>>(
+    k_lane_batched<Elem, W><<<blocks, kLaneItems, L.bytes, stream>>>(
         static_cast<Elem *>(data), offsets, items, nitems, max_n, sc, seed, inst_base);
     return hipGetLastError();
 }
@@ -1471,10 +1551,15 @@ hipError_t launch_batched_lane(void *data, const uint64_t *offsets, const uint32
                                uint64_t seed, uint64_t inst_base, hipStream_t stream)
 {
     if (max_n > lane_tier_max_n()) return hipErrorInvalidValue;
-    return eb == 4 ? batched_lane_t<uint32_t>(data, offsets, items, nitems, max_n, sc, seed,
-                                              inst_base, stream)
-                   : batched_lane_t<uint64_t>(data, offsets, items, nitems, max_n, sc, seed,
-                                              inst_base, stream);
+    if (sc.words != BRR_WORDS_PHILOX64)
+        return eb == 4 ? batched_lane_t<uint32_t, true>(data, offsets, items, nitems, max_n, sc,
+                                                        seed, inst_base, stream)
+                       : batched_lane_t<uint64_t, true>(data, offsets, items, nitems, max_n, sc,
+                                                        seed, inst_base, stream);
+    return eb == 4 ? batched_lane_t<uint32_t, false>(data, offsets, items, nitems, max_n, sc, seed,
+                                                     inst_base, stream)
+                   : batched_lane_t<uint64_t, false>(data, offsets, items, nitems, max_n, sc, seed,
+                                                     inst_base, stream);
 }
 uint32_t peel_tier_max_n() { return kPeelTierMax; }
 
@@ -1482,46 +1567,46 @@ hipError_t launch_batched_peel(void *data, const uint64_t *offsets, const uint32
                                uint32_t nitems, uint32_t eb, const DevSched &sc, uint64_t seed,
                                uint64_t inst_base, hipStream_t stream)
 {
-    return eb == 4 ? batched_peel_t<uint32_t>(data, offsets, items, nitems, sc, seed, inst_base,
-                                              stream)
-                   : batched_peel_t<uint64_t>(data, offsets, items, nitems, sc, seed, inst_base,
-                                              stream);
+    if (sc.words != BRR_WORDS_PHILOX64)
+        return eb == 4 ? batched_peel_t<uint32_t, true>(data, offsets, items, nitems, sc, seed,
+                                                        inst_base, stream)
+                       : batched_peel_t<uint64_t, true>(data, offsets, items, nitems, sc, seed,
+                                                        inst_base, stream);
+    return eb == 4 ? batched_peel_t<uint32_t, false>(data, offsets, items, nitems, sc, seed,
+                                                     inst_base, stream)
+                   : batched_peel_t<uint64_t, false>(data, offsets, items, nitems, sc, seed,
+                                                     inst_base, stream);
 }
 
 hipError_t prepare_shuffle_kernels()
 {
     const int wg = (int)lds_bytes(kWgThreads * kWgP);
-    const void *fns[] = {(const void *)k_lds_single<uint32_t, kWgThreads, kWgP>,
-                         (const void *)k_lds_single<uint64_t, kWgThreads, kWgP>,
-                         (const void *)k_lds_single<uint32_t, 512, 16>,
-                         (const void *)k_lds_single<uint64_t, 512, 16>,
-                         (const void *)k_lds_batched<uint32_t, 64, kWaveP>,
-                         (const void *)k_lds_batched<uint64_t, 64, kWaveP>,
-                         (const void *)k_lds_batched<uint32_t, 256, 8>,
-                         (const void *)k_lds_batched<uint64_t, 256, 8>,
-                         (const void *)k_lds_batched<uint32_t, 256, 16>,
-                         (const void *)k_lds_batched<uint64_t, 256, 16>,
-                         (const void *)k_lds_batched<uint32_t, 512, 16>,
-                         (const void *)k_lds_batched<uint64_t, 512, 16>,
-                         (const void *)k_lds_batched<uint32_t, kWgThreads, kWgP>,
-                         (const void *)k_lds_batched<uint64_t, kWgThreads, kWgP>};
-    const int bytes[] = {wg,
-                         wg,
-                         (int)lds_bytes(lds_class_max_n(3)),
-                         (int)lds_bytes(lds_class_max_n(3)),
-                         (int)lds_bytes(lds_class_max_n(0)),
-                         (int)lds_bytes(lds_class_max_n(0)),
-                         (int)lds_bytes(lds_class_max_n(1)),
-                         (int)lds_bytes(lds_class_max_n(1)),
-                         (int)lds_bytes(lds_class_max_n(2)),
-                         (int)lds_bytes(lds_class_max_n(2)),
-                         (int)lds_bytes(lds_class_max_n(3)),
-                         (int)lds_bytes(lds_class_max_n(3)),
-                         wg,
-                         wg};
-    for (int f = 0; f < (int)(sizeof(bytes) / sizeof(bytes[0])); ++f) {
+    const int c0 = (int)lds_bytes(lds_class_max_n(0)), c1 = (int)lds_bytes(lds_class_max_n(1));
+    const int c2 = (int)lds_bytes(lds_class_max_n(2)), c3 = (int)lds_bytes(lds_class_max_n(3));
+    struct Attr {
+        const void *fn;
+        int bytes;
+    };
+#define BRR_LDS_ATTRS(W)                                                                   \
+    {(const void *)k_lds_single<uint32_t, kWgThreads, kWgP, W>, wg},                       \
+        {(const void *)k_lds_single<uint64_t, kWgThreads, kWgP, W>, wg},                   \
+        {(const void *)k_lds_single<uint32_t, 512, 16, W>, c3},                            \
+        {(const void *)k_lds_single<uint64_t, 512, 16, W>, c3},                            \
+        {(const void *)k_lds_batched<uint32_t, 64, kWaveP, W>, c0},                        \
+        {(const void *)k_lds_batched<uint64_t, 64, kWaveP, W>, c0},                        \
+        {(const void *)k_lds_batched<uint32_t, 256, 8, W>, c1},                            \
+        {(const void *)k_lds_batched<uint64_t, 256, 8, W>, c1},                            \
+        {(const void *)k_lds_batched<uint32_t, 256, 16, W>, c2},                           \
+        {(const void *)k_lds_batched<uint64_t, 256, 16, W>, c2},                           \
+        {(const void *)k_lds_batched<uint32_t, 512, 16, W>, c3},                           \
+        {(const void *)k_lds_batched<uint64_t, 512, 16, W>, c3},                           \
+        {(const void *)k_lds_batched<uint32_t, kWgThreads, kWgP, W>, wg},                  \
+        {(const void *)k_lds_batched<uint64_t, kWgThreads, kWgP, W>, wg}
+    const Attr attrs[] = {BRR_LDS_ATTRS(false), BRR_LDS_ATTRS(true)};
+#undef BRR_LDS_ATTRS
+    for (const Attr &a : attrs) {
         const hipError_t e =
-            hipFuncSetAttribute(fns[f], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[f]);
+            hipFuncSetAttribute(a.fn, hipFuncAttributeMaxDynamicSharedMemorySize, a.bytes);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1537,10 +1622,15 @@ hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t ou
 {
     if (n > lds_tier_max_n() || steps == 0 || steps >= n || out_lo > n - steps)
         return hipErrorInvalidValue;
-    return eb == 4 ? lds_single_t<uint32_t>(data, n, steps, out_lo, out, sc, seed, inst, claim,
-                                            stream)
-                   : lds_single_t<uint64_t>(data, n, steps, out_lo, out, sc, seed, inst, claim,
-                                            stream);
+    if (sc.words != BRR_WORDS_PHILOX64)
+        return eb == 4 ? lds_single_t<uint32_t, true>(data, n, steps, out_lo, out, sc, seed, inst,
+                                                      claim, stream)
+                       : lds_single_t<uint64_t, true>(data, n, steps, out_lo, out, sc, seed, inst,
+                                                      claim, stream);
+    return eb == 4 ? lds_single_t<uint32_t, false>(data, n, steps, out_lo, out, sc, seed, inst,
+                                                   claim, stream)
+                   : lds_single_t<uint64_t, false>(data, n, steps, out_lo, out, sc, seed, inst,
+                                                   claim, stream);
 }
 
 uint64_t one_scratch_bytes(uint64_t n, uint32_t eb)
@@ -1563,6 +1653,7 @@ hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, u
     a.eb = eb;
     a.seed = seed;
     a.claim = claim;
+    a.words = ds.words;
     a.nitems = 1;
     a.npos = n;
     a.npairs = (st.S + 1) / 2;
@@ -1599,8 +1690,11 @@ hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream)
         P.pos_tile = a.pos_tile;
         P.pair_tile = a.pair_tile;
     }
-    return a.eb == 4 ? gproblem_t<uint32_t>(P, a.data, a.seed, a.scratch, stream)
-                     : gproblem_t<uint64_t>(P, a.data, a.seed, a.scratch, stream);
+    if (a.words != BRR_WORDS_PHILOX64)
+        return a.eb == 4 ? gproblem_t<uint32_t, true>(P, a.data, a.seed, a.scratch, stream)
+                         : gproblem_t<uint64_t, true>(P, a.data, a.seed, a.scratch, stream);
+    return a.eb == 4 ? gproblem_t<uint32_t, false>(P, a.data, a.seed, a.scratch, stream)
+                     : gproblem_t<uint64_t, false>(P, a.data, a.seed, a.scratch, stream);
 }
 
 uint32_t lds_class_max_n(int c)
@@ -1615,11 +1709,16 @@ hipError_t launch_batched_lds(int c, void *data, const uint64_t *offsets, const 
                               uint64_t seed, uint64_t inst_base, hipStream_t stream)
 {
     if (max_n > lds_class_max_n(c)) return hipErrorInvalidValue;
-#define BRR_LDS_CLASS(B, P)                                                                    \
-    return eb == 4 ? batched_lds_t<uint32_t, B, P>(data, offsets, items, nitems, max_n, sc, seed,  \
-                                                   inst_base, stream)                          \
-                   : batched_lds_t<uint64_t, B, P>(data, offsets, items, nitems, max_n, sc, seed,  \
-                                                   inst_base, stream)
+    const bool w = sc.words != BRR_WORDS_PHILOX64;
+#define BRR_LDS_CLASS(B, P)                                                                      \
+    return w ? (eb == 4 ? batched_lds_t<uint32_t, B, P, true>(data, offsets, items, nitems, max_n, \
+                                                              sc, seed, inst_base, stream)        \
+                        : batched_lds_t<uint64_t, B, P, true>(data, offsets, items, nitems, max_n, \
+                                                              sc, seed, inst_base, stream))       \
+             : (eb == 4 ? batched_lds_t<uint32_t, B, P, false>(data, offsets, items, nitems,       \
+                                                               max_n, sc, seed, inst_base, stream) \
+                        : batched_lds_t<uint64_t, B, P, false>(data, offsets, items, nitems,       \
+                                                               max_n, sc, seed, inst_base, stream))
     switch (c) {
     case 0: BRR_LDS_CLASS(64, kWaveP);
     case 1: BRR_LDS_CLASS(256, 8);

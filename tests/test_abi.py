@@ -75,6 +75,38 @@ def test_kmax_schedule_host(orc, kcap):
         brr.brr_schedule_kmax(17)
 
 
+def test_word_stream_schedules_host(orc):
+    """Word streams in schedules: the L = 32 cost model gives Table 2's L = 32
+    column and reads the 32-bit stream; products are checked against 2^L;
+    division steps need 64-bit words; unknown streams are rejected."""
+    from paper_2408_06213_amd import brr
+
+    s = brr.brr_schedule_from_costs(4, pow2=False, smooth=False, l32=True)
+    table = {(int(k), int(L)): int(n) for k, L, n in (r.split()[:3] for r in golden_rows("table2.txt"))}
+    assert s.words == brr.BRR_WORDS_PHILOX32
+    assert [st[0] for st in s.steps()[:3]] == [table[(2, 32)], table[(3, 32)], table[(4, 32)]]
+    o = orc.Schedule.from_segments(s.steps(), tail=bool(s.tail), u_tail=s.u_tail, words=1)
+    for n in (2, 5, 110, 582, 20725, 10**6, 2**32 - 1):
+        assert brr.brr_schedule_check(s, n) == brr.BRR_OK
+        if n < 2**30:
+            assert brr.brr_schedule_batches(s, n, n - 1) == orc.count_batches(n, n - 1, o)
+    # a pair at 2^17 elements is 2^34 > 2^32
+    pairs32 = brr.brr_schedule.from_steps([(1, 2, 0)], tail=False, words=brr.BRR_WORDS_PHILOX32)
+    assert brr.brr_schedule_check(pairs32, 60000) == brr.BRR_OK
+    assert brr.brr_schedule_check(pairs32, 1 << 17) == brr.BRR_EOVERFLOW
+    div32 = brr.brr_schedule.from_steps([(1, 2, 0)], tail=False, forms=[1],
+                                        words=brr.BRR_WORDS_PHILOX32)
+    assert brr.brr_schedule_check(div32, 100) == brr.BRR_EINVAL
+    divcc = brr.brr_schedule.from_steps([(1, 2, 0)], tail=False, forms=[1],
+                                        words=brr.BRR_WORDS_CHACHA20)
+    assert brr.brr_schedule_check(divcc, 100) == brr.BRR_OK
+    bad = brr.brr_schedule.from_steps([(1, 1, 0)], tail=False, words=3)
+    assert brr.brr_schedule_check(bad, 100) == brr.BRR_EINVAL
+    bad = brr.brr_schedule.from_steps([(1, 1, 0)], tail=False)
+    bad.reserved = 1
+    assert brr.brr_schedule_check(bad, 100) == brr.BRR_EINVAL
+
+
 def test_naive2_schedule_host(orc):
     """The division-form comparison schedule: same steps, forms and batch
     counts on the host side as the oracle's; unknown forms are rejected."""

@@ -346,3 +346,78 @@ def test_kmax_batched_every_tier(gpu, orc):
     assert orc.shuffle_batched(want, off, os_, 41, 9) == 0
     for got in results:
         assert np.array_equal(got, want)
+
+
+# ---------------------------------------------------------------------------
+# Other word streams: 32-bit halves (L = 32) and ChaCha20 words
+# ---------------------------------------------------------------------------
+
+def word_stream_schedules(gpu, orc, words):
+    if words == "l32":  # Table 2's L = 32 column, exact thresholds
+        gs = gpu.brr_schedule_from_costs(4, pow2=False, smooth=False, l32=True)
+        os_ = orc.Schedule.from_segments(gs.steps(), tail=bool(gs.tail), u_tail=gs.u_tail,
+                                         words=orc.WORDS_PHILOX32)
+    else:  # shuffle_6 on ChaCha20 words
+        steps = gpu.brr_schedule_paper(6).steps()
+        gs = gpu.brr_schedule.from_steps(steps, tail=True, u_tail=720,
+                                         words=gpu.BRR_WORDS_CHACHA20)
+        os_ = orc.Schedule.from_segments(steps, tail=True, u_tail=720, words=orc.WORDS_CHACHA20)
+    return gs, os_
+
+
+@pytest.mark.parametrize("words", ["l32", "chacha"])
+@pytest.mark.parametrize("tier", ["lds", "global"])
+def test_word_stream_shuffle_parity(gpu, orc, words, tier):
+    gs, os_ = word_stream_schedules(gpu, orc, words)
+    sizes = LDS_SIZES if tier == "lds" else GLOBAL_SIZES
+    for n in sizes:
+        say("shuffle", words, tier, n)
+        a = np.arange(n, dtype=np.uint64) * 11 + 5
+        got = gpu_shuffle(gpu, a, gs, seed=808, inst=n)
+        want = a.copy()
+        assert orc.shuffle(want, os_, 808, n) == 0
+        assert np.array_equal(got, want), (words, n)
+
+
+@pytest.mark.parametrize("words", ["l32", "chacha"])
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_word_stream_batched_every_tier(gpu, orc, words, dtype):
+    gs, os_ = word_stream_schedules(gpu, orc, words)
+    sizes = np.concatenate([np.arange(258), [511, 512, 513, 2049, 4097, 8193, 16384, 16385, 40000,
+                                             (1 << 20), (1 << 20) + 1]]).astype(np.uint64)
+    say("batched", words, np.dtype(dtype).name)
+    data, off, results = run_batched(gpu, sizes, dtype, seed=27, inst_base=6, reps=2, sched=gs,
+                                     lane_max=256)
+    want = data.copy()
+    assert orc.shuffle_batched(want, off, os_, 27, 6) == 0
+    for got in results:
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("words", ["l32", "chacha"])
+def test_word_stream_sample_parity(gpu, orc, words):
+    gs, os_ = word_stream_schedules(gpu, orc, words)
+    rng = np.random.default_rng(12)
+    for n, m in ((5, 5), (1000, 100), (16384, 1638), (100003, 10000), ((1 << 21) + 1, 1000)):
+        say("sample", words, n, m)
+        data = rng.integers(0, 2**31, size=n).astype(np.uint32)
+        d = to_dev(data)
+        out = to_dev(np.zeros(m, np.uint32))
+        gpu.check(gpu.brr_sample(d, n, m, 4, out, gs, 35, n), "brr_sample")
+        assert gpu.brr_sync_status() == 0
+        err, want = orc.sample(data, m, os_, 35, n)
+        assert err == 0 and np.array_equal(to_host(out), want), (words, n, m)
+
+
+def test_chacha_division_schedule(gpu, orc):
+    """Division-form pairs on ChaCha20 words."""
+    steps = [(1 << 32, 1, 0), (1, 2, 0)]
+    gs = gpu.brr_schedule.from_steps(steps, tail=False, forms=[1, 1], words=gpu.BRR_WORDS_CHACHA20)
+    os_ = orc.Schedule.from_segments(steps, tail=False, forms=[1, 1], words=orc.WORDS_CHACHA20)
+    for n in (9, 5000, 70001):
+        say("chacha division", n)
+        a = np.arange(n, dtype=np.uint32)
+        got = gpu_shuffle(gpu, a, gs, seed=3, inst=1)
+        want = a.copy()
+        assert orc.shuffle(want, os_, 3, 1) == 0
+        assert np.array_equal(got, want), n
