@@ -12,8 +12,10 @@ the bound product, dice by successive remainders) and with bounds below
 shuffles of 256 elements, 20,000 ragged shuffles (also autotuned,
 exhaustively and by the learned model), one 10,000-element shuffle and one
 2^26-element shuffle, each batched (shuffle_6), unbatched (k = 1) and with
-the division-based pairs of the paper's comparison (naive shuffle_2), and
-the serving loop's latency under Poisson load.
+the division-based pairs of the paper's comparison (naive shuffle_2),
+shuffle_6 and k = 1 again on ChaCha20 words, and the L = 32 cost-model
+schedule on 32-bit words; and the serving loop's latency under Poisson
+load.
 
 Prints one JSON line. Timing: HIP events recorded on the stream the kernels
 are launched on (torch's current stream), K steps after W warmup steps.
@@ -195,8 +197,16 @@ def secondary(brr, workloads, up, steps, only=None):
     out = {}
     s6 = brr.brr_schedule_paper(6)
     s1 = brr.brr_schedule_paper(1)
-    # the paper's comparisons: unbatched (k1) and two dice by division (naive2)
-    scheds = (("k6", s6), ("k1", s1), ("naive2", brr.brr_schedule_naive2()))
+    # the paper's comparisons: unbatched (k1) and two dice by division (naive2);
+    # shuffle_6 and k1 again on ChaCha20 words (its slow generator); the
+    # L = 32 cost-model schedule on 32-bit words
+    cc6 = brr.brr_schedule.from_steps(s6.steps(), tail=True, u_tail=720,
+                                      words=brr.BRR_WORDS_CHACHA20)
+    cc1 = brr.brr_schedule.from_steps(s1.steps(), tail=bool(s1.tail), u_tail=s1.u_tail,
+                                      words=brr.BRR_WORDS_CHACHA20)
+    l32 = brr.brr_schedule_from_costs(6, l32=True)
+    scheds = (("k6", s6), ("k1", s1), ("naive2", brr.brr_schedule_naive2()),
+              ("k6_chacha20", cc6), ("k1_chacha20", cc1), ("costs_l32", l32))
 
     def batched(sizes, tag):
         off = workloads.csr_offsets(sizes)
@@ -221,6 +231,7 @@ def secondary(brr, workloads, up, steps, only=None):
                 plan.close()
         res["speedup_k6_vs_k1"] = res["k1"]["ms"] / res["k6"]["ms"]
         res["speedup_k6_vs_naive2"] = res["naive2"]["ms"] / res["k6"]["ms"]
+        res["chacha20_speedup_k6_vs_k1"] = res["k1_chacha20"]["ms"] / res["k6_chacha20"]["ms"]
         res["hbm_frac_k6"] = 2 * 4 * data.size / (res["k6"]["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS
         out[tag] = res
 
@@ -241,6 +252,7 @@ def secondary(brr, workloads, up, steps, only=None):
             res[name] = {"ms": ms, "elems_per_s": n / (ms * 1e-3)}
         res["speedup_k6_vs_k1"] = res["k1"]["ms"] / res["k6"]["ms"]
         res["speedup_k6_vs_naive2"] = res["naive2"]["ms"] / res["k6"]["ms"]
+        res["chacha20_speedup_k6_vs_k1"] = res["k1_chacha20"]["ms"] / res["k6_chacha20"]["ms"]
         out[tag] = res
     if only in (None, "tuned"):
         out["ragged_20000_u32_tuned"] = tuned_ragged(brr, workloads, up, steps)
