@@ -16,6 +16,11 @@
  * is x2 | x3 << 32. Attempt a (0 = first) of group/batch s of an instance
  * with S groups/batches reads word c = a*S + s. Results are therefore a pure
  * function of (inputs, seed, inst, schedule), independent of launch shape.
+ * Two other streams follow the same addressing: the 32-bit halves of these
+ * words (L = 32: brr_dice32, BRR_WORDS_PHILOX32 schedules) and ChaCha20
+ * words (brr_dice_chacha, BRR_WORDS_CHACHA20 schedules). The division form
+ * of Sec. 2.1 (brr_dice_div, BRR_FORM_DIVISION steps) reads the same words
+ * as the multiply chain and splits the same value differently.
  *
  * Conventions for every entry point:
  *  - Pointers named d_* are device pointers (HIP device memory, aligned to
