@@ -153,7 +153,8 @@ def tuned_ragged(brr, workloads, up, steps):
 
 def pmc_pass(brr, workloads, up):
     """For counter runs: a plain copy of 2^28 int32 (1 GiB read, 1 GiB written)
-    and one 2^28-roll dice stream per k = 1..4."""
+    and one 2^28-roll dice stream per k = 1..4, then the other forms and word
+    streams once each."""
     import numpy as np
     import torch
 
@@ -166,8 +167,16 @@ def pmc_pass(brr, workloads, up):
     out = torch.empty(COUNT, dtype=torch.uint32, device="cuda")
     for k in (1, 2, 3, 4):
         brr.check(brr.brr_dice(bounds, out, COUNT, k, 7, 0))
+    # the other forms and word streams once each, after the headline kernels
+    for k in (1, 2, 3, 4):
+        brr.check(brr.brr_dice_div(bounds, out, COUNT, k, 7, 0))
+        brr.check(brr.brr_dice_chacha(bounds, out, COUNT, k, 7, 0))
+    for k in (1, 2):
+        brr.check(brr.brr_dice32(bounds, out, COUNT, k, 7, 0))
     torch.cuda.synchronize()
-    print(json.dumps({"pmc_pass": "copy + dice k=1..4", "source_hash": kernel_source_hash()}))
+    print(json.dumps({"pmc_pass": "copy + dice k=1..4, then the division form, ChaCha20 words "
+                                  "(k=1..4) and 32-bit words (k=1, 2)",
+                      "source_hash": kernel_source_hash()}))
 
 
 def ceilings(brr, torch):
