@@ -114,6 +114,10 @@ def lib():
         L.orc_word_chacha.restype = u64
         L.orc_dice_chacha.argtypes = [p, p, u64, ctypes.c_uint, u64, u64]
         L.orc_dice_chacha.restype = ctypes.c_int
+        L.orc_dice32_group.argtypes = [p, ctypes.c_uint, u64, u64, u64, u64, p]
+        L.orc_dice32_group.restype = ctypes.c_int
+        L.orc_dice_chacha_group.argtypes = [p, ctypes.c_uint, u64, u64, u64, u64, p]
+        L.orc_dice_chacha_group.restype = ctypes.c_int
         L.orc_dice32.argtypes = [p, p, u64, ctypes.c_uint, u64, u64]
         L.orc_dice32.restype = ctypes.c_int
         L.orc_word32.argtypes = [u64, u64, u64]
@@ -242,6 +246,20 @@ def dice_group(group_bounds, S: int, s: int, seed: int, inst: int = 0):
     b = np.ascontiguousarray(group_bounds, dtype=np.uint32)
     out = np.zeros(b.size, dtype=np.uint32)
     err = lib().orc_dice_group(_ptr(b), b.size, S, s, seed, inst, _ptr(out))
+    return err, out
+
+
+def dice32_group(group_bounds, S: int, s: int, seed: int, inst: int = 0):
+    b = np.ascontiguousarray(group_bounds, dtype=np.uint32)
+    out = np.zeros(b.size, dtype=np.uint32)
+    err = lib().orc_dice32_group(_ptr(b), b.size, S, s, seed, inst, _ptr(out))
+    return err, out
+
+
+def dice_chacha_group(group_bounds, S: int, s: int, seed: int, inst: int = 0):
+    b = np.ascontiguousarray(group_bounds, dtype=np.uint32)
+    out = np.zeros(b.size, dtype=np.uint32)
+    err = lib().orc_dice_chacha_group(_ptr(b), b.size, S, s, seed, inst, _ptr(out))
     return err, out
 
 

@@ -259,6 +259,19 @@ int orc_dice_chacha(const uint32_t *bounds, uint32_t *out, uint64_t count, unsig
     return status;
 }
 
+/* Group s alone of a ChaCha20-word stream with S groups. */
+int orc_dice_chacha_group(const uint32_t *group_bounds, unsigned kk, uint64_t S, uint64_t s,
+                          uint64_t seed, uint64_t inst, uint32_t *out)
+{
+    if (kk == 0 || kk > 64) return ORC_EINVAL;
+    uint64_t b[64], a[64];
+    for (unsigned i = 0; i < kk; ++i) b[i] = group_bounds[i];
+    const int err = roll_group_chacha(b, kk, seed, inst, S, s, a);
+    if (err) return err;
+    for (unsigned i = 0; i < kk; ++i) out[i] = (uint32_t)a[i];
+    return ORC_OK;
+}
+
 /* Group g holds bounds[g*k .. g*k+k-1]; the last group keeps count mod k
  * bounds when that is non-zero. out[j] is the die rolled against bounds[j]. */
 int orc_dice(const uint32_t *bounds, uint32_t *out, uint64_t count, unsigned k, uint64_t seed,
@@ -401,6 +414,19 @@ static int roll_group32(const uint64_t *b, unsigned k, uint64_t seed, uint64_t i
             r = orc_chain(32, b, k, orc_word32(seed, inst, attempt * S + s), a);
         }
     }
+    return ORC_OK;
+}
+
+/* Group s alone of an L = 32 stream with S groups (its kk bounds given). */
+int orc_dice32_group(const uint32_t *group_bounds, unsigned kk, uint64_t S, uint64_t s,
+                     uint64_t seed, uint64_t inst, uint32_t *out)
+{
+    if (kk == 0 || kk > 32) return ORC_EINVAL;
+    uint64_t b[32], a[32];
+    for (unsigned i = 0; i < kk; ++i) b[i] = group_bounds[i];
+    const int err = roll_group32(b, kk, seed, inst, S, s, a);
+    if (err) return err;
+    for (unsigned i = 0; i < kk; ++i) out[i] = (uint32_t)a[i];
     return ORC_OK;
 }
 

@@ -333,3 +333,45 @@ def test_dice_tuple_equals_dice_on_tiled_bounds(gpu):
     gpu.check(gpu.brr_dice(tiled, b, count, len(tup), 5, 9), "brr_dice")
     assert gpu.brr_sync_status() == 0
     assert np.array_equal(to_host(a), to_host(b))
+
+
+# ---------------------------------------------------------------------------
+# Full size (2^28 rolls, the benchmark's stream) for the other forms and
+# word streams, in the launch configuration the benchmark times
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("entry,k", [("div", 2), ("div", 4), ("chacha", 2), ("chacha", 4),
+                                     ("l32", 1), ("l32", 2), ("tuple", 4)])
+def test_other_streams_full_size_sampled(gpu, orc, entry, k):
+    """Every output below its bound; the first and last 300 groups and 6000
+    random ones checked one by one against the oracle."""
+    import torch
+
+    count = 1 << 28
+    say("full size", entry, k)
+    if entry == "tuple":
+        tup = [6, 10, 12, 20]
+        bounds = np.resize(np.array(tup, np.uint32), count)
+    else:
+        bounds = workloads.dice_bounds(count, seed=7)
+    out = torch.empty(count, dtype=torch.uint32, device="cuda")
+    if entry == "tuple":
+        gpu.check(gpu.brr_dice_tuple(tup, out, count, 7, 0), "brr_dice_tuple")
+    else:
+        b = to_dev(bounds)
+        fn = {"div": gpu.brr_dice_div, "chacha": gpu.brr_dice_chacha, "l32": gpu.brr_dice32}[entry]
+        gpu.check(fn(b, out, count, k, 7, 0), entry)
+        del b
+    assert gpu.brr_sync_status() == 0
+    got = to_host(out)
+    del out
+    assert np.all(got < bounds)
+    group = {"div": orc.dice_div_group, "chacha": orc.dice_chacha_group, "l32": orc.dice32_group,
+             "tuple": orc.dice_group}[entry]
+    S = -(-count // k)
+    rng = np.random.default_rng(100 + k)
+    for g in np.concatenate([np.arange(300), np.arange(S - 300, S), rng.integers(0, S, 6000)]):
+        lo, hi = int(g) * k, min(count, int(g) * k + k)
+        err, want = group(bounds[lo:hi], S, int(g), 7, 0)
+        assert err == 0
+        assert np.array_equal(got[lo:hi], want), (entry, k, int(g))

@@ -901,3 +901,22 @@ def test_word_stream_chi2_all_24_permutations(orc, words):
     assert hist.size == 24 and hist.min() > 0
     stat = float(((hist - trials / 24) ** 2 / (trials / 24)).sum())
     assert stat < chi2.ppf(1 - 1e-3, 23), stat
+
+
+def test_stream_group_entries_equal_streams(orc):
+    """The single-group entries used for full-size sampling reproduce the
+    whole-stream oracles group by group (32-bit words, ChaCha20 words, the
+    division form), short last group included."""
+    rng = np.random.default_rng(78)
+    for k, count in ((1, 301), (2, 1001), (3, 1000)):
+        b16 = rng.integers(1, 1 << 16, size=count, dtype=np.uint32)
+        b10 = rng.integers(1, 1 << 10, size=count, dtype=np.uint32)
+        S = -(-count // k)
+        cases = ((orc.dice32, orc.dice32_group, b10), (orc.dice_chacha, orc.dice_chacha_group, b16),
+                 (orc.dice_div, orc.dice_div_group, b16))
+        for stream, group, bounds in cases:
+            err, out = stream(bounds, k, 9, 2)
+            assert err == 0
+            for g in range(S):
+                e, got = group(bounds[g * k:(g + 1) * k], S, g, 9, 2)
+                assert e == 0 and np.array_equal(got, out[g * k:(g + 1) * k]), (stream, k, g)
