@@ -51,10 +51,10 @@ def run_mix(gpu, reqs, order, **cfg):
     return results, counters, stats
 
 
-def expected(orc, reqs, order, seed):
+def expected(orc, reqs, order, seed, sched=None):
     """Oracle result of each request at instance session * 2^40 + j, where j
     counts the earlier submissions of its session."""
-    s6 = orc.schedule_paper(6)
+    s6 = sched if sched is not None else orc.schedule_paper(6)
     seen = {}
     want = {}
     for i in order:
@@ -113,3 +113,27 @@ def test_server_budget_limits_footprint(gpu):
     assert 0 < st["peak_footprint"] <= 64 << 20
     for d in bufs:  # each is a permutation
         assert np.array_equal(np.sort(to_host(d)), np.arange(1 << 20, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("words", ["chacha", "l32"])
+def test_server_other_word_streams(gpu, orc, words):
+    """A server whose schedule reads ChaCha20 words (shuffle_6) or 32-bit
+    words (Table 2's L = 32 schedule) serves what the oracle computes with
+    that schedule."""
+    if words == "chacha":
+        steps = gpu.brr_schedule_paper(6).steps()
+        gs = gpu.brr_schedule.from_steps(steps, tail=True, u_tail=720,
+                                         words=gpu.BRR_WORDS_CHACHA20)
+        os_ = orc.Schedule.from_segments(steps, tail=True, u_tail=720, words=orc.WORDS_CHACHA20)
+    else:
+        gs = gpu.brr_schedule_from_costs(4, pow2=False, smooth=False, l32=True)
+        os_ = orc.Schedule.from_segments(gs.steps(), tail=bool(gs.tail), u_tail=gs.u_tail,
+                                         words=orc.WORDS_PHILOX32)
+    reqs = make_requests(2, 30)
+    order = list(range(len(reqs)))
+    want, seen = expected(orc, reqs, order, seed=5, sched=os_)
+    say("server", words)
+    got, counters, _ = run_mix(gpu, reqs, order, seed=5, nstreams=4, max_inflight=8, sched=gs)
+    for i in order:
+        assert np.array_equal(got[i], want[i]), (words, i)
+    assert counters == seen
