@@ -40,3 +40,35 @@ def test_plan_autotune_parity(gpu, orc, dtype):
     assert orc.shuffle_batched(want, off, osched, 5, 3) == 0
     assert np.array_equal(to_host(d), want)
     plan.close()
+
+
+@pytest.mark.parametrize("words", ["chacha", "l32"])
+def test_plan_autotune_keeps_word_stream(gpu, orc, words):
+    """Tuning picks batch sizes and the mapping, never the word stream: a
+    plan on ChaCha20 or 32-bit words stays on it, and the tuned plan is
+    bit-exact with the oracle under the schedule it reports."""
+    rng = np.random.default_rng(22)
+    sizes = np.floor(2 ** rng.uniform(4, 15.5, size=200)).astype(np.uint64)
+    off = workloads.csr_offsets(sizes)
+    data = workloads.iota_segments(sizes, np.uint32)
+    d, d_off = to_dev(data), to_dev(off)
+    if words == "chacha":
+        w = gpu.BRR_WORDS_CHACHA20
+        s0 = gpu.brr_schedule.from_steps(gpu.brr_schedule_paper(6).steps(), tail=True, u_tail=720,
+                                         words=w)
+    else:
+        w = gpu.BRR_WORDS_PHILOX32
+        s0 = gpu.brr_schedule_from_costs(4, pow2=False, smooth=False, l32=True)
+    plan = gpu.Plan(off, 4, s0)
+    say("plan autotune", words)
+    rep = plan.autotune(d, d_off, seed=6, inst_base=1)
+    sched = plan.schedule()
+    assert sched.words == w and rep.candidates >= 2
+    gpu.check(gpu.brr_shuffle_batched(d, d_off, sizes.size, 4, plan, 6, 1))
+    assert gpu.brr_sync_status() == 0
+    want = data.copy()
+    osched = orc.Schedule.from_segments(sched.steps(), tail=bool(sched.tail), u_tail=sched.u_tail,
+                                        forms=sched.forms(), words=int(sched.words))
+    assert orc.shuffle_batched(want, off, osched, 6, 1) == 0
+    assert np.array_equal(to_host(d), want)
+    plan.close()
