@@ -7,7 +7,12 @@
 // r >= 2^64 mod i^(falling k); the schedule's guard u only decides when that
 // threshold is formed (r >= u >= product implies acceptance). Die l of the
 // batch is j_p for position p = i-1-l: step p swaps z[p] with z[j_p], j_p <= p.
-// Every batch is independent, so all dice are rolled at once.
+// Every batch is independent, so all dice are rolled at once. A schedule
+// may instead read the 32-bit halves of the words (chain and threshold at
+// L = 32) or ChaCha20 words, and a step may take its dice in the division
+// form of Sec. 2.1 (V below i^(falling k) by Lemire's method, then
+// successive remainders); batch_state and next_die cover every case, and
+// kernels that carry the other word streams are separate instantiations.
 //
 // Swaps. Sequential Fisher-Yates runs p = n-1 down to 1. Position p is final
 // after its own step, so the value it ends with is what z[j_p] held just
