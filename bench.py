@@ -73,6 +73,41 @@ def time_launches(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per step
 
 
+def launch_stats(fn, launches=20):
+    """Per-launch times (HIP events around each launch on the launch
+    stream): median, min, mean, and whether the min is within 10% of the
+    mean."""
+    import statistics
+
+    import torch
+
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(launches)]
+    for a, b in ev:
+        a.record(s)
+        fn()
+        b.record(s)
+    torch.cuda.synchronize()
+    t = [a.elapsed_time(b) for a, b in ev]
+    mean = sum(t) / len(t)
+    return {"launches": launches, "median_ms": statistics.median(t), "min_ms": min(t),
+            "mean_ms": mean, "min_within_10pct_of_mean": min(t) >= 0.9 * mean}
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def serving(brr, workloads, up, rates=(1000, 4000, 16000), count=400, clients=64):
     """Poisson arrivals at each rate: requests (shuffle or sample, n
     log-uniform in [2^4, 2^22], u64 payload, m <= n/10) from `clients`
@@ -225,8 +260,16 @@ def secondary(brr, workloads, up, steps, only=None):
         sets = min(8, max(1, -(-(512 << 20) // data.nbytes)))
         ds, d_off = [up(data) for _ in range(sets)], up(off)
         res = {"buffer_sets": sets}
-        for name, sched in scheds:
+        variants = list(scheds)
+        if tag.startswith("ragged"):  # the same plan launched without its hip graph
+            variants.append(("k6_no_graph", s6))
+        for name, sched in variants:
             plans = [brr.Plan(off, 4, sched) for _ in range(sets)]
+            if name.endswith("no_graph"):
+                for plan in plans:
+                    m = plan.mapping()
+                    m.use_graph = 0
+                    brr.check(plan.set_mapping(m), "set_mapping")
             turn = [0]
 
             def f():
@@ -241,6 +284,8 @@ def secondary(brr, workloads, up, steps, only=None):
         res["speedup_k6_vs_k1"] = res["k1"]["ms"] / res["k6"]["ms"]
         res["speedup_k6_vs_naive2"] = res["naive2"]["ms"] / res["k6"]["ms"]
         res["chacha20_speedup_k6_vs_k1"] = res["k1_chacha20"]["ms"] / res["k6_chacha20"]["ms"]
+        if "k6_no_graph" in res:
+            res["graph_speedup_k6"] = res["k6_no_graph"]["ms"] / res["k6"]["ms"]
         res["hbm_frac_k6"] = 2 * 4 * data.size / (res["k6"]["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS
         out[tag] = res
 
@@ -354,6 +399,7 @@ def main():
     brr.check(brr.brr_sync_status(), "device status")
     k_head = min((2, 3, 4), key=lambda k: ms_k[k]) if args.k == "best" else int(args.k)
     ms = ms_k[k_head]
+    head_stats = launch_stats(step(k_head))
     value = COUNT / (ms * 1e-3)
     achieved = BYTES_PER_ROLL * COUNT / (ms * 1e-3) / 1e9
     traffic = measured_traffic(k_head)
@@ -390,6 +436,10 @@ def main():
                              "hbm_frac": BYTES_PER_ROLL * COUNT / (v * 1e-3) / 1e9 / PEAK_HBM_GBS}
                     for k, v in ms_k.items()},
         "speedup_vs_k1": ms_k[1] / ms,
+        # per-launch spread of the headline kernel, and the write-only share
+        # of the HBM peak (1 GiB of dice written per launch)
+        "headline_launch_stats": head_stats,
+        "hbm_write_only_frac": (COUNT * 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
         "l32_sweep": {str(k): {"ms": v, "rolls_per_s": COUNT / (v * 1e-3),
                                "hbm_frac": BYTES_PER_ROLL * COUNT / (v * 1e-3) / 1e9 / PEAK_HBM_GBS}
                       for k, v in ms_32.items()},
@@ -424,6 +474,7 @@ def main():
             "kind": "oracle",
             "sample": f"the whole 2^28-roll stream at k={k_head}, plain C oracle, one thread "
                       f"({dt:.1f} s)",
+            "host": host_cpu(),
         }
     print(json.dumps(rec), flush=True)
 
