@@ -918,7 +918,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
 //   init:    sort keys "none", sort values = own position, heads "none"
 //   dice:    jj[x] = j_p; sort key of step x = its global target (steps
 //            with j_p = p keep "none")
-//   sort:    stable LSD radix sort of (target, step) pairs, 8-bit digits;
+//   sort:    stable LSD radix sort of (target, step) pairs, 8..10-bit digits;
 //            steps into one target end up adjacent and in increasing order
 //   links:   over the sorted pairs: head[t] = first step of t's run, and
 //            each step's successor is the next one in its run
@@ -927,10 +927,14 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
 //   copy:    in-place shuffles copy the gathered values back
 // ---------------------------------------------------------------------------
 
-constexpr uint32_t kSortThreads = 256;
+constexpr uint32_t kSortThreads = 512;
 constexpr uint32_t kSortItems = 8;
 constexpr uint32_t kSortTile = kSortThreads * kSortItems; // pairs per sort block
 static_assert(kSortThreads % 64 == 0 && kSortTile < 65536, "16-bit split counters");
+// A pass sorts on a digit of 8..kSortDigitMax bits: as few passes as the
+// key width allows, each digit as narrow as that many passes allow (wider
+// digits split a tile into shorter runs, whose writes coalesce worse).
+constexpr uint32_t kSortDigitMax = 10;
 constexpr uint32_t kSortNone = 0xFFFFFFFFu;               // sorts after every target
 
 constexpr uint64_t kCountMaxPositions = 1ull << 21;
@@ -958,7 +962,7 @@ __host__ __device__ inline uint64_t sort_blocks(uint64_t npos)
 
 __host__ __device__ inline uint64_t garrays_bytes(uint64_t npos, uint32_t eb)
 {
-    const uint64_t w = align256(4 * npos), nh = 256 * sort_blocks(npos);
+    const uint64_t w = align256(4 * npos), nh = ((uint64_t)1 << kSortDigitMax) * sort_blocks(npos);
     const uint64_t nt = scan_tiles(nh > npos + 1 ? nh : npos + 1);
     return 7 * w + align256(4 * (npos + 1)) + align256(4 * nh) + align256(4 * nt) +
            align256(eb * npos);
@@ -967,7 +971,7 @@ __host__ __device__ inline uint64_t garrays_bytes(uint64_t npos, uint32_t eb)
 __host__ __device__ inline GArrays garrays(void *base, uint64_t npos)
 {
     char *p = static_cast<char *>(base);
-    const uint64_t w = align256(4 * npos), nh = 256 * sort_blocks(npos);
+    const uint64_t w = align256(4 * npos), nh = ((uint64_t)1 << kSortDigitMax) * sort_blocks(npos);
     GArrays g;
     uint32_t **arr[7] = {&g.jj, &g.key[0], &g.val[0], &g.key[1], &g.val[1], &g.head, &g.succ};
     for (int a = 0; a < 7; ++a) {
@@ -1219,42 +1223,72 @@ __device__ __forceinline__ uint64_t sort_block_scan(uint64_t v, uint64_t *wsum, 
 
 __device__ __forceinline__ uint32_t sort_pad(uint32_t i) { return i + (i >> 3); }
 
-// Radix sort, pass on bits sh .. sh+7: digit counts of every block's tile.
+// The hardware deals the workgroups of a launch to the chip's 8 XCDs in turn
+// (workgroup w to XCD w mod 8), and each XCD has an L2 of its own. This maps
+// workgroup w of n to a tile so that every XCD takes one contiguous range of
+// tiles: workgroups resident together on an XCD then hold neighbouring tiles,
+// and their short writes into one output line meet in the same L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t w, uint32_t n)
+{
+    constexpr uint32_t kXcds = 8;
+    const uint32_t q = n / kXcds, r = n % kXcds, x = w % kXcds;
+    return x * q + (x < r ? x : r) + w / kXcds;
+}
+
+// Digit of a sort key: RB bits from bit sh on (the host keeps sh + RB <= 32).
+template <uint32_t RB>
+__device__ __forceinline__ uint32_t sort_digit(uint32_t key, uint32_t sh)
+{
+    return (key >> sh) & ((1u << RB) - 1u);
+}
+
+// Radix sort, pass on the RB-bit digit at bit sh: digit counts of every
+// block's tile (one LDS histogram per wavefront, summed at the end).
+template <uint32_t RB>
 __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *keys, uint64_t n,
                                                           uint32_t sh, uint32_t *hist,
                                                           uint32_t nblk)
 {
-    __shared__ uint32_t cnt[256];
-    for (uint32_t d = threadIdx.x; d < 256; d += kSortThreads) cnt[d] = 0;
+    constexpr uint32_t NB = 1u << RB, NW = kSortThreads / 64;
+    __shared__ uint32_t cnt[NW][NB];
+    for (uint32_t d = threadIdx.x; d < NW * NB; d += kSortThreads) (&cnt[0][0])[d] = 0;
     __syncthreads();
+    uint32_t *mine = cnt[threadIdx.x >> 6];
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
 #pragma unroll
     for (uint32_t u = 0; u < kSortItems; ++u) {
         const uint64_t i = base + u * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> sh) & 255u], 1u);
+        if (i < n) atomicAdd(&mine[sort_digit<RB>(keys[i], sh)], 1u);
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < 256; d += kSortThreads)
-        hist[(uint64_t)d * nblk + blockIdx.x] = cnt[d];
+    for (uint32_t d = threadIdx.x; d < NB; d += kSortThreads) {
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < NW; ++w) c += cnt[w][d];
+        hist[(uint64_t)d * nblk + blockIdx.x] = c;
+    }
 }
 
-// Radix sort, pass on bits sh .. sh+7: the block sorts its tile by the digit
-// in LDS (four stable 2-bit splits), then writes each digit's run to its
-// place: the scanned count of that digit over all earlier digits and
-// blocks, plus the rank inside the tile's run.
+// Radix sort, pass on the RB-bit digit at bit sh: the block sorts its tile
+// by the digit in LDS (stable splits on 2 bits at a time, the last on 1
+// when RB is odd), then writes each digit's run to its place: the scanned
+// count of that digit over all earlier digits and blocks, plus the rank
+// inside the tile's run.
+template <uint32_t RB>
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin,
                                                              const uint32_t *vin, uint32_t *kout,
                                                              uint32_t *vout, uint64_t n,
                                                              uint32_t sh, const uint32_t *hist,
                                                              uint32_t nblk)
 {
-    // tile index i lives at i + i/8: a thread's eight consecutive items then
-    // fall in distinct banks
+    constexpr uint32_t NB = 1u << RB;
+    // tile index i lives at i + i/8: a thread's consecutive items then fall
+    // in distinct banks
     __shared__ uint32_t sk[kSortTile + kSortTile / 8], sv[kSortTile + kSortTile / 8];
-    __shared__ uint32_t first[256], dst[256];
+    __shared__ uint32_t first[NB], dst[NB];
     __shared__ uint64_t wsum[kSortThreads / 64];
-    const uint32_t tid = threadIdx.x;
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint32_t tid = threadIdx.x, tile = xcd_tile(blockIdx.x, nblk);
+    const uint64_t base = (uint64_t)tile * kSortTile;
     const uint32_t valid = (uint32_t)min<uint64_t>(kSortTile, n - base);
 #pragma unroll
     for (uint32_t u = 0; u < kSortItems; ++u) { // coalesced; padding sorts last
@@ -1262,23 +1296,25 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
         sk[sort_pad(i)] = (i < valid) ? kin[base + i] : kSortNone;
         sv[sort_pad(i)] = (i < valid) ? vin[base + i] : 0u;
     }
-    for (uint32_t d = tid; d < 256; d += kSortThreads) dst[d] = hist[(uint64_t)d * nblk + blockIdx.x];
+    for (uint32_t d = tid; d < NB; d += kSortThreads) dst[d] = hist[(uint64_t)d * nblk + tile];
     __syncthreads();
     uint32_t k[kSortItems], v[kSortItems];
 #pragma unroll
-    for (uint32_t u = 0; u < kSortItems; ++u) { // thread tid: tile items 8*tid ..
+    for (uint32_t u = 0; u < kSortItems; ++u) { // thread tid: consecutive tile items
         k[u] = sk[sort_pad(tid * kSortItems + u)];
         v[u] = sv[sort_pad(tid * kSortItems + u)];
     }
     __syncthreads();
-    for (uint32_t r = 0; r < 4; ++r) {
+#pragma unroll
+    for (uint32_t r = 0; r < (RB + 1) / 2; ++r) {
         const uint32_t b = sh + 2 * r;
-        // per thread: running count of each 2-bit value in 16-bit fields
+        const uint32_t mask = (2 * r + 1 < RB) ? 3u : 1u;
+        // per thread: running count of each split value in 16-bit fields
         uint64_t run = 0;
         uint32_t before[kSortItems];
 #pragma unroll
         for (uint32_t u = 0; u < kSortItems; ++u) {
-            const uint32_t d = (k[u] >> b) & 3u;
+            const uint32_t d = (k[u] >> b) & mask;
             before[u] = (uint32_t)(run >> (16 * d)) & 0xFFFFu;
             run += 1ull << (16 * d);
         }
@@ -1289,7 +1325,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
         const uint32_t start[4] = {0, t0, t0 + t1, t0 + t1 + t2};
 #pragma unroll
         for (uint32_t u = 0; u < kSortItems; ++u) {
-            const uint32_t d = (k[u] >> b) & 3u;
+            const uint32_t d = (k[u] >> b) & mask;
             const uint32_t pos = start[d] + ((uint32_t)(excl >> (16 * d)) & 0xFFFFu) + before[u];
             sk[sort_pad(pos)] = k[u];
             sv[sort_pad(pos)] = v[u];
@@ -1306,15 +1342,15 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
 #pragma unroll
     for (uint32_t u = 0; u < kSortItems; ++u) {
         const uint32_t i = tid * kSortItems + u;
-        const uint32_t d = (k[u] >> sh) & 255u;
-        if (i == 0 || ((sk[sort_pad(i - 1)] >> sh) & 255u) != d) first[d] = i;
+        const uint32_t d = sort_digit<RB>(k[u], sh);
+        if (i == 0 || sort_digit<RB>(sk[sort_pad(i - 1)], sh) != d) first[d] = i;
     }
     __syncthreads();
 #pragma unroll
     for (uint32_t u = 0; u < kSortItems; ++u) {
         const uint32_t i = u * kSortThreads + tid;
         if (i < valid) {
-            const uint32_t key = sk[sort_pad(i)], d = (key >> sh) & 255u;
+            const uint32_t key = sk[sort_pad(i)], d = sort_digit<RB>(key, sh);
             const uint32_t o = dst[d] + (i - first[d]);
             kout[o] = key;
             vout[o] = sv[sort_pad(i)];
@@ -1442,6 +1478,18 @@ void scan_exclusive(uint32_t *a, uint32_t *tiles, uint64_t len, hipStream_t stre
     k_gp_scan_apply<<<(uint32_t)ntiles, kScanThreads, 0, stream>>>(a, tiles, len);
 }
 
+// One radix sort pass on the RB-bit digit at bit sh, from buffer cur into
+// cur ^ 1.
+template <uint32_t RB>
+void sort_pass(const GArrays &g, int cur, uint64_t npos, uint32_t sh, uint32_t nblk,
+               hipStream_t stream)
+{
+    k_rs_hist<RB><<<nblk, kSortThreads, 0, stream>>>(g.key[cur], npos, sh, g.hist, nblk);
+    scan_exclusive(g.hist, g.tiles, ((uint64_t)1 << RB) * nblk, stream);
+    k_rs_scatter<RB><<<nblk, kSortThreads, 0, stream>>>(g.key[cur], g.val[cur], g.key[cur ^ 1],
+                                                        g.val[cur ^ 1], npos, sh, g.hist, nblk);
+}
+
 template <typename Elem, bool W>
 hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratch,
                       hipStream_t stream)
@@ -1466,12 +1514,13 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
     uint32_t bits = 0;
     while (bits < 32 && (P.npos >> bits) != 0) ++bits;
     const uint32_t nblk = (uint32_t)sort_blocks(P.npos);
+    const uint32_t passes = (bits + kSortDigitMax - 1) / kSortDigitMax;
+    const uint32_t rb0 = (bits + passes - 1) / passes, rb = rb0 < 8 ? 8 : rb0;
     int cur = 0;
-    for (uint32_t sh = 0; sh < bits; sh += 8, cur ^= 1) {
-        k_rs_hist<<<nblk, kSortThreads, 0, stream>>>(g.key[cur], P.npos, sh, g.hist, nblk);
-        scan_exclusive(g.hist, g.tiles, (uint64_t)256 * nblk, stream);
-        k_rs_scatter<<<nblk, kSortThreads, 0, stream>>>(g.key[cur], g.val[cur], g.key[cur ^ 1],
-                                                        g.val[cur ^ 1], P.npos, sh, g.hist, nblk);
+    for (uint32_t sh = 0; sh < bits; sh += rb, cur ^= 1) {
+        if (rb == 8) sort_pass<8>(g, cur, P.npos, sh, nblk, stream);
+        else if (rb == 9) sort_pass<9>(g, cur, P.npos, sh, nblk, stream);
+        else sort_pass<10>(g, cur, P.npos, sh, nblk, stream);
     }
     k_gp_links<<<grid_for(P.npos, 256), 256, 0, stream>>>(g, g.key[cur], g.val[cur], P.npos);
     k_gp_resolve<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,

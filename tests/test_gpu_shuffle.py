@@ -228,6 +228,20 @@ def test_shuffle_2_26(gpu, orc):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.slow
+def test_shuffle_2_27_plus_3(gpu, orc):
+    """2^27 + 3 positions: 28-bit sort keys, sorted in three passes of
+    10-bit digits (2^26 takes 9-bit digits, 2^21 + 5 8-bit ones)."""
+    n = (1 << 27) + 3
+    s6g, s6o = both_schedules(gpu, orc, 6)
+    say("shuffle 2^27 + 3")
+    a = np.arange(n, dtype=np.uint32)
+    got = gpu_shuffle(gpu, a, s6g, seed=43, inst=2)
+    want = a.copy()
+    assert orc.shuffle(want, s6o, 43, 2) == 0
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
 @pytest.mark.parametrize("wave_max", [512, 100])
 def test_batched_tier_boundaries(gpu, orc, dtype, wave_max):
