@@ -216,16 +216,23 @@ def pmc_pass(brr, workloads, up):
 
 def ceilings(brr, torch):
     """Measured context for the roofline: a plain elementwise pass over the
-    stream's bytes (1 GiB read + 1 GiB written, torch's own kernel) and the
+    stream's bytes (1 GiB read + 1 GiB written, torch's own kernel), a bare
+    copy of the same bytes in the fastest copy shape measured, and the
     rate at which the vector ALUs chain dice (Theorem 1 steps with no memory
     traffic and no word generation)."""
     a = torch.arange(COUNT, dtype=torch.int32, device="cuda")
     b = torch.empty_like(a)
     ms = time_launches(lambda: torch.bitwise_or(a, 0, out=b), 10, 2)
+    copy_bps = brr.brr_probe_copy_rate(a, b, 4 * COUNT, 10)
     del a, b
     torch.cuda.empty_cache()
     return {"elementwise_GBps": BYTES_PER_ROLL * COUNT / (ms * 1e-3) / 1e9,
             "elementwise_kernel": "torch.bitwise_or over 2^28 int32 (1 GiB in, 1 GiB out)",
+            "copy_probe_GBps": copy_bps / 1e9,
+            "copy_probe_kernel": "brr_probe_copy_rate: 1 GiB copied, one 16-byte "
+                                 "nontemporal vector per lane (the fastest copy shape "
+                                 "measured), read + written bytes",
+            "frac_of_copy_probe": None,
             "chain_dice_per_s": brr.brr_probe_chain_rate(4096)}
 
 
@@ -454,6 +461,7 @@ def main():
                                 for k, v in ms_div.items()},
         "ceilings": ceilings(brr, torch),
     }
+    rec["ceilings"]["frac_of_copy_probe"] = achieved / rec["ceilings"]["copy_probe_GBps"]
     del out, bounds
     torch.cuda.empty_cache()
 

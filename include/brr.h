@@ -485,6 +485,19 @@ void brr_server_destroy(brr_server *server);
  * synchronizes it; *dice_per_s receives the rate of the second. */
 brr_status brr_probe_chain_rate(uint32_t iters, double *dice_per_s);
 
+/* Measures the memory ceiling of a stream that reads and writes the same
+ * number of bytes, as a dice stream does: copies `bytes` (a multiple of 16)
+ * from device buffer src to device buffer dst (both 16-byte aligned, not
+ * overlapping, owned by the caller) with the fastest copy shape measured on
+ * MI355X (one 16-byte nontemporal load and store per lane, one contiguous
+ * tile per workgroup), once to warm up and then `reps` times on `stream`,
+ * which it synchronizes. *bytes_per_s receives
+ * the bytes moved (read plus written, 2 * bytes per copy) per second over
+ * the timed copies. BRR_EINVAL for null pointers, zero sizes, misaligned
+ * pointers or sizes. */
+brr_status brr_probe_copy_rate(const void *src, void *dst, uint64_t bytes, uint32_t reps,
+                               void *stream, double *bytes_per_s);
+
 /* ------------------------------------------------------------------------ */
 
 /* Waits for `stream`, then returns and clears the first device-detected

@@ -30,7 +30,7 @@ EXPORTS = (
     "brr_server_destroy", "brr_mlp_create", "brr_mlp_destroy", "brr_mlp_num_params",
     "brr_mlp_get_params", "brr_mlp_set_params", "brr_mlp_get_grads", "brr_mlp_forward",
     "brr_mlp_backward", "brr_mlp_adam_step", "brr_mlp_train", "brr_plan_features",
-    "brr_plan_autotune_learned", "brr_probe_chain_rate", "brr_dice32", "brr_dice_div",
+    "brr_plan_autotune_learned", "brr_probe_chain_rate", "brr_probe_copy_rate", "brr_dice32", "brr_dice_div",
     "brr_schedule_naive2", "brr_dice_chacha", "brr_dice_tuple", "brr_schedule_kmax",
 )
 BRR_PLAN_FEATURES = 16
@@ -167,6 +167,7 @@ def _load():
         "brr_plan_autotune_learned": (st, [p, p, u32, p, p, u64, u64, p,
                                            ctypes.POINTER(brr_tune_report)]),
         "brr_probe_chain_rate": (st, [u32, ctypes.POINTER(ctypes.c_double)]),
+        "brr_probe_copy_rate": (st, [p, p, u64, u32, p, ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -515,4 +516,13 @@ def brr_probe_chain_rate(iters: int = 4096) -> float:
     """Dice per second the vector ALUs can chain (no memory, no word generation)."""
     out = ctypes.c_double()
     check(lib.brr_probe_chain_rate(iters, ctypes.byref(out)), "brr_probe_chain_rate")
+    return out.value
+
+
+def brr_probe_copy_rate(src, dst, nbytes: int, reps: int = 10, stream=None) -> float:
+    """Bytes per second (read + written) of a bare copy with the dice stream's
+    access pattern, src -> dst, nbytes each."""
+    out = ctypes.c_double()
+    check(lib.brr_probe_copy_rate(_addr(src), _addr(dst), nbytes, reps, _stream(stream),
+                                  ctypes.byref(out)), "brr_probe_copy_rate")
     return out.value

@@ -165,6 +165,11 @@ def test_host_argument_errors_need_no_device():
     assert brr.lib.brr_shuffle_batched(odd4, 0x20000, 3, 4, None, 1, 0, None) == brr.BRR_EINVAL
     assert brr.lib.brr_shuffle_batched(0x20000, odd8, 3, 4, None, 1, 0, None) == brr.BRR_EINVAL
     assert brr.lib.brr_probe_chain_rate(0, None) == brr.BRR_EINVAL
+    out = ctypes.c_double()
+    assert brr.lib.brr_probe_copy_rate(0x20000, 0x40000, 24, 1, None, ctypes.byref(out)) == brr.BRR_EINVAL
+    assert brr.lib.brr_probe_copy_rate(0x20008, 0x40000, 32, 1, None, ctypes.byref(out)) == brr.BRR_EINVAL
+    assert brr.lib.brr_probe_copy_rate(0x20000, 0x40000, 32, 0, None, ctypes.byref(out)) == brr.BRR_EINVAL
+    assert brr.lib.brr_probe_copy_rate(None, 0x40000, 32, 1, None, ctypes.byref(out)) == brr.BRR_EINVAL
     # known bounds: products checked on the host (eight 32-bit factors
     # would wrap a 128-bit product if it were not capped)
     assert brr.lib.brr_dice_const(2**32 - 1, 0x20000, 10, 5, 1, 0, None) == brr.BRR_EOVERFLOW

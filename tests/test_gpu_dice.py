@@ -375,3 +375,16 @@ def test_other_streams_full_size_sampled(gpu, orc, entry, k):
         err, want = group(bounds[lo:hi], S, int(g), 7, 0)
         assert err == 0
         assert np.array_equal(got[lo:hi], want), (entry, k, int(g))
+
+
+def test_copy_probe_copies(gpu):
+    """The roofline's copy probe moves the bytes it claims: dst equals src
+    after it, with a ragged last tile (1 MiB + 48 bytes)."""
+    nbytes = (1 << 20) + 48
+    rng = np.random.default_rng(21)
+    src_np = rng.integers(0, 2**32, size=nbytes // 4, dtype=np.uint32)
+    src, dst = to_dev(src_np), to_dev(np.zeros_like(src_np))
+    say("copy probe", nbytes)
+    rate = gpu.brr_probe_copy_rate(src, dst, nbytes, 2)
+    assert rate > 0
+    assert np.array_equal(to_host(dst), src_np)
