@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 COUNT = 1 << 28
 BYTES_PER_ROLL = 8  # 4 B bound read + 4 B die written
+KNOWN_BOUND = 65535  # the known-bounds stream: one bound, 65535^4 < 2^64
 
 
 def kernel_source_hash():
@@ -389,6 +390,12 @@ def main():
     ms_div = {k: time_launches(lambda k=k: brr.check(brr.brr_dice_div(bounds, out, COUNT, k, 7, 0),
                                                      "brr_dice_div"), args.steps, args.warmup)
               for k in (1, 2, 3, 4)}
+    # known bounds (Algorithm 2: one bound, threshold computed once): the
+    # stream only writes, 4 B per roll, so its roofline is the write roofline
+    ms_const = {k: time_launches(lambda k=k: brr.check(brr.brr_dice_const(KNOWN_BOUND, out, COUNT, k,
+                                                                          7, 0),
+                                                       "brr_dice_const"), args.steps, args.warmup)
+                for k in (1, 2, 3, 4)}
     # ChaCha20 words (the paper's slow generator): batching saves words
     ms_cc = {k: time_launches(lambda k=k: brr.check(brr.brr_dice_chacha(bounds, out, COUNT, k, 7, 0),
                                                     "brr_dice_chacha"), args.steps, args.warmup)
@@ -459,6 +466,14 @@ def main():
         "division_form_sweep": {str(k): {"ms": v, "rolls_per_s": COUNT / (v * 1e-3),
                                          "multiply_form_speedup": v / ms_k[k]}
                                 for k, v in ms_div.items()},
+        "known_bounds_sweep": {
+            "bound": KNOWN_BOUND,
+            **{str(k): {"ms": v, "rolls_per_s": COUNT / (v * 1e-3),
+                        "write_GBps": 4 * COUNT / (v * 1e-3) / 1e9,
+                        "hbm_write_frac": 4 * COUNT / (v * 1e-3) / 1e9 / PEAK_HBM_GBS}
+               for k, v in ms_const.items()},
+            "speedup_best_vs_k1": ms_const[1] / min(ms_const[k] for k in (2, 3, 4)),
+        },
         "ceilings": ceilings(brr, torch),
     }
     rec["ceilings"]["frac_of_copy_probe"] = achieved / rec["ceilings"]["copy_probe_GBps"]

@@ -10,6 +10,8 @@ namespace brr {
 // Native 4 x u32 vector (16-byte global loads/stores, nontemporal builtins).
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// three dwords at 4-byte alignment: one 12-byte load or store
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3), aligned(4)));
 
 // Bits of the per-device status word (see brr_sync_status).
 enum : uint32_t { kDevZeroBound = 1u, kDevOverflow = 2u };

@@ -93,6 +93,11 @@ __device__ __forceinline__ void load_group(const uint32_t *__restrict__ p, uint3
         const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
         b[0] = v.x;
         b[1] = v.y;
+    } else if (K == 3) { // one 12-byte access (4-byte alignment suffices)
+        const u32x3 v = __builtin_nontemporal_load(reinterpret_cast<const u32x3 *>(p));
+        b[0] = v.x;
+        b[1] = v.y;
+        b[2] = v.z;
     } else {
 #pragma unroll
         for (int i = 0; i < K; ++i) b[i] = __builtin_nontemporal_load(p + i);
@@ -108,6 +113,9 @@ __device__ __forceinline__ void store_group(uint32_t *__restrict__ p, const uint
     } else if (VEC && K == 2) {
         const u32x2 v = {a[0], a[1]};
         __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(p));
+    } else if (K == 3) {
+        const u32x3 v = {a[0], a[1], a[2]};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x3 *>(p));
     } else {
 #pragma unroll
         for (int i = 0; i < K; ++i) __builtin_nontemporal_store(a[i], p + i);
