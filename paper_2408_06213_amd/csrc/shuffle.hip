@@ -1227,7 +1227,9 @@ __device__ __forceinline__ uint32_t sort_pad(uint32_t i) { return i + (i >> 3); 
 // (workgroup w to XCD w mod 8), and each XCD has an L2 of its own. This maps
 // workgroup w of n to a tile so that every XCD takes one contiguous range of
 // tiles: workgroups resident together on an XCD then hold neighbouring tiles,
-// and their short writes into one output line meet in the same L2.
+// and their short writes into one output line meet in the same L2. The map
+// is a bijection of [0, n) for any n, so a part with another XCD count (or
+// another dispatch order) only loses the locality, never correctness.
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t w, uint32_t n)
 {
     constexpr uint32_t kXcds = 8;
