@@ -450,10 +450,11 @@ def main():
                              "hbm_frac": BYTES_PER_ROLL * COUNT / (v * 1e-3) / 1e9 / PEAK_HBM_GBS}
                     for k, v in ms_k.items()},
         "speedup_vs_k1": ms_k[1] / ms,
-        # per-launch spread of the headline kernel, and the write-only share
-        # of the HBM peak (1 GiB of dice written per launch)
+        # per-launch spread of the headline kernel, and the share of the HBM
+        # peak its written bytes alone take (1 GiB of dice per launch; it
+        # reads as much again, which the roofline above counts)
         "headline_launch_stats": head_stats,
-        "hbm_write_only_frac": (COUNT * 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        "headline_written_bytes_frac": (COUNT * 4) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
         "l32_sweep": {str(k): {"ms": v, "rolls_per_s": COUNT / (v * 1e-3),
                                "hbm_frac": BYTES_PER_ROLL * COUNT / (v * 1e-3) / 1e9 / PEAK_HBM_GBS}
                       for k, v in ms_32.items()},
@@ -473,6 +474,9 @@ def main():
                         "hbm_write_frac": 4 * COUNT / (v * 1e-3) / 1e9 / PEAK_HBM_GBS}
                for k, v in ms_const.items()},
             "speedup_best_vs_k1": ms_const[1] / min(ms_const[k] for k in (2, 3, 4)),
+            "best_k": min((2, 3, 4), key=lambda k: ms_const[k]),
+            "best_hbm_write_frac": 4 * COUNT / (min(ms_const[k] for k in (2, 3, 4)) * 1e-3) / 1e9
+                                   / PEAK_HBM_GBS,
         },
         "ceilings": ceilings(brr, torch),
     }
