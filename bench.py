@@ -35,6 +35,17 @@ COUNT = 1 << 28
 BYTES_PER_ROLL = 8  # 4 B bound read + 4 B die written
 KNOWN_BOUND = 65535  # the known-bounds stream: one bound, 65535^4 < 2^64
 
+# Context, not a target: the paper's speed ratios of shuffle_6 over an
+# unbatched Fisher-Yates shuffle of 64-bit elements on CPUs, ranges over its
+# array sizes (Experiments section, speed-ratio figure and its discussion).
+# The GPU ratios beside them are the secondary workloads' speedup_k6_vs_k1
+# (Philox words: the fast generator) and chacha20_speedup_k6_vs_k1.
+PAPER_CPU_SPEEDUPS = {
+    "Intel Xeon Gold 6338 (3.2 GHz)": {"Lehmer128": [1.4, 1.8], "PCG64": [1.8, 2.5],
+                                       "ChaCha": [2.9, 4.7]},
+    "Apple M2 (3.49 GHz)": {"Lehmer128": [1.5, 2.3], "PCG64": [1.9, 2.6], "ChaCha": [2.6, 3.9]},
+}
+
 
 def kernel_source_hash():
     h = hashlib.sha256()
@@ -486,6 +497,7 @@ def main():
 
     if not args.no_secondary:
         rec["secondary"] = secondary(brr, workloads, up, max(5, args.steps // 2))
+        rec["secondary"]["paper_cpu_speedups"] = PAPER_CPU_SPEEDUPS
 
     if not args.no_cpu_baseline:
         import oracle
