@@ -72,7 +72,7 @@ __device__ __noinline__ uint64_t chacha_word_at(uint64_t c, StreamKey key)
 struct WordPair {
     uint64_t w0, w1;
 };
-__device__ __noinline__ WordPair chacha_pair_at(uint64_t m, StreamKey key)
+[[maybe_unused]] __device__ __noinline__ WordPair chacha_pair_at(uint64_t m, StreamKey key)
 {
     uint32_t x[16];
     chacha20_block(key, m / (kWordsPerBlock / 2), x);
