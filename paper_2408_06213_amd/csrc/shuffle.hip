@@ -654,8 +654,21 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const u
             u32x4 *vd = reinterpret_cast<u32x4 *>(dst + cur.head);
             for (uint32_t i = lane; i < cur.nv; i += kLaneItems) {
                 Elem tmp[V];
+                // the V elements of one vector usually sit in one array and in
+                // one word of its byte permutation: one division, one
+                // permutation read for all of them
+                const uint32_t e0 = cur.head + i * V;
+                const uint32_t lt = lane_div(e0, n0, rcp), x0 = e0 - lt * n0;
+                if ((x0 & 3u) + V <= 4 && x0 + V <= n0) {
+                    const uint32_t pw = *reinterpret_cast<const uint32_t *>(
+                        perm_bytes + (cur.t0 + lt) * RW * 4 + (x0 & ~3u));
+                    const Elem *row = stage + cur.sh + lt * n0;
 #pragma unroll
-                for (uint32_t j = 0; j < V; ++j) tmp[j] = out(cur.head + i * V + j);
+                    for (uint32_t j = 0; j < V; ++j) tmp[j] = row[(pw >> (8 * ((x0 & 3u) + j))) & 255u];
+                } else {
+#pragma unroll
+                    for (uint32_t j = 0; j < V; ++j) tmp[j] = out(e0 + j);
+                }
                 u32x4 w;
                 __builtin_memcpy(&w, tmp, 16);
                 __builtin_nontemporal_store(w, vd + i);
