@@ -1269,7 +1269,8 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *keys, 
     for (uint32_t d = threadIdx.x; d < NW * NB; d += kSortThreads) (&cnt[0][0])[d] = 0;
     __syncthreads();
     uint32_t *mine = cnt[threadIdx.x >> 6];
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint32_t tile = xcd_tile(blockIdx.x, nblk);
+    const uint64_t base = (uint64_t)tile * kSortTile;
 #pragma unroll
     for (uint32_t u = 0; u < kSortItems; ++u) {
         const uint64_t i = base + u * kSortThreads + threadIdx.x;
@@ -1280,7 +1281,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *keys, 
         uint32_t c = 0;
 #pragma unroll
         for (uint32_t w = 0; w < NW; ++w) c += cnt[w][d];
-        hist[(uint64_t)d * nblk + blockIdx.x] = c;
+        hist[(uint64_t)d * nblk + tile] = c;
     }
 }
 
