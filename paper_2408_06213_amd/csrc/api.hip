@@ -196,6 +196,10 @@ struct brr_plan {
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // recorded on the caller's stream after every run: the executable graph
+    // (and everything else the plan owns) is released or replaced only
+    // after the last run that may use it has finished
+    hipEvent_t done = nullptr;
     void *g_data = nullptr;
     const uint64_t *g_offsets = nullptr;
     uint64_t g_seed = 0, g_inst = 0;
@@ -205,6 +209,11 @@ namespace {
 
 void release(brr_plan *p)
 {
+    if (p->done) {
+        (void)hipEventSynchronize(p->done);
+        (void)hipEventDestroy(p->done);
+        p->done = nullptr;
+    }
     for (int t = 0; t < kTiers - 1; ++t) {
         if (p->branch[t]) (void)hipStreamDestroy(p->branch[t]);
         if (p->join[t]) (void)hipEventDestroy(p->join[t]);
@@ -423,10 +432,20 @@ brr_status run_plan(brr_plan *p, void *data, const uint64_t *offsets, uint64_t s
         const brr_status st = classify(p);
         if (st != BRR_OK) return st;
     }
-    if (!p->map.use_graph) return hip_status(enqueue(p, data, offsets, seed, inst, s));
+    if (!p->done && hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
+        p->done = nullptr;
+        return BRR_EHIP;
+    }
+    if (!p->map.use_graph) {
+        const hipError_t e = enqueue(p, data, offsets, seed, inst, s);
+        return hip_status(e == hipSuccess ? hipEventRecord(p->done, s) : e);
+    }
     const bool rebind = !p->exec || p->g_data != data || p->g_offsets != offsets ||
                         p->g_seed != seed || p->g_inst != inst;
     if (rebind) {
+        // the executable about to be replaced may still run from the last
+        // call (on any stream): wait for it before it is destroyed
+        if (p->exec && hipEventSynchronize(p->done) != hipSuccess) return BRR_EHIP;
         if (!p->capture_stream &&
             hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)
             return BRR_EHIP;
@@ -449,7 +468,8 @@ brr_status run_plan(brr_plan *p, void *data, const uint64_t *offsets, uint64_t s
         p->g_seed = seed;
         p->g_inst = inst;
     }
-    return hip_status(hipGraphLaunch(p->exec, s));
+    const hipError_t e = hipGraphLaunch(p->exec, s);
+    return hip_status(e == hipSuccess ? hipEventRecord(p->done, s) : e);
 }
 
 } // namespace

@@ -205,6 +205,31 @@ def test_batched_equal_size_full(gpu, orc, lane_max):
         assert np.array_equal(got, want)
 
 
+def test_plan_rebinds_while_running(gpu, orc):
+    """A plan called again with another buffer and instance before its last
+    run has finished (no synchronization between calls) replaces its graph:
+    the replaced graph must outlive that run. Every tier is present (lane,
+    LDS classes, peel, device-wide); every result equals the oracle's."""
+    sizes = np.array([256, 100, 2048, 4097, 16384, 16385, 65536, 70001, 5, (1 << 20) + 1],
+                     dtype=np.uint64)
+    off = workloads.csr_offsets(sizes)
+    data = workloads.iota_segments(sizes, np.uint32)
+    d_off = to_dev(off)
+    bufs = [to_dev(data) for _ in range(4)]
+    plan = gpu.Plan(off, 4)
+    say("plan rebinds while running", int(sizes.sum()))
+    for r, d in enumerate(bufs):
+        gpu.check(gpu.brr_shuffle_batched(d, d_off, len(sizes), 4, plan, 5, 100 + r),
+                  "brr_shuffle_batched")
+    assert gpu.brr_sync_status() == 0
+    got = [to_host(d) for d in bufs]
+    plan.close()
+    for r in range(4):
+        want = data.copy()
+        assert orc.shuffle_batched(want, off, orc.schedule_paper(6), 5, 100 + r) == 0
+        assert np.array_equal(got[r], want), r
+
+
 @pytest.mark.slow
 def test_batched_ragged_full(gpu, orc):
     """20,000 shuffles, n log-uniform in [16, 65536) (seed 3), u32 payload."""
