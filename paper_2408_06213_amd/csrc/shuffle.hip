@@ -720,6 +720,7 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const u
 constexpr uint32_t kPeel = 6144;       // positions per peel
 constexpr uint32_t kPeelHashBits = 13; // 8192 chains of u16 heads, load factor <= 0.75
 constexpr uint32_t kPeelTierMax = 1u << 20;
+__host__ __device__ constexpr int peel_threads(uint32_t eb) { return eb == 4 ? 512 : 1024; }
 
 __device__ __forceinline__ uint32_t peel_hash(uint32_t q)
 {
@@ -754,7 +755,10 @@ __device__ __forceinline__ uint32_t peel_query(const PeelState &ps, uint32_t q, 
 }
 
 // Peel tier: one workgroup per shuffle, positions taken top-down in peels of
-// whole batches (at most kPeel positions); the array stays in HBM/L2. For a
+// whole batches (at most kPeel positions); the array stays in HBM/L2. A
+// workgroup of peel_threads(eb) threads: 512 for 4-byte elements, whose
+// registers then allow two workgroups per CU (their LDS fits twice), 1024
+// for 8-byte elements, which would fit only one 512-thread workgroup. For a
 // peel [i_end, i_begin), with z the array after the peels above:
 //  - the head chain of a position x of the peel, x -> smallest step above x
 //    targeting x -> ..., ends at a position whose value is z at that
@@ -764,13 +768,13 @@ __device__ __forceinline__ uint32_t peel_query(const PeelState &ps, uint32_t q, 
 //    targets q, else z[q];
 //  - a target q below the peel receives, from the smallest step that targets
 //    it, the value at root of that step.
-template <typename Elem, bool W>
-__global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const uint64_t *offsets,
+template <typename Elem, bool W, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_peel_batched(Elem *data, const uint64_t *offsets,
                                                              const uint32_t *items, DevSched sc,
                                                              uint64_t seed, uint64_t inst_base)
 {
     constexpr uint32_t PEEL = kPeel;
-    constexpr int P = (PEEL + kWgThreads - 1) / kWgThreads;
+    constexpr int P = (PEEL + BLOCK - 1) / BLOCK;
     __shared__ uint32_t qof[kPeel];
     __shared__ uint16_t nxt[kPeel];
     __shared__ uint32_t root[kPeel]; // head-chain parent, then chain end (local)
@@ -803,11 +807,11 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
             next_s = s;
             next_i = i;
         }
-        for (uint32_t x = tid; x < (1u << kPeelHashBits); x += kWgThreads) table[x] = kNone16;
-        for (uint32_t x = tid; x < PEEL; x += kWgThreads) root[x] = kNone32;
+        for (uint32_t x = tid; x < (1u << kPeelHashBits); x += BLOCK) table[x] = kNone16;
+        for (uint32_t x = tid; x < PEEL; x += BLOCK) root[x] = kNone32;
         __syncthreads();
         const uint32_t s_end = next_s, i_end = next_i, H = i_begin - i_end;
-        for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += kWgThreads) {
+        for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += BLOCK) {
             uint64_t w[2];
             first_pair((W ? st.words : BRR_WORDS_PHILOX64), m, key, w[0], w[1]);
 #pragma unroll
@@ -826,7 +830,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
         // hash chains of the steps that move an element; the head-chain parent
         // of a peel position (its smallest step above that targets it) by
         // atomic minimum
-        for (uint32_t e = tid; e < H; e += kWgThreads) {
+        for (uint32_t e = tid; e < H; e += BLOCK) {
             const uint32_t q = qof[e];
             if (q != i_end + e) {
                 // push e on its chain: a compare-and-swap on the word holding
@@ -849,7 +853,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
         // another thread has already advanced is harmless
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-            const uint32_t e = tid + r * kWgThreads;
+            const uint32_t e = tid + r * BLOCK;
             if (e >= H) continue;
             uint32_t x = e;
             for (uint32_t guard = 0; guard < H; ++guard) {
@@ -867,7 +871,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
         Elem val[P], ext_val[P];
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-            const uint32_t e = tid + r * kWgThreads;
+            const uint32_t e = tid + r * BLOCK;
             if (e >= H) continue;
             const uint32_t p = i_end + e, q = qof[e];
             const uint32_t re = root[e];
@@ -898,7 +902,7 @@ __global__ __launch_bounds__(kWgThreads) void k_peel_batched(Elem *data, const u
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-            const uint32_t e = tid + r * kWgThreads;
+            const uint32_t e = tid + r * BLOCK;
             if (e >= H) continue;
             z[i_end + e] = val[r];
             if (ext_mask & (1u << r)) z[ext_q[r]] = ext_val[r];
@@ -1592,8 +1596,9 @@ hipError_t batched_peel_t(void *data, const uint64_t *offsets, const uint32_t *i
                           hipStream_t stream)
 {
     if (nitems == 0) return hipSuccess;
-    k_peel_batched<Elem, W><<<nitems, kWgThreads, 0, stream>>>(static_cast<Elem *>(data), offsets,
-                                                           items, sc, seed, inst_base);
+    constexpr int B = peel_threads(sizeof(Elem));
+    k_peel_batched<Elem, W, B><<<nitems, B, 0, stream>>>(static_cast<Elem *>(data), offsets, items,
+                                                         sc, seed, inst_base);
     return hipGetLastError();
 }
 
