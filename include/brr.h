@@ -277,7 +277,11 @@ brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_
  * one wavefront, one workgroup, or device-wide per shuffle), owns the device
  * copies of that classification, any scratch it needs, and a hip graph of
  * the launch sequence. h_offsets: host u64[count + 1], non-decreasing,
- * offsets[0] = 0. sched = NULL uses shuffle_6; it is copied. */
+ * offsets[0] = 0. sched = NULL uses shuffle_6; it is copied. The graph is
+ * bound to the buffers, seed and instance of the run that captured it; a
+ * run with others captures it again, and first waits on the host for the
+ * plan's previous run to finish. brr_plan_destroy also waits for the
+ * plan's last run, then releases everything the plan owns. */
 typedef struct brr_plan brr_plan;
 brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t count,
                            uint32_t elem_bytes, const brr_schedule *sched);
