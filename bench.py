@@ -117,7 +117,11 @@ def host_cpu():
                     break
     except OSError:
         pass
-    return {"model": model, "logical_cpus": os.cpu_count()}
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def serving(brr, workloads, up, rates=(1000, 4000, 16000), count=400, clients=64):
@@ -196,6 +200,61 @@ def tuned_ragged(brr, workloads, up, steps):
     plan.close()
     net.close()
     return res
+
+
+def cpu_baseline(brr, workloads, up, bounds_np, head_out, k_head):
+    """The oracle on every host core: the whole 2^28-roll headline stream
+    (its groups split over the cores; also one thread alone), and the equal
+    and ragged shuffle batches (shuffles split over the cores). Each oracle
+    output is compared bit for bit with the GPU's output of the same
+    workload (the headline stream as timed; one fresh shuffle_6 run of each
+    batch)."""
+    import numpy as np
+
+    import oracle
+
+    threads = oracle.host_threads()
+    t0 = time.perf_counter()
+    err, want = oracle.dice_stream(oracle.STREAM_MULTIPLY, bounds_np, k_head, 7, 0, threads=threads)
+    dt = time.perf_counter() - t0
+    assert err == 0
+    exact = {"dice_stream_2p28": bool(np.array_equal(head_out, want))}
+    del want
+    t0 = time.perf_counter()
+    err, _ = oracle.dice(bounds_np, k_head, 7, 0)
+    dt1 = time.perf_counter() - t0
+    assert err == 0
+    base = {
+        "value": COUNT / dt,
+        "unit": "rolls/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"the whole 2^28-roll stream at k={k_head}, plain C oracle, its group range "
+                  f"split over {threads} threads ({dt:.2f} s)",
+        "host": host_cpu(),
+        "one_thread": {"value": COUNT / dt1, "seconds": dt1},
+        "secondary": {},
+    }
+    s6 = oracle.schedule_paper(6)
+    batches = (("equal_65536x256_u32", np.full(65536, 256, dtype=np.uint64)),
+               ("ragged_20000_u32", workloads.ragged_sizes(20000, seed=3)))
+    for tag, sizes in batches:
+        off = workloads.csr_offsets(sizes)
+        data = workloads.iota_segments(sizes)
+        d, d_off = up(data), up(off)
+        plan = brr.Plan(off, 4)
+        brr.check(brr.brr_shuffle_batched(d, d_off, sizes.size, 4, plan, 1, 0))
+        got = d.cpu().numpy()
+        plan.close()
+        del d, d_off
+        t0 = time.perf_counter()
+        assert oracle.shuffle_batched_threads(data, off, s6, 1, 0, threads=threads) == 0
+        dt = time.perf_counter() - t0
+        exact[tag] = bool(np.array_equal(got, data))
+        base["secondary"][tag] = {"elems_per_s": data.size / dt, "seconds": dt, "cores": threads,
+                                  "sample": "the whole batch, shuffle_6, shuffles split over "
+                                            f"{threads} threads"}
+    return base, exact
 
 
 def pmc_pass(brr, workloads, up):
@@ -425,6 +484,10 @@ def main():
     k_head = min((2, 3, 4), key=lambda k: ms_k[k]) if args.k == "best" else int(args.k)
     ms = ms_k[k_head]
     head_stats = launch_stats(step(k_head))
+    # the headline stream as the timed launches wrote it, for the bit-exact
+    # comparison with the oracle
+    step(k_head)()
+    head_out = out.cpu().numpy()
     value = COUNT / (ms * 1e-3)
     achieved = BYTES_PER_ROLL * COUNT / (ms * 1e-3) / 1e9
     traffic = measured_traffic(k_head)
@@ -500,21 +563,11 @@ def main():
         rec["secondary"]["paper_cpu_speedups"] = PAPER_CPU_SPEEDUPS
 
     if not args.no_cpu_baseline:
-        import oracle
-
-        t0 = time.perf_counter()
-        err, _ = oracle.dice(bounds_np, k_head, 7, 0)
-        dt = time.perf_counter() - t0
-        assert err == 0
-        rec["cpu_baseline"] = {
-            "value": COUNT / dt,
-            "unit": "rolls/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"the whole 2^28-roll stream at k={k_head}, plain C oracle, one thread "
-                      f"({dt:.1f} s)",
-            "host": host_cpu(),
-        }
+        rec["cpu_baseline"], rec["bit_exact"] = cpu_baseline(brr, workloads, up, bounds_np, head_out,
+                                                             k_head)
+        if not all(rec["bit_exact"].values()):
+            print(json.dumps(rec), flush=True)
+            sys.exit("bench: a GPU output differs from the oracle: " + json.dumps(rec["bit_exact"]))
     print(json.dumps(rec), flush=True)
 
 

@@ -36,7 +36,11 @@
  *    above 2^64 in a dice stream) are recorded in a per-device status word
  *    that brr_sync_status() returns; the affected outputs are unspecified.
  *  - Thread safety: calls may come from several host threads; work on one
- *    stream is ordered, work on different streams may overlap.
+ *    stream is ordered, work on different streams may overlap. A brr_plan
+ *    serialises the host calls made on it, and each of its runs is ordered
+ *    after its previous run whatever stream either was enqueued on (the runs
+ *    share the plan's scratch); brr_plan_destroy must not overlap another
+ *    call on the same plan.
  */
 #ifndef BRR_H
 #define BRR_H
@@ -157,6 +161,18 @@ uint64_t brr_schedule_batches(const brr_schedule *sched, uint64_t n, uint64_t st
  * BRR_EINVAL or BRR_EOVERFLOW. */
 brr_status brr_schedule_check(const brr_schedule *sched, uint64_t n);
 
+/* Checks a schedule for every shuffle of at most max_n elements and every
+ * sample from one (what a plan or a server may meet): the checks of
+ * brr_schedule_check at max_n, and for every step the largest batch it can
+ * roll at any such size, which is its first batch at size
+ * min(max_n, n_above of the step before) (the tail's at min(max_n, the last
+ * n_above)): its product at most 2^L and at most the step's non-zero upper
+ * bound. brr_schedule_check(max_n) alone does not imply this, since where a
+ * step's first batch falls depends on n; and, without a tail, a last step
+ * that runs down to one element (n_above <= 1, else a shuffle of n_above
+ * elements would roll nothing). BRR_OK, BRR_EINVAL or BRR_EOVERFLOW. */
+brr_status brr_schedule_check_upto(const brr_schedule *sched, uint64_t max_n);
+
 /* ------------------------------------------------------------------------ */
 /* Planning: the cost model of Sec. 6.1 and schedules derived from it        */
 /* ------------------------------------------------------------------------ */
@@ -266,8 +282,10 @@ brr_status brr_dice32(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count,
  * shuffle_6. The result is the permutation that the sequential batched
  * Fisher-Yates shuffle produces: batch at size i rolls bounds i, i-1, ...,
  * i-k+1 and swaps z[i-1] with z[a_1] first. n <= 1 is a no-op;
- * n < 2^32. Large n allocates device scratch (about 24 bytes per element)
- * on first use; it is cached per device and reused. */
+ * n < 2^32. n above 16,384 takes device scratch of about 33 bytes plus
+ * elem_bytes per element from the stream-ordered allocator on `stream`
+ * (hipMallocAsync), freed on the same stream when the call's kernels end;
+ * BRR_ENOMEM if it cannot be had. */
 brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_schedule *sched,
                        uint64_t seed, uint64_t inst, void *stream);
 

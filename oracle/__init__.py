@@ -12,6 +12,7 @@ of the method's arithmetic.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import ctypes
 import os
 import subprocess
@@ -142,6 +143,8 @@ def lib():
         L.orc_partial_shuffle.restype = ctypes.c_int
         L.orc_sample.argtypes = [p, u64, u64, ctypes.c_uint, p, ctypes.POINTER(Schedule), u64, u64]
         L.orc_sample.restype = ctypes.c_int
+        L.orc_dice_range.argtypes = [ctypes.c_uint, p, p, u64, ctypes.c_uint, u64, u64, u64, u64]
+        L.orc_dice_range.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -326,3 +329,66 @@ def sample(data: np.ndarray, m: int, sched: Schedule, seed: int, inst: int = 0):
     err = lib().orc_sample(_ptr(data), data.size, m, data.itemsize, _ptr(out), ctypes.byref(sched),
                            seed, inst)
     return err, out
+
+
+# ----------------------------------------------------------------------------
+# whole streams and batches on every host core
+# ----------------------------------------------------------------------------
+
+STREAM_MULTIPLY, STREAM_DIVISION, STREAM_CHACHA20, STREAM_L32 = 0, 1, 2, 3
+
+
+def host_threads() -> int:
+    """Host threads the process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def _split(total: int, parts: int):
+    parts = max(1, min(parts, total)) if total else 1
+    edges = [total * i // parts for i in range(parts + 1)]
+    return list(zip(edges[:-1], edges[1:]))
+
+
+def dice_range(kind: int, bounds: np.ndarray, out: np.ndarray, k: int, g0: int, g1: int,
+               seed: int, inst: int = 0) -> int:
+    """Groups g0..g1-1 of the stream of ``kind`` (STREAM_*) into ``out``."""
+    return lib().orc_dice_range(kind, _ptr(bounds), _ptr(out), bounds.size, k, g0, g1, seed, inst)
+
+
+def dice_stream(kind: int, bounds: np.ndarray, k: int, seed: int, inst: int = 0,
+                threads: int | None = None):
+    """The whole dice stream of ``kind`` (the output of dice, dice_div,
+    dice_chacha or dice32), its group range split over ``threads`` host
+    threads (default: every core this process may use). Returns (err, out)."""
+    bounds = np.ascontiguousarray(bounds, dtype=np.uint32)
+    out = np.zeros(bounds.size, dtype=np.uint32)
+    S = -(-bounds.size // k) if k else 0
+    threads = threads or host_threads()
+    lib()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        errs = list(ex.map(lambda r: dice_range(kind, bounds, out, k, r[0], r[1], seed, inst),
+                           _split(S, threads)))
+    return next((e for e in errs if e), OK), out
+
+
+def shuffle_batched_threads(data: np.ndarray, offsets: np.ndarray, sched: Schedule, seed: int,
+                            inst_base: int = 0, threads: int | None = None) -> int:
+    """shuffle_batched with its shuffles split over ``threads`` host threads
+    (contiguous ranges of shuffles; shuffle q keeps instance inst_base + q)."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    count = offsets.size - 1
+    threads = threads or host_threads()
+    L = lib()
+
+    def part(r):
+        q0, q1 = r
+        op = offsets.ctypes.data + 8 * q0
+        return L.orc_shuffle_batched(_ptr(data), ctypes.c_void_p(op), q1 - q0, data.itemsize,
+                                     ctypes.byref(sched), seed, inst_base + q0)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        errs = list(ex.map(part, _split(count, threads)))
+    return next((e for e in errs if e), OK)

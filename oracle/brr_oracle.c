@@ -870,3 +870,49 @@ int orc_sample(const void *data, uint64_t n, uint64_t m, unsigned eb, void *out,
 /* Number of words (Philox halves) that the first attempts of a dice stream
  * or a shuffle consume: S. Exposed so tests can check word accounting. */
 uint64_t orc_dice_groups(uint64_t count, unsigned k) { return k ? ceil_div(count, k) : 0; }
+
+/* ------------------------------------------------------------------ */
+/* Group ranges of a dice stream                                       */
+/* ------------------------------------------------------------------ */
+
+/* Groups g0 .. g1-1 of the dice stream that the whole-stream function of
+ * `kind` rolls over `count` bounds in groups of k (S = ceil(count / k)
+ * groups; the last keeps count mod k bounds when that is non-zero); out and
+ * bounds are the whole stream's arrays, and only out[g0*k .. min(g1*k,
+ * count)-1] is written. kind: 0 Theorem 1 on Philox words (orc_dice),
+ * 1 the division form (orc_dice_div), 2 ChaCha20 words (orc_dice_chacha),
+ * 3 word width 32 (orc_dice32). Every group is rolled by the same routine
+ * the whole-stream function calls, so disjoint ranges can run on separate
+ * threads and together write what that function writes. */
+int orc_dice_range(unsigned kind, const uint32_t *bounds, uint32_t *out, uint64_t count,
+                   unsigned k, uint64_t g0, uint64_t g1, uint64_t seed, uint64_t inst)
+{
+    if (k == 0 || k > 64 || kind > 3 || (kind == 3 && k > 32)) return ORC_EINVAL;
+    const uint64_t S = ceil_div(count, k);
+    if (g1 > S) g1 = S;
+    int status = ORC_OK;
+    for (uint64_t s = g0; s < g1; ++s) {
+        const uint64_t first = s * k;
+        const unsigned kk = (unsigned)((count - first < k) ? count - first : k);
+        uint64_t b[64], a[64];
+        for (unsigned i = 0; i < kk; ++i) b[i] = bounds[first + i];
+        int err;
+        if (kind == 0) {
+            err = roll_group_alg3(b, kk, seed, inst, S, s, a);
+        } else if (kind == 1) {
+            u128 prod;
+            err = bound_product(64, b, kk, &prod);
+            if (!err) division_digits(lemire_value(prod, seed, inst, S, s), b, kk, a);
+        } else if (kind == 2) {
+            err = roll_group_chacha(b, kk, seed, inst, S, s, a);
+        } else {
+            err = roll_group32(b, kk, seed, inst, S, s, a);
+        }
+        if (err) {
+            if (!status) status = err;
+            continue;
+        }
+        for (unsigned i = 0; i < kk; ++i) out[first + i] = (uint32_t)a[i];
+    }
+    return status;
+}

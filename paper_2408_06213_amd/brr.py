@@ -20,7 +20,8 @@ BRR_MAX_K = 20
 
 # every symbol include/brr.h declares
 EXPORTS = (
-    "brr_schedule_paper", "brr_schedule_batches", "brr_schedule_check", "brr_dice",
+    "brr_schedule_paper", "brr_schedule_batches", "brr_schedule_check",
+    "brr_schedule_check_upto", "brr_dice",
     "brr_dice_const", "brr_shuffle", "brr_plan_create", "brr_plan_destroy",
     "brr_plan_get_mapping", "brr_plan_set_mapping", "brr_shuffle_batched", "brr_sample",
     "brr_sync_status", "brr_strerror", "brr_cost_per_die", "brr_cost_thresholds",
@@ -124,6 +125,7 @@ def _load():
         "brr_dice_tuple": (st, [p, u32, p, u64, u64, u64, p]),
         "brr_schedule_batches": (u64, [sched_p, u64, u64]),
         "brr_schedule_check": (st, [sched_p, u64]),
+        "brr_schedule_check_upto": (st, [sched_p, u64]),
         "brr_dice": (st, [p, p, u64, u32, u64, u64, p]),
         "brr_dice_const": (st, [u32, p, u64, u32, u64, u64, p]),
         "brr_dice32": (st, [p, p, u64, u32, u64, u64, p]),
@@ -240,6 +242,10 @@ def brr_schedule_batches(sched: brr_schedule, n: int, steps: int) -> int:
 
 def brr_schedule_check(sched: brr_schedule, n: int) -> int:
     return lib.brr_schedule_check(ctypes.byref(sched), n)
+
+
+def brr_schedule_check_upto(sched: brr_schedule, max_n: int) -> int:
+    return lib.brr_schedule_check_upto(ctypes.byref(sched), max_n)
 
 
 def brr_cost_per_die(n: int, k: int, L: int = 64, c_rng: float = 2.0, c_div: float = 16.0) -> float:

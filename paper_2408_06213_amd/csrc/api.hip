@@ -151,6 +151,44 @@ brr_status check_for(const brr_schedule &sc, uint64_t n, uint64_t steps)
     return e;
 }
 
+// Every shuffle of at most max_n elements (and every sample from one), as a
+// plan or a server meets them. check_for(max_n) alone does not cover them:
+// where a segment's first batch falls depends on n, so a guard that covers
+// the first batch of the largest shuffle can be below the product of a
+// smaller one's. The largest batch a segment can roll is its first at the
+// largest size it can start from, min(max_n, n_above of the segment before)
+// (k dice, fewer where fewer steps remain); the tail's is at min(max_n, the
+// last n_above). Falling products grow with the size, so these bound every
+// batch of every such shuffle; check_for(max_n) adds the completeness check
+// (no element left without a step), and without a tail the last step must
+// run down to one element (n_above <= 1), else the smallest shuffles stop
+// short.
+brr_status check_upto(const brr_schedule &sc, uint64_t max_n)
+{
+    brr_status e = check_for(sc, max_n, max_n ? max_n - 1 : 0);
+    if (e != BRR_OK || max_n <= 1) return e;
+    const u128 two_l = (u128)1 << (sc.words == BRR_WORDS_PHILOX32 ? 32 : 64);
+    uint64_t top = max_n;
+    for (uint32_t g = 0; g < sc.nsteps; ++g) {
+        const brr_step &st = sc.step[g];
+        if (top > st.n_above && top > 1) {
+            const u128 p = falling(top, std::min<uint64_t>(st.k, top - 1));
+            if (p > two_l) return BRR_EOVERFLOW;
+            if (st.u0 && (u128)st.u0 < p) return BRR_EINVAL;
+        }
+        top = std::min<uint64_t>(top, st.n_above);
+    }
+    if (sc.tail && top > 1) {
+        const u128 p = falling(top, top - 1);
+        if (p > two_l) return BRR_EOVERFLOW;
+        if (sc.u_tail && (u128)sc.u_tail < p) return BRR_EINVAL;
+    }
+    // without a tail a shuffle of top elements (2 <= top <= the last
+    // n_above) would roll no batch at all
+    if (!sc.tail && top > 1) return BRR_EINVAL;
+    return BRR_OK;
+}
+
 DevSched to_dev(const brr_schedule &sc) { return dev_schedule(sc); }
 
 } // namespace
@@ -200,6 +238,9 @@ struct brr_plan {
     // (and everything else the plan owns) is released or replaced only
     // after the last run that may use it has finished
     hipEvent_t done = nullptr;
+    bool ran = false; // done has been recorded at least once
+    // serialises host calls on the plan (runs, mapping, tuning)
+    std::mutex mu;
     void *g_data = nullptr;
     const uint64_t *g_offsets = nullptr;
     uint64_t g_seed = 0, g_inst = 0;
@@ -436,9 +477,14 @@ brr_status run_plan(brr_plan *p, void *data, const uint64_t *offsets, uint64_t s
         p->done = nullptr;
         return BRR_EHIP;
     }
+    // runs on any stream follow the plan's previous run: they share its
+    // scratch and its branch streams
+    if (p->ran && hipStreamWaitEvent(s, p->done, 0) != hipSuccess) return BRR_EHIP;
     if (!p->map.use_graph) {
         const hipError_t e = enqueue(p, data, offsets, seed, inst, s);
-        return hip_status(e == hipSuccess ? hipEventRecord(p->done, s) : e);
+        const brr_status st = hip_status(e == hipSuccess ? hipEventRecord(p->done, s) : e);
+        if (st == BRR_OK) p->ran = true;
+        return st;
     }
     const bool rebind = !p->exec || p->g_data != data || p->g_offsets != offsets ||
                         p->g_seed != seed || p->g_inst != inst;
@@ -469,7 +515,9 @@ brr_status run_plan(brr_plan *p, void *data, const uint64_t *offsets, uint64_t s
         p->g_inst = inst;
     }
     const hipError_t e = hipGraphLaunch(p->exec, s);
-    return hip_status(e == hipSuccess ? hipEventRecord(p->done, s) : e);
+    const brr_status st = hip_status(e == hipSuccess ? hipEventRecord(p->done, s) : e);
+    if (st == BRR_OK) p->ran = true;
+    return st;
 }
 
 } // namespace
@@ -563,6 +611,12 @@ brr_status brr_schedule_check(const brr_schedule *sched, uint64_t n)
 {
     if (!sched) return BRR_EINVAL;
     return check_for(*sched, n, n ? n - 1 : 0);
+}
+
+brr_status brr_schedule_check_upto(const brr_schedule *sched, uint64_t max_n)
+{
+    if (!sched) return BRR_EINVAL;
+    return check_upto(*sched, max_n);
 }
 
 brr_status brr_dice(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
@@ -721,8 +775,8 @@ brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t c
         max_n = std::max<uint64_t>(max_n, h_offsets[q + 1] - h_offsets[q]);
     }
     if (max_n > 0xFFFFFFFFull) return BRR_EINVAL;
-    // the largest product of every segment occurs in the largest shuffle
-    brr_status st = check_for(sc, max_n, max_n ? max_n - 1 : 0);
+    // every size up to the largest shuffle's may occur
+    brr_status st = check_upto(sc, max_n);
     if (st != BRR_OK) return st;
     st = device_ready(nullptr);
     if (st != BRR_OK) return st;
@@ -754,6 +808,7 @@ void brr_plan_destroy(brr_plan *plan)
 brr_status brr_plan_get_mapping(const brr_plan *plan, brr_mapping *out)
 {
     if (!plan || !out) return BRR_EINVAL;
+    std::lock_guard<std::mutex> lock(const_cast<brr_plan *>(plan)->mu);
     *out = plan->map;
     return BRR_OK;
 }
@@ -761,6 +816,7 @@ brr_status brr_plan_get_mapping(const brr_plan *plan, brr_mapping *out)
 brr_status brr_plan_set_mapping(brr_plan *plan, const brr_mapping *m)
 {
     if (!plan || !m) return BRR_EINVAL;
+    std::lock_guard<std::mutex> lock(plan->mu);
     if (plan->classified) return BRR_EINVAL; // the mapping is fixed by the first run
     if (m->lane_max > lane_tier_max_n()) return BRR_EINVAL;
     if (m->wave_max > wave_tier_max_n()) return BRR_EINVAL;
@@ -784,6 +840,7 @@ brr_status brr_shuffle_batched(void *d_data, const uint64_t *d_offsets, uint64_t
         (void)hipGetDevice(&dev);
         if (dev != plan->device) return BRR_EINVAL;
         try {
+            std::lock_guard<std::mutex> lock(plan->mu);
             return run_plan(plan, d_data, d_offsets, seed, inst_base, s);
         } catch (...) {
             return BRR_ENOMEM;
@@ -951,7 +1008,7 @@ std::vector<Candidate> candidates(const brr_plan *plan, uint64_t max_n)
     const int lflag = (words == BRR_WORDS_PHILOX32) ? BRR_COSTS_L32 : 0;
     auto add = [&](brr_schedule c) {
         c.words = words;
-        if (check_for(c, max_n, max_n ? max_n - 1 : 0) != BRR_OK) return;
+        if (check_upto(c, max_n) != BRR_OK) return;
         for (const brr_schedule &o : scheds)
             if (same_steps(o, c)) return;
         scheds.push_back(c);
@@ -988,6 +1045,7 @@ brr_status tune_plan(brr_plan *plan, brr_mlp *model, uint32_t top, const void *d
                      brr_tune_report *report)
 {
     if (!plan || !d_data || !d_offsets) return BRR_EINVAL;
+    std::lock_guard<std::mutex> plan_lock(plan->mu);
     if (plan->classified) return BRR_EINVAL; // must precede the first run
     brr_status st = device_ready(nullptr);
     if (st != BRR_OK) return st;
@@ -1168,6 +1226,7 @@ brr_status brr_dice_autotune(uint32_t max_bound, uint64_t count, void *stream, u
 brr_status brr_plan_get_schedule(const brr_plan *plan, brr_schedule *out)
 {
     if (!plan || !out) return BRR_EINVAL;
+    std::lock_guard<std::mutex> lock(const_cast<brr_plan *>(plan)->mu);
     *out = plan->sched;
     return BRR_OK;
 }

@@ -227,7 +227,7 @@ brr_status brr_server_create(brr_server **out, const brr_server_config *cfg)
     brr_schedule s6;
     brr_schedule_paper(6, &s6);
     const brr_schedule &sc = cfg->schedule ? *cfg->schedule : s6;
-    if (brr_schedule_check(&sc, 0xFFFFFFFFull) != BRR_OK) return BRR_EINVAL;
+    if (brr_schedule_check_upto(&sc, 0xFFFFFFFFull) != BRR_OK) return BRR_EINVAL;
     const brr_status st = ensure_device();
     if (st != BRR_OK) return st;
     brr_server *sv = new (std::nothrow) brr_server();

@@ -140,6 +140,55 @@ def test_schedule_check_host():
     assert brr.brr_schedule_check(bad, 1000) == brr.BRR_EINVAL
 
 
+def test_schedule_check_upto_covers_every_smaller_size(orc):
+    """A plan or a server meets every size up to its largest. The check for
+    them agrees with running the oracle's own per-size checks on every size
+    (brute force): the oracle accepts a schedule for n elements exactly when
+    every batch of that n-element shuffle passes Algorithm 4's requirements.
+    The first case is one where a guard covers the largest shuffle's first
+    batch of a step but not a smaller shuffle's (the step's first batch
+    lands higher there)."""
+    import numpy as np
+
+    from paper_2408_06213_amd import brr
+
+    def oracle_ok(steps, tail, u_tail, n):
+        o = orc.Schedule.from_segments(steps, tail=tail, u_tail=u_tail)
+        return orc.shuffle(np.arange(n, dtype=np.uint32), o, 1, 0) == 0
+
+    steps, tail = [(20, 2, 0), (2, 3, 5814)], True
+    s = brr.brr_schedule.from_steps(steps, tail=tail, u_tail=720)
+    assert brr.brr_schedule_check(s, 21) == brr.BRR_OK  # 21 alone is fine
+    assert oracle_ok(steps, tail, 720, 21) and not oracle_ok(steps, tail, 720, 20)
+    assert brr.brr_schedule_check_upto(s, 21) == brr.BRR_EINVAL
+    assert brr.brr_schedule_check_upto(s, 19) == brr.BRR_OK
+    # a plan over sizes 21 and 20 is refused before any device work
+    off = (ctypes.c_uint64 * 3)(0, 21, 41)
+    plan = ctypes.c_void_p()
+    assert brr.lib.brr_plan_create(ctypes.byref(plan), off, 2, 4, ctypes.byref(s)) == brr.BRR_EINVAL
+    rng = np.random.default_rng(12)
+    for _ in range(300):
+        nseg = int(rng.integers(1, 4))
+        thr = sorted((int(x) for x in rng.integers(2, 40, size=nseg)), reverse=True)
+        segs = []
+        for g in range(nseg):
+            k = int(rng.integers(1, min(6, thr[g] + 1) + 1))
+            top = 60 if g == 0 else thr[g - 1]
+            # guards near the products of the step's largest batches
+            p = 1
+            for l in range(k):
+                p *= max(1, top - l)
+            u = 0 if rng.random() < 0.3 else int(p * rng.uniform(0.2, 1.2)) + 1
+            segs.append((thr[g], k, u))
+        tl = bool(rng.random() < 0.8)
+        ut = int(rng.choice([0, 720, 5040, 40320, 10**6]))
+        s = brr.brr_schedule.from_steps(segs, tail=tl, u_tail=ut)
+        for max_n in (2, 10, 25, 60):
+            want = all(oracle_ok(segs, tl, ut, n) for n in range(2, max_n + 1))
+            got = brr.brr_schedule_check_upto(s, max_n) == brr.BRR_OK
+            assert got == want, (segs, tl, ut, max_n)
+
+
 def test_host_argument_errors_need_no_device():
     from paper_2408_06213_amd import brr
 

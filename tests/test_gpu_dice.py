@@ -95,34 +95,6 @@ def test_dice_const_overflow_rejected_on_host(gpu):
     assert gpu.brr_dice_const(2**32 - 1, out, 16, 3, 1, 0) == gpu.BRR_EOVERFLOW
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("k", [1, 2, 3, 4])
-def test_dice_full_size_sampled(gpu, orc, k):
-    """2^28 rolls, bounds in [1, 2^16) from seed 7 (the benchmark's stream):
-    every output below its bound; 20000 random groups plus the first and
-    last 500 checked one by one against the oracle."""
-    import torch
-
-    count = 1 << 28
-    say("dice full size", k)
-    bounds = workloads.dice_bounds(count, seed=7)
-    b = to_dev(bounds)
-    out = torch.empty(count, dtype=torch.uint32, device="cuda")
-    gpu.check(gpu.brr_dice(b, out, count, k, 7, 0), "brr_dice")
-    assert gpu.brr_sync_status() == 0
-    got = to_host(out)
-    del b, out
-    assert np.all(got < bounds)
-    S = -(-count // k)
-    rng = np.random.default_rng(k)
-    groups = np.concatenate([np.arange(500), np.arange(S - 500, S), rng.integers(0, S, 20000)])
-    for g in groups:
-        lo, hi = int(g) * k, min(count, int(g) * k + k)
-        err, want = orc.dice_group(bounds[lo:hi], S, int(g), 7, 0)
-        assert err == 0
-        assert np.array_equal(got[lo:hi], want), (k, int(g))
-
-
 # ---------------------------------------------------------------------------
 # Word width 32 (brr_dice32)
 # ---------------------------------------------------------------------------
@@ -336,45 +308,68 @@ def test_dice_tuple_equals_dice_on_tiled_bounds(gpu):
 
 
 # ---------------------------------------------------------------------------
-# Full size (2^28 rolls, the benchmark's stream) for the other forms and
-# word streams, in the launch configuration the benchmark times
+# Full size: every 2^28-roll stream the benchmark times, in the launch
+# configuration it times, compared whole with the oracle (its group range
+# split over every host core)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("entry,k", [("div", 2), ("div", 4), ("chacha", 2), ("chacha", 4),
-                                     ("l32", 1), ("l32", 2), ("tuple", 4)])
-def test_other_streams_full_size_sampled(gpu, orc, entry, k):
-    """Every output below its bound; the first and last 300 groups and 6000
-    random ones checked one by one against the oracle."""
+FULL = 1 << 28
+
+
+@pytest.fixture(scope="module")
+def full_bounds():
+    """The benchmark's two 2^28 bound streams: uniform in [1, 2^16) from
+    seed 7, and uniform in [1, 2^12) from seed 8."""
+    return {7: workloads.dice_bounds(FULL, seed=7), 8: workloads.dice_bounds(FULL, seed=8, high=1 << 12)}
+
+
+FULL_CASES = ([("mul", k, 7) for k in (1, 2, 3, 4)] + [("div", k, 7) for k in (1, 2, 3, 4)]
+              + [("chacha", k, 7) for k in (1, 2, 3, 4)] + [("l32", k, 7) for k in (1, 2)]
+              + [("const", k, 7) for k in (1, 2, 3, 4)] + [("tuple", 4, 7)]
+              + [("mul", k, 8) for k in (1, 2)] + [("l32", k, 8) for k in (1, 2)]
+              + [("chacha", k, 8) for k in (1, 2, 3, 4)])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("entry,k,seed", FULL_CASES)
+def test_full_size_stream_whole(gpu, orc, full_bounds, entry, k, seed):
+    """All 2^28 outputs bit for bit: brr_dice (k = 1..4), brr_dice_div,
+    brr_dice_chacha, brr_dice32 and the known-bounds streams (one bound
+    65535, Algorithm 2, k = 1..4; the tuple (6, 10, 12, 20)) on the seed-7
+    bounds, and the seed-8 stream (bounds below 2^12) at both word widths
+    and on ChaCha20 words. Known-bound streams are compared with Algorithm 3
+    on the bounds written out (the two are equal: oracle pins)."""
     import torch
 
-    count = 1 << 28
-    say("full size", entry, k)
-    if entry == "tuple":
+    say("full size whole", entry, k, seed)
+    if entry == "const":
+        bounds = np.full(FULL, 65535, np.uint32)
+    elif entry == "tuple":
         tup = [6, 10, 12, 20]
-        bounds = np.resize(np.array(tup, np.uint32), count)
+        bounds = np.resize(np.array(tup, np.uint32), FULL)
     else:
-        bounds = workloads.dice_bounds(count, seed=7)
-    out = torch.empty(count, dtype=torch.uint32, device="cuda")
-    if entry == "tuple":
-        gpu.check(gpu.brr_dice_tuple(tup, out, count, 7, 0), "brr_dice_tuple")
+        bounds = full_bounds[seed]
+    out = torch.empty(FULL, dtype=torch.uint32, device="cuda")
+    if entry == "const":
+        gpu.check(gpu.brr_dice_const(65535, out, FULL, k, seed, 0), "brr_dice_const")
+    elif entry == "tuple":
+        gpu.check(gpu.brr_dice_tuple(tup, out, FULL, seed, 0), "brr_dice_tuple")
     else:
         b = to_dev(bounds)
-        fn = {"div": gpu.brr_dice_div, "chacha": gpu.brr_dice_chacha, "l32": gpu.brr_dice32}[entry]
-        gpu.check(fn(b, out, count, k, 7, 0), entry)
+        fn = {"mul": gpu.brr_dice, "div": gpu.brr_dice_div, "chacha": gpu.brr_dice_chacha,
+              "l32": gpu.brr_dice32}[entry]
+        gpu.check(fn(b, out, FULL, k, seed, 0), entry)
         del b
     assert gpu.brr_sync_status() == 0
     got = to_host(out)
     del out
-    assert np.all(got < bounds)
-    group = {"div": orc.dice_div_group, "chacha": orc.dice_chacha_group, "l32": orc.dice32_group,
-             "tuple": orc.dice_group}[entry]
-    S = -(-count // k)
-    rng = np.random.default_rng(100 + k)
-    for g in np.concatenate([np.arange(300), np.arange(S - 300, S), rng.integers(0, S, 6000)]):
-        lo, hi = int(g) * k, min(count, int(g) * k + k)
-        err, want = group(bounds[lo:hi], S, int(g), 7, 0)
-        assert err == 0
-        assert np.array_equal(got[lo:hi], want), (entry, k, int(g))
+    kind = {"mul": orc.STREAM_MULTIPLY, "const": orc.STREAM_MULTIPLY, "tuple": orc.STREAM_MULTIPLY,
+            "div": orc.STREAM_DIVISION, "chacha": orc.STREAM_CHACHA20, "l32": orc.STREAM_L32}[entry]
+    err, want = orc.dice_stream(kind, bounds, k, seed, 0)
+    assert err == 0
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError(f"{entry} k={k}: {bad.size} of {FULL} rolls differ, first at {bad[0]}")
 
 
 def test_copy_probe_copies(gpu):

@@ -49,6 +49,41 @@ def test_forward_and_gradients_match_reference(gpu):
     net.close()
 
 
+def test_adam_moments_over_many_steps(gpu):
+    """Eight successive backward + Adam steps on the device against the
+    float64 reference carrying its own first and second moments and step
+    count: at every step the device gradient matches the reference gradient
+    at the device's current parameters, and the device parameters match the
+    reference's Adam trajectory fed those gradients (bias corrections for
+    steps 1..8, moments accumulated across steps)."""
+    import torch
+
+    rng = np.random.default_rng(5)
+    n_in, h, B, lr = 16, 32, 200, 0.02
+    net = make_net(gpu, n_in, h, seed=9)
+    x = rng.normal(size=(B, n_in)).astype(np.float32)
+    t = rng.normal(size=B).astype(np.float32)
+    d_x, d_t = to_dev(x), to_dev(t)
+    p_ref = net.params().astype(np.float64)
+    m = np.zeros_like(p_ref)
+    v = np.zeros_like(p_ref)
+    for step in range(1, 9):
+        say("mlp adam step", step)
+        p_dev = net.params().astype(np.float64)
+        net.backward(d_x, d_t, B)
+        torch.cuda.synchronize()
+        g = net.grads().astype(np.float64)
+        g_ref = mlp.grad(p_dev, x.astype(np.float64), t.astype(np.float64), n_in, h)
+        assert np.allclose(g, g_ref, rtol=1e-3, atol=1e-4 * np.abs(g_ref).max()), step
+        net.adam_step(lr)
+        torch.cuda.synchronize()
+        p_ref, m, v = mlp.adam(p_ref, g, m, v, step, lr)
+        # each update moves a parameter by at most ~lr; fp32 rounding of the
+        # moments and of the parameters themselves stays far below 1e-5
+        assert np.allclose(net.params(), p_ref, rtol=1e-4, atol=1e-5), step
+    net.close()
+
+
 def test_training_fits_a_smooth_target(gpu):
     rng = np.random.default_rng(2)
     X = rng.uniform(-1, 1, size=(512, 16)).astype(np.float32)

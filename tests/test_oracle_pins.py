@@ -920,3 +920,54 @@ def test_stream_group_entries_equal_streams(orc):
             for g in range(S):
                 e, got = group(bounds[g * k:(g + 1) * k], S, g, 9, 2)
                 assert e == 0 and np.array_equal(got, out[g * k:(g + 1) * k]), (stream, k, g)
+
+
+def test_dice_ranges_equal_streams(orc):
+    """The group-range entry (whole streams on every host core) writes what
+    the whole-stream oracles write, for each stream kind, over uneven
+    splits that cut at arbitrary groups, short last group included; ranges
+    past the end and empty ranges write nothing; an error in one group is
+    reported and leaves the others written."""
+    rng = np.random.default_rng(79)
+    streams = ((orc.STREAM_MULTIPLY, orc.dice, 16), (orc.STREAM_DIVISION, orc.dice_div, 16),
+               (orc.STREAM_CHACHA20, orc.dice_chacha, 16), (orc.STREAM_L32, orc.dice32, 8))
+    for kind, whole, bits in streams:
+        for k, count in ((1, 997), (2, 1001), (3, 3001), (4, 4003)):
+            bounds = rng.integers(1, 1 << (bits if k < 4 else bits // 2), size=count,
+                                  dtype=np.uint32)
+            err, want = whole(bounds, k, 9, 2)
+            assert err == 0
+            S = -(-count // k)
+            cuts = np.sort(rng.integers(0, S + 1, size=5))
+            edges = [0, *cuts.tolist(), S + 7]
+            got = np.full(count, 0xFFFFFFFF, np.uint32)
+            for g0, g1 in zip(edges[:-1], edges[1:]):
+                assert orc.dice_range(kind, bounds, got, k, g0, g1, 9, 2) == 0
+            assert np.array_equal(got, want), (kind, k)
+            for threads in (1, 3, 8):
+                e, got = orc.dice_stream(kind, bounds, k, 9, 2, threads=threads)
+                assert e == 0 and np.array_equal(got, want), (kind, k, threads)
+    bounds = rng.integers(1, 1 << 16, size=100, dtype=np.uint32)
+    bounds[37] = 0
+    err, want = orc.dice(bounds, 2, 9, 2)
+    assert err == orc.EINVAL
+    e, got = orc.dice_stream(orc.STREAM_MULTIPLY, bounds, 2, 9, 2, threads=4)
+    assert e == orc.EINVAL
+    keep = np.ones(100, bool)
+    keep[36:38] = False
+    assert np.array_equal(got[keep], want[keep])
+
+
+def test_threaded_batched_shuffle_equals_batched(orc):
+    """shuffle_batched split over threads by shuffle ranges equals the
+    single-threaded batch (instances inst_base + q kept)."""
+    from paper_2408_06213_amd import workloads
+
+    sizes = workloads.ragged_sizes(300, seed=3)
+    off = workloads.csr_offsets(sizes)
+    a = workloads.iota_segments(sizes)
+    b = a.copy()
+    s6 = orc.schedule_paper(6)
+    assert orc.shuffle_batched(a, off, s6, 1, 5) == 0
+    assert orc.shuffle_batched_threads(b, off, s6, 1, 5, threads=7) == 0
+    assert np.array_equal(a, b)
