@@ -115,6 +115,13 @@ class brr_server_stats(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    # torch ships its own HIP runtime library. Loaded first, it is the one
+    # libbrr binds to (same soname), so the library and the device memory
+    # and streams torch hands it share one runtime; loaded the other way
+    # round, the process would hold two runtimes and the library's could not
+    # use the device.
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(LIB_PATH)
     u64, u32, p, st = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
     sched_p = ctypes.POINTER(brr_schedule)

@@ -26,6 +26,22 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(brr.lib, s), s
 
 
+def test_binding_loads_one_hip_runtime():
+    """Importing the binding before torch still leaves one HIP runtime in
+    the process (torch's): libbrr must share the runtime that owns the
+    device memory and streams torch hands it."""
+    import subprocess
+    import sys
+
+    code = ("from paper_2408_06213_amd import brr\n"
+            "import torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         check=True)
+    assert out.stdout.strip().splitlines()[-1] == "1", out.stdout
+
+
 def test_strerror():
     from paper_2408_06213_amd import brr
 
