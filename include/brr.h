@@ -289,6 +289,25 @@ brr_status brr_dice32(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count,
 brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_schedule *sched,
                        uint64_t seed, uint64_t inst, void *stream);
 
+/* brr_shuffle for callers that cannot allocate (code under hip graph
+ * capture, serving loops, harnesses that forbid allocation): the same
+ * result as brr_shuffle with the same arguments, but nothing is allocated.
+ * Arrays above 16,384 elements use a scratch array that the library holds
+ * in device memory, one of BRR_NOALLOC_SCRATCH_BYTES per device, from the
+ * first call on that device until the process ends. n is limited to
+ * BRR_NOALLOC_MAX_N (2^21) elements; a larger n returns BRR_EINVAL with
+ * nothing enqueued. Every call initialises the parts of the scratch it
+ * reads, so no clearing is needed between calls. All calls on one device
+ * share that one array: calls that may overlap on the device (on different
+ * streams, or from several host threads without ordering) race and give
+ * unspecified results; order them on one stream. Other arguments, results
+ * and errors as brr_shuffle. */
+#define BRR_NOALLOC_MAX_N (1ull << 21)
+#define BRR_NOALLOC_SCRATCH_BYTES (96ull << 20)
+brr_status brr_shuffle_noalloc(void *d_data, uint64_t n, uint32_t elem_bytes,
+                               const brr_schedule *sched, uint64_t seed, uint64_t inst,
+                               void *stream);
+
 /* A plan for a batch of shuffles given in CSR form: shuffle q covers
  * elements offsets[q] .. offsets[q+1]-1 of one array and uses instance
  * inst_base + q. The plan sorts the shuffles into size classes (one lane,

@@ -13,6 +13,9 @@
 
 using namespace brr;
 
+// Scratch of brr_shuffle_noalloc (file scope; see noalloc_scratch).
+static __device__ __align__(256) char scratch[BRR_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 typedef unsigned __int128 u128;
@@ -27,6 +30,36 @@ struct DeviceState {
 
 std::mutex g_mu;
 DeviceState g_dev[kMaxDevices];
+
+// Scratch of brr_shuffle_noalloc: one array per device, held while the
+// process lives. Host code never passes its name (a host-side stand-in) to a
+// kernel or a copy; it uses the device address that hipGetSymbolAddress
+// returns for the current device (noalloc_scratch below).
+constexpr uint64_t kNoAllocScratchBytes = BRR_NOALLOC_SCRATCH_BYTES;
+
+struct NoAllocState {
+    bool done = false;
+    void *ptr = nullptr;
+};
+NoAllocState g_noalloc[kMaxDevices];
+
+// The device address of the current device's scratch array, looked up once
+// per device (with that device current) and kept.
+brr_status noalloc_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BRR_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_mu);
+    NoAllocState &d = g_noalloc[dev];
+    if (!d.done) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BRR_EHIP;
+        d.ptr = ptr;
+        d.done = true;
+    }
+    *out = d.ptr;
+    return BRR_OK;
+}
 
 // Checks once per device that it is a gfx950 and allocates its status word.
 brr_status device_ready(uint32_t **status_out)
@@ -737,6 +770,29 @@ brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_
     if (st != BRR_OK) return st;
     return hip_status(launch_one(d_data, (uint32_t)n, (uint32_t)(n - 1), 0, elem_bytes, nullptr,
                                  to_dev(sc), seed, inst, DevClaim{}, static_cast<hipStream_t>(stream)));
+}
+
+brr_status brr_shuffle_noalloc(void *d_data, uint64_t n, uint32_t elem_bytes,
+                               const brr_schedule *sched, uint64_t seed, uint64_t inst,
+                               void *stream)
+{
+    if (elem_bytes != 4 && elem_bytes != 8) return BRR_EINVAL;
+    if (n <= 1) return BRR_OK;
+    if (!d_data || misaligned(d_data, elem_bytes)) return BRR_EINVAL;
+    if (n > BRR_NOALLOC_MAX_N || one_scratch_bytes(n, elem_bytes) > kNoAllocScratchBytes)
+        return BRR_EINVAL;
+    const brr_schedule &sc = sched ? *sched : paper6();
+    brr_status st = check_for(sc, n, n - 1);
+    if (st != BRR_OK) return st;
+    st = device_ready(nullptr);
+    if (st != BRR_OK) return st;
+    void *scr = nullptr;
+    st = noalloc_scratch(&scr);
+    if (st != BRR_OK) return st;
+    // the kernels initialise every part of the scratch they read
+    return hip_status(launch_one(d_data, (uint32_t)n, (uint32_t)(n - 1), 0, elem_bytes, nullptr,
+                                 to_dev(sc), seed, inst, DevClaim{},
+                                 static_cast<hipStream_t>(stream), scr));
 }
 
 brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_bytes, void *d_out,

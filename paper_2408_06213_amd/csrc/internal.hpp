@@ -199,12 +199,13 @@ uint64_t gtier_scratch_bytes(uint64_t npos, uint32_t eb);
 constexpr uint64_t kMaxGtierPositions = 0xFFFFFFFFull;
 
 // One shuffle (out == nullptr) or sample through the LDS tier or, for
-// n > lds_tier_max_n(), the device-wide tier with stream-ordered scratch of
-// one_scratch_bytes(n, eb) bytes.
+// n > lds_tier_max_n(), the device-wide tier with one_scratch_bytes(n, eb)
+// bytes of scratch: the caller's (scratch != nullptr; nothing is allocated)
+// or taken from the stream-ordered allocator and freed on the stream.
 uint64_t one_scratch_bytes(uint64_t n, uint32_t eb);
 hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
                       void *out, const DevSched &ds, uint64_t seed, uint64_t inst,
-                      const DevClaim &claim, hipStream_t s);
+                      const DevClaim &claim, hipStream_t s, void *scratch = nullptr);
 uint32_t gtier_tile_shift(); // log2 of the indices per tile-table entry
 hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream);
 

@@ -1715,7 +1715,7 @@ uint64_t one_scratch_bytes(uint64_t n, uint32_t eb)
 
 hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
                       void *out, const DevSched &ds, uint64_t seed, uint64_t inst,
-                      const DevClaim &claim, hipStream_t s)
+                      const DevClaim &claim, hipStream_t s, void *scratch_given)
 {
     if (n <= lds_tier_max_n())
         return launch_lds_single(data, n, steps, out_lo, eb, out, ds, seed, inst, claim, s);
@@ -1734,6 +1734,10 @@ hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, u
     a.npairs = (st.S + 1) / 2;
     a.one_item = &it;
     a.one_seg = &st;
+    if (scratch_given) {
+        a.scratch = scratch_given;
+        return launch_gtier(a, s);
+    }
     void *scratch = nullptr;
     hipError_t e = hipMallocAsync(&scratch, gtier_scratch_bytes(n, eb), s);
     if (e != hipSuccess) return e;
