@@ -928,20 +928,41 @@ __global__ __launch_bounds__(BLOCK) void k_peel_batched(Elem *data, const uint64
 //            target (returning atomic add on cnt[target])
 //   scan:    cnt = exclusive prefix of the per-target counts
 //   scatter: bucket[cnt[target] + slot[x]] = x
-//   links:   per target: head[t] = smallest step of its bucket, and each
-//            step's successor = the next larger one there
 //  sorting (larger problems, where returning atomics on scattered counters
 //  cost more than sorting):
-//   init:    sort keys "none", sort values = own position, heads "none"
-//   dice:    jj[x] = j_p; sort key of step x = its global target (steps
-//            with j_p = p keep "none")
+//   init:    target flags cleared; positions that take no step get the sort
+//            key "none" and their own position as value
+//   dice:    sort key of step x = its global target (steps with j_p = p
+//            keep "none"), value = x
 //   sort:    stable LSD radix sort of (target, step) pairs, 8..10-bit digits;
 //            steps into one target end up adjacent and in increasing order
-//   links:   over the sorted pairs: head[t] = first step of t's run, and
-//            each step's successor is the next one in its run
-// then, either way (steps, heads and successors as global positions):
-//   resolve: source of every output position, gathered from the input
-//   copy:    in-place shuffles copy the gathered values back
+// Then the permutation is resolved forwards, element by element (the
+// element first at y, A0[y]):
+//   - if steps take y as their target, the first of them in time, the
+//     largest p in T(y), swaps A0[y] into p, which is final: dest(y) =
+//     max T(y);
+//   - else A0[y] is at y when step y runs. If j_y = y (or y takes no step)
+//     it stays: dest = y. Else it moves to x = j_y, where the next step
+//     into x in time, the largest step of T(x) below y (y's predecessor in
+//     T(x)), moves it on to that step's position, which is final; if y is
+//     the smallest step into x, nothing moves it until step x, and from x it
+//     goes on in the same way.
+// So every position z, as a step, gets a move: "stay" (no step or j_z = z),
+// "prev q" (q is z's predecessor among the steps into j_z) or "down x"
+// (z is the smallest step into x = j_z). The group pass writes these moves
+// and every target's largest step; an element goes to its position's
+// largest step if it has one, else to the end of the moves followed from
+// its position (the walk pass). The "down" moves link positions into disjoint
+// paths (a position is the smallest step into at most one target, and at
+// most one step is the smallest into it), so every position is passed by
+// one walk at most: about half a random read per position. The passes keep
+// random reads and random writes apart, and each writes one array at random
+// (moves; placed values), since random writes are cheap only while their
+// array fits the last-level cache.
+//   group:   moves, and each target's largest step (in target order)
+//   walk:    the destination of every element that no step targets
+//   place:   every element written at its destination
+//   copy:    in-place shuffles copy the placed values back
 // ---------------------------------------------------------------------------
 
 constexpr uint32_t kSortThreads = 512;
@@ -957,16 +978,30 @@ constexpr uint32_t kSortNone = 0xFFFFFFFFu;               // sorts after every t
 constexpr uint64_t kCountMaxPositions = 1ull << 21;
 
 struct GArrays {
-    uint32_t *jj;              // j_p of every position (item-local)
+    uint32_t *jj;              // counting: j_p of every position (item-local)
     uint32_t *key[2], *val[2]; // sort ping-pong: global target, global step
                                // (counting: slot = key[0], bucket = key[1])
     uint32_t *cnt;             // counting: per-target counts, then offsets
-    uint32_t *head;            // smallest step into each global target
-    uint32_t *succ;            // next larger step into the same target
+    void *move;                // per position as a step: its move (Move words)
+    uint32_t *last;            // per position as a target: largest step into it, or kNone32
     uint32_t *hist;            // per-block digit counts, digit-major, then scanned
     uint32_t *tiles;           // scan partial sums
-    void *tmp;                 // gathered values of in-place shuffles
+    void *tmp;                 // placed values of in-place shuffles
 };
+
+// Move of an element that arrives at position z (z as a step): the kind in
+// the top two bits of a Move word, a global position below them. Problems
+// below 2^30 positions use 32-bit words (the array that the group pass
+// writes at random then stays within the last-level cache longer), larger
+// ones 64-bit words.
+template <typename Move> struct MoveBits {
+    static constexpr uint32_t kShift = 8 * sizeof(Move) - 2;
+    static constexpr Move kDown = 0;                   // on to target j_z (z is its smallest step)
+    static constexpr Move kPrev = (Move)1 << kShift;   // to the previous step into j_z: final
+    static constexpr Move kStay = (Move)2 << kShift;   // stays at z: final
+    static constexpr Move kPos = ((Move)1 << kShift) - 1;
+};
+constexpr uint64_t kMove32MaxPositions = 1ull << 30;
 
 __host__ __device__ inline uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
 
@@ -981,8 +1016,9 @@ __host__ __device__ inline uint64_t garrays_bytes(uint64_t npos, uint32_t eb)
 {
     const uint64_t w = align256(4 * npos), nh = ((uint64_t)1 << kSortDigitMax) * sort_blocks(npos);
     const uint64_t nt = scan_tiles(nh > npos + 1 ? nh : npos + 1);
-    return 7 * w + align256(4 * (npos + 1)) + align256(4 * nh) + align256(4 * nt) +
-           align256(eb * npos);
+    const uint64_t mb = npos < kMove32MaxPositions ? 4 : 8;
+    return 6 * w + align256(mb * npos) + align256(4 * (npos + 1)) + align256(4 * nh) +
+           align256(4 * nt) + align256(eb * npos);
 }
 
 __host__ __device__ inline GArrays garrays(void *base, uint64_t npos)
@@ -990,11 +1026,13 @@ __host__ __device__ inline GArrays garrays(void *base, uint64_t npos)
     char *p = static_cast<char *>(base);
     const uint64_t w = align256(4 * npos), nh = ((uint64_t)1 << kSortDigitMax) * sort_blocks(npos);
     GArrays g;
-    uint32_t **arr[7] = {&g.jj, &g.key[0], &g.val[0], &g.key[1], &g.val[1], &g.head, &g.succ};
-    for (int a = 0; a < 7; ++a) {
+    uint32_t **arr[6] = {&g.jj, &g.key[0], &g.val[0], &g.key[1], &g.val[1], &g.last};
+    for (int a = 0; a < 6; ++a) {
         *arr[a] = reinterpret_cast<uint32_t *>(p);
         p += w;
     }
+    g.move = p;
+    p += align256((npos < kMove32MaxPositions ? 4 : 8) * npos);
     g.cnt = reinterpret_cast<uint32_t *>(p);
     p += align256(4 * (npos + 1));
     g.hist = reinterpret_cast<uint32_t *>(p);
@@ -1048,14 +1086,14 @@ __device__ __forceinline__ uint32_t item_of_pos(const GProblem &P, uint64_t x)
     return P.items ? find_item(P.pos_tile, P.pos_base, P.nitems, x) : 0u;
 }
 
-// Heads start empty; positions that take no step (below n - steps) get their
-// sort pair here, every other one from the dice.
+// No target has a step into it yet; positions that take no step (below
+// n - steps) get their sort pair here, every other one from the dice.
 __global__ __launch_bounds__(256) void k_gp_init(GProblem P, GArrays g, uint64_t npos)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0 && P.claim.counter) (void)take_claim(P.claim);
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npos;
          x += (uint64_t)gridDim.x * blockDim.x) {
-        g.head[x] = kNone32;
+        g.last[x] = kNone32;
         const GItem &it = item_at(P, item_of_pos(P, x));
         if (x - it.pos_base < it.n - it.steps) {
             g.key[0][x] = kSortNone;
@@ -1078,8 +1116,7 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
         const StreamKey key = make_key(seed, ib + it.inst);
         uint64_t wd[2];
         first_pair(src, m, key, wd[0], wd[1]);
-        uint32_t *jj = g.jj + it.pos_base, *sk = g.key[0] + it.pos_base;
-        uint32_t *sv = g.val[0] + it.pos_base;
+        uint32_t *sk = g.key[0] + it.pos_base, *sv = g.val[0] + it.pos_base;
         const uint32_t tb = (uint32_t)it.pos_base;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -1092,7 +1129,6 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
             for (uint32_t l = 0; l < k; ++l) {
                 const uint32_t p = i0 - 1 - l;
                 const uint32_t a = next_die(src, f, i0 - l, r);
-                jj[p] = a;
                 sk[p] = (a < p) ? tb + a : kSortNone;
                 sv[p] = tb + p;
             }
@@ -1185,31 +1221,59 @@ __global__ __launch_bounds__(256) void k_gc_scatter(GProblem P, GArrays g)
     }
 }
 
-// Position x as a target: the head of its bucket; as a step into q: its
-// successor, the next larger step in q's bucket (kNone32 for the largest).
-// One bucket scan each, so no thread pays for a whole bucket's pairs.
-__global__ __launch_bounds__(256) void k_gc_links(GProblem P, GArrays g)
+// Writes an element's final value: into the placement buffer of an in-place
+// shuffle, or, for a sample, into its output if the destination is one of
+// the positions sampled.
+template <typename Elem>
+__device__ __forceinline__ void place(const GItem &it, Elem *tmp, uint64_t dest, Elem v)
 {
+    if (it.out) {
+        const uint32_t p = (uint32_t)(dest - it.pos_base);
+        if (p >= it.out_lo) static_cast<Elem *>(it.out)[it.n - 1 - p] = v;
+    } else {
+        tmp[dest] = v;
+    }
+}
+
+// Counting form of the group pass. Position x as a step that stays (no step,
+// or j_p = p) gets "stay"; as a target with steps into it (its bucket,
+// unordered): the smallest step moves down to x, every other one to its
+// predecessor in the bucket, and the largest is recorded as x's last step.
+template <typename Move>
+__global__ __launch_bounds__(256) void k_gc_group(GProblem P, GArrays g)
+{
+    using MB = MoveBits<Move>;
     const uint32_t *bucket = g.key[1];
+    Move *move = static_cast<Move *>(g.move);
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
          x += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t b0 = g.cnt[x], b1 = g.cnt[x + 1];
-        uint32_t h = kNone32;
-        for (uint32_t e = b0; e < b1; ++e) h = min(h, bucket[e]);
-        g.head[x] = h;
         const GItem &it = item_at(P, item_of_pos(P, x));
         const uint32_t p = (uint32_t)(x - it.pos_base);
-        if (p < it.n - it.steps) continue;
-        const uint32_t q = g.jj[x];
-        if (q >= p) continue;
-        const uint64_t t = it.pos_base + q;
-        const uint32_t c0 = g.cnt[t], c1 = g.cnt[t + 1];
-        uint32_t sc = kNone32;
-        for (uint32_t f = c0; f < c1; ++f) {
-            const uint32_t w2 = bucket[f];
-            if (w2 > x && w2 < sc) sc = w2;
+        if (p < it.n - it.steps || g.jj[x] == p) move[x] = MB::kStay;
+        const uint32_t b0 = g.cnt[x], b1 = g.cnt[x + 1];
+        uint32_t lo = kNone32, hi = kNone32;
+        if (b1 > b0) {
+            hi = 0;
+            for (uint32_t e = b0; e < b1; ++e) {
+                const uint32_t t = bucket[e];
+                lo = min(lo, t);
+                hi = max(hi, t);
+            }
         }
-        g.succ[x] = sc;
+        g.last[x] = hi;
+        for (uint32_t e = b0; e < b1; ++e) {
+            const uint32_t t = bucket[e];
+            if (t == lo) {
+                move[t] = MB::kDown | (Move)x;
+                continue;
+            }
+            uint32_t pred = lo;
+            for (uint32_t f = b0; f < b1; ++f) {
+                const uint32_t u = bucket[f];
+                if (u < t && u > pred) pred = u;
+            }
+            move[t] = MB::kPrev | (Move)pred;
+        }
     }
 }
 
@@ -1378,54 +1442,64 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
     }
 }
 
-// Over the sorted pairs: runs of equal targets give heads and successors.
-__global__ __launch_bounds__(256) void k_gp_links(GArrays g, const uint32_t *keys,
-                                                  const uint32_t *vals, uint64_t npos)
+// Sorting form of the group pass, over the sorted pairs (runs of steps into
+// one target, steps increasing): each step's move (down for the first of
+// its run, else to the step before it), and each target's last step.
+template <typename Move>
+__global__ __launch_bounds__(256) void k_gp_group(GProblem P, GArrays g, const uint32_t *keys,
+                                                  const uint32_t *vals)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npos;
+    using MB = MoveBits<Move>;
+    Move *move = static_cast<Move *>(g.move);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.npos;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t t = keys[i];
-        if (t == kSortNone) continue;
-        const uint32_t x = vals[i];
-        if (i == 0 || keys[i - 1] != t) g.head[t] = x;
-        g.succ[x] = (i + 1 < npos && keys[i + 1] == t) ? vals[i + 1] : kNone32;
+        const uint32_t x = keys[i], z = vals[i];
+        if (x == kSortNone) { // no step, or j_p = p
+            move[z] = MB::kStay;
+            continue;
+        }
+        const bool first = i == 0 || keys[i - 1] != x;
+        const bool last = i + 1 == P.npos || keys[i + 1] != x;
+        move[z] = first ? (MB::kDown | (Move)x) : (MB::kPrev | (Move)vals[i - 1]);
+        if (last) g.last[x] = z;
     }
 }
 
+// Walk pass: the destination of the element first at x. If some step
+// targets x it is x's last step, already in last[x]; else the walk follows
+// the moves from x and stores where it ends in last[x]. Only reads are
+// random here; the values move in the place pass.
+template <typename Move>
+__global__ __launch_bounds__(256) void k_g_walk(GProblem P, GArrays g)
+{
+    using MB = MoveBits<Move>;
+    const Move *move = static_cast<const Move *>(g.move);
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        if (g.last[x] != kNone32) continue;
+        const GItem &it = item_at(P, item_of_pos(P, x));
+        Move m = move[x];
+        uint64_t z = x;
+        // every move down ends at a smaller position, so a walk is shorter
+        // than its array; the cap only bounds it against corrupted scratch
+        for (uint32_t guard = 0; guard < it.n && (m >> MB::kShift) == 0; ++guard) {
+            z = m & MB::kPos;
+            m = move[z];
+        }
+        g.last[x] = (m >> MB::kShift) == 1 ? (uint32_t)(m & MB::kPos) : (uint32_t)z;
+    }
+}
+
+// Place pass: every element written at its destination (the only random
+// writes of the pass).
 template <typename Elem>
-__global__ __launch_bounds__(256) void k_gp_resolve(GProblem P, GArrays g, const Elem *data)
+__global__ __launch_bounds__(256) void k_g_place(GProblem P, GArrays g, const Elem *data)
 {
     Elem *tmp = static_cast<Elem *>(g.tmp);
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
          x += (uint64_t)gridDim.x * blockDim.x) {
         const GItem &it = item_at(P, item_of_pos(P, x));
-        const uint32_t p = (uint32_t)(x - it.pos_base);
-        if (p < it.out_lo) continue;
-        const uint32_t lo = it.n - it.steps;
-        const uint32_t q = (p >= lo) ? g.jj[x] : p;
-        const uint32_t *head = g.head + it.pos_base;
-        uint32_t y = p, src;
-        bool walk = true;
-        if (p >= lo && q != p) {
-            const uint32_t sc = g.succ[x];
-            if (sc == kNone32) {
-                walk = false;
-                src = q;
-            } else {
-                y = sc - (uint32_t)it.pos_base;
-            }
-        }
-        if (walk) {
-            uint32_t h;
-            for (uint32_t guard = 0; guard < it.n && (h = head[y]) != kNone32; ++guard)
-                y = h - (uint32_t)it.pos_base;
-            src = y;
-        }
-        const Elem v = data[it.data_off + src];
-        if (it.out)
-            static_cast<Elem *>(it.out)[it.n - 1 - p] = v;
-        else
-            tmp[x] = v;
+        place(it, tmp, g.last[x], data[it.data_off + (x - it.pos_base)]);
     }
 }
 
@@ -1520,8 +1594,9 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
         k_gc_dice<W><<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
         scan_exclusive(g.cnt, g.tiles, P.npos + 1, stream);
         k_gc_scatter<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
-        k_gc_links<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
-        k_gp_resolve<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(
+        k_gc_group<uint32_t><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
+        k_g_walk<uint32_t><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
+        k_g_place<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(
             P, g, static_cast<const Elem *>(data));
         k_gp_copy<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,
                                                                    static_cast<Elem *>(data));
@@ -1542,9 +1617,17 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
         else if (rb == 9) sort_pass<9>(g, cur, P.npos, sh, nblk, stream);
         else sort_pass<10>(g, cur, P.npos, sh, nblk, stream);
     }
-    k_gp_links<<<grid_for(P.npos, 256), 256, 0, stream>>>(g, g.key[cur], g.val[cur], P.npos);
-    k_gp_resolve<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,
-                                                                  static_cast<const Elem *>(data));
+    if (P.npos < kMove32MaxPositions) {
+        k_gp_group<uint32_t><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, g.key[cur],
+                                                                        g.val[cur]);
+        k_g_walk<uint32_t><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
+    } else {
+        k_gp_group<uint64_t><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, g.key[cur],
+                                                                        g.val[cur]);
+        k_g_walk<uint64_t><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
+    }
+    k_g_place<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,
+                                                               static_cast<const Elem *>(data));
     k_gp_copy<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, static_cast<Elem *>(data));
     return hipGetLastError();
 }
