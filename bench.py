@@ -313,6 +313,35 @@ def torch_sync():
     torch.cuda.synchronize()
 
 
+def sample_sweep(brr, up, steps):
+    """Samples without replacement far smaller than their array: time and
+    device scratch against m, beside the full shuffle of the same array
+    (n = 2^22 u64, the serving workload's largest, and n = 2^26 u32)."""
+    import numpy as np
+    import torch
+
+    s6 = brr.brr_schedule_paper(6)
+    res = {}
+    for n, dt, ms in ((1 << 22, np.uint64, (4194, 41943, 419430)), (1 << 26, np.uint32, (6710886,))):
+        eb = np.dtype(dt).itemsize
+        d = up(np.arange(n, dtype=dt))
+        rows = {}
+        for m in ms:
+            o = torch.empty(m * eb, dtype=torch.uint8, device="cuda")
+            t = time_launches(lambda: brr.check(brr.brr_sample(d, n, m, eb, o, s6, 5, 0)),
+                              max(5, steps), 2)
+            rows[str(m)] = {"ms": t, "sampled_per_s": m / (t * 1e-3),
+                            "scratch_bytes": brr.brr_scratch_bytes(n, m, eb)}
+            del o
+        t = time_launches(lambda: brr.check(brr.brr_shuffle(d, n, eb, s6, 5, 0)), max(3, steps // 2), 1)
+        res[f"n_{n}_{np.dtype(dt).name}"] = {
+            "samples": rows,
+            "full_shuffle": {"ms": t, "scratch_bytes": brr.brr_scratch_bytes(n, 0, eb)}}
+        del d
+        torch.cuda.empty_cache()
+    return res
+
+
 def secondary(brr, workloads, up, steps, only=None):
     import numpy as np
 
@@ -386,6 +415,8 @@ def secondary(brr, workloads, up, steps, only=None):
         res["speedup_k6_vs_naive2"] = res["naive2"]["ms"] / res["k6"]["ms"]
         res["chacha20_speedup_k6_vs_k1"] = res["k1_chacha20"]["ms"] / res["k6_chacha20"]["ms"]
         out[tag] = res
+    if only in (None, "sample"):
+        out["sample_sparse"] = sample_sweep(brr, up, steps)
     if only in (None, "tuned"):
         out["ragged_20000_u32_tuned"] = tuned_ragged(brr, workloads, up, steps)
     if only in (None, "serving"):
@@ -403,7 +434,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--only", choices=["equal", "ragged", "single10000", "single2p26", "serving",
-                                       "tuned", "pmc"],
+                                       "tuned", "sample", "pmc"],
                     help="run one shuffle workload only (for profiling); prints its timings")
     args = ap.parse_args()
 

@@ -445,11 +445,23 @@ brr_status brr_plan_autotune_learned(brr_plan *plan, brr_mlp *model, uint32_t to
 /* Sampling without replacement (partial Fisher-Yates, Algorithm 4 Ensure)  */
 /* ------------------------------------------------------------------------ */
 
-/* d_out[t] = z[n-1-t], t < m, where z is d_data after the first m steps of
+/* Sampling without replacement (Algorithm 4's partial shuffle, Sec. 6):
+ * d_out[t] = z[n-1-t], t < m, where z is d_data after the first m steps of
  * the scheduled shuffle of d_data (the last batch cut to the dice needed).
- * d_data is not modified. m <= n, elem_bytes 4 or 8, n < 2^32. */
+ * d_data is not modified. m <= n, elem_bytes 4 or 8, n < 2^32. Above 16,384
+ * elements the work and the device scratch are O(m), whatever n: only the
+ * m steps are rolled and resolved, and only the at most 2m positions they
+ * touch are read (brr_scratch_bytes gives the scratch; it comes from the
+ * stream-ordered allocator on `stream`). */
 brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_bytes, void *d_out,
                       const brr_schedule *sched, uint64_t seed, uint64_t inst, void *stream);
+
+/* Bytes of device scratch that brr_shuffle (m = 0) or brr_sample (m > 0)
+ * takes for an array of n elements of elem_bytes each: 0 up to 16,384
+ * elements (one workgroup's LDS does), else about 33 + elem_bytes bytes per
+ * element for a shuffle and 28 bytes per sampled element for a sample.
+ * Returns 0 for invalid sizes (elem_bytes not 4 or 8, m > n, n >= 2^32). */
+uint64_t brr_scratch_bytes(uint64_t n, uint64_t m, uint32_t elem_bytes);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of shuffle and sample requests              */

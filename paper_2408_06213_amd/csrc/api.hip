@@ -795,6 +795,12 @@ brr_status brr_shuffle_noalloc(void *d_data, uint64_t n, uint32_t elem_bytes,
                                  static_cast<hipStream_t>(stream), scr));
 }
 
+uint64_t brr_scratch_bytes(uint64_t n, uint64_t m, uint32_t elem_bytes)
+{
+    if ((elem_bytes != 4 && elem_bytes != 8) || m > n || n > 0xFFFFFFFFull) return 0;
+    return one_scratch_bytes(n, elem_bytes, m);
+}
+
 brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_bytes, void *d_out,
                       const brr_schedule *sched, uint64_t seed, uint64_t inst, void *stream)
 {

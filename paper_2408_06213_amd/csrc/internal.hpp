@@ -198,11 +198,13 @@ uint64_t gtier_scratch_bytes(uint64_t npos, uint32_t eb);
 // Positions (summed over items) one device-wide launch takes: indices are u32.
 constexpr uint64_t kMaxGtierPositions = 0xFFFFFFFFull;
 
-// One shuffle (out == nullptr) or sample through the LDS tier or, for
-// n > lds_tier_max_n(), the device-wide tier with one_scratch_bytes(n, eb)
-// bytes of scratch: the caller's (scratch != nullptr; nothing is allocated)
-// or taken from the stream-ordered allocator and freed on the stream.
-uint64_t one_scratch_bytes(uint64_t n, uint32_t eb);
+// One shuffle (out == nullptr) or sample of m = n - out_lo elements through
+// the LDS tier or, for n > lds_tier_max_n(), the device-wide tier (a
+// shuffle) or the sparse sample path (O(m) work and scratch), with
+// one_scratch_bytes(n, eb, m) bytes of scratch (m = 0 for a shuffle): the
+// caller's (scratch != nullptr; nothing is allocated) or taken from the
+// stream-ordered allocator and freed on the stream.
+uint64_t one_scratch_bytes(uint64_t n, uint32_t eb, uint64_t m = 0);
 hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
                       void *out, const DevSched &ds, uint64_t seed, uint64_t inst,
                       const DevClaim &claim, hipStream_t s, void *scratch = nullptr);

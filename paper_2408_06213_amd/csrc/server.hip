@@ -273,7 +273,7 @@ brr_status brr_server_submit(brr_server *sv, const brr_request *req, uint64_t *i
     if (r.kind == BRR_REQ_SAMPLE && (r.m > r.n || (r.m && !r.d_out))) return BRR_EINVAL;
     Req q;
     q.r = r;
-    q.footprint = one_scratch_bytes(r.n, r.elem_bytes);
+    q.footprint = one_scratch_bytes(r.n, r.elem_bytes, r.kind == BRR_REQ_SAMPLE ? r.m : 0);
     q.t_submit = clock_t_::now();
     std::lock_guard<std::mutex> lock(sv->mu);
     if (sv->stop) return BRR_EINVAL;

@@ -930,10 +930,11 @@ __global__ __launch_bounds__(BLOCK) void k_peel_batched(Elem *data, const uint64
 //   scatter: bucket[cnt[target] + slot[x]] = x
 //  sorting (larger problems, where returning atomics on scattered counters
 //  cost more than sorting):
-//   init:    target flags cleared; positions that take no step get the sort
-//            key "none" and their own position as value
+//   init:    no target has a step yet; positions that take no step get the
+//            sort key "none"
 //   dice:    sort key of step x = its global target (steps with j_p = p
-//            keep "none"), value = x
+//            keep "none"); the value of the key at index x is x, which the
+//            first sort pass generates
 //   sort:    stable LSD radix sort of (target, step) pairs, 8..10-bit digits;
 //            steps into one target end up adjacent and in increasing order
 // Then the permutation is resolved forwards, element by element (the
@@ -1095,10 +1096,7 @@ __global__ __launch_bounds__(256) void k_gp_init(GProblem P, GArrays g, uint64_t
          x += (uint64_t)gridDim.x * blockDim.x) {
         g.last[x] = kNone32;
         const GItem &it = item_at(P, item_of_pos(P, x));
-        if (x - it.pos_base < it.n - it.steps) {
-            g.key[0][x] = kSortNone;
-            g.val[0][x] = (uint32_t)x;
-        }
+        if (x - it.pos_base < it.n - it.steps) g.key[0][x] = kSortNone;
     }
 }
 
@@ -1116,7 +1114,7 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
         const StreamKey key = make_key(seed, ib + it.inst);
         uint64_t wd[2];
         first_pair(src, m, key, wd[0], wd[1]);
-        uint32_t *sk = g.key[0] + it.pos_base, *sv = g.val[0] + it.pos_base;
+        uint32_t *sk = g.key[0] + it.pos_base;
         const uint32_t tb = (uint32_t)it.pos_base;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -1130,7 +1128,6 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
                 const uint32_t p = i0 - 1 - l;
                 const uint32_t a = next_die(src, f, i0 - l, r);
                 sk[p] = (a < p) ? tb + a : kSortNone;
-                sv[p] = tb + p;
             }
         }
     }
@@ -1358,7 +1355,9 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *keys, 
 // when RB is odd), then writes each digit's run to its place: the scanned
 // count of that digit over all earlier digits and blocks, plus the rank
 // inside the tile's run.
-template <uint32_t RB>
+// IOTA: the pass's input values are their own indices (the first pass, whose
+// value for the key at index x is x), generated rather than read.
+template <uint32_t RB, bool IOTA>
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin,
                                                              const uint32_t *vin, uint32_t *kout,
                                                              uint32_t *vout, uint64_t n,
@@ -1378,7 +1377,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
     for (uint32_t u = 0; u < kSortItems; ++u) { // coalesced; padding sorts last
         const uint32_t i = u * kSortThreads + tid;
         sk[sort_pad(i)] = (i < valid) ? kin[base + i] : kSortNone;
-        sv[sort_pad(i)] = (i < valid) ? vin[base + i] : 0u;
+        sv[sort_pad(i)] = IOTA ? (uint32_t)(base + i) : ((i < valid) ? vin[base + i] : 0u);
     }
     for (uint32_t d = tid; d < NB; d += kSortThreads) dst[d] = hist[(uint64_t)d * nblk + tile];
     __syncthreads();
@@ -1580,8 +1579,12 @@ void sort_pass(const GArrays &g, int cur, uint64_t npos, uint32_t sh, uint32_t n
 {
     k_rs_hist<RB><<<nblk, kSortThreads, 0, stream>>>(g.key[cur], npos, sh, g.hist, nblk);
     scan_exclusive(g.hist, g.tiles, ((uint64_t)1 << RB) * nblk, stream);
-    k_rs_scatter<RB><<<nblk, kSortThreads, 0, stream>>>(g.key[cur], g.val[cur], g.key[cur ^ 1],
-                                                        g.val[cur ^ 1], npos, sh, g.hist, nblk);
+    if (sh == 0)
+        k_rs_scatter<RB, true><<<nblk, kSortThreads, 0, stream>>>(
+            g.key[cur], nullptr, g.key[cur ^ 1], g.val[cur ^ 1], npos, sh, g.hist, nblk);
+    else
+        k_rs_scatter<RB, false><<<nblk, kSortThreads, 0, stream>>>(
+            g.key[cur], g.val[cur], g.key[cur ^ 1], g.val[cur ^ 1], npos, sh, g.hist, nblk);
 }
 
 template <typename Elem, bool W>
@@ -1629,6 +1632,178 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
     k_g_place<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,
                                                                static_cast<const Elem *>(data));
     k_gp_copy<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, static_cast<Elem *>(data));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sparse samples: m of n without replacement for n above the LDS tier. Only
+// positions base .. n-1 (base = n - m) are output and only the steps p >= lo
+// (lo = n - steps) run. A step's head chain climbs through larger steps, so
+// every chain that decides an output stays among positions base .. n-1:
+// index arrays of m entries (entry e = position base + e) suffice, and the
+// work is O(m) sort passes and gathers whatever n is.
+//   init:    heads "none"; entries below lo (position 0, when m = n) take no
+//            step: j = own position, sort key "none"
+//   dice:    j_p of every step and its sort key (target, or "none" if j_p = p)
+//   sort:    the (target, entry) pairs by target (targets below 2^bits, bits
+//            the bit length of n), as in the device-wide tier
+//   links:   over the sorted runs: head[x - base] = smallest step into x for
+//            every target x >= base; succ[e] = next larger step into the
+//            target of entry e
+//   resolve: the source of every output position, as in the LDS tier: a
+//            position that takes no step or targets itself follows the head
+//            chain from itself; another follows it from its successor, or
+//            takes its target's original element if it has none
+// ---------------------------------------------------------------------------
+
+struct SArrays {
+    uint32_t *jj;              // j_p of each entry's position
+    uint32_t *key[2], *val[2]; // sort ping-pong: target, entry
+    uint32_t *head;            // per entry as a target: smallest step into it
+    uint32_t *succ;            // per entry as a step: next larger step into its target
+    uint32_t *hist, *tiles;    // sort histograms, scan partial sums
+};
+
+__host__ __device__ inline uint64_t sarrays_bytes(uint64_t m)
+{
+    const uint64_t w = align256(4 * m), nh = ((uint64_t)1 << kSortDigitMax) * sort_blocks(m);
+    return 7 * w + align256(4 * nh) + align256(4 * scan_tiles(nh > m + 1 ? nh : m + 1));
+}
+
+inline SArrays sarrays(void *base, uint64_t m)
+{
+    char *p = static_cast<char *>(base);
+    const uint64_t w = align256(4 * m), nh = ((uint64_t)1 << kSortDigitMax) * sort_blocks(m);
+    SArrays a;
+    uint32_t **arr[7] = {&a.jj, &a.key[0], &a.val[0], &a.key[1], &a.val[1], &a.head, &a.succ};
+    for (int i = 0; i < 7; ++i) {
+        *arr[i] = reinterpret_cast<uint32_t *>(p);
+        p += w;
+    }
+    a.hist = reinterpret_cast<uint32_t *>(p);
+    p += align256(4 * nh);
+    a.tiles = reinterpret_cast<uint32_t *>(p);
+    return a;
+}
+
+// What the sparse-sample kernels share: the sample, its batches and the
+// instance (with the server's claim added, if any).
+struct SProblem {
+    uint32_t n, steps, m, base; // base = n - m; steps run at positions >= n - steps
+    SegTable seg;
+    uint64_t inst;
+    DevClaim claim;
+};
+
+__global__ __launch_bounds__(256) void k_sp_init(SProblem Q, SArrays a)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0 && Q.claim.counter) (void)take_claim(Q.claim);
+    const uint32_t lo = Q.n - Q.steps;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < Q.m; e += gridDim.x * blockDim.x) {
+        a.head[e] = kNone32;
+        const uint32_t p = Q.base + e;
+        if (p < lo) {
+            a.jj[e] = p;
+            a.key[0][e] = kSortNone;
+        }
+    }
+}
+
+template <bool W>
+__global__ __launch_bounds__(256) void k_sp_dice(SProblem Q, SArrays a, uint64_t seed)
+{
+    const uint32_t npairs = (Q.seg.S + 1) / 2;
+    const uint32_t src = W ? Q.seg.words : BRR_WORDS_PHILOX64;
+    const StreamKey key = make_key(seed, Q.inst + (Q.claim.counter ? *Q.claim.slot : 0));
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < npairs;
+         w += gridDim.x * blockDim.x) {
+        uint64_t wd[2];
+        first_pair(src, w, key, wd[0], wd[1]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t s = 2 * w + h;
+            if (s >= Q.seg.S) continue;
+            uint32_t i0, k, f;
+            uint64_t u;
+            batch_at(s, Q.seg.seg, Q.seg.nseg, i0, k, u, f);
+            uint64_t r = batch_state(src, f, i0, k, u, wd[h], Q.seg.S, s, key);
+            for (uint32_t l = 0; l < k; ++l) {
+                const uint32_t p = i0 - 1 - l;
+                const uint32_t t = next_die(src, f, i0 - l, r);
+                a.jj[p - Q.base] = t;
+                a.key[0][p - Q.base] = (t < p) ? t : kSortNone;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sp_links(SProblem Q, SArrays a, const uint32_t *keys,
+                                                  const uint32_t *vals)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < Q.m; i += gridDim.x * blockDim.x) {
+        const uint32_t x = keys[i], e = vals[i];
+        if (x == kSortNone) continue;
+        if ((i == 0 || keys[i - 1] != x) && x >= Q.base) a.head[x - Q.base] = Q.base + e;
+        a.succ[e] = (i + 1 < Q.m && keys[i + 1] == x) ? Q.base + vals[i + 1] : kNone32;
+    }
+}
+
+template <typename Elem>
+__global__ __launch_bounds__(256) void k_sp_resolve(SProblem Q, SArrays a, const Elem *data,
+                                                    Elem *out)
+{
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < Q.m; e += gridDim.x * blockDim.x) {
+        const uint32_t p = Q.base + e, q = a.jj[e];
+        uint32_t y = p, src;
+        bool walk = true;
+        if (q != p) {
+            const uint32_t sc = a.succ[e];
+            if (sc == kNone32) {
+                walk = false;
+                src = q;
+            } else {
+                y = sc;
+            }
+        }
+        if (walk) {
+            uint32_t h;
+            for (uint32_t guard = 0; guard < Q.m && (h = a.head[y - Q.base]) != kNone32; ++guard)
+                y = h;
+            src = y;
+        }
+        out[Q.n - 1 - p] = data[src];
+    }
+}
+
+template <typename Elem, bool W>
+hipError_t sample_sparse_t(const SProblem &Q, const void *data, void *out, uint64_t seed,
+                           void *scratch, hipStream_t stream)
+{
+    const SArrays a = sarrays(scratch, Q.m);
+    k_sp_init<<<grid_for(Q.m, 256), 256, 0, stream>>>(Q, a);
+    k_sp_dice<W><<<grid_for((Q.seg.S + 1) / 2, 256), 256, 0, stream>>>(Q, a, seed);
+    uint32_t bits = 0;
+    while (bits < 32 && (Q.n >> bits) != 0) ++bits;
+    GArrays g;
+    std::memset(&g, 0, sizeof g);
+    for (int c = 0; c < 2; ++c) {
+        g.key[c] = a.key[c];
+        g.val[c] = a.val[c];
+    }
+    g.hist = a.hist;
+    g.tiles = a.tiles;
+    const uint32_t nblk = (uint32_t)sort_blocks(Q.m);
+    const uint32_t passes = (bits + kSortDigitMax - 1) / kSortDigitMax;
+    const uint32_t rb0 = (bits + passes - 1) / passes, rb = rb0 < 8 ? 8 : rb0;
+    int cur = 0;
+    for (uint32_t sh = 0; sh < bits; sh += rb, cur ^= 1) {
+        if (rb == 8) sort_pass<8>(g, cur, Q.m, sh, nblk, stream);
+        else if (rb == 9) sort_pass<9>(g, cur, Q.m, sh, nblk, stream);
+        else sort_pass<10>(g, cur, Q.m, sh, nblk, stream);
+    }
+    k_sp_links<<<grid_for(Q.m, 256), 256, 0, stream>>>(Q, a, a.key[cur], a.val[cur]);
+    k_sp_resolve<Elem><<<grid_for(Q.m, 256), 256, 0, stream>>>(
+        Q, a, static_cast<const Elem *>(data), static_cast<Elem *>(out));
     return hipGetLastError();
 }
 
@@ -1791,9 +1966,10 @@ hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t ou
                                                    claim, stream);
 }
 
-uint64_t one_scratch_bytes(uint64_t n, uint32_t eb)
+uint64_t one_scratch_bytes(uint64_t n, uint32_t eb, uint64_t m)
 {
-    return n <= lds_tier_max_n() ? 0 : gtier_scratch_bytes(n, eb);
+    if (n <= lds_tier_max_n()) return 0;
+    return m ? sarrays_bytes(m) : gtier_scratch_bytes(n, eb);
 }
 
 hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
@@ -1804,6 +1980,28 @@ hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, u
         return launch_lds_single(data, n, steps, out_lo, eb, out, ds, seed, inst, claim, s);
     SegTable st;
     build_segments(n, steps, ds, st);
+    if (out) {
+        SProblem Q;
+        std::memset(&Q, 0, sizeof Q);
+        Q.n = n;
+        Q.steps = steps;
+        Q.m = n - out_lo;
+        Q.base = out_lo;
+        Q.seg = st;
+        Q.inst = inst;
+        Q.claim = claim;
+        void *scratch = scratch_given;
+        hipError_t e = hipSuccess;
+        if (!scratch && (e = hipMallocAsync(&scratch, sarrays_bytes(Q.m), s)) != hipSuccess) return e;
+        const bool w = ds.words != BRR_WORDS_PHILOX64;
+        e = eb == 4 ? (w ? sample_sparse_t<uint32_t, true>(Q, data, out, seed, scratch, s)
+                         : sample_sparse_t<uint32_t, false>(Q, data, out, seed, scratch, s))
+                    : (w ? sample_sparse_t<uint64_t, true>(Q, data, out, seed, scratch, s)
+                         : sample_sparse_t<uint64_t, false>(Q, data, out, seed, scratch, s));
+        if (scratch_given) return e;
+        const hipError_t f = hipFreeAsync(scratch, s);
+        return e != hipSuccess ? e : f;
+    }
     const GItem it{0, 0, inst, n, steps, out_lo, 0, out};
     GTierArgs a;
     std::memset(&a, 0, sizeof a);

@@ -205,6 +205,25 @@ def test_schedule_check_upto_covers_every_smaller_size(orc):
             assert got == want, (segs, tl, ut, max_n)
 
 
+def test_scratch_bytes_scale_with_the_sample():
+    """A sample's device scratch grows with m, not with n; up to 16,384
+    elements nothing is allocated; invalid sizes give 0."""
+    from paper_2408_06213_amd import brr
+
+    n = 1 << 22
+    full = brr.brr_scratch_bytes(n, 0, 8)
+    assert full > 33 * n
+    tenth = brr.brr_scratch_bytes(n, n // 10, 8)
+    assert tenth < full / 10
+    assert brr.brr_scratch_bytes(1 << 26, n // 10, 8) == tenth  # the same m, 16x the n
+    for m in (1000, 10_000, 100_000):
+        b = brr.brr_scratch_bytes(n, m, 8)
+        assert 28 * m <= b <= 28 * m + (1 << 20), m
+    assert brr.brr_scratch_bytes(16384, 100, 4) == 0 and brr.brr_scratch_bytes(16384, 0, 8) == 0
+    assert brr.brr_scratch_bytes(n, n + 1, 8) == 0 and brr.brr_scratch_bytes(n, 5, 3) == 0
+    assert brr.brr_scratch_bytes(1 << 32, 5, 4) == 0
+
+
 def test_host_argument_errors_need_no_device():
     from paper_2408_06213_amd import brr
 

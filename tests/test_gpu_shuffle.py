@@ -98,6 +98,28 @@ def test_sample_parity(gpu, orc, dtype):
         assert np.array_equal(to_host(d), data)  # input untouched
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("n,dtype,ms", [((1 << 26) + 3, np.uint32, (1, 999, ((1 << 26) + 3) // 10)),
+                                       (1 << 22, np.uint64, (1, 4194, (1 << 22) // 10,
+                                                             (1 << 22) - 1, 1 << 22))])
+def test_sparse_sample_parity(gpu, orc, n, dtype, ms):
+    """Samples far smaller than their array (the sparse path: only the m
+    steps and the positions they touch) and up to the whole array, against
+    the oracle's partial shuffle of a copy; the input stays untouched."""
+    s6g, s6o = both_schedules(gpu, orc, 6)
+    data = (np.arange(n, dtype=np.uint64) * 0x9E3779B97F4A7C15 % (1 << 63)).astype(dtype)
+    d = to_dev(data)
+    for m in ms:
+        say("sparse sample", np.dtype(dtype).name, n, m)
+        out = to_dev(np.zeros(m, dtype))
+        gpu.check(gpu.brr_sample(d, n, m, data.itemsize, out, s6g, 41, m), "brr_sample")
+        assert gpu.brr_sync_status() == 0
+        err, want = orc.sample(data, m, s6o, 41, m)
+        assert err == 0
+        assert np.array_equal(to_host(out), want), (n, m)
+    assert np.array_equal(to_host(d), data)
+
+
 def run_batched(gpu, sizes, dtype, seed, inst_base, plan=True, graph=True, reps=1, sched=None,
                 **mapping):
     off = workloads.csr_offsets(sizes)
