@@ -259,7 +259,11 @@ brr_status brr_dice_div(const uint32_t *d_bounds, uint32_t *d_out, uint64_t coun
  * (lo32 seed, hi32 seed, 0, 0, 0, 0, 0, 0), the 64-bit block counter c/8 in
  * words 12-13 and the 64-bit nonce inst in words 14-15. Dice, acceptance,
  * attempt addressing (attempt a of group s reads word a*S + s), arguments
- * and errors as brr_dice. */
+ * and errors as brr_dice. Groups rejected on their first word are rerolled
+ * by a second kernel from a queue in device scratch of 8 bytes per queued
+ * group, at most max(S/8, 2^16) of them, taken from the stream-ordered
+ * allocator on `stream`; groups beyond it, or all of them if the scratch
+ * cannot be had, are rerolled in place (the same dice, more slowly). */
 brr_status brr_dice_chacha(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
                            uint64_t seed, uint64_t inst, void *stream);
 

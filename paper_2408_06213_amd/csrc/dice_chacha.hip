@@ -16,10 +16,21 @@
 // octet hold eight consecutive groups per j, which share one ChaCha block:
 // lane q of the octet computes the block of slot j = q, and an 8 x 8
 // transpose in registers (three exchange stages, partners q ^ 1, q ^ 2,
-// q ^ 4) hands every lane its word of all eight blocks. Rerolls are
-// compacted: each pass computes one block per lane, for the lowest group of
-// that lane still rejected, so a pass costs one block however many of the
-// lane's groups are pending.
+// q ^ 4) hands every lane its word of all eight blocks.
+//
+// Rerolls. A reroll costs one block for one word, and the lanes of a
+// wavefront compute in lockstep, so a wave that rerolls its own few
+// rejected groups pays a full block per pass for each of them while most of
+// its lanes idle (and as many passes as its unluckiest group needs). So the
+// first pass records each tile's rejected groups (up to kTileSlots of them)
+// in device memory, and a second kernel of persistent waves works through
+// them with every lane busy: each wave owns a run of tiles, a lane takes
+// the next recorded group as soon as its current one is accepted, and keeps
+// rerolling a group until it is. A tile with more rejected groups rerolls
+// them in place, one block per lane and pass for the lane's lowest rejected
+// group (as does every tile when the memory cannot be had).
+#include <algorithm>
+
 #include "chacha.hpp"
 #include "device.hpp"
 #include "internal.hpp"
@@ -193,12 +204,24 @@ __device__ __forceinline__ void store_dice(uint32_t *__restrict__ out, uint64_t 
 // wavefronts than it saved in latency: k = 2 took 0.76 ms that way, 0.57 ms
 // this way). A rejected group is left for the reroll passes, which reload
 // its bounds.
+// Rejected groups of the first pass, per tile of 512 groups: count[t] and
+// their offsets in the tile, slot[t * kTileSlots + i] (t counts tiles from
+// the start of the stream). tiles = 0: no record, every tile rerolls in
+// place.
+constexpr uint32_t kTileSlots = 32;
+constexpr uint64_t kNoGroup = ~0ull;
+struct RerollRecord {
+    uint32_t *count;
+    uint16_t *slot;
+    uint64_t tiles;
+};
+
 template <int K, bool VEC>
 __global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__restrict__ bounds,
                                                           uint32_t *__restrict__ out,
                                                           uint64_t count, uint64_t S,
                                                           uint64_t full, StreamKey key,
-                                                          uint32_t *status)
+                                                          uint32_t *status, RerollRecord rec)
 {
     constexpr int G = 8; // groups per lane
     const uint32_t lane = threadIdx.x & 63;
@@ -221,9 +244,24 @@ __global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__rest
         else
             store_dice<K, VEC>(out, g, kk, whole, a);
     }
-    // rerolls, compacted: a lane works on its lowest pending group; each
-    // attempt is rejected with probability t / 2^64 < 1/2 and the cap only
-    // bounds the loop against corrupted inputs
+    // record the rejected groups for the reroll kernel, if they fit
+    if (rec.tiles) {
+        const uint64_t t = g0 / (64 * 8);
+        const uint32_t mine = __builtin_popcount(pending);
+        const uint32_t incl = wave_inclusive_scan(mine);
+        const uint32_t total = __shfl(incl, 63, 64);
+        if (total <= kTileSlots) {
+            uint32_t slot = incl - mine;
+            for (uint32_t p = pending; p; p &= p - 1, ++slot)
+                rec.slot[t * kTileSlots + slot] = (uint16_t)(64 * __builtin_ctz(p) + lane);
+            pending = 0;
+        }
+        if (lane == 0) rec.count[t] = total <= kTileSlots ? total : 0;
+    }
+    // rerolls in place (more than kTileSlots rejected), compacted: a lane works on its
+    // lowest pending group; each attempt is rejected with probability
+    // t / 2^64 < 1/2 and the cap only bounds the loop against corrupted
+    // inputs
     uint64_t attempt = 1;
     while (__any(pending != 0)) {
         if (pending) {
@@ -249,6 +287,66 @@ __global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__rest
     if (err) atomicOr(status, err);
 }
 
+// Works through the recorded rejected groups: wave w owns the tiles
+// [w * per, (w + 1) * per). A lane holding a group tries its next attempt;
+// idle lanes take the next recorded groups in tile order. A group is
+// rerolled until accepted (or at the attempt cap), so its attempts run in
+// order and its first accepted word is the one that counts.
+template <int K>
+__global__ __launch_bounds__(256) void dice_chacha_rerolls(const uint32_t *__restrict__ bounds,
+                                                           uint32_t *__restrict__ out,
+                                                           uint64_t count, uint64_t S,
+                                                           uint64_t full, StreamKey key,
+                                                           RerollRecord rec, uint64_t per)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    uint64_t t = wave * per;                                  // next tile to take from
+    const uint64_t t_end = std::min<uint64_t>(t + per, rec.tiles);
+    uint32_t used = 0, avail = t < t_end ? rec.count[t] : 0; // of tile t
+    uint64_t g = kNoGroup, attempt = 1;
+    while (true) {
+        // idle lanes take groups, from up to four tiles per round
+        for (int rounds = 0; rounds < 4 && t < t_end; ++rounds) {
+            const uint64_t idle = __ballot(g == kNoGroup);
+            if (!idle) break;
+            const uint32_t take = std::min<uint32_t>((uint32_t)__builtin_popcountll(idle),
+                                                     avail - used);
+            const uint32_t rank = (uint32_t)__builtin_popcountll(idle & ((1ull << lane) - 1));
+            if (g == kNoGroup && rank < take) {
+                g = t * (64 * 8) + rec.slot[t * kTileSlots + used + rank];
+                attempt = 1;
+            }
+            used += take;
+            if (used == avail) {
+                ++t;
+                used = 0;
+                avail = t < t_end ? rec.count[t] : 0;
+            }
+        }
+        if (!__any(g != kNoGroup)) {
+            if (t >= t_end) break;
+            continue; // only empty tiles so far
+        }
+        if (g != kNoGroup) {
+            const int kk = group_dice<K>(g, full, S, count);
+            uint32_t b[K], a[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) b[i] = (i < kk) ? bounds[(uint64_t)K * g + i] : 1u;
+            const uint64_t rr = chain<K>(b, kk, a, chacha_word_at(attempt * S + g, key));
+            uint32_t e = 0;
+            if (rr >= group_threshold<K>(b, kk, rr, e) || attempt >= kMaxAttemptsChaCha) {
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+                    if (i < kk) out[(uint64_t)K * g + i] = a[i];
+                g = kNoGroup;
+            } else {
+                ++attempt;
+            }
+        }
+    }
+}
+
 template <int K>
 hipError_t launch_dice_chacha_k(const uint32_t *bounds, uint32_t *out, uint64_t count,
                                 StreamKey key, uint32_t *status, hipStream_t stream)
@@ -258,13 +356,37 @@ hipError_t launch_dice_chacha_k(const uint32_t *bounds, uint32_t *out, uint64_t 
     const uint64_t waves = (S + 64 * 8 - 1) / (64 * 8); // 8 groups per lane
     const uint64_t blocks = (waves + 3) / 4;           // 4 wavefronts per block
     if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    // the record: a count and kTileSlots offsets per tile (68 bytes per 512
+    // groups); without the memory for it, every tile rerolls in place
+    RerollRecord rec{nullptr, nullptr, waves};
+    void *mem = nullptr;
+    if (hipMallocAsync(&mem, waves * (4 + 2 * kTileSlots), stream) != hipSuccess) {
+        (void)hipGetLastError();
+        mem = nullptr;
+        rec.tiles = 0;
+    }
+    if (mem) {
+        rec.count = static_cast<uint32_t *>(mem);
+        rec.slot = reinterpret_cast<uint16_t *>(rec.count + waves);
+    }
     const bool vec = ((((uintptr_t)bounds) | ((uintptr_t)out)) & 15) == 0;
     if (vec)
         dice_chacha_kernel<K, true><<<(uint32_t)blocks, 256, 0, stream>>>(bounds, out, count, S,
-                                                                          full, key, status);
+                                                                          full, key, status, rec);
     else
         dice_chacha_kernel<K, false><<<(uint32_t)blocks, 256, 0, stream>>>(bounds, out, count, S,
-                                                                           full, key, status);
+                                                                           full, key, status, rec);
+    if (mem) {
+        // persistent waves, four per block (16 per CU), each owning a run of
+        // tiles
+        const uint64_t rwaves = std::min<uint64_t>(waves, 4096);
+        const uint64_t per = (waves + rwaves - 1) / rwaves;
+        dice_chacha_rerolls<K><<<(uint32_t)((rwaves + 3) / 4), 256, 0, stream>>>(
+            bounds, out, count, S, full, key, rec, per);
+        hipError_t e = hipGetLastError();
+        const hipError_t f = hipFreeAsync(mem, stream);
+        return e != hipSuccess ? e : f;
+    }
     return hipGetLastError();
 }
 
