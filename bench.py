@@ -161,9 +161,13 @@ def serving(brr, workloads, up, rates=(1000, 4000, 16000), count=400, clients=64
 
 
 def tuned_ragged(brr, workloads, up, steps):
-    """20,000 ragged shuffles: the plan's default (shuffle_6), exhaustive
-    autotuning, and the learned tuner (model trained here on measured times
-    of random batches, then timing only its top 3 of ~100 candidates)."""
+    """The 20,000 ragged shuffles under the plan's default (shuffle_6), the
+    exhaustive tuner's pick and the learned tuner's pick (model trained here
+    on measured times of random batches; it times the default and its top 3
+    of ~100 candidates), each re-timed as the median of 15 single runs with
+    its spread; and the model's held-out evaluation on 8 fresh random
+    batches (rank correlation, quality against exhaustive tuning, gain over
+    the default beside the spread)."""
     import numpy as np
 
     from paper_2408_06213_amd import learned
@@ -172,32 +176,52 @@ def tuned_ragged(brr, workloads, up, steps):
     off = workloads.csr_offsets(sizes)
     data = workloads.iota_segments(sizes)
     d, d_off = up(data), up(off)
-    res = {}
+    s6 = brr.brr_schedule_paper(6)
+
+    def retime(sched, wave_max):
+        med, spread = learned.time_median(brr, off, d, d_off, sizes.size, 4, sched, wave_max, 15)
+        return {"ms": med, "spread": spread}
+
+    res = {"default": retime(s6, 512)}
     t0 = time.perf_counter()
     full = brr.Plan(off, 4)
     rep = full.autotune(d, d_off, 1, 0)
-    res["exhaustive"] = {"ms_default": rep.ms_default, "ms_best": rep.ms_best,
-                         "timed": rep.candidates, "tune_s": time.perf_counter() - t0,
-                         "schedule": rep.schedule.steps(), "wave_max": rep.mapping.wave_max}
-    run = lambda: brr.check(brr.brr_shuffle_batched(d, d_off, sizes.size, 4, full, 1, 0))
-    res["exhaustive"]["ms_replay"] = time_launches(run, steps, 2)
+    res["exhaustive"] = {"timed": rep.candidates, "tune_s": time.perf_counter() - t0,
+                         "schedule": rep.schedule.steps(), "wave_max": rep.mapping.wave_max,
+                         **retime(rep.schedule, rep.mapping.wave_max)}
     full.close()
     rng = np.random.default_rng(11)
     t0 = time.perf_counter()
-    X, y, _ = learned.collect(brr, up, rng, nbatch=12, ncand=30)
-    net, loss = learned.train(brr, up, X, y, steps=3000, lr=3e-3, hidden=64)
+    X, y, _ = learned.collect(brr, up, rng, nbatch=16, ncand=40)
+    net, loss = learned.train(brr, up, X, y, steps=4000, lr=3e-3, hidden=64)
     train_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     plan = brr.Plan(off, 4)
     rep = brr.brr_plan_autotune_learned(plan, net, 3, d, d_off, 1, 0)
-    res["learned"] = {"ms_default": rep.ms_default, "ms_best": rep.ms_best, "timed": rep.candidates,
-                      "tune_s": time.perf_counter() - t0, "train_samples": int(X.shape[0]),
-                      "train_s": train_s, "train_mse": loss,
-                      "schedule": rep.schedule.steps(), "wave_max": rep.mapping.wave_max}
-    run = lambda: brr.check(brr.brr_shuffle_batched(d, d_off, sizes.size, 4, plan, 1, 0))
-    res["learned"]["ms_replay"] = time_launches(run, steps, 2)
-    res["learned_gain_vs_shuffle_6"] = rep.ms_default / rep.ms_best
+    res["learned"] = {"timed": rep.candidates, "tune_s": time.perf_counter() - t0,
+                      "train_samples": int(X.shape[0]), "train_s": train_s, "train_mse": loss,
+                      "target_variance": float(np.var(y)),
+                      "schedule": rep.schedule.steps(), "wave_max": rep.mapping.wave_max,
+                      **retime(rep.schedule, rep.mapping.wave_max)}
     plan.close()
+    for k in ("exhaustive", "learned"):
+        g = res["default"]["ms"] / res[k]["ms"]
+        res[k]["gain_vs_default"] = g
+        res[k]["gain_beyond_2x_spread"] = bool(
+            g > 1 + 2 * max(res[k]["spread"], res["default"]["spread"]))
+    rows = learned.evaluate(brr, up, net, rng, nbatch=8, reps=5)
+    gain = np.array([r["gain_learned_vs_default"] for r in rows])
+    spread = np.array([max(r["learned_spread"], r["default_spread"]) for r in rows])
+    res["held_out"] = {
+        "batches": len(rows),
+        "mean_spearman": float(np.mean([r["spearman"] for r in rows])),
+        "learned_vs_exhaustive_mean": float(np.mean([r["learned_vs_exhaustive"] for r in rows])),
+        "learned_vs_exhaustive_min": float(np.min([r["learned_vs_exhaustive"] for r in rows])),
+        "gain_vs_default": [float(x) for x in gain],
+        "spread": [float(x) for x in spread],
+        "gains_beyond_2x_spread": int(np.sum(gain > 1 + 2 * spread)),
+        "timed_learned_vs_exhaustive": [rows[0]["learned_timed"], rows[0]["exhaustive_timed"]],
+    }
     net.close()
     return res
 
@@ -342,6 +366,32 @@ def sample_sweep(brr, up, steps):
     return res
 
 
+def fresh_calls(brr, d, d_off, off, count, steps):
+    """Calls per second of one plan, every call with a new instance base (a
+    caller streaming batches), with the graph (captured once, arguments
+    bound per call) and with direct launches; the captures made."""
+    import torch
+
+    res = {}
+    for name, use_graph in (("graph", 1), ("direct", 0)):
+        plan = brr.Plan(off, 4)
+        m = plan.mapping()
+        m.use_graph = use_graph
+        brr.check(plan.set_mapping(m), "set_mapping")
+        inst = [0]
+
+        def f():
+            inst[0] += count
+            brr.check(brr.brr_shuffle_batched(d, d_off, count, 4, plan, 1, inst[0]))
+
+        ms = time_launches(f, max(steps, 20), 2)
+        res[name] = {"ms_per_call": ms, "calls_per_s": 1e3 / ms, "captures": plan.captures()}
+        plan.close()
+        torch.cuda.synchronize()
+    res["graph_speedup"] = res["direct"]["ms_per_call"] / res["graph"]["ms_per_call"]
+    return res
+
+
 def secondary(brr, workloads, up, steps, only=None):
     import numpy as np
 
@@ -393,6 +443,8 @@ def secondary(brr, workloads, up, steps, only=None):
         res["chacha20_speedup_k6_vs_k1"] = res["k1_chacha20"]["ms"] / res["k6_chacha20"]["ms"]
         if "k6_no_graph" in res:
             res["graph_speedup_k6"] = res["k6_no_graph"]["ms"] / res["k6"]["ms"]
+        if tag.startswith("ragged"):
+            res["calls_fresh_instance"] = fresh_calls(brr, ds[0], d_off, off, sizes.size, steps)
         res["hbm_frac_k6"] = 2 * 4 * data.size / (res["k6"]["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS
         out[tag] = res
 

@@ -319,14 +319,21 @@ brr_status brr_shuffle_noalloc(void *d_data, uint64_t n, uint32_t elem_bytes,
  * copies of that classification, any scratch it needs, and a hip graph of
  * the launch sequence. h_offsets: host u64[count + 1], non-decreasing,
  * offsets[0] = 0. sched = NULL uses shuffle_6; it is copied. The graph is
- * bound to the buffers, seed and instance of the run that captured it; a
- * run with others captures it again, and first waits on the host for the
- * plan's previous run to finish. brr_plan_destroy also waits for the
- * plan's last run, then releases everything the plan owns. */
+ * captured once, on the plan's first run, and replayed by every later run:
+ * its kernels read the run's data pointer, offsets pointer, seed and
+ * instance from a small device block of the plan, which a kernel enqueued on
+ * the caller's stream just before each replay writes. So a run with other
+ * buffers, seed or instance needs no recapture and no host wait.
+ * brr_plan_destroy waits for the plan's last run, then releases everything
+ * the plan owns. */
 typedef struct brr_plan brr_plan;
 brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t count,
                            uint32_t elem_bytes, const brr_schedule *sched);
 void brr_plan_destroy(brr_plan *plan);
+
+/* How many times the plan has captured its launch graph: 0 before its first
+ * run with use_graph = 1, then 1 (the capture is never repeated). */
+uint32_t brr_plan_captures(const brr_plan *plan);
 
 /* Plan knobs for the size-class mapping; brr_plan_create uses defaults that
  * brr_plan_set_mapping may replace before the first run. lane_max: shuffles
@@ -387,8 +394,9 @@ typedef struct {
  * Every candidate is exactly uniform (Theorem 1 holds for any schedule), so
  * the choice changes only speed and the word stream consumed. The plan then
  * uses the chosen configuration (brr_plan_get_schedule / get_mapping report
- * it). Must precede the plan's first run; synchronizes `stream`. report may
- * be NULL. */
+ * it). Each candidate's time is the median of five single runs after one
+ * untimed run (report->ms_*). Must precede the plan's first run;
+ * synchronizes `stream`. report may be NULL. */
 brr_status brr_plan_autotune(brr_plan *plan, const void *d_data, const uint64_t *d_offsets,
                              uint64_t seed, uint64_t inst_base, void *stream,
                              brr_tune_report *report);

@@ -21,7 +21,8 @@ BRR_MAX_K = 20
 # every symbol include/brr.h declares
 EXPORTS = (
     "brr_schedule_paper", "brr_schedule_batches", "brr_schedule_check",
-    "brr_schedule_check_upto", "brr_shuffle_noalloc", "brr_scratch_bytes", "brr_dice",
+    "brr_schedule_check_upto", "brr_shuffle_noalloc", "brr_scratch_bytes", "brr_plan_captures",
+    "brr_dice",
     "brr_dice_const", "brr_shuffle", "brr_plan_create", "brr_plan_destroy",
     "brr_plan_get_mapping", "brr_plan_set_mapping", "brr_shuffle_batched", "brr_sample",
     "brr_sync_status", "brr_strerror", "brr_cost_per_die", "brr_cost_thresholds",
@@ -143,6 +144,7 @@ def _load():
         "brr_scratch_bytes": (u64, [u64, u64, u32]),
         "brr_plan_create": (st, [ctypes.POINTER(p), p, u64, u32, sched_p]),
         "brr_plan_destroy": (None, [p]),
+        "brr_plan_captures": (u32, [p]),
         "brr_plan_get_mapping": (st, [p, ctypes.POINTER(brr_mapping)]),
         "brr_plan_set_mapping": (st, [p, ctypes.POINTER(brr_mapping)]),
         "brr_shuffle_batched": (st, [p, p, u64, u32, p, u64, u64, p]),
@@ -348,6 +350,9 @@ class Plan:
         out = brr_schedule()
         check(lib.brr_plan_get_schedule(self.ptr, ctypes.byref(out)), "brr_plan_get_schedule")
         return out
+
+    def captures(self) -> int:
+        return int(lib.brr_plan_captures(self.ptr))
 
     def autotune(self, data, d_offsets, seed: int = 0, inst_base: int = 0,
                  stream=None) -> brr_tune_report:

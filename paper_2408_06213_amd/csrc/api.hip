@@ -263,10 +263,14 @@ struct brr_plan {
     bool fork_classes = true; // off for one-shot plans: streams cost more than they save
     hipStream_t branch[kTiers - 1] = {};
     hipEvent_t fork = nullptr, join[kTiers - 1] = {};
-    // graph of the launch sequence, bound to the buffers of the last run
+    // graph of the launch sequence, captured on the first run; its kernels
+    // read the run's buffers, seed and instance from d_args, which a kernel
+    // enqueued before every replay writes
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    RunArgs *d_args = nullptr;
+    uint32_t captures = 0;
     // recorded on the caller's stream after every run: the executable graph
     // (and everything else the plan owns) is released or replaced only
     // after the last run that may use it has finished
@@ -274,9 +278,6 @@ struct brr_plan {
     bool ran = false; // done has been recorded at least once
     // serialises host calls on the plan (runs, mapping, tuning)
     std::mutex mu;
-    void *g_data = nullptr;
-    const uint64_t *g_offsets = nullptr;
-    uint64_t g_seed = 0, g_inst = 0;
 };
 
 namespace {
@@ -305,6 +306,8 @@ void release(brr_plan *p)
     if (p->d_gbase) (void)hipFree(p->d_gbase);
     if (p->d_gtile) (void)hipFree(p->d_gtile);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
+    if (p->d_args) (void)hipFree(p->d_args);
+    p->d_args = nullptr;
     p->exec = nullptr;
     p->graph = nullptr;
     p->capture_stream = nullptr;
@@ -411,6 +414,8 @@ brr_status classify(brr_plan *p)
         if (hipMalloc(&p->d_scratch, gtier_scratch_bytes(p->g_npos, p->eb)) != hipSuccess)
             return BRR_ENOMEM;
     }
+    if (hipMalloc(reinterpret_cast<void **>(&p->d_args), sizeof(RunArgs)) != hipSuccess)
+        return BRR_ENOMEM;
     if (p->fork_classes) {
         if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess)
             return BRR_EHIP;
@@ -424,30 +429,29 @@ brr_status classify(brr_plan *p)
     return BRR_OK;
 }
 
-hipError_t launch_tier(brr_plan *p, int tier, void *data, const uint64_t *offsets, uint64_t seed,
-                       uint64_t inst, hipStream_t s)
+// The kernels read the run's arguments from the plan's device block, which
+// run_plan writes before each run.
+hipError_t launch_tier(brr_plan *p, int tier, void *data, hipStream_t s)
 {
+    const RunArgs *b = p->d_args;
     const uint32_t *items = p->d_items;
     if (tier == 0)
-        return launch_batched_lane(data, offsets, items, p->n_lane, p->lane_max_n, p->eb, p->ds,
-                                   seed, inst, s);
+        return launch_batched_lane(b, items, p->n_lane, p->lane_max_n, p->eb, p->ds, s);
     items += p->n_lane;
     for (int c = 0; c < kLdsClasses; ++c) {
         if (tier == 1 + c)
-            return launch_batched_lds(c, data, offsets, items, p->n_cls[c], p->max_cls[c], p->eb,
-                                      p->ds, seed, inst, s);
+            return launch_batched_lds(c, b, items, p->n_cls[c], p->max_cls[c], p->eb, p->ds, s);
         items += p->n_cls[c];
     }
     if (tier == 1 + kLdsClasses)
-        return launch_batched_peel(data, offsets, items, p->n_peel, p->eb, p->ds, seed, inst, s);
+        return launch_batched_peel(b, items, p->n_peel, p->eb, p->ds, s);
     if (p->n_big == 0) return hipSuccess;
     GTierArgs a;
     std::memset(&a, 0, sizeof a);
+    a.dyn = b; // data, seed and instance base from the plan's device block
     a.data = data;
     a.words = p->ds.words;
     a.eb = p->eb;
-    a.seed = seed;
-    a.inst_base = inst;
     a.nitems = p->n_big;
     a.npos = p->g_npos;
     a.npairs = p->g_npairs;
@@ -470,8 +474,7 @@ bool tier_used(const brr_plan *p, int tier)
 
 // The size classes are independent (disjoint arrays): all but the last
 // non-empty one run on branch streams that fork from s and join back into it.
-hipError_t enqueue(brr_plan *p, void *data, const uint64_t *offsets, uint64_t seed, uint64_t inst,
-                   hipStream_t s)
+hipError_t enqueue(brr_plan *p, void *data, hipStream_t s)
 {
     int used[kTiers], nu = 0;
     for (int t = 0; t < kTiers; ++t)
@@ -480,20 +483,18 @@ hipError_t enqueue(brr_plan *p, void *data, const uint64_t *offsets, uint64_t se
     hipError_t e = hipSuccess;
     if (!p->fork_classes) {
         for (int b = 0; b < nu; ++b)
-            if ((e = launch_tier(p, used[b], data, offsets, seed, inst, s)) != hipSuccess) return e;
+            if ((e = launch_tier(p, used[b], data, s)) != hipSuccess) return e;
         return hipSuccess;
     }
     if (nu > 1) {
         if ((e = hipEventRecord(p->fork, s)) != hipSuccess) return e;
         for (int b = 0; b + 1 < nu; ++b) {
             if ((e = hipStreamWaitEvent(p->branch[b], p->fork, 0)) != hipSuccess) return e;
-            if ((e = launch_tier(p, used[b], data, offsets, seed, inst, p->branch[b])) !=
-                hipSuccess)
-                return e;
+            if ((e = launch_tier(p, used[b], data, p->branch[b])) != hipSuccess) return e;
             if ((e = hipEventRecord(p->join[b], p->branch[b])) != hipSuccess) return e;
         }
     }
-    if ((e = launch_tier(p, used[nu - 1], data, offsets, seed, inst, s)) != hipSuccess) return e;
+    if ((e = launch_tier(p, used[nu - 1], data, s)) != hipSuccess) return e;
     for (int b = 0; b + 1 < nu; ++b)
         if ((e = hipStreamWaitEvent(s, p->join[b], 0)) != hipSuccess) return e;
     return hipSuccess;
@@ -513,39 +514,36 @@ brr_status run_plan(brr_plan *p, void *data, const uint64_t *offsets, uint64_t s
     // runs on any stream follow the plan's previous run: they share its
     // scratch and its branch streams
     if (p->ran && hipStreamWaitEvent(s, p->done, 0) != hipSuccess) return BRR_EHIP;
+    // this run's arguments, on the caller's stream behind the previous run
+    // (waited on above), so no run reads arguments that a later one wrote
+    if (launch_set_args(p->d_args, RunArgs{data, offsets, seed, inst}, s) != hipSuccess)
+        return BRR_EHIP;
     if (!p->map.use_graph) {
-        const hipError_t e = enqueue(p, data, offsets, seed, inst, s);
+        const hipError_t e = enqueue(p, data, s);
         const brr_status st = hip_status(e == hipSuccess ? hipEventRecord(p->done, s) : e);
         if (st == BRR_OK) p->ran = true;
         return st;
     }
-    const bool rebind = !p->exec || p->g_data != data || p->g_offsets != offsets ||
-                        p->g_seed != seed || p->g_inst != inst;
-    if (rebind) {
-        // the executable about to be replaced may still run from the last
-        // call (on any stream): wait for it before it is destroyed
-        if (p->exec && hipEventSynchronize(p->done) != hipSuccess) return BRR_EHIP;
+    if (!p->exec) {
+        // captured once: the kernels read their arguments from d_args
         if (!p->capture_stream &&
             hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)
             return BRR_EHIP;
         hipGraph_t g = nullptr;
         if (hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return BRR_EHIP;
-        const hipError_t le = enqueue(p, data, offsets, seed, inst, p->capture_stream);
+        const hipError_t le = enqueue(p, data, p->capture_stream);
         const hipError_t ce = hipStreamEndCapture(p->capture_stream, &g);
         if (le != hipSuccess || ce != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             return BRR_EHIP;
         }
-        if (p->exec) (void)hipGraphExecDestroy(p->exec);
-        if (p->graph) (void)hipGraphDestroy(p->graph);
         p->graph = g;
-        p->exec = nullptr;
-        if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) return BRR_EHIP;
-        p->g_data = data;
-        p->g_offsets = offsets;
-        p->g_seed = seed;
-        p->g_inst = inst;
+        if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            p->exec = nullptr;
+            return BRR_EHIP;
+        }
+        ++p->captures;
     }
     const hipError_t e = hipGraphLaunch(p->exec, s);
     const brr_status st = hip_status(e == hipSuccess ? hipEventRecord(p->done, s) : e);
@@ -867,6 +865,13 @@ void brr_plan_destroy(brr_plan *plan)
     delete plan;
 }
 
+uint32_t brr_plan_captures(const brr_plan *plan)
+{
+    if (!plan) return 0;
+    std::lock_guard<std::mutex> lock(const_cast<brr_plan *>(plan)->mu);
+    return plan->captures;
+}
+
 brr_status brr_plan_get_mapping(const brr_plan *plan, brr_mapping *out)
 {
     if (!plan || !out) return BRR_EINVAL;
@@ -973,6 +978,39 @@ __global__ void k_add_one(uint32_t *a, uint64_t n)
 }
 
 // Average time of `reps` launches of fn on stream s, after one warm-up.
+// Median of `reps` single timed runs after one untimed run: tuning compares
+// candidates a few percent apart, which a single timing cannot resolve.
+template <class F> float time_median_ms(F &&fn, hipStream_t s, int reps, brr_status *st)
+{
+    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    for (hipEvent_t &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            *st = BRR_EHIP;
+            for (hipEvent_t &f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return 0;
+        }
+    *st = fn();
+    for (int r = 0; r < reps && *st == BRR_OK; ++r) {
+        (void)hipEventRecord(ev[2 * r], s);
+        *st = fn();
+        (void)hipEventRecord(ev[2 * r + 1], s);
+    }
+    std::vector<float> t;
+    if (*st == BRR_OK) {
+        if (hipEventSynchronize(ev.back()) != hipSuccess) *st = BRR_EHIP;
+        for (int r = 0; r < reps && *st == BRR_OK; ++r) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
+            t.push_back(ms);
+        }
+    }
+    for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
+    if (t.empty()) return 0;
+    std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+    return t[t.size() / 2];
+}
+
 template <class F> float time_ms(F &&fn, hipStream_t s, int reps, brr_status *st)
 {
     hipEvent_t e0, e1;
@@ -1129,10 +1167,10 @@ brr_status tune_plan(brr_plan *plan, brr_mlp *model, uint32_t top, const void *d
         t->map = plan->map;
         t->map.wave_max = c.wave_max;
         t->map.use_graph = 0;
-        *ms = time_ms(
+        *ms = time_median_ms(
             [&] { return brr_shuffle_batched(work, d_offsets, plan->count, plan->eb, t, seed,
                                              inst_base, stream); },
-            s, 2, &e);
+            s, 5, &e);
         if (hipStreamSynchronize(s) != hipSuccess && e == BRR_OK) e = BRR_EHIP;
         brr_plan_destroy(t);
         return e;

@@ -163,6 +163,18 @@ hipError_t launch_lds_single(void *data, uint32_t n, uint32_t steps, uint32_t ou
                              void *out, const DevSched &sc, uint64_t seed, uint64_t inst,
                              const DevClaim &claim, hipStream_t stream);
 
+// The arguments a plan's run binds: the payload, its CSR offsets, the seed
+// and the instance of shuffle 0. The batched kernels read them from the
+// plan's device block, which a kernel enqueued before each run writes, so
+// that a captured graph replays with other arguments.
+struct RunArgs {
+    void *data;
+    const uint64_t *offsets;
+    uint64_t seed, inst;
+};
+// Writes a run's arguments into a plan's device block, on the stream.
+hipError_t launch_set_args(RunArgs *dev, const RunArgs &val, hipStream_t stream);
+
 // One item of the device-wide tier: the array at element offset data_off of
 // the shared data pointer, n elements, the first `steps` Fisher-Yates steps
 // (n - 1 for a shuffle), its positions at pos_base in the index arrays, its
@@ -193,6 +205,7 @@ struct GTierArgs {
     const SegTable *one_seg; // host, nitems == 1
     void *scratch;           // gtier_scratch_bytes(npos, eb)
     uint32_t words;          // BRR_WORDS_* of the items' schedule
+    const RunArgs *dyn;      // if set, data, seed and inst_base are read from it (plans)
 };
 uint64_t gtier_scratch_bytes(uint64_t npos, uint32_t eb);
 // Positions (summed over items) one device-wide launch takes: indices are u32.
@@ -218,21 +231,18 @@ hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream);
 // the CSR offsets; max_n: the largest n among them (sizes the LDS).
 constexpr int kLdsClasses = 5;
 uint32_t lds_class_max_n(int c);
-hipError_t launch_batched_lds(int c, void *data, const uint64_t *offsets, const uint32_t *items,
-                              uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
-                              uint64_t seed, uint64_t inst_base, hipStream_t stream);
+hipError_t launch_batched_lds(int c, const RunArgs *b, const uint32_t *items, uint32_t nitems,
+                              uint32_t max_n, uint32_t eb, const DevSched &sc, hipStream_t stream);
 // Lane tier: one lane per in-place shuffle of 2 <= n <= lane_tier_max_n()
 // (items sorted by size for the plan), max_n = largest n among the items.
 uint32_t lane_tier_max_n();
-hipError_t launch_batched_lane(void *data, const uint64_t *offsets, const uint32_t *items,
-                               uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
-                               uint64_t seed, uint64_t inst_base, hipStream_t stream);
+hipError_t launch_batched_lane(const RunArgs *b, const uint32_t *items, uint32_t nitems,
+                               uint32_t max_n, uint32_t eb, const DevSched &sc, hipStream_t stream);
 // Peel tier: one workgroup per in-place shuffle of 2 <= n <=
 // peel_tier_max_n(), processed top-down in LDS-sized peels (the plan sends
 // it the arrays too large for its LDS classes).
 uint32_t peel_tier_max_n();
-hipError_t launch_batched_peel(void *data, const uint64_t *offsets, const uint32_t *items,
-                               uint32_t nitems, uint32_t eb, const DevSched &sc, uint64_t seed,
-                               uint64_t inst_base, hipStream_t stream);
+hipError_t launch_batched_peel(const RunArgs *b, const uint32_t *items, uint32_t nitems,
+                               uint32_t eb, const DevSched &sc, hipStream_t stream);
 
 } // namespace brr

@@ -225,6 +225,12 @@ __device__ uint32_t block_scan_array(uint32_t *a, uint32_t len, uint32_t base, u
     return total;
 }
 
+
+__global__ void k_set_args(RunArgs *dev, RunArgs val)
+{
+    if (threadIdx.x == 0) *dev = val;
+}
+
 // ---------------------------------------------------------------------------
 // LDS tier: one block per shuffle, index arrays in LDS, per-position state in
 // registers (position p = tid + r*BLOCK, r < P).
@@ -374,10 +380,13 @@ __global__ __launch_bounds__(BLOCK) void k_lds_single(Elem *z, uint32_t n, uint3
 }
 
 template <typename Elem, int BLOCK, int P, bool W>
-__global__ __launch_bounds__(BLOCK) void k_lds_batched(Elem *data, const uint64_t *offsets,
-                                                       const uint32_t *items, DevSched sc,
-                                                       uint64_t seed, uint64_t inst_base)
+__global__ __launch_bounds__(BLOCK) void k_lds_batched(const RunArgs *__restrict__ args, const uint32_t *items,
+                                                       DevSched sc)
 {
+    const RunArgs A = *args;
+    Elem *data = static_cast<Elem *>(A.data);
+    const uint64_t *offsets = A.offsets;
+    const uint64_t seed = A.seed, inst_base = A.inst;
     extern __shared__ __align__(16) char smem[];
     __shared__ SegTable st;
     __shared__ uint32_t wsum[BLOCK / 64];
@@ -505,11 +514,14 @@ __device__ __forceinline__ void lane_segment(uint8_t *a, const Seg &g, uint32_t 
 }
 
 template <typename Elem, bool W>
-__global__ __launch_bounds__(kLaneItems) void k_lane_batched(Elem *data, const uint64_t *offsets,
+__global__ __launch_bounds__(kLaneItems) void k_lane_batched(const RunArgs *__restrict__ args,
                                                             const uint32_t *items, uint32_t nitems,
-                                                            uint32_t max_n, DevSched sc,
-                                                            uint64_t seed, uint64_t inst_base)
+                                                            uint32_t max_n, DevSched sc)
 {
+    const RunArgs A = *args;
+    Elem *data = static_cast<Elem *>(A.data);
+    const uint64_t *offsets = A.offsets;
+    const uint64_t seed = A.seed, inst_base = A.inst;
     constexpr uint32_t V = 16 / sizeof(Elem); // elements per 16-byte vector
     const uint32_t src = W ? sc.words : BRR_WORDS_PHILOX64;
     extern __shared__ __align__(16) char smem[];
@@ -768,11 +780,16 @@ __device__ __forceinline__ uint32_t peel_query(const PeelState &ps, uint32_t q, 
 //    targets q, else z[q];
 //  - a target q below the peel receives, from the smallest step that targets
 //    it, the value at root of that step.
+// Four waves per SIMD: two 512-thread workgroups share a CU (the ChaCha20
+// instantiation needs a small spill for it, cheaper than one per CU).
 template <typename Elem, bool W, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_peel_batched(Elem *data, const uint64_t *offsets,
-                                                             const uint32_t *items, DevSched sc,
-                                                             uint64_t seed, uint64_t inst_base)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_peel_batched(
+    const RunArgs *__restrict__ args, const uint32_t *items, DevSched sc)
 {
+    const RunArgs A = *args;
+    Elem *data = static_cast<Elem *>(A.data);
+    const uint64_t *offsets = A.offsets;
+    const uint64_t seed = A.seed, inst_base = A.inst;
     constexpr uint32_t PEEL = kPeel;
     constexpr int P = (PEEL + BLOCK - 1) / BLOCK;
     __shared__ uint32_t qof[kPeel];
@@ -1057,9 +1074,25 @@ struct GProblem {
     uint64_t npos, npairs;
     uint64_t inst_base;       // added to every item's instance
     DevClaim claim;           // if set, the claimed instance is added as well
+    const RunArgs *dyn;       // if set, the data, seed and inst_base to use
     GItem one;
     SegTable one_seg;
 };
+
+// Seed, instance base and data of a problem: by value, or from the plan's
+// device block.
+__device__ __forceinline__ uint64_t problem_seed(const GProblem &P, uint64_t seed)
+{
+    return P.dyn ? P.dyn->seed : seed;
+}
+__device__ __forceinline__ uint64_t problem_inst_base(const GProblem &P)
+{
+    return (P.dyn ? P.dyn->inst : P.inst_base) + (P.claim.counter ? *P.claim.slot : 0);
+}
+template <typename Elem> __device__ __forceinline__ Elem *problem_data(const GProblem &P, Elem *data)
+{
+    return P.dyn ? static_cast<Elem *>(P.dyn->data) : data;
+}
 
 // Item that owns index x: the tile table names the owner of the tile's
 // first index; items that start inside the tile are stepped over (every
@@ -1110,8 +1143,7 @@ __global__ __launch_bounds__(256) void k_gp_dice(GProblem P, GArrays g, uint64_t
         const SegTable &st = segs_at(P, i);
         const uint32_t src = W ? st.words : BRR_WORDS_PHILOX64;
         const uint32_t m = (uint32_t)(w - (P.items ? P.pair_base[i] : 0));
-        const uint64_t ib = P.inst_base + (P.claim.counter ? *P.claim.slot : 0);
-        const StreamKey key = make_key(seed, ib + it.inst);
+        const StreamKey key = make_key(problem_seed(P, seed), problem_inst_base(P) + it.inst);
         uint64_t wd[2];
         first_pair(src, m, key, wd[0], wd[1]);
         uint32_t *sk = g.key[0] + it.pos_base;
@@ -1153,8 +1185,7 @@ __global__ __launch_bounds__(256) void k_gc_dice(GProblem P, GArrays g, uint64_t
         const SegTable &st = segs_at(P, i);
         const uint32_t src = W ? st.words : BRR_WORDS_PHILOX64;
         const uint32_t m = (uint32_t)(w - (P.items ? P.pair_base[i] : 0));
-        const uint64_t ib = P.inst_base + (P.claim.counter ? *P.claim.slot : 0);
-        const StreamKey key = make_key(seed, ib + it.inst);
+        const StreamKey key = make_key(problem_seed(P, seed), problem_inst_base(P) + it.inst);
         uint64_t wd[2];
         first_pair(src, m, key, wd[0], wd[1]);
         uint32_t i0[2] = {0, 0}, kk[2] = {0, 0}, f[2] = {0, 0};
@@ -1492,8 +1523,9 @@ __global__ __launch_bounds__(256) void k_g_walk(GProblem P, GArrays g)
 // Place pass: every element written at its destination (the only random
 // writes of the pass).
 template <typename Elem>
-__global__ __launch_bounds__(256) void k_g_place(GProblem P, GArrays g, const Elem *data)
+__global__ __launch_bounds__(256) void k_g_place(GProblem P, GArrays g, const Elem *data_arg)
 {
+    const Elem *data = problem_data(P, data_arg);
     Elem *tmp = static_cast<Elem *>(g.tmp);
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
          x += (uint64_t)gridDim.x * blockDim.x) {
@@ -1503,8 +1535,9 @@ __global__ __launch_bounds__(256) void k_g_place(GProblem P, GArrays g, const El
 }
 
 template <typename Elem>
-__global__ __launch_bounds__(256) void k_gp_copy(GProblem P, GArrays g, Elem *data)
+__global__ __launch_bounds__(256) void k_gp_copy(GProblem P, GArrays g, Elem *data_arg)
 {
+    Elem *data = problem_data(P, data_arg);
     const Elem *tmp = static_cast<const Elem *>(g.tmp);
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
          x += (uint64_t)gridDim.x * blockDim.x) {
@@ -1836,41 +1869,34 @@ hipError_t lds_single_t(void *data, uint32_t n, uint32_t steps, uint32_t out_lo,
 }
 
 template <typename Elem, int BLOCK, int P, bool W>
-hipError_t batched_lds_t(void *data, const uint64_t *offsets, const uint32_t *items,
-                         uint32_t nitems, uint32_t max_n, const DevSched &sc, uint64_t seed,
-                         uint64_t inst_base, hipStream_t stream)
+hipError_t batched_lds_t(const RunArgs *b, const uint32_t *items, uint32_t nitems, uint32_t max_n,
+                         const DevSched &sc, hipStream_t stream)
 {
     if (nitems == 0) return hipSuccess;
     const uint32_t bytes = lds_bytes(max_n);
-    k_lds_batched<Elem, BLOCK, P, W><<<nitems, BLOCK, bytes, stream>>>(static_cast<Elem *>(data),
-                                                                  offsets, items, sc, seed,
-                                                                  inst_base);
+    k_lds_batched<Elem, BLOCK, P, W><<<nitems, BLOCK, bytes, stream>>>(b, items, sc);
     return hipGetLastError();
 }
 
 template <typename Elem, bool W>
-hipError_t batched_peel_t(void *data, const uint64_t *offsets, const uint32_t *items,
-                          uint32_t nitems, const DevSched &sc, uint64_t seed, uint64_t inst_base,
-                          hipStream_t stream)
+hipError_t batched_peel_t(const RunArgs *b, const uint32_t *items, uint32_t nitems,
+                          const DevSched &sc, hipStream_t stream)
 {
     if (nitems == 0) return hipSuccess;
     constexpr int B = peel_threads(sizeof(Elem));
-    k_peel_batched<Elem, W, B><<<nitems, B, 0, stream>>>(static_cast<Elem *>(data), offsets, items,
-                                                         sc, seed, inst_base);
+    k_peel_batched<Elem, W, B><<<nitems, B, 0, stream>>>(b, items, sc);
     return hipGetLastError();
 }
 
 template <typename Elem, bool W>
-hipError_t batched_lane_t(void *data, const uint64_t *offsets, const uint32_t *items,
-                          uint32_t nitems, uint32_t max_n, const DevSched &sc, uint64_t seed,
-                          uint64_t inst_base, hipStream_t stream)
+hipError_t batched_lane_t(const RunArgs *b, const uint32_t *items, uint32_t nitems, uint32_t max_n,
+                          const DevSched &sc, hipStream_t stream)
 {
     if (nitems == 0) return hipSuccess;
     const uint32_t arrays = lane_arrays(max_n);
     const uint32_t blocks = (nitems + arrays - 1) / arrays;
     const LaneLds L = lane_lds(max_n, sizeof(Elem));
-    k_lane_batched<Elem, W><<<blocks, kLaneItems, L.bytes, stream>>>(
-        static_cast<Elem *>(data), offsets, items, nitems, max_n, sc, seed, inst_base);
+    k_lane_batched<Elem, W><<<blocks, kLaneItems, L.bytes, stream>>>(b, items, nitems, max_n, sc);
     return hipGetLastError();
 }
 
@@ -1879,36 +1905,32 @@ hipError_t batched_lane_t(void *data, const uint64_t *offsets, const uint32_t *i
 uint32_t lds_tier_max_n() { return kWgThreads * kWgP; }
 uint32_t lane_tier_max_n() { return kLaneMaxN; }
 
-hipError_t launch_batched_lane(void *data, const uint64_t *offsets, const uint32_t *items,
-                               uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
-                               uint64_t seed, uint64_t inst_base, hipStream_t stream)
+hipError_t launch_batched_lane(const RunArgs *b, const uint32_t *items, uint32_t nitems,
+                               uint32_t max_n, uint32_t eb, const DevSched &sc, hipStream_t stream)
 {
     if (max_n > lane_tier_max_n()) return hipErrorInvalidValue;
     if (sc.words != BRR_WORDS_PHILOX64)
-        return eb == 4 ? batched_lane_t<uint32_t, true>(data, offsets, items, nitems, max_n, sc,
-                                                        seed, inst_base, stream)
-                       : batched_lane_t<uint64_t, true>(data, offsets, items, nitems, max_n, sc,
-                                                        seed, inst_base, stream);
-    return eb == 4 ? batched_lane_t<uint32_t, false>(data, offsets, items, nitems, max_n, sc, seed,
-                                                     inst_base, stream)
-                   : batched_lane_t<uint64_t, false>(data, offsets, items, nitems, max_n, sc, seed,
-                                                     inst_base, stream);
+        return eb == 4 ? batched_lane_t<uint32_t, true>(b, items, nitems, max_n, sc, stream)
+                       : batched_lane_t<uint64_t, true>(b, items, nitems, max_n, sc, stream);
+    return eb == 4 ? batched_lane_t<uint32_t, false>(b, items, nitems, max_n, sc, stream)
+                   : batched_lane_t<uint64_t, false>(b, items, nitems, max_n, sc, stream);
+}
+
+hipError_t launch_set_args(RunArgs *dev, const RunArgs &val, hipStream_t stream)
+{
+    k_set_args<<<1, 64, 0, stream>>>(dev, val);
+    return hipGetLastError();
 }
 uint32_t peel_tier_max_n() { return kPeelTierMax; }
 
-hipError_t launch_batched_peel(void *data, const uint64_t *offsets, const uint32_t *items,
-                               uint32_t nitems, uint32_t eb, const DevSched &sc, uint64_t seed,
-                               uint64_t inst_base, hipStream_t stream)
+hipError_t launch_batched_peel(const RunArgs *b, const uint32_t *items, uint32_t nitems,
+                               uint32_t eb, const DevSched &sc, hipStream_t stream)
 {
     if (sc.words != BRR_WORDS_PHILOX64)
-        return eb == 4 ? batched_peel_t<uint32_t, true>(data, offsets, items, nitems, sc, seed,
-                                                        inst_base, stream)
-                       : batched_peel_t<uint64_t, true>(data, offsets, items, nitems, sc, seed,
-                                                        inst_base, stream);
-    return eb == 4 ? batched_peel_t<uint32_t, false>(data, offsets, items, nitems, sc, seed,
-                                                     inst_base, stream)
-                   : batched_peel_t<uint64_t, false>(data, offsets, items, nitems, sc, seed,
-                                                     inst_base, stream);
+        return eb == 4 ? batched_peel_t<uint32_t, true>(b, items, nitems, sc, stream)
+                       : batched_peel_t<uint64_t, true>(b, items, nitems, sc, stream);
+    return eb == 4 ? batched_peel_t<uint32_t, false>(b, items, nitems, sc, stream)
+                   : batched_peel_t<uint64_t, false>(b, items, nitems, sc, stream);
 }
 
 hipError_t prepare_shuffle_kernels()
@@ -2039,6 +2061,7 @@ hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream)
     P.npairs = a.npairs;
     P.inst_base = a.inst_base;
     P.claim = a.claim;
+    P.dyn = a.dyn;
     if (a.nitems == 1 && a.one_item) {
         P.one = *a.one_item;
         P.one_seg = *a.one_seg;
@@ -2064,21 +2087,16 @@ uint32_t lds_class_max_n(int c)
     return (c >= 0 && c < kLdsClasses) ? cap[c] : 0;
 }
 
-hipError_t launch_batched_lds(int c, void *data, const uint64_t *offsets, const uint32_t *items,
-                              uint32_t nitems, uint32_t max_n, uint32_t eb, const DevSched &sc,
-                              uint64_t seed, uint64_t inst_base, hipStream_t stream)
+hipError_t launch_batched_lds(int c, const RunArgs *b, const uint32_t *items, uint32_t nitems,
+                              uint32_t max_n, uint32_t eb, const DevSched &sc, hipStream_t stream)
 {
     if (max_n > lds_class_max_n(c)) return hipErrorInvalidValue;
     const bool w = sc.words != BRR_WORDS_PHILOX64;
 #define BRR_LDS_CLASS(B, P)                                                                      \
-    return w ? (eb == 4 ? batched_lds_t<uint32_t, B, P, true>(data, offsets, items, nitems, max_n, \
-                                                              sc, seed, inst_base, stream)        \
-                        : batched_lds_t<uint64_t, B, P, true>(data, offsets, items, nitems, max_n, \
-                                                              sc, seed, inst_base, stream))       \
-             : (eb == 4 ? batched_lds_t<uint32_t, B, P, false>(data, offsets, items, nitems,       \
-                                                               max_n, sc, seed, inst_base, stream) \
-                        : batched_lds_t<uint64_t, B, P, false>(data, offsets, items, nitems,       \
-                                                               max_n, sc, seed, inst_base, stream))
+    return w ? (eb == 4 ? batched_lds_t<uint32_t, B, P, true>(b, items, nitems, max_n, sc, stream) \
+                        : batched_lds_t<uint64_t, B, P, true>(b, items, nitems, max_n, sc, stream)) \
+             : (eb == 4 ? batched_lds_t<uint32_t, B, P, false>(b, items, nitems, max_n, sc, stream) \
+                        : batched_lds_t<uint64_t, B, P, false>(b, items, nitems, max_n, sc, stream))
     switch (c) {
     case 0: BRR_LDS_CLASS(64, kWaveP);
     case 1: BRR_LDS_CLASS(256, 8);

@@ -97,39 +97,57 @@ def test_training_fits_a_smooth_target(gpu):
 
 
 @pytest.mark.slow
-def test_learned_tuner_gain(gpu, orc):
-    """Trained on measured times of random batches, the model ranks held-out
-    configurations; the learned tuner times 3 of ~100 candidates and its
-    choice is compared with the paper's rule (shuffle_6, default mapping) and
-    with exhaustive search. Outputs stay bit-exact with the oracle."""
+def test_learned_model_held_out(gpu, orc):
+    """What the trained network gains, measured on batches it never saw.
+    Trained on measured times of random batches (each batch's candidates
+    relative to their mean), the model ranks every candidate configuration
+    (schedule x wavefront limit) of 8 fresh random batches; each
+    candidate's time is the median of 7 single runs. Checked: the learned
+    tuner, which times the shuffle_6 default and the model's top 3 (4
+    configurations), picks a configuration within 10% on average (15% at
+    worst) of the exhaustive tuner's pick (29 timed): the network buys an
+    eighth of the tuning runs at that cost; and its pick is never slower
+    than the default beyond twice the measured spread. Reported, not
+    asserted: the model's Spearman rank correlation with the measured times
+    (weak, about 0.3: most candidates lie within the run-to-run spread of
+    each other) and the gain over the default (within the spread on most
+    batches: the analytic default is close to the best). Outputs under the
+    learned choice stay bit-exact with the oracle."""
     from paper_2408_06213_amd import learned, workloads
 
     rng = np.random.default_rng(7)
     say("learned: collect")
-    X, y, _ = learned.collect(gpu, to_dev, rng, nbatch=12, ncand=30)
-    net, loss = learned.train(gpu, to_dev, X, y, steps=3000, lr=3e-3, hidden=64)
+    X, y, _ = learned.collect(gpu, to_dev, rng, nbatch=16, ncand=40)
+    net, loss = learned.train(gpu, to_dev, X, y, steps=4000, lr=3e-3, hidden=64)
+    print("train mse", loss, "target variance", float(np.var(y)))
     assert loss < np.var(y)  # better than predicting the mean
-    gains, found = [], []
-    for b in range(3):
-        sizes = learned.random_batch(rng)
-        off = workloads.csr_offsets(sizes)
-        data = workloads.iota_segments(sizes)
-        d, d_off = to_dev(data), to_dev(off)
-        say("learned: held-out batch", b, sizes.size)
-        plan = gpu.Plan(off, 4)
-        rep = gpu.brr_plan_autotune_learned(plan, net, 3, d, d_off, seed=2, inst_base=0)
-        assert rep.candidates == 4 and rep.ms_best <= rep.ms_default
-        gains.append(rep.ms_default / rep.ms_best)
-        ex = gpu.Plan(off, 4)
-        full = ex.autotune(d, d_off, seed=2, inst_base=0)
-        found.append(full.ms_best / rep.ms_best)
-        ex.close()
-        gpu.check(gpu.brr_shuffle_batched(d, d_off, sizes.size, 4, plan, 2, 0))
-        sched = plan.schedule()
-        want = data.copy()
-        osched = orc.Schedule.from_segments(sched.steps(), tail=bool(sched.tail), u_tail=sched.u_tail)
-        assert orc.shuffle_batched(want, off, osched, 2, 0) == 0
-        assert np.array_equal(to_host(d), want)
-        plan.close()
-    print("learned tuner: gain over shuffle_6", gains, "best-found ratio", found)
-    assert min(gains) >= 1.0
+    say("learned: held-out evaluation")
+    rows = learned.evaluate(gpu, to_dev, net, rng, nbatch=8, reps=7)
+    for r in rows:
+        print("held-out", {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()})
+    rho = np.array([r["spearman"] for r in rows])
+    quality = np.array([r["learned_vs_exhaustive"] for r in rows])
+    gain = np.array([r["gain_learned_vs_default"] for r in rows])
+    spread = np.array([max(r["learned_spread"], r["default_spread"]) for r in rows])
+    print("mean spearman", rho.mean(), "learned/exhaustive", quality, "gain", gain,
+          "spread", spread, "significant gains", int(np.sum(gain > 1 + 2 * spread)))
+    # near the exhaustive tuner's pick at an eighth of its tuning runs
+    assert quality.mean() >= 0.9 and quality.min() >= 0.85, quality
+    assert all(4 * r["learned_timed"] <= r["exhaustive_timed"] for r in rows)
+    # never measurably slower than the shuffle_6 default
+    assert np.all(gain >= 1 / (1 + 2 * spread)), (gain, spread)
+    # outputs under a learned choice stay bit-exact
+    sizes = learned.random_batch(rng)
+    off = workloads.csr_offsets(sizes)
+    data = workloads.iota_segments(sizes)
+    d, d_off = to_dev(data), to_dev(off)
+    plan = gpu.Plan(off, 4)
+    gpu.brr_plan_autotune_learned(plan, net, 3, d, d_off, seed=2, inst_base=0)
+    gpu.check(gpu.brr_shuffle_batched(d, d_off, sizes.size, 4, plan, 2, 0))
+    sched = plan.schedule()
+    want = data.copy()
+    osched = orc.Schedule.from_segments(sched.steps(), tail=bool(sched.tail), u_tail=sched.u_tail)
+    assert orc.shuffle_batched(want, off, osched, 2, 0) == 0
+    assert np.array_equal(to_host(d), want)
+    plan.close()
+    net.close()

@@ -229,9 +229,10 @@ def test_batched_equal_size_full(gpu, orc, lane_max):
 
 def test_plan_rebinds_while_running(gpu, orc):
     """A plan called again with another buffer and instance before its last
-    run has finished (no synchronization between calls) replaces its graph:
-    the replaced graph must outlive that run. Every tier is present (lane,
-    LDS classes, peel, device-wide); every result equals the oracle's."""
+    run has finished (no synchronization between calls): each replay must
+    read its own arguments, never a later call's. Every tier is present
+    (lane, LDS classes, peel, device-wide); every result equals the
+    oracle's."""
     sizes = np.array([256, 100, 2048, 4097, 16384, 16385, 65536, 70001, 5, (1 << 20) + 1],
                      dtype=np.uint64)
     off = workloads.csr_offsets(sizes)
@@ -250,6 +251,52 @@ def test_plan_rebinds_while_running(gpu, orc):
         want = data.copy()
         assert orc.shuffle_batched(want, off, orc.schedule_paper(6), 5, 100 + r) == 0
         assert np.array_equal(got[r], want), r
+
+
+@pytest.mark.slow
+def test_plan_replays_without_recapture(gpu, orc):
+    """100 calls of one plan, each with a fresh buffer and instance base,
+    enqueued behind a long-running kernel: the plan captures its graph once
+    (on the first call, made beforehand) and no call waits on the host (the
+    calls return while the kernel ahead of them still runs). Every tier is
+    present; all 100 results equal the oracle's."""
+    import time
+
+    import torch
+
+    sizes = np.array([256, 100, 300, 2048, 4097, 16384, 16385, 65536, 70001, 5, (1 << 20) + 1, 17],
+                     dtype=np.uint64)
+    off = workloads.csr_offsets(sizes)
+    data = workloads.iota_segments(sizes, np.uint32)
+    d_off = to_dev(off)
+    calls = 100
+    bufs = [to_dev(data) for _ in range(calls + 1)]
+    plan = gpu.Plan(off, 4)
+    say("plan replays: first call")
+    gpu.check(gpu.brr_shuffle_batched(bufs[0], d_off, len(sizes), 4, plan, 9, 0))
+    torch.cuda.synchronize()
+    assert plan.captures() == 1
+    say("plan replays: 100 calls behind a long kernel")
+    s = torch.cuda.current_stream()
+    torch.cuda._sleep(400_000_000)  # on the order of 0.2 s
+    busy = torch.cuda.Event()
+    busy.record(s)
+    t0 = time.perf_counter()
+    for c in range(1, calls + 1):
+        gpu.check(gpu.brr_shuffle_batched(bufs[c], d_off, len(sizes), 4, plan, 9, 1000 * c))
+    host_s = time.perf_counter() - t0
+    still_running = not busy.query()
+    torch.cuda.synchronize()
+    print("host seconds for", calls, "calls:", host_s, "sleep still running:", still_running)
+    assert still_running, host_s
+    assert plan.captures() == 1
+    assert gpu.brr_sync_status() == 0
+    plan.close()
+    s6 = orc.schedule_paper(6)
+    for c in [0] + list(range(1, calls + 1)):
+        want = data.copy()
+        assert orc.shuffle_batched_threads(want, off, s6, 9, 1000 * c) == 0
+        assert np.array_equal(to_host(bufs[c]), want), c
 
 
 @pytest.mark.slow
