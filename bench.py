@@ -124,7 +124,8 @@ def host_cpu():
     return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
-def serving(brr, workloads, up, rates=(1000, 4000, 16000), count=400, clients=64):
+def serving(brr, workloads, up, rates=(1000, 2000, 4000, 8000, 16000, 32000, 64000), count=400,
+            clients=64):
     """Poisson arrivals at each rate: requests (shuffle or sample, n
     log-uniform in [2^4, 2^22], u64 payload, m <= n/10) from `clients`
     independent clients (request i belongs to session i mod clients; a

@@ -480,15 +480,19 @@ uint64_t brr_scratch_bytes(uint64_t n, uint64_t m, uint32_t elem_bytes);
 /* ------------------------------------------------------------------------ */
 
 /* A server admits requests in arrival order as in-flight slots and its
- * device-scratch budget allow, runs them concurrently on a pool of HIP
- * streams (a session's requests share one stream, in submission order), and
- * retires them when their completion events fire. Each session's generator
- * counter lives on the device: request j of session s (j = 0, 1, ...) uses
- * instance s * 2^40 + j, claimed by a kernel on the session's stream, so a
- * result depends only on (seed, session, j, inputs), never on the mix it ran
- * in. A request that needs more scratch than the whole budget still runs,
- * alone. Shuffles follow brr_shuffle, samples brr_sample, with the server's
- * schedule. */
+ * device-scratch budget allow, and retires them when their completion
+ * events fire (continuous batching). What one pass of its worker admits is
+ * launched together: requests of at most 16,384 elements as one launch per
+ * size class and element width (one workgroup each), larger ones each on
+ * one of a pool of HIP streams, all overlapping on the device. Each
+ * session's generator counter lives on the device: request j of session s
+ * (j = 0, 1, ... in submission order) uses instance s * 2^40 + j, claimed by
+ * a kernel in submission order, so a result depends only on (seed, session,
+ * j, inputs), never on the mix it ran in or on what ran beside it. Requests
+ * run concurrently and may finish in any order, also within a session: a
+ * buffer must not be used by two requests in flight at once. A request that
+ * needs more scratch than the whole budget still runs, alone. Shuffles
+ * follow brr_shuffle, samples brr_sample, with the server's schedule. */
 typedef struct brr_server brr_server;
 
 typedef struct {
@@ -531,7 +535,7 @@ brr_status brr_server_drain(brr_server *server, double timeout_s);
 brr_status brr_server_get_stats(brr_server *server, brr_server_stats *out);
 brr_status brr_server_reset_stats(brr_server *server);
 /* The device counter of a session (requests claimed so far); synchronizes
- * the session's stream. */
+ * the server's claims. */
 brr_status brr_server_session_counter(brr_server *server, uint64_t session, uint64_t *value);
 /* Finishes every queued request, then releases the server. */
 void brr_server_destroy(brr_server *server);

@@ -148,7 +148,9 @@ hipError_t prepare_shuffle_kernels();
 // A device-side instance claim. With counter set, the first kernel of a
 // launch takes c = *counter, stores c + 1 back and base + c into *slot (one
 // thread), and the launch's instance is inst + base + c. Claims on one
-// stream therefore follow stream order. counter == nullptr: no claim.
+// stream therefore follow stream order. counter == nullptr and slot set:
+// the instance was claimed by an earlier kernel on the stream, and is
+// inst + *slot. Neither set: no claim.
 struct DevClaim {
     uint64_t *counter;
     uint64_t *slot;
@@ -223,6 +225,25 @@ hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, u
                       const DevClaim &claim, hipStream_t s, void *scratch = nullptr);
 uint32_t gtier_tile_shift(); // log2 of the indices per tile-table entry
 hipError_t launch_gtier(const GTierArgs &a, hipStream_t stream);
+
+// Independent requests in one launch (the server's small requests): each
+// a shuffle (out == nullptr, steps = n - 1, out_lo = 0) or a sample of
+// separate arrays, n <= lds_class_max_n(c) for the launch's class c, its
+// instance in slots[slot].
+struct ReqDesc {
+    void *data, *out;
+    uint32_t n, steps, out_lo, slot;
+};
+constexpr uint32_t kMaxFusedRequests = 32;
+struct ReqBatch {
+    ReqDesc r[kMaxFusedRequests];
+    uint32_t count;
+};
+// The LDS class of an array of n elements (-1 above lds_tier_max_n()).
+int lds_request_class(uint32_t n);
+hipError_t launch_lds_requests(int c, uint32_t eb, const ReqBatch &b, uint32_t max_n,
+                               const DevSched &sc, uint64_t seed, const uint64_t *slots,
+                               hipStream_t stream);
 
 // Batched shuffles of one LDS size class: one block per shuffle with its
 // index arrays in LDS, class c holding n <= lds_class_max_n(c) (0: one

@@ -1,12 +1,19 @@
 // Serving loop with continuous batching: shuffle and sample requests are
-// admitted as in-flight slots and device scratch free up, run concurrently on
-// a pool of HIP streams, and retired as their completion events fire.
-//
-// Generator counters live on the device: every session owns a counter, and a
-// one-thread claim kernel on the session's stream hands each request the
-// next instance (session * 2^40 + counter) in submission order. A request's
-// result is therefore fixed by (session, its place in the session), whatever
-// else runs beside it.
+// admitted as in-flight slots and device scratch free up, and retired as
+// their completion events fire. Each pass of the worker admits what it can
+// (a tick) and launches the tick's requests together:
+//   - one claim kernel on the control stream hands every admitted request,
+//     in submission order, the next instance of its session from the
+//     session's counter in device memory (session * 2^40 + counter); a
+//     request's result is therefore fixed by (session, its place in the
+//     session), whatever else runs beside it;
+//   - the requests small enough for one workgroup's LDS run as one launch
+//     per LDS size class and element width (one block per request) on the
+//     control stream, behind the claim;
+//   - larger ones (the device-wide shuffle tier, sparse samples) each run
+//     their own kernels on a pool of streams, after the claim;
+// so a tick of many small requests costs a few launches, not one or more
+// per request, and the large requests overlap with them and each other.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -30,11 +37,25 @@ using clock_t_ = std::chrono::steady_clock;
 constexpr uint32_t kMaxSessions = 4096;
 constexpr uint64_t kSessionShift = 40;
 
-__global__ void k_claim(uint64_t *counter, uint64_t *slot, uint64_t session)
+constexpr uint32_t kMaxTick = 64; // requests admitted per tick
+
+// The instances of one tick's requests, in submission order: request e takes
+// the next value of its session's counter.
+struct ClaimBatch {
+    uint32_t count;
+    uint32_t sidx[kMaxTick];    // session counter
+    uint32_t slot[kMaxTick];    // where the instance goes
+    uint64_t session[kMaxTick];
+};
+
+__global__ void k_claim_tick(uint64_t *counters, uint64_t *slots, ClaimBatch b)
 {
-    const uint64_t c = *counter;
-    *counter = c + 1;
-    *slot = (session << kSessionShift) + c;
+    if (threadIdx.x != 0) return;
+    for (uint32_t e = 0; e < b.count; ++e) {
+        const uint64_t c = counters[b.sidx[e]];
+        counters[b.sidx[e]] = c + 1;
+        slots[b.slot[e]] = (b.session[e] << kSessionShift) + c;
+    }
 }
 
 struct Req {
@@ -59,6 +80,8 @@ struct brr_server {
     brr_server_config cfg;
     int device = 0;
     DevSched ds;
+    hipStream_t control = nullptr;  // claims, fused small requests
+    hipEvent_t claimed = nullptr;   // the last tick's claims are done
     std::vector<hipStream_t> streams;
     uint64_t *d_counters = nullptr; // [kMaxSessions]
     uint64_t *d_slots = nullptr;    // [max_inflight] instance of each in-flight request
@@ -82,56 +105,142 @@ struct brr_server {
 
 namespace {
 
-// Launches an admitted request on its session's stream (lock held).
-brr_status launch(brr_server *sv, Req &q)
+uint32_t session_of(brr_server *sv, uint64_t session, bool *ok)
 {
-    const brr_request &r = q.r;
-    uint32_t sidx;
-    auto it = sv->session_index.find(r.session);
-    if (it == sv->session_index.end()) {
-        if (sv->session_index.size() >= kMaxSessions) return BRR_EINVAL;
-        sidx = (uint32_t)sv->session_index.size();
-        sv->session_index.emplace(r.session, sidx);
-    } else {
-        sidx = it->second;
+    auto it = sv->session_index.find(session);
+    if (it != sv->session_index.end()) return it->second;
+    if (sv->session_index.size() >= kMaxSessions) {
+        *ok = false;
+        return 0;
     }
-    q.stream = sidx % (uint32_t)sv->streams.size();
-    hipStream_t s = sv->streams[q.stream];
-    uint64_t *slot = sv->d_slots + q.slot;
-    // the request's first kernel claims its instance; a request that runs no
-    // kernel still takes one, so every session's counter advances once per
-    // request in submission order
-    const DevClaim claim{sv->d_counters + sidx, slot, r.session << kSessionShift};
-    const uint64_t n = r.n;
+    const uint32_t sidx = (uint32_t)sv->session_index.size();
+    sv->session_index.emplace(session, sidx);
+    return sidx;
+}
+
+// Launches one tick of admitted requests (lock held); sets each request's
+// status and completion event. Requests that fail are finished by the
+// caller.
+void launch_tick(brr_server *sv, const std::vector<uint64_t> &ids)
+{
+    ClaimBatch cb;
+    std::memset(&cb, 0, sizeof cb);
+    std::vector<uint64_t> fused, big, trivial;
+    for (uint64_t id : ids) {
+        Req &q = sv->reqs[id];
+        bool ok = true;
+        const uint32_t sidx = session_of(sv, q.r.session, &ok);
+        if (!ok) {
+            q.status = BRR_EINVAL;
+            continue;
+        }
+        // every request takes its instance, even one that runs no kernel, so
+        // each session's counter advances once per request in order
+        cb.sidx[cb.count] = sidx;
+        cb.slot[cb.count] = (uint32_t)q.slot;
+        cb.session[cb.count] = q.r.session;
+        ++cb.count;
+        q.stream = sidx % (uint32_t)sv->streams.size();
+        const uint64_t n = q.r.n;
+        const bool work = q.r.kind == BRR_REQ_SHUFFLE ? n > 1 : (n > 1 && q.r.m > 0);
+        if (!work)
+            trivial.push_back(id);
+        else if (n <= lds_tier_max_n())
+            fused.push_back(id);
+        else
+            big.push_back(id);
+    }
+    hipStream_t ctl = sv->control;
     hipError_t e = hipSuccess;
-    bool claimed = false;
-    if (r.kind == BRR_REQ_SHUFFLE) {
-        if (n > 1) {
-            e = launch_one(r.d_data, (uint32_t)n, (uint32_t)(n - 1), 0, r.elem_bytes, nullptr,
-                           sv->ds, sv->cfg.seed, 0, claim, s);
-            claimed = true;
-        }
-    } else {
-        if (n == 1) {
-            e = hipMemcpyAsync(r.d_out, r.d_data, r.elem_bytes, hipMemcpyDeviceToDevice, s);
-        } else if (r.m > 0) {
-            e = launch_one(r.d_data, (uint32_t)n, (uint32_t)std::min<uint64_t>(r.m, n - 1),
-                           (uint32_t)(n - r.m), r.elem_bytes, r.d_out, sv->ds, sv->cfg.seed, 0,
-                           claim, s);
-            claimed = true;
-        }
+    if (cb.count) {
+        k_claim_tick<<<1, 64, 0, ctl>>>(sv->d_counters, sv->d_slots, cb);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(sv->claimed, ctl);
     }
-    // a device-wide request whose scratch could not be allocated failed before
-    // its first kernel: its instance is still taken
-    if (!claimed || e == hipErrorOutOfMemory) {
-        k_claim<<<1, 1, 0, s>>>(sv->d_counters + sidx, slot, r.session);
-        const hipError_t f = hipGetLastError();
-        if (e == hipSuccess) e = f;
+    auto fail = [&](Req &q, hipError_t err) {
+        q.status = err == hipErrorOutOfMemory ? BRR_ENOMEM : BRR_EHIP;
+    };
+    // small requests: one launch per (class, element width), up to
+    // kMaxFusedRequests requests each
+    if (e == hipSuccess) {
+        for (int c = 0; c < kLdsClasses; ++c)
+            for (uint32_t eb : {4u, 8u}) {
+                ReqBatch rb;
+                rb.count = 0;
+                uint32_t max_n = 0;
+                auto flush = [&] {
+                    if (!rb.count || e != hipSuccess) return;
+                    e = launch_lds_requests(c, eb, rb, max_n, sv->ds, sv->cfg.seed, sv->d_slots,
+                                            ctl);
+                    rb.count = 0;
+                    max_n = 0;
+                };
+                for (uint64_t id : fused) {
+                    const Req &q = sv->reqs[id];
+                    if (q.r.elem_bytes != eb || lds_request_class((uint32_t)q.r.n) != c) continue;
+                    const uint32_t n = (uint32_t)q.r.n;
+                    const bool sample = q.r.kind == BRR_REQ_SAMPLE;
+                    const uint32_t steps = sample ? (uint32_t)std::min<uint64_t>(q.r.m, n - 1) : n - 1;
+                    rb.r[rb.count++] = ReqDesc{q.r.d_data, sample ? q.r.d_out : nullptr, n, steps,
+                                               sample ? (uint32_t)(n - q.r.m) : 0u,
+                                               (uint32_t)q.slot};
+                    max_n = std::max(max_n, n);
+                    if (rb.count == kMaxFusedRequests) flush();
+                }
+                flush();
+            }
     }
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? BRR_ENOMEM : BRR_EHIP;
-    q.ev = sv->slot_events[q.slot];
-    if (hipEventRecord(q.ev, s) != hipSuccess) return BRR_EHIP;
-    return BRR_OK;
+    for (uint64_t id : trivial) {
+        Req &q = sv->reqs[id];
+        if (e == hipSuccess && q.r.kind == BRR_REQ_SAMPLE && q.r.n == 1 && q.r.m == 1)
+            e = hipMemcpyAsync(q.r.d_out, q.r.d_data, q.r.elem_bytes, hipMemcpyDeviceToDevice, ctl);
+    }
+    for (uint64_t id : fused) {
+        Req &q = sv->reqs[id];
+        if (e != hipSuccess) fail(q, e);
+    }
+    for (uint64_t id : trivial) {
+        Req &q = sv->reqs[id];
+        if (e != hipSuccess) fail(q, e);
+    }
+    // the tick's small and trivial requests complete with the control stream
+    for (uint64_t id : fused) {
+        Req &q = sv->reqs[id];
+        if (q.status != BRR_OK) continue;
+        q.ev = sv->slot_events[q.slot];
+        if (hipEventRecord(q.ev, ctl) != hipSuccess) q.status = BRR_EHIP;
+    }
+    for (uint64_t id : trivial) {
+        Req &q = sv->reqs[id];
+        if (q.status != BRR_OK) continue;
+        q.ev = sv->slot_events[q.slot];
+        if (hipEventRecord(q.ev, ctl) != hipSuccess) q.status = BRR_EHIP;
+    }
+    // large requests: each on its session's stream, behind the claims
+    for (uint64_t id : big) {
+        Req &q = sv->reqs[id];
+        if (e != hipSuccess) {
+            fail(q, e);
+            continue;
+        }
+        hipStream_t st = sv->streams[q.stream];
+        const DevClaim claim{nullptr, sv->d_slots + q.slot, 0};
+        const uint64_t n = q.r.n;
+        hipError_t f = hipStreamWaitEvent(st, sv->claimed, 0);
+        if (f == hipSuccess && q.r.kind == BRR_REQ_SHUFFLE)
+            f = launch_one(q.r.d_data, (uint32_t)n, (uint32_t)(n - 1), 0, q.r.elem_bytes, nullptr,
+                           sv->ds, sv->cfg.seed, 0, claim, st);
+        else if (f == hipSuccess)
+            f = launch_one(q.r.d_data, (uint32_t)n, (uint32_t)std::min<uint64_t>(q.r.m, n - 1),
+                           (uint32_t)(n - q.r.m), q.r.elem_bytes, q.r.d_out, sv->ds,
+                           sv->cfg.seed, 0, claim, st);
+        if (f != hipSuccess) {
+            fail(q, f);
+            continue;
+        }
+        q.ev = sv->slot_events[q.slot];
+        if (hipEventRecord(q.ev, st) != hipSuccess) q.status = BRR_EHIP;
+    }
 }
 
 void finish(brr_server *sv, Req &q, uint64_t id)
@@ -171,9 +280,11 @@ void worker_loop(brr_server *sv)
             finish(sv, q, id);
             progress = true;
         }
-        // admit in arrival order while a slot and the scratch budget allow; an
-        // idle device always takes the next request, whatever its footprint
-        while (!sv->pending.empty()) {
+        // admit in arrival order while a slot and the scratch budget allow (an
+        // idle device always takes the next request, whatever its
+        // footprint), up to a tick's worth, then launch the tick together
+        std::vector<uint64_t> tick;
+        while (!sv->pending.empty() && tick.size() < kMaxTick) {
             const uint64_t id = sv->pending.front();
             Req &q = sv->reqs[id];
             const bool fits = sv->footprint + q.footprint <= sv->cfg.hbm_budget;
@@ -186,8 +297,14 @@ void worker_loop(brr_server *sv)
             sv->peak_footprint = std::max(sv->peak_footprint, sv->footprint);
             sv->inflight.push_back(id);
             sv->peak_inflight = std::max<uint32_t>(sv->peak_inflight, (uint32_t)sv->inflight.size());
-            q.status = launch(sv, q);
-            if (q.status != BRR_OK) finish(sv, q, id);
+            tick.push_back(id);
+        }
+        if (!tick.empty()) {
+            launch_tick(sv, tick);
+            for (uint64_t id : tick) {
+                Req &q = sv->reqs[id];
+                if (q.status != BRR_OK) finish(sv, q, id);
+            }
             progress = true;
         }
         if (progress) sv->cv.notify_all();
@@ -237,7 +354,9 @@ brr_status brr_server_create(brr_server **out, const brr_server_config *cfg)
     (void)hipGetDevice(&sv->device);
     // DevSched from the checked schedule
     sv->ds = dev_schedule(sc);
-    bool ok = hipMalloc(reinterpret_cast<void **>(&sv->d_counters), kMaxSessions * 8) == hipSuccess &&
+    bool ok = hipStreamCreateWithFlags(&sv->control, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&sv->claimed, hipEventDisableTiming) == hipSuccess &&
+              hipMalloc(reinterpret_cast<void **>(&sv->d_counters), kMaxSessions * 8) == hipSuccess &&
               hipMalloc(reinterpret_cast<void **>(&sv->d_slots), cfg->max_inflight * 8ull) == hipSuccess &&
               hipMemset(sv->d_counters, 0, kMaxSessions * 8) == hipSuccess &&
               hipDeviceSynchronize() == hipSuccess;
@@ -368,8 +487,7 @@ brr_status brr_server_session_counter(brr_server *sv, uint64_t session, uint64_t
             return BRR_OK;
         }
         sidx = it->second;
-        hipStream_t s = sv->streams[sidx % sv->streams.size()];
-        if (hipStreamSynchronize(s) != hipSuccess) return BRR_EHIP;
+        if (hipStreamSynchronize(sv->control) != hipSuccess) return BRR_EHIP;
     }
     if (hipMemcpy(value, sv->d_counters + sidx, 8, hipMemcpyDeviceToHost) != hipSuccess)
         return BRR_EHIP;
@@ -389,6 +507,11 @@ void brr_server_destroy(brr_server *sv)
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
     }
+    if (sv->control) {
+        (void)hipStreamSynchronize(sv->control);
+        (void)hipStreamDestroy(sv->control);
+    }
+    if (sv->claimed) (void)hipEventDestroy(sv->claimed);
     for (hipEvent_t ev : sv->slot_events) (void)hipEventDestroy(ev);
     if (sv->d_counters) (void)hipFree(sv->d_counters);
     if (sv->d_slots) (void)hipFree(sv->d_slots);

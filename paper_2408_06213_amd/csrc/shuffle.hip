@@ -372,7 +372,7 @@ __global__ __launch_bounds__(BLOCK) void k_lds_single(Elem *z, uint32_t n, uint3
     __shared__ uint32_t wsum[BLOCK / 64];
     __shared__ uint64_t claimed;
     if (threadIdx.x < st.nseg) seg[threadIdx.x] = st.seg[threadIdx.x];
-    if (threadIdx.x == 0) claimed = claim.counter ? take_claim(claim) : 0;
+    if (threadIdx.x == 0) claimed = claim.counter ? take_claim(claim) : (claim.slot ? *claim.slot : 0);
     __syncthreads();
     const StreamKey key = make_key(seed, inst + claimed);
     lds_tier_run<Elem, BLOCK, P, W>(z, n, steps, out_lo, out, seg, st.nseg, st.S, st.words, key,
@@ -398,6 +398,24 @@ __global__ __launch_bounds__(BLOCK) void k_lds_batched(const RunArgs *__restrict
     __syncthreads();
     lds_tier_run<Elem, BLOCK, P, W>(data + off, n, n - 1, 0, nullptr, st.seg, st.nseg, st.S,
                                     st.words, make_key(seed, inst_base + q), smem, wsum);
+}
+
+// Independent requests (shuffles or samples of separate arrays) in one
+// launch, one block each, every one with its instance in slots[] (written
+// by an earlier kernel on the stream).
+template <typename Elem, int BLOCK, int P, bool W>
+__global__ __launch_bounds__(BLOCK) void k_lds_requests(ReqBatch b, DevSched sc, uint64_t seed,
+                                                        const uint64_t *slots)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ SegTable st;
+    __shared__ uint32_t wsum[BLOCK / 64];
+    const ReqDesc r = b.r[blockIdx.x];
+    if (threadIdx.x == 0) build_segments(r.n, r.steps, sc, st);
+    __syncthreads();
+    lds_tier_run<Elem, BLOCK, P, W>(static_cast<Elem *>(r.data), r.n, r.steps, r.out_lo,
+                                    static_cast<Elem *>(r.out), st.seg, st.nseg, st.S, st.words,
+                                    make_key(seed, slots[r.slot]), smem, wsum);
 }
 
 // ---------------------------------------------------------------------------
@@ -1087,7 +1105,7 @@ __device__ __forceinline__ uint64_t problem_seed(const GProblem &P, uint64_t see
 }
 __device__ __forceinline__ uint64_t problem_inst_base(const GProblem &P)
 {
-    return (P.dyn ? P.dyn->inst : P.inst_base) + (P.claim.counter ? *P.claim.slot : 0);
+    return (P.dyn ? P.dyn->inst : P.inst_base) + (P.claim.slot ? *P.claim.slot : 0);
 }
 template <typename Elem> __device__ __forceinline__ Elem *problem_data(const GProblem &P, Elem *data)
 {
@@ -1747,7 +1765,7 @@ __global__ __launch_bounds__(256) void k_sp_dice(SProblem Q, SArrays a, uint64_t
 {
     const uint32_t npairs = (Q.seg.S + 1) / 2;
     const uint32_t src = W ? Q.seg.words : BRR_WORDS_PHILOX64;
-    const StreamKey key = make_key(seed, Q.inst + (Q.claim.counter ? *Q.claim.slot : 0));
+    const StreamKey key = make_key(seed, Q.inst + (Q.claim.slot ? *Q.claim.slot : 0));
     for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < npairs;
          w += gridDim.x * blockDim.x) {
         uint64_t wd[2];
@@ -1956,7 +1974,17 @@ hipError_t prepare_shuffle_kernels()
         {(const void *)k_lds_batched<uint32_t, 512, 16, W>, c3},                           \
         {(const void *)k_lds_batched<uint64_t, 512, 16, W>, c3},                           \
         {(const void *)k_lds_batched<uint32_t, kWgThreads, kWgP, W>, wg},                  \
-        {(const void *)k_lds_batched<uint64_t, kWgThreads, kWgP, W>, wg}
+        {(const void *)k_lds_batched<uint64_t, kWgThreads, kWgP, W>, wg},                  \
+        {(const void *)k_lds_requests<uint32_t, 64, kWaveP, W>, c0},                       \
+        {(const void *)k_lds_requests<uint64_t, 64, kWaveP, W>, c0},                       \
+        {(const void *)k_lds_requests<uint32_t, 256, 8, W>, c1},                           \
+        {(const void *)k_lds_requests<uint64_t, 256, 8, W>, c1},                           \
+        {(const void *)k_lds_requests<uint32_t, 256, 16, W>, c2},                          \
+        {(const void *)k_lds_requests<uint64_t, 256, 16, W>, c2},                          \
+        {(const void *)k_lds_requests<uint32_t, 512, 16, W>, c3},                          \
+        {(const void *)k_lds_requests<uint64_t, 512, 16, W>, c3},                          \
+        {(const void *)k_lds_requests<uint32_t, kWgThreads, kWgP, W>, wg},                 \
+        {(const void *)k_lds_requests<uint64_t, kWgThreads, kWgP, W>, wg}
     const Attr attrs[] = {BRR_LDS_ATTRS(false), BRR_LDS_ATTRS(true)};
 #undef BRR_LDS_ATTRS
     for (const Attr &a : attrs) {
@@ -2085,6 +2113,40 @@ uint32_t lds_class_max_n(int c)
     static const uint32_t cap[kLdsClasses] = {64 * kWaveP, 256 * 8, 256 * 16, 512 * 16,
                                               kWgThreads * kWgP};
     return (c >= 0 && c < kLdsClasses) ? cap[c] : 0;
+}
+
+int lds_request_class(uint32_t n)
+{
+    for (int c = 0; c < kLdsClasses; ++c)
+        if (n <= lds_class_max_n(c)) return c;
+    return -1;
+}
+
+hipError_t launch_lds_requests(int c, uint32_t eb, const ReqBatch &b, uint32_t max_n,
+                               const DevSched &sc, uint64_t seed, const uint64_t *slots,
+                               hipStream_t stream)
+{
+    if (b.count == 0) return hipSuccess;
+    if (b.count > kMaxFusedRequests || max_n > lds_class_max_n(c)) return hipErrorInvalidValue;
+    const bool w = sc.words != BRR_WORDS_PHILOX64;
+    const uint32_t bytes = lds_bytes(max_n);
+#define BRR_REQ_CLASS(B, P)                                                                       \
+    if (eb == 4) {                                                                                \
+        if (w) k_lds_requests<uint32_t, B, P, true><<<b.count, B, bytes, stream>>>(b, sc, seed, slots); \
+        else k_lds_requests<uint32_t, B, P, false><<<b.count, B, bytes, stream>>>(b, sc, seed, slots); \
+    } else {                                                                                      \
+        if (w) k_lds_requests<uint64_t, B, P, true><<<b.count, B, bytes, stream>>>(b, sc, seed, slots); \
+        else k_lds_requests<uint64_t, B, P, false><<<b.count, B, bytes, stream>>>(b, sc, seed, slots); \
+    }
+    switch (c) {
+    case 0: BRR_REQ_CLASS(64, kWaveP) break;
+    case 1: BRR_REQ_CLASS(256, 8) break;
+    case 2: BRR_REQ_CLASS(256, 16) break;
+    case 3: BRR_REQ_CLASS(512, 16) break;
+    default: BRR_REQ_CLASS(kWgThreads, kWgP) break;
+    }
+#undef BRR_REQ_CLASS
+    return hipGetLastError();
 }
 
 hipError_t launch_batched_lds(int c, const RunArgs *b, const uint32_t *items, uint32_t nitems,

@@ -1,6 +1,7 @@
 """Serving with continuous batching: every request's result equals the
 oracle's for its (session, place in session) instance, whatever mix,
-interleaving, stream count or budget it ran under."""
+interleaving, stream count or budget it ran under, and equals what the same
+request gives alone."""
 import numpy as np
 import pytest
 
@@ -95,6 +96,39 @@ def test_server_results_match_oracle_in_any_mix(gpu, orc):
         assert np.array_equal(got_b[i], want[i]), i
     assert counters_a == seen == counters_b
     assert stats_a["completed"] == len(reqs) and stats_a["p99_us"] >= stats_a["p50_us"] > 0
+
+
+def test_server_request_alone_equals_in_mix(gpu, orc):
+    """Every request of a mix, run alone in a fresh server at the same
+    (session, j) (its j earlier requests of the session replaced by
+    one-element shuffles, which take an instance and move nothing), gives
+    bit for bit the result it gave in the mix; both equal the oracle's."""
+    reqs = make_requests(3, 40)
+    order = list(range(len(reqs)))
+    say("server mix for alone-vs-mix")
+    mixed, _, stats = run_mix(gpu, reqs, order, seed=17, nstreams=4, max_inflight=32)
+    assert stats["peak_inflight"] > 1  # the mix did overlap
+    want, _ = expected(orc, reqs, order, seed=17)
+    seen = {}
+    for i in order:
+        r = reqs[i]
+        j = seen.get(r["session"], 0)
+        seen[r["session"]] = j + 1
+        say("server alone", i, r["kind"], r["n"], "session", r["session"], "j", j)
+        srv = gpu.Server(seed=17, nstreams=2, max_inflight=4)
+        pads = [to_dev(np.zeros(1, np.uint32)) for _ in range(j)]
+        for pad in pads:
+            srv.submit(gpu.BRR_REQ_SHUFFLE, pad, 1, 4, r["session"])
+        d = to_dev(r["data"])
+        out = to_dev(np.zeros(r["m"], r["data"].dtype)) if r["kind"] == "sample" else None
+        kind = gpu.BRR_REQ_SAMPLE if r["kind"] == "sample" else gpu.BRR_REQ_SHUFFLE
+        srv.wait(srv.submit(kind, d, r["n"], r["data"].itemsize, r["session"], r["m"], out))
+        srv.drain()
+        assert srv.counter(r["session"]) == j + 1
+        srv.close()
+        alone = to_host(out if out is not None else d)
+        assert np.array_equal(alone, mixed[i]), i
+        assert np.array_equal(alone, want[i]), i
 
 
 def test_server_budget_limits_footprint(gpu):
