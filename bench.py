@@ -338,6 +338,46 @@ def torch_sync():
     torch.cuda.synchronize()
 
 
+def ragged_classes(brr, workloads, up, steps):
+    """The 20,000 ragged shuffles split by the plan's size class (one lane
+    per array up to 256 elements; one wavefront up to 512; workgroups of
+    256, 256, 512 and 1,024 threads up to 2,048, 4,096, 8,192 and 16,384; one
+    workgroup in peels beyond), each class timed alone as its own batch
+    (shuffle_6, its own plan and graph): the time each class costs when
+    nothing runs beside it, against the whole batch (where the classes
+    overlap on forked streams)."""
+    import numpy as np
+
+    sizes = workloads.ragged_sizes(20000, seed=3)
+    bounds = [(2, 256, "lane"), (257, 512, "wavefront"), (513, 2048, "wg256x8"),
+              (2049, 4096, "wg256x16"), (4097, 8192, "wg512x16"), (8193, 16384, "wg1024x16"),
+              (16385, 1 << 20, "peel")]
+    res = {}
+    for lo, hi, name in bounds:
+        sub = sizes[(sizes >= lo) & (sizes <= hi)]
+        if sub.size == 0:
+            continue
+        off = workloads.csr_offsets(sub)
+        d, d_off = up(workloads.iota_segments(sub)), up(off)
+        plan = brr.Plan(off, 4)
+        ms = time_launches(lambda: brr.check(brr.brr_shuffle_batched(d, d_off, sub.size, 4, plan, 1, 0)),
+                           max(steps, 10), 3)
+        plan.close()
+        res[name] = {"arrays": int(sub.size), "elements": int(sub.sum()), "ms": ms,
+                     "elems_per_s": float(sub.sum()) / (ms * 1e-3),
+                     "hbm_frac": 8 * float(sub.sum()) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        del d, d_off
+    off = workloads.csr_offsets(sizes)
+    d, d_off = up(workloads.iota_segments(sizes)), up(off)
+    plan = brr.Plan(off, 4)
+    res["whole_batch_ms"] = time_launches(
+        lambda: brr.check(brr.brr_shuffle_batched(d, d_off, sizes.size, 4, plan, 1, 0)),
+        max(steps, 10), 3)
+    plan.close()
+    res["sum_of_classes_ms"] = sum(v["ms"] for v in res.values() if isinstance(v, dict))
+    return res
+
+
 def sample_sweep(brr, up, steps):
     """Samples without replacement far smaller than their array: time and
     device scratch against m, beside the full shuffle of the same array
@@ -468,6 +508,8 @@ def secondary(brr, workloads, up, steps, only=None):
         res["speedup_k6_vs_naive2"] = res["naive2"]["ms"] / res["k6"]["ms"]
         res["chacha20_speedup_k6_vs_k1"] = res["k1_chacha20"]["ms"] / res["k6_chacha20"]["ms"]
         out[tag] = res
+    if only in (None, "ragged_classes"):
+        out["ragged_20000_u32_classes"] = ragged_classes(brr, workloads, up, steps)
     if only in (None, "sample"):
         out["sample_sparse"] = sample_sweep(brr, up, steps)
     if only in (None, "tuned"):
@@ -487,7 +529,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--only", choices=["equal", "ragged", "single10000", "single2p26", "serving",
-                                       "tuned", "sample", "pmc"],
+                                       "tuned", "sample", "ragged_classes", "pmc"],
                     help="run one shuffle workload only (for profiling); prints its timings")
     args = ap.parse_args()
 
