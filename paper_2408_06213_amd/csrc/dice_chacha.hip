@@ -301,8 +301,19 @@ __global__ __launch_bounds__(256) void dice_chacha_rerolls(const uint32_t *__res
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    uint64_t t = wave * per;                                  // next tile to take from
-    const uint64_t t_end = std::min<uint64_t>(t + per, rec.tiles);
+    const uint64_t t_begin = std::min<uint64_t>(wave * per, rec.tiles);
+    const uint64_t t_end = std::min<uint64_t>(t_begin + per, rec.tiles);
+    // the first tile at or after `from` with recorded groups (t_end if
+    // none): 64 counts per step, most tiles having none
+    auto next_tile = [&](uint64_t from) -> uint64_t {
+        for (uint64_t base = from; base < t_end; base += 64) {
+            const uint64_t tt = base + lane;
+            const uint64_t nz = __ballot(tt < t_end && rec.count[tt] != 0);
+            if (nz) return base + (uint64_t)__builtin_ctzll(nz);
+        }
+        return t_end;
+    };
+    uint64_t t = next_tile(t_begin);                          // next tile to take from
     uint32_t used = 0, avail = t < t_end ? rec.count[t] : 0; // of tile t
     uint64_t g = kNoGroup, attempt = 1;
     while (true) {
@@ -319,14 +330,14 @@ __global__ __launch_bounds__(256) void dice_chacha_rerolls(const uint32_t *__res
             }
             used += take;
             if (used == avail) {
-                ++t;
+                t = next_tile(t + 1);
                 used = 0;
                 avail = t < t_end ? rec.count[t] : 0;
             }
         }
         if (!__any(g != kNoGroup)) {
             if (t >= t_end) break;
-            continue; // only empty tiles so far
+            continue;
         }
         if (g != kNoGroup) {
             const int kk = group_dice<K>(g, full, S, count);
