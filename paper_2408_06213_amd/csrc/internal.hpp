@@ -174,6 +174,20 @@ struct RunArgs {
     const uint64_t *offsets;
     uint64_t seed, inst;
 };
+// Pointers that reach a kernel through memory (an argument block) rather
+// than as kernel arguments are generic to the compiler, which then accesses
+// them with flat instructions; those count against the LDS wait counter as
+// well, so every wait for an LDS read also waits for the global loads in
+// flight. Data buffers are always device memory: kernels hold them as
+// global_t pointers, which compile to global loads and stores.
+template <typename T>
+using global_t = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ global_t<T> *as_global(T *p)
+{
+    return (global_t<T> *)p;
+}
+
 // Writes a run's arguments into a plan's device block, on the stream.
 hipError_t launch_set_args(RunArgs *dev, const RunArgs &val, hipStream_t stream);
 

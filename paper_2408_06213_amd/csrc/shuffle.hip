@@ -246,7 +246,8 @@ __host__ __device__ inline uint32_t lds_bytes(uint32_t n)
 // separate instantiation, so that the Philox-only kernels carry none of that
 // code); the same holds for every kernel below that takes W.
 template <typename Elem, int BLOCK, int P, bool W>
-__device__ void lds_tier_run(Elem *z, uint32_t n, uint32_t steps, uint32_t out_lo, Elem *out,
+__device__ void lds_tier_run(global_t<Elem> *z, uint32_t n, uint32_t steps, uint32_t out_lo,
+                             global_t<Elem> *out,
                              const Seg *seg, uint32_t nseg, uint32_t S, uint32_t words,
                              const StreamKey &key, char *smem, uint32_t *wsum)
 {
@@ -375,7 +376,8 @@ __global__ __launch_bounds__(BLOCK) void k_lds_single(Elem *z, uint32_t n, uint3
     if (threadIdx.x == 0) claimed = claim.counter ? take_claim(claim) : (claim.slot ? *claim.slot : 0);
     __syncthreads();
     const StreamKey key = make_key(seed, inst + claimed);
-    lds_tier_run<Elem, BLOCK, P, W>(z, n, steps, out_lo, out, seg, st.nseg, st.S, st.words, key,
+    lds_tier_run<Elem, BLOCK, P, W>(as_global(z), n, steps, out_lo, as_global(out), seg, st.nseg, st.S,
+                                    st.words, key,
                                     smem, wsum);
 }
 
@@ -384,8 +386,8 @@ __global__ __launch_bounds__(BLOCK) void k_lds_batched(const RunArgs *__restrict
                                                        DevSched sc)
 {
     const RunArgs A = *args;
-    Elem *data = static_cast<Elem *>(A.data);
-    const uint64_t *offsets = A.offsets;
+    global_t<Elem> *data = as_global(static_cast<Elem *>(A.data));
+    const global_t<const uint64_t> *offsets = as_global(A.offsets);
     const uint64_t seed = A.seed, inst_base = A.inst;
     extern __shared__ __align__(16) char smem[];
     __shared__ SegTable st;
@@ -413,8 +415,8 @@ __global__ __launch_bounds__(BLOCK) void k_lds_requests(ReqBatch b, DevSched sc,
     const ReqDesc r = b.r[blockIdx.x];
     if (threadIdx.x == 0) build_segments(r.n, r.steps, sc, st);
     __syncthreads();
-    lds_tier_run<Elem, BLOCK, P, W>(static_cast<Elem *>(r.data), r.n, r.steps, r.out_lo,
-                                    static_cast<Elem *>(r.out), st.seg, st.nseg, st.S, st.words,
+    lds_tier_run<Elem, BLOCK, P, W>(as_global(static_cast<Elem *>(r.data)), r.n, r.steps, r.out_lo,
+                                    as_global(static_cast<Elem *>(r.out)), st.seg, st.nseg, st.S, st.words,
                                     make_key(seed, slots[r.slot]), smem, wsum);
 }
 
@@ -537,8 +539,8 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(const RunArgs *__re
                                                             uint32_t max_n, DevSched sc)
 {
     const RunArgs A = *args;
-    Elem *data = static_cast<Elem *>(A.data);
-    const uint64_t *offsets = A.offsets;
+    global_t<Elem> *data = as_global(static_cast<Elem *>(A.data));
+    const global_t<const uint64_t> *offsets = as_global(A.offsets);
     const uint64_t seed = A.seed, inst_base = A.inst;
     constexpr uint32_t V = 16 / sizeof(Elem); // elements per 16-byte vector
     const uint32_t src = W ? sc.words : BRR_WORDS_PHILOX64;
@@ -594,10 +596,10 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(const RunArgs *__re
     u32x4 v[kLaneU];
     Elem hv = 0, tv = 0;
     auto issue = [&](const Chunk &c) {
-        const Elem *src = data + off0 + (uint64_t)c.t0 * n0;
+        const global_t<Elem> *src = data + off0 + (uint64_t)c.t0 * n0;
         if (lane < c.head) hv = src[lane];
         if (c.tail0 + lane < c.E) tv = src[c.tail0 + lane];
-        const u32x4 *vs = reinterpret_cast<const u32x4 *>(src + c.head);
+        const global_t<u32x4> *vs = reinterpret_cast<const global_t<u32x4> *>(src + c.head);
 #pragma unroll
         for (int u = 0; u < kLaneU; ++u) {
             const uint32_t i = u * kLaneItems + lane;
@@ -673,7 +675,7 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(const RunArgs *__re
                 issue(nxt);
             }
             // chunk element e is x = e mod n0 of local array e / n0
-            Elem *dst = data + off0 + (uint64_t)cur.t0 * n0;
+            global_t<Elem> *dst = data + off0 + (uint64_t)cur.t0 * n0;
             auto out = [&](uint32_t e) {
                 const uint32_t lt = lane_div(e, n0, rcp), x = e - lt * n0;
                 const uint32_t px = perm_bytes[(cur.t0 + lt) * RW * 4 + x];
@@ -681,7 +683,7 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(const RunArgs *__re
             };
             if (lane < cur.head) dst[lane] = out(lane);
             if (cur.tail0 + lane < cur.E) dst[cur.tail0 + lane] = out(cur.tail0 + lane);
-            u32x4 *vd = reinterpret_cast<u32x4 *>(dst + cur.head);
+            global_t<u32x4> *vd = reinterpret_cast<global_t<u32x4> *>(dst + cur.head);
             for (uint32_t i = lane; i < cur.nv; i += kLaneItems) {
                 Elem tmp[V];
                 // the V elements of one vector usually sit in one array and in
@@ -747,49 +749,74 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(const RunArgs *__re
     }
 }
 
-constexpr uint32_t kPeel = 6144;       // positions per peel
-constexpr uint32_t kPeelHashBits = 13; // 8192 chains of u16 heads, load factor <= 0.75
+constexpr uint32_t kPeel = 6144;        // positions per peel while the array is in HBM/L2
+constexpr uint32_t kPeelHashBits = 13;  // 8192 chains of u16 heads, load factor <= 0.75
+constexpr uint32_t kPeelRes = 6144;     // positions per peel once the array is in LDS
+constexpr uint32_t kPeelResHashBits = 13;
 constexpr uint32_t kPeelTierMax = 1u << 20;
-__host__ __device__ constexpr int peel_threads(uint32_t eb) { return eb == 4 ? 512 : 1024; }
+constexpr int kPeelThreads = 1024;
+// One dynamic LDS buffer per workgroup (one workgroup per CU): the peel
+// state, or the resident rest of the array followed by the state of the
+// smaller peels.
+constexpr uint32_t kPeelLdsBytes = 160u * 1024u - 1024u;
 
+__host__ __device__ constexpr uint32_t peel_state_bytes(uint32_t peel, uint32_t hash_bits)
+{
+    return peel * (4u + 2u + 4u) + (2u << hash_bits); // qof, nxt, root, heads
+}
+// Positions that stay in LDS together with the state of their peels.
+__host__ __device__ constexpr uint32_t peel_resident_max(uint32_t eb)
+{
+    return (kPeelLdsBytes - peel_state_bytes(kPeelRes, kPeelResHashBits)) / eb / 4u * 4u;
+}
+static_assert(peel_state_bytes(kPeel, kPeelHashBits) <= kPeelLdsBytes, "peel state exceeds LDS");
+
+template <uint32_t HB>
 __device__ __forceinline__ uint32_t peel_hash(uint32_t q)
 {
-    return (q * 2654435761u) >> (32 - kPeelHashBits);
+    return (q * 2654435761u) >> (32 - HB);
 }
 
-struct PeelState {
-    const uint32_t *qof;   // target of the step at local position e (= p - i_end)
-    const uint16_t *nxt;   // next entry of the same hash chain
-    const uint16_t *table; // chain heads (local positions)
-    uint32_t i_end, H;
+template <uint32_t PEEL, uint32_t HB>
+struct PeelLds {
+    uint32_t *qof;   // target of the step at local position e (= p - i_end)
+    uint16_t *nxt;   // next entry of the same hash chain
+    uint32_t *root;  // head-chain parent, then chain end (local)
+    uint16_t *table; // chain heads (local positions), two per 32-bit word
+    __device__ explicit PeelLds(char *base)
+    {
+        qof = reinterpret_cast<uint32_t *>(base);
+        root = qof + PEEL;
+        nxt = reinterpret_cast<uint16_t *>(root + PEEL);
+        table = nxt + PEEL;
+    }
 };
 
 // One pass over the hash chain of q: the smallest step (global position)
 // of the peel above lo that targets q (kNone32 if none), and whether some
 // step below lo targets q.
-__device__ __forceinline__ uint32_t peel_query(const PeelState &ps, uint32_t q, uint32_t lo,
-                                               bool &below)
+template <uint32_t PEEL, uint32_t HB>
+__device__ __forceinline__ uint32_t peel_query(const PeelLds<PEEL, HB> &L, uint32_t i_end, uint32_t H,
+                                               uint32_t q, uint32_t lo, bool &below)
 {
     uint32_t above = kNone32;
     below = false;
-    uint32_t e = ps.table[peel_hash(q)];
-    for (uint32_t guard = 0; e != kNone16 && guard < ps.H; ++guard) {
-        if (ps.qof[e] == q) {
-            const uint32_t pg = ps.i_end + e;
+    uint32_t e = L.table[peel_hash<HB>(q)];
+    for (uint32_t guard = 0; e != kNone16 && guard < H; ++guard) {
+        if (L.qof[e] == q) {
+            const uint32_t pg = i_end + e;
             if (pg > lo && pg < above) above = pg;
             below |= pg < lo;
         }
-        e = ps.nxt[e];
+        e = L.nxt[e];
     }
     return above;
 }
 
-// Peel tier: one workgroup per shuffle, positions taken top-down in peels of
-// whole batches (at most kPeel positions); the array stays in HBM/L2. A
-// workgroup of peel_threads(eb) threads: 512 for 4-byte elements, whose
-// registers then allow two workgroups per CU (their LDS fits twice), 1024
-// for 8-byte elements, which would fit only one 512-thread workgroup. For a
-// peel [i_end, i_begin), with z the array after the peels above:
+// One peel: the whole batches from batch s_begin (at i_begin elements left)
+// that fit in PEEL positions, applied to z (the array after the peels
+// above, in HBM or in LDS); advances s_begin and i_begin. For the peel
+// [i_end, i_begin):
 //  - the head chain of a position x of the peel, x -> smallest step above x
 //    targeting x -> ..., ends at a position whose value is z at that
 //    position; root[] holds every chain's parent, then its end;
@@ -798,157 +825,199 @@ __device__ __forceinline__ uint32_t peel_query(const PeelState &ps, uint32_t q, 
 //    targets q, else z[q];
 //  - a target q below the peel receives, from the smallest step that targets
 //    it, the value at root of that step.
-// Four waves per SIMD: two 512-thread workgroups share a CU (the ChaCha20
-// instantiation needs a small spill for it, cheaper than one per CU).
-template <typename Elem, bool W, int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_peel_batched(
-    const RunArgs *__restrict__ args, const uint32_t *items, DevSched sc)
+// Entered and left with every thread past a barrier.
+template <typename Elem, bool W, int BLOCK, uint32_t PEEL, uint32_t HB, typename ZP>
+__device__ __forceinline__ void peel_round(ZP z, const PeelLds<PEEL, HB> &L, const SegTable &st,
+                                           const StreamKey &key, uint32_t &s_begin,
+                                           uint32_t &i_begin, uint32_t &next_s, uint32_t &next_i)
 {
-    const RunArgs A = *args;
-    Elem *data = static_cast<Elem *>(A.data);
-    const uint64_t *offsets = A.offsets;
-    const uint64_t seed = A.seed, inst_base = A.inst;
-    constexpr uint32_t PEEL = kPeel;
     constexpr int P = (PEEL + BLOCK - 1) / BLOCK;
-    __shared__ uint32_t qof[kPeel];
-    __shared__ uint16_t nxt[kPeel];
-    __shared__ uint32_t root[kPeel]; // head-chain parent, then chain end (local)
-    __shared__ uint16_t table[1u << kPeelHashBits]; // two heads per 32-bit word
+    const uint32_t tid = threadIdx.x;
+    const uint32_t src_words = W ? st.words : BRR_WORDS_PHILOX64;
+    if (tid == 0) { // whole batches, at most PEEL positions, a segment at a time
+        uint32_t s = s_begin, i = i_begin, g = 0;
+        while (g + 1 < st.nseg && s >= st.seg[g + 1].s0) ++g;
+        for (; g < st.nseg && s < st.S; ++g) {
+            const Seg &sg = st.seg[g];
+            const uint32_t left = sg.s0 + sg.cnt - s;
+            uint32_t nb = (PEEL - (i_begin - i)) / sg.k;
+            if (nb > left) nb = left;
+            s += nb;
+            i -= nb * sg.k;
+            if (nb < left) break;
+        }
+        next_s = s;
+        next_i = i;
+    }
+    for (uint32_t x = tid; x < (1u << HB); x += BLOCK) L.table[x] = kNone16;
+    for (uint32_t x = tid; x < PEEL; x += BLOCK) L.root[x] = kNone32;
+    __syncthreads();
+    const uint32_t s_end = next_s, i_end = next_i, H = i_begin - i_end;
+    for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += BLOCK) {
+        uint64_t w[2];
+        first_pair(src_words, m, key, w[0], w[1]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t s = 2 * m + h;
+            if (s < s_begin || s >= s_end) continue;
+            uint32_t i, k, f;
+            uint64_t u;
+            batch_at(s, st.seg, st.nseg, i, k, u, f);
+            uint64_t r = batch_state(src_words, f, i, k, u, w[h], st.S, s, key);
+            for (uint32_t l = 0; l < k; ++l)
+                L.qof[i - 1 - l - i_end] = next_die(src_words, f, i - l, r);
+        }
+    }
+    __syncthreads();
+    // hash chains of the steps that move an element; the head-chain parent
+    // of a peel position (its smallest step above that targets it) by
+    // atomic minimum
+    for (uint32_t e = tid; e < H; e += BLOCK) {
+        const uint32_t q = L.qof[e];
+        if (q != i_end + e) {
+            // push e on its chain: a compare-and-swap on the word holding
+            // the chain's 16-bit head (each round lets one contender in)
+            const uint32_t bkt = peel_hash<HB>(q), sh = (bkt & 1u) * 16u;
+            uint32_t *word = reinterpret_cast<uint32_t *>(L.table) + (bkt >> 1);
+            uint32_t cur = *word, seen;
+            do {
+                seen = cur;
+                cur = atomicCAS(word, seen, (seen & ~(0xFFFFu << sh)) | (e << sh));
+            } while (cur != seen);
+            L.nxt[e] = (uint16_t)(seen >> sh);
+            if (q >= i_end) atomicMin(&L.root[q - i_end], e);
+        }
+    }
+    __syncthreads();
+    // to the end of each chain (a position without a parent keeps kNone32);
+    // links only ever move up the same chain, so reading a link another
+    // thread has already advanced is harmless
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const uint32_t e = tid + r * BLOCK;
+        if (e >= H) continue;
+        uint32_t x = e;
+        for (uint32_t guard = 0; guard < H; ++guard) {
+            const uint32_t y = L.root[x];
+            if (y == kNone32) break;
+            x = y;
+        }
+        if (x != e) L.root[e] = x;
+    }
+    __syncthreads();
+    // sources from LDS; each gather is issued as soon as its source is
+    // known, so it is in flight while the next position is worked out
+    uint32_t ext_q[P];
+    uint32_t ext_mask = 0;
+    Elem val[P], ext_val[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const uint32_t e = tid + r * BLOCK;
+        if (e >= H) continue;
+        const uint32_t p = i_end + e, q = L.qof[e];
+        const uint32_t re = L.root[e];
+        const uint32_t own = i_end + (re == kNone32 ? e : re);
+        uint32_t src;
+        if (q == p) {
+            src = own;
+        } else {
+            bool below;
+            const uint32_t succ = peel_query(L, i_end, H, q, p, below);
+            if (succ == kNone32) {
+                src = q;
+            } else {
+                const uint32_t rs = L.root[succ - i_end];
+                src = i_end + (rs == kNone32 ? succ - i_end : rs);
+            }
+            if (q < i_end && !below) {
+                ext_mask |= 1u << r;
+                ext_q[r] = q;
+                ext_val[r] = z[own];
+            }
+        }
+        val[r] = z[src];
+    }
+    // Every read of z precedes every write. Only this workgroup touches its
+    // array, with plain loads and stores; its wavefronts share the CU's
+    // vector cache, so workgroup-scope ordering suffices.
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const uint32_t e = tid + r * BLOCK;
+        if (e >= H) continue;
+        z[i_end + e] = val[r];
+        if (ext_mask & (1u << r)) z[ext_q[r]] = ext_val[r];
+    }
+    // The next peel reads z only after the barrier that follows its bounds
+    // and table clearing, which orders these writes before its gathers; it
+    // writes the state only after this peel's last state read, which
+    // precedes the barrier above.
+    s_begin = s_end;
+    i_begin = i_end;
+}
+
+// Peel tier: one workgroup of kPeelThreads per shuffle (one per CU, it
+// takes the whole LDS), positions taken top-down in peels of whole batches.
+// While more than peel_resident_max(eb) positions are left, the peels read
+// and write the array in HBM/L2, one random gather per position; the rest
+// of the array then moves into LDS (one coalesced read), the remaining
+// peels run there on smaller peel state, and it goes back in one coalesced
+// write. Arrays up to that size never leave LDS between load and store.
+template <typename Elem, bool W, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_peel_batched(const RunArgs *__restrict__ args,
+                                                        const uint32_t *items, DevSched sc)
+{
+    extern __shared__ __align__(16) char smem[];
     __shared__ SegTable st;
     __shared__ uint32_t next_s, next_i;
+    const RunArgs A = *args;
+    global_t<Elem> *data = as_global(static_cast<Elem *>(A.data));
+    const global_t<const uint64_t> *offsets = as_global(A.offsets);
     const uint32_t tid = threadIdx.x;
     const uint32_t q_item = items[blockIdx.x];
     const uint64_t off = offsets[q_item];
     const uint32_t n = (uint32_t)(offsets[q_item + 1] - off);
     if (n <= 1) return;
-    Elem *z = data + off;
-    const StreamKey key = make_key(seed, inst_base + q_item);
+    global_t<Elem> *z = data + off;
+    const StreamKey key = make_key(A.seed, A.inst + q_item);
     if (tid == 0) build_segments(n, n - 1, sc, st);
     __syncthreads();
+    constexpr uint32_t R = peel_resident_max(sizeof(Elem));
     uint32_t s_begin = 0, i_begin = n;
-    while (s_begin < st.S) {
-        if (tid == 0) { // whole batches, at most PEEL positions, a segment at a time
-            uint32_t s = s_begin, i = i_begin, g = 0;
-            while (g + 1 < st.nseg && s >= st.seg[g + 1].s0) ++g;
-            for (; g < st.nseg && s < st.S; ++g) {
-                const Seg &sg = st.seg[g];
-                const uint32_t left = sg.s0 + sg.cnt - s;
-                uint32_t nb = (PEEL - (i_begin - i)) / sg.k;
-                if (nb > left) nb = left;
-                s += nb;
-                i -= nb * sg.k;
-                if (nb < left) break;
-            }
-            next_s = s;
-            next_i = i;
-        }
-        for (uint32_t x = tid; x < (1u << kPeelHashBits); x += BLOCK) table[x] = kNone16;
-        for (uint32_t x = tid; x < PEEL; x += BLOCK) root[x] = kNone32;
-        __syncthreads();
-        const uint32_t s_end = next_s, i_end = next_i, H = i_begin - i_end;
-        for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += BLOCK) {
-            uint64_t w[2];
-            first_pair((W ? st.words : BRR_WORDS_PHILOX64), m, key, w[0], w[1]);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const uint32_t s = 2 * m + h;
-                if (s < s_begin || s >= s_end) continue;
-                uint32_t i, k, f;
-                uint64_t u;
-                batch_at(s, st.seg, st.nseg, i, k, u, f);
-                uint64_t r = batch_state((W ? st.words : BRR_WORDS_PHILOX64), f, i, k, u, w[h], st.S, s, key);
-                for (uint32_t l = 0; l < k; ++l)
-                    qof[i - 1 - l - i_end] = next_die((W ? st.words : BRR_WORDS_PHILOX64), f, i - l, r);
-            }
-        }
-        __syncthreads();
-        // hash chains of the steps that move an element; the head-chain parent
-        // of a peel position (its smallest step above that targets it) by
-        // atomic minimum
-        for (uint32_t e = tid; e < H; e += BLOCK) {
-            const uint32_t q = qof[e];
-            if (q != i_end + e) {
-                // push e on its chain: a compare-and-swap on the word holding
-                // the chain's 16-bit head (each round lets one contender in)
-                const uint32_t bkt = peel_hash(q), sh = (bkt & 1u) * 16u;
-                uint32_t *word = reinterpret_cast<uint32_t *>(table) + (bkt >> 1);
-                uint32_t cur = *word, seen;
-                do {
-                    seen = cur;
-                    cur = atomicCAS(word, seen, (seen & ~(0xFFFFu << sh)) | (e << sh));
-                } while (cur != seen);
-                nxt[e] = (uint16_t)(seen >> sh);
-                if (q >= i_end) atomicMin(&root[q - i_end], e);
-            }
-        }
-        __syncthreads();
-        const PeelState ps{qof, nxt, table, i_end, H};
-        // to the end of each chain (a position without a parent keeps
-        // kNone32); links only ever move up the same chain, so reading a link
-        // another thread has already advanced is harmless
-#pragma unroll
-        for (int r = 0; r < P; ++r) {
-            const uint32_t e = tid + r * BLOCK;
-            if (e >= H) continue;
-            uint32_t x = e;
-            for (uint32_t guard = 0; guard < H; ++guard) {
-                const uint32_t y = root[x];
-                if (y == kNone32) break;
-                x = y;
-            }
-            if (x != e) root[e] = x;
-        }
-        __syncthreads();
-        // sources from LDS; each gather is issued as soon as its source is
-        // known, so it is in flight while the next position is worked out
-        uint32_t ext_q[P];
-        uint32_t ext_mask = 0;
-        Elem val[P], ext_val[P];
-#pragma unroll
-        for (int r = 0; r < P; ++r) {
-            const uint32_t e = tid + r * BLOCK;
-            if (e >= H) continue;
-            const uint32_t p = i_end + e, q = qof[e];
-            const uint32_t re = root[e];
-            const uint32_t own = i_end + (re == kNone32 ? e : re);
-            uint32_t src;
-            if (q == p) {
-                src = own;
-            } else {
-                bool below;
-                const uint32_t succ = peel_query(ps, q, p, below);
-                if (succ == kNone32) {
-                    src = q;
-                } else {
-                    const uint32_t rs = root[succ - i_end];
-                    src = i_end + (rs == kNone32 ? succ - i_end : rs);
-                }
-                if (q < i_end && !below) {
-                    ext_mask |= 1u << r;
-                    ext_q[r] = q;
-                    ext_val[r] = z[own];
-                }
-            }
-            val[r] = z[src];
-        }
-        // Every read of z precedes every write. Only this workgroup touches
-        // its array, with plain loads and stores; its wavefronts share the
-        // CU's vector cache, so workgroup-scope ordering suffices.
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < P; ++r) {
-            const uint32_t e = tid + r * BLOCK;
-            if (e >= H) continue;
-            z[i_end + e] = val[r];
-            if (ext_mask & (1u << r)) z[ext_q[r]] = ext_val[r];
-        }
-        // The next peel reads z only after several barriers (the first one
-        // follows its bounds and table clearing), which order these writes
-        // before its gathers; it writes LDS only after this peel's last LDS
-        // read, which precedes the barrier above.
-        s_begin = s_end;
-        i_begin = i_end;
+    {
+        const PeelLds<kPeel, kPeelHashBits> L(smem);
+        while (s_begin < st.S && i_begin > R)
+            peel_round<Elem, W, BLOCK>(z, L, st, key, s_begin, i_begin, next_s, next_i);
     }
+    if (s_begin >= st.S) return;
+    // The rest of the array, positions below i_begin, into LDS, after the
+    // last peel's writes to z (the barrier orders them before these reads;
+    // that peel's state reads all precede its last barrier).
+    __syncthreads();
+    const uint32_t nres = i_begin;
+    Elem *zl = reinterpret_cast<Elem *>(smem);
+    constexpr int U = 8;
+    for (uint32_t x0 = 0; x0 < nres; x0 += U * BLOCK) {
+        Elem v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t x = x0 + u * BLOCK + tid;
+            if (x < nres) v[u] = z[x];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t x = x0 + u * BLOCK + tid;
+            if (x < nres) zl[x] = v[u];
+        }
+    }
+    __syncthreads();
+    {
+        const PeelLds<kPeelRes, kPeelResHashBits> L(smem + R * sizeof(Elem));
+        while (s_begin < st.S)
+            peel_round<Elem, W, BLOCK>(zl, L, st, key, s_begin, i_begin, next_s, next_i);
+    }
+    __syncthreads();
+    for (uint32_t x = tid; x < nres; x += BLOCK) z[x] = zl[x];
 }
 
 // ---------------------------------------------------------------------------
@@ -1107,9 +1176,10 @@ __device__ __forceinline__ uint64_t problem_inst_base(const GProblem &P)
 {
     return (P.dyn ? P.dyn->inst : P.inst_base) + (P.claim.slot ? *P.claim.slot : 0);
 }
-template <typename Elem> __device__ __forceinline__ Elem *problem_data(const GProblem &P, Elem *data)
+template <typename Elem>
+__device__ __forceinline__ global_t<Elem> *problem_data(const GProblem &P, Elem *data)
 {
-    return P.dyn ? static_cast<Elem *>(P.dyn->data) : data;
+    return as_global(P.dyn ? static_cast<Elem *>(P.dyn->data) : data);
 }
 
 // Item that owns index x: the tile table names the owner of the tile's
@@ -1543,7 +1613,7 @@ __global__ __launch_bounds__(256) void k_g_walk(GProblem P, GArrays g)
 template <typename Elem>
 __global__ __launch_bounds__(256) void k_g_place(GProblem P, GArrays g, const Elem *data_arg)
 {
-    const Elem *data = problem_data(P, data_arg);
+    const global_t<const Elem> *data = problem_data(P, data_arg);
     Elem *tmp = static_cast<Elem *>(g.tmp);
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
          x += (uint64_t)gridDim.x * blockDim.x) {
@@ -1555,7 +1625,7 @@ __global__ __launch_bounds__(256) void k_g_place(GProblem P, GArrays g, const El
 template <typename Elem>
 __global__ __launch_bounds__(256) void k_gp_copy(GProblem P, GArrays g, Elem *data_arg)
 {
-    Elem *data = problem_data(P, data_arg);
+    global_t<Elem> *data = problem_data(P, data_arg);
     const Elem *tmp = static_cast<const Elem *>(g.tmp);
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < P.npos;
          x += (uint64_t)gridDim.x * blockDim.x) {
@@ -1901,8 +1971,7 @@ hipError_t batched_peel_t(const RunArgs *b, const uint32_t *items, uint32_t nite
                           const DevSched &sc, hipStream_t stream)
 {
     if (nitems == 0) return hipSuccess;
-    constexpr int B = peel_threads(sizeof(Elem));
-    k_peel_batched<Elem, W, B><<<nitems, B, 0, stream>>>(b, items, sc);
+    k_peel_batched<Elem, W, kPeelThreads><<<nitems, kPeelThreads, kPeelLdsBytes, stream>>>(b, items, sc);
     return hipGetLastError();
 }
 
@@ -1985,7 +2054,12 @@ hipError_t prepare_shuffle_kernels()
         {(const void *)k_lds_requests<uint64_t, 512, 16, W>, c3},                          \
         {(const void *)k_lds_requests<uint32_t, kWgThreads, kWgP, W>, wg},                 \
         {(const void *)k_lds_requests<uint64_t, kWgThreads, kWgP, W>, wg}
-    const Attr attrs[] = {BRR_LDS_ATTRS(false), BRR_LDS_ATTRS(true)};
+    const int pl = (int)kPeelLdsBytes;
+    const Attr attrs[] = {BRR_LDS_ATTRS(false), BRR_LDS_ATTRS(true),
+                          {(const void *)k_peel_batched<uint32_t, false, kPeelThreads>, pl},
+                          {(const void *)k_peel_batched<uint64_t, false, kPeelThreads>, pl},
+                          {(const void *)k_peel_batched<uint32_t, true, kPeelThreads>, pl},
+                          {(const void *)k_peel_batched<uint64_t, true, kPeelThreads>, pl}};
 #undef BRR_LDS_ATTRS
     for (const Attr &a : attrs) {
         const hipError_t e =
