@@ -749,10 +749,10 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(const RunArgs *__re
     }
 }
 
-constexpr uint32_t kPeel = 6144;        // positions per peel while the array is in HBM/L2
-constexpr uint32_t kPeelHashBits = 13;  // 8192 chains of u16 heads, load factor <= 0.75
-constexpr uint32_t kPeelRes = 6144;     // positions per peel once the array is in LDS
-constexpr uint32_t kPeelResHashBits = 13;
+constexpr uint32_t kPeel = 6144;       // positions per peel while the array is in HBM/L2
+constexpr uint32_t kPeelHashBits = 13; // 8192 hash chains, load factor <= 0.75
+constexpr uint32_t kPeelRes = 4096;    // positions per peel once the array is in LDS
+constexpr uint32_t kPeelResHashBits = 12;
 constexpr uint32_t kPeelTierMax = 1u << 20;
 constexpr int kPeelThreads = 1024;
 // One dynamic LDS buffer per workgroup (one workgroup per CU): the peel
@@ -762,7 +762,7 @@ constexpr uint32_t kPeelLdsBytes = 160u * 1024u - 1024u;
 
 __host__ __device__ constexpr uint32_t peel_state_bytes(uint32_t peel, uint32_t hash_bits)
 {
-    return peel * (4u + 2u + 4u) + (2u << hash_bits); // qof, nxt, root, heads
+    return peel * (4u + 2u + 4u) + (4u << hash_bits); // qof, nxt, root, heads
 }
 // Positions that stay in LDS together with the state of their peels.
 __host__ __device__ constexpr uint32_t peel_resident_max(uint32_t eb)
@@ -777,183 +777,181 @@ __device__ __forceinline__ uint32_t peel_hash(uint32_t q)
     return (q * 2654435761u) >> (32 - HB);
 }
 
+// Peel state. Chain heads and head-chain parents carry the round that wrote
+// them in their upper 16 bits, so a round never clears what an earlier one
+// left: an entry of another round reads as empty.
+//  table[b]: round << 16 | the last local position pushed on chain b
+//  root[x]:  round << 16 | (0xFFFF - e), e the smallest step above x that
+//            targets x (kept by atomic maximum)
 template <uint32_t PEEL, uint32_t HB>
 struct PeelLds {
     uint32_t *qof;   // target of the step at local position e (= p - i_end)
+    uint32_t *root;
+    uint32_t *table;
     uint16_t *nxt;   // next entry of the same hash chain
-    uint32_t *root;  // head-chain parent, then chain end (local)
-    uint16_t *table; // chain heads (local positions), two per 32-bit word
     __device__ explicit PeelLds(char *base)
     {
         qof = reinterpret_cast<uint32_t *>(base);
         root = qof + PEEL;
-        nxt = reinterpret_cast<uint16_t *>(root + PEEL);
-        table = nxt + PEEL;
+        table = root + PEEL;
+        nxt = reinterpret_cast<uint16_t *>(table + (1u << HB));
+    }
+    // every entry empty (rounds count from 1)
+    __device__ void clear(int block) const
+    {
+        for (uint32_t x = threadIdx.x; x < PEEL; x += block) root[x] = 0;
+        for (uint32_t x = threadIdx.x; x < (1u << HB); x += block) table[x] = 0;
     }
 };
 
-// One pass over the hash chain of q: the smallest step (global position)
-// of the peel above lo that targets q (kNone32 if none), and whether some
-// step below lo targets q.
-template <uint32_t PEEL, uint32_t HB>
-__device__ __forceinline__ uint32_t peel_query(const PeelLds<PEEL, HB> &L, uint32_t i_end, uint32_t H,
-                                               uint32_t q, uint32_t lo, bool &below)
+// Bounds of the peel that starts at batch s (i elements left): whole
+// batches, at most PEEL positions, a segment at a time.
+template <uint32_t PEEL>
+__device__ inline void peel_bounds(const SegTable &st, uint32_t s, uint32_t i, uint32_t &s_end,
+                                   uint32_t &i_end)
 {
-    uint32_t above = kNone32;
-    below = false;
-    uint32_t e = L.table[peel_hash<HB>(q)];
-    for (uint32_t guard = 0; e != kNone16 && guard < H; ++guard) {
-        if (L.qof[e] == q) {
-            const uint32_t pg = i_end + e;
-            if (pg > lo && pg < above) above = pg;
-            below |= pg < lo;
-        }
-        e = L.nxt[e];
+    const uint32_t i0 = i;
+    uint32_t g = 0;
+    while (g + 1 < st.nseg && s >= st.seg[g + 1].s0) ++g;
+    for (; g < st.nseg && s < st.S; ++g) {
+        const Seg &sg = st.seg[g];
+        const uint32_t left = sg.s0 + sg.cnt - s;
+        uint32_t nb = (PEEL - (i0 - i)) / sg.k;
+        if (nb > left) nb = left;
+        s += nb;
+        i -= nb * sg.k;
+        if (nb < left) break;
     }
-    return above;
+    s_end = s;
+    i_end = i;
 }
 
-// One peel: the whole batches from batch s_begin (at i_begin elements left)
-// that fit in PEEL positions, applied to z (the array after the peels
-// above, in HBM or in LDS); advances s_begin and i_begin. For the peel
-// [i_end, i_begin):
-//  - the head chain of a position x of the peel, x -> smallest step above x
-//    targeting x -> ..., ends at a position whose value is z at that
-//    position; root[] holds every chain's parent, then its end;
-//  - step p with target q: the final value at p is the value at root(p) if
-//    q = p, else at root(succ) where succ is the next step above p that
-//    targets q, else z[q];
-//  - a target q below the peel receives, from the smallest step that targets
-//    it, the value at root of that step.
-// Entered and left with every thread past a barrier.
+// A peel run over z (the array in HBM or in LDS), from batch s_begin at
+// i_begin elements left, while batches remain and (until_le) more than
+// until_le elements are left; returns with s_begin/i_begin advanced, every
+// write done and every thread past a barrier.
+//
+// Each peel [i_end, i_begin) takes two phases:
+//  A: roll its dice; push every moving step on the hash chain of its target
+//     and offer it as head-chain parent of its target (if in the peel);
+//     meanwhile write the previous peel's results;
+//  B: for each step p with target q, the value that ends at p: the value at
+//     the end of p's head chain if q = p (x -> smallest step above x that
+//     targets x -> ...; the chain's end holds its value unmoved), else the
+//     value at the chain end of the next step above p that targets q, else
+//     z[q]; a target q below the peel receives, from the smallest step that
+//     targets it, the value at that step's chain end.
+// A barrier follows each phase; the next peel's phase A writes this one's
+// results, which phase B holds in registers.
 template <typename Elem, bool W, int BLOCK, uint32_t PEEL, uint32_t HB, typename ZP>
-__device__ __forceinline__ void peel_round(ZP z, const PeelLds<PEEL, HB> &L, const SegTable &st,
-                                           const StreamKey &key, uint32_t &s_begin,
-                                           uint32_t &i_begin, uint32_t &next_s, uint32_t &next_i)
+__device__ __forceinline__ void peel_run(ZP z, const PeelLds<PEEL, HB> &L, const SegTable &st,
+                                         const StreamKey &key, uint32_t &s_begin, uint32_t &i_begin,
+                                         uint32_t until_le, uint32_t (&next)[2][2])
 {
     constexpr int P = (PEEL + BLOCK - 1) / BLOCK;
     const uint32_t tid = threadIdx.x;
     const uint32_t src_words = W ? st.words : BRR_WORDS_PHILOX64;
-    if (tid == 0) { // whole batches, at most PEEL positions, a segment at a time
-        uint32_t s = s_begin, i = i_begin, g = 0;
-        while (g + 1 < st.nseg && s >= st.seg[g + 1].s0) ++g;
-        for (; g < st.nseg && s < st.S; ++g) {
-            const Seg &sg = st.seg[g];
-            const uint32_t left = sg.s0 + sg.cnt - s;
-            uint32_t nb = (PEEL - (i_begin - i)) / sg.k;
-            if (nb > left) nb = left;
-            s += nb;
-            i -= nb * sg.k;
-            if (nb < left) break;
-        }
-        next_s = s;
-        next_i = i;
-    }
-    for (uint32_t x = tid; x < (1u << HB); x += BLOCK) L.table[x] = kNone16;
-    for (uint32_t x = tid; x < PEEL; x += BLOCK) L.root[x] = kNone32;
+    if (tid == 0) peel_bounds<PEEL>(st, s_begin, i_begin, next[0][0], next[0][1]);
     __syncthreads();
-    const uint32_t s_end = next_s, i_end = next_i, H = i_begin - i_end;
-    for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += BLOCK) {
-        uint64_t w[2];
-        first_pair(src_words, m, key, w[0], w[1]);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const uint32_t s = 2 * m + h;
-            if (s < s_begin || s >= s_end) continue;
-            uint32_t i, k, f;
-            uint64_t u;
-            batch_at(s, st.seg, st.nseg, i, k, u, f);
-            uint64_t r = batch_state(src_words, f, i, k, u, w[h], st.S, s, key);
-            for (uint32_t l = 0; l < k; ++l)
-                L.qof[i - 1 - l - i_end] = next_die(src_words, f, i - l, r);
-        }
-    }
-    __syncthreads();
-    // hash chains of the steps that move an element; the head-chain parent
-    // of a peel position (its smallest step above that targets it) by
-    // atomic minimum
-    for (uint32_t e = tid; e < H; e += BLOCK) {
-        const uint32_t q = L.qof[e];
-        if (q != i_end + e) {
-            // push e on its chain: a compare-and-swap on the word holding
-            // the chain's 16-bit head (each round lets one contender in)
-            const uint32_t bkt = peel_hash<HB>(q), sh = (bkt & 1u) * 16u;
-            uint32_t *word = reinterpret_cast<uint32_t *>(L.table) + (bkt >> 1);
-            uint32_t cur = *word, seen;
-            do {
-                seen = cur;
-                cur = atomicCAS(word, seen, (seen & ~(0xFFFFu << sh)) | (e << sh));
-            } while (cur != seen);
-            L.nxt[e] = (uint16_t)(seen >> sh);
-            if (q >= i_end) atomicMin(&L.root[q - i_end], e);
-        }
-    }
-    __syncthreads();
-    // to the end of each chain (a position without a parent keeps kNone32);
-    // links only ever move up the same chain, so reading a link another
-    // thread has already advanced is harmless
-#pragma unroll
-    for (int r = 0; r < P; ++r) {
-        const uint32_t e = tid + r * BLOCK;
-        if (e >= H) continue;
-        uint32_t x = e;
-        for (uint32_t guard = 0; guard < H; ++guard) {
-            const uint32_t y = L.root[x];
-            if (y == kNone32) break;
-            x = y;
-        }
-        if (x != e) L.root[e] = x;
-    }
-    __syncthreads();
-    // sources from LDS; each gather is issued as soon as its source is
-    // known, so it is in flight while the next position is worked out
+    uint32_t s_end = next[0][0], i_end = next[0][1];
+    // results of the previous peel, written in the next phase A
+    uint32_t w_lo = 0, w_cnt = 0, ext_mask = 0;
     uint32_t ext_q[P];
-    uint32_t ext_mask = 0;
     Elem val[P], ext_val[P];
+    auto write_back = [&]() {
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-        const uint32_t e = tid + r * BLOCK;
-        if (e >= H) continue;
-        const uint32_t p = i_end + e, q = L.qof[e];
-        const uint32_t re = L.root[e];
-        const uint32_t own = i_end + (re == kNone32 ? e : re);
-        uint32_t src;
-        if (q == p) {
-            src = own;
-        } else {
-            bool below;
-            const uint32_t succ = peel_query(L, i_end, H, q, p, below);
-            if (succ == kNone32) {
-                src = q;
-            } else {
-                const uint32_t rs = L.root[succ - i_end];
-                src = i_end + (rs == kNone32 ? succ - i_end : rs);
-            }
-            if (q < i_end && !below) {
-                ext_mask |= 1u << r;
-                ext_q[r] = q;
-                ext_val[r] = z[own];
+        for (int r = 0; r < P; ++r) {
+            const uint32_t e = tid + r * BLOCK;
+            if (e >= w_cnt) continue;
+            z[w_lo + e] = val[r];
+            if (ext_mask & (1u << r)) z[ext_q[r]] = ext_val[r];
+        }
+    };
+    for (uint32_t round = 1; s_begin < s_end && i_begin > until_le; ++round) {
+        const uint32_t tag = round << 16, H = i_begin - i_end;
+        // phase A
+        if (tid == 0)
+            peel_bounds<PEEL>(st, s_end, i_end, next[round & 1][0], next[round & 1][1]);
+        write_back();
+        for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += BLOCK) {
+            uint64_t w[2];
+            first_pair(src_words, m, key, w[0], w[1]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t s = 2 * m + h;
+                if (s < s_begin || s >= s_end) continue;
+                uint32_t i, k, f;
+                uint64_t u;
+                batch_at(s, st.seg, st.nseg, i, k, u, f);
+                uint64_t r = batch_state(src_words, f, i, k, u, w[h], st.S, s, key);
+                for (uint32_t l = 0; l < k; ++l) {
+                    const uint32_t q = next_die(src_words, f, i - l, r);
+                    const uint32_t e = i - 1 - l - i_end;
+                    L.qof[e] = q;
+                    if (q == i - 1 - l) continue; // stays
+                    // push e on the chain of q: compare-and-swap on its head
+                    uint32_t *head = L.table + peel_hash<HB>(q);
+                    uint32_t cur = *head, seen;
+                    do {
+                        seen = cur;
+                        cur = atomicCAS(head, seen, tag | e);
+                    } while (cur != seen);
+                    L.nxt[e] = (seen & 0xFFFF0000u) == tag ? (uint16_t)seen : kNone16;
+                    if (q >= i_end) atomicMax(&L.root[q - i_end], tag | (0xFFFFu - e));
+                }
             }
         }
-        val[r] = z[src];
-    }
-    // Every read of z precedes every write. Only this workgroup touches its
-    // array, with plain loads and stores; its wavefronts share the CU's
-    // vector cache, so workgroup-scope ordering suffices.
-    __syncthreads();
+        __syncthreads();
+        // phase B
+        auto chain_end = [&](uint32_t x) {
+            for (uint32_t guard = 0; guard < H; ++guard) {
+                const uint32_t v = L.root[x];
+                if ((v & 0xFFFF0000u) != tag) break;
+                x = 0xFFFFu - (v & 0xFFFFu);
+            }
+            return x;
+        };
+        ext_mask = 0;
 #pragma unroll
-    for (int r = 0; r < P; ++r) {
-        const uint32_t e = tid + r * BLOCK;
-        if (e >= H) continue;
-        z[i_end + e] = val[r];
-        if (ext_mask & (1u << r)) z[ext_q[r]] = ext_val[r];
+        for (int r = 0; r < P; ++r) {
+            const uint32_t e = tid + r * BLOCK;
+            if (e >= H) continue;
+            const uint32_t p = i_end + e, q = L.qof[e];
+            const uint32_t own = i_end + chain_end(e);
+            uint32_t src = own;
+            if (q != p) {
+                // the chain of q: the smallest step above p that targets q,
+                // and whether a step below p targets q
+                uint32_t succ = kNone32;
+                bool below = false;
+                const uint32_t hv = L.table[peel_hash<HB>(q)];
+                uint32_t c = (hv & 0xFFFF0000u) == tag ? (hv & 0xFFFFu) : kNone16;
+                for (uint32_t guard = 0; c != kNone16 && guard < H; ++guard) {
+                    if (L.qof[c] == q) {
+                        if (c > e && c < succ) succ = c;
+                        below |= c < e;
+                    }
+                    c = L.nxt[c];
+                }
+                src = succ == kNone32 ? q : i_end + chain_end(succ);
+                if (q < i_end && !below) {
+                    ext_mask |= 1u << r;
+                    ext_q[r] = q;
+                    ext_val[r] = z[own];
+                }
+            }
+            val[r] = z[src];
+        }
+        w_lo = i_end;
+        w_cnt = H;
+        __syncthreads();
+        s_begin = s_end;
+        i_begin = i_end;
+        s_end = next[round & 1][0];
+        i_end = next[round & 1][1];
     }
-    // The next peel reads z only after the barrier that follows its bounds
-    // and table clearing, which orders these writes before its gathers; it
-    // writes the state only after this peel's last state read, which
-    // precedes the barrier above.
-    s_begin = s_end;
-    i_begin = i_end;
+    write_back();
+    __syncthreads();
 }
 
 // Peel tier: one workgroup of kPeelThreads per shuffle (one per CU, it
@@ -961,15 +959,15 @@ __device__ __forceinline__ void peel_round(ZP z, const PeelLds<PEEL, HB> &L, con
 // While more than peel_resident_max(eb) positions are left, the peels read
 // and write the array in HBM/L2, one random gather per position; the rest
 // of the array then moves into LDS (one coalesced read), the remaining
-// peels run there on smaller peel state, and it goes back in one coalesced
-// write. Arrays up to that size never leave LDS between load and store.
+// peels run there, and it goes back in one coalesced write. Arrays up to
+// that size never leave LDS between load and store.
 template <typename Elem, bool W, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_peel_batched(const RunArgs *__restrict__ args,
                                                         const uint32_t *items, DevSched sc)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ SegTable st;
-    __shared__ uint32_t next_s, next_i;
+    __shared__ uint32_t next[2][2];
     const RunArgs A = *args;
     global_t<Elem> *data = as_global(static_cast<Elem *>(A.data));
     const global_t<const uint64_t> *offsets = as_global(A.offsets);
@@ -980,22 +978,24 @@ __global__ __launch_bounds__(BLOCK) void k_peel_batched(const RunArgs *__restric
     if (n <= 1) return;
     global_t<Elem> *z = data + off;
     const StreamKey key = make_key(A.seed, A.inst + q_item);
-    if (tid == 0) build_segments(n, n - 1, sc, st);
-    __syncthreads();
     constexpr uint32_t R = peel_resident_max(sizeof(Elem));
-    uint32_t s_begin = 0, i_begin = n;
-    {
+    if (tid == 0) build_segments(n, n - 1, sc, st);
+    if (n > R) {
         const PeelLds<kPeel, kPeelHashBits> L(smem);
-        while (s_begin < st.S && i_begin > R)
-            peel_round<Elem, W, BLOCK>(z, L, st, key, s_begin, i_begin, next_s, next_i);
+        L.clear(BLOCK);
+    }
+    __syncthreads();
+    uint32_t s_begin = 0, i_begin = n;
+    if (n > R) {
+        const PeelLds<kPeel, kPeelHashBits> L(smem);
+        peel_run<Elem, W, BLOCK>(z, L, st, key, s_begin, i_begin, R, next);
     }
     if (s_begin >= st.S) return;
-    // The rest of the array, positions below i_begin, into LDS, after the
-    // last peel's writes to z (the barrier orders them before these reads;
-    // that peel's state reads all precede its last barrier).
-    __syncthreads();
+    // the rest of the array, positions below i_begin, into LDS (the peels
+    // above ended with their writes and a barrier)
     const uint32_t nres = i_begin;
     Elem *zl = reinterpret_cast<Elem *>(smem);
+    const PeelLds<kPeelRes, kPeelResHashBits> L(smem + R * sizeof(Elem));
     constexpr int U = 8;
     for (uint32_t x0 = 0; x0 < nres; x0 += U * BLOCK) {
         Elem v[U];
@@ -1010,13 +1010,9 @@ __global__ __launch_bounds__(BLOCK) void k_peel_batched(const RunArgs *__restric
             if (x < nres) zl[x] = v[u];
         }
     }
+    L.clear(BLOCK);
     __syncthreads();
-    {
-        const PeelLds<kPeelRes, kPeelResHashBits> L(smem + R * sizeof(Elem));
-        while (s_begin < st.S)
-            peel_round<Elem, W, BLOCK>(zl, L, st, key, s_begin, i_begin, next_s, next_i);
-    }
-    __syncthreads();
+    peel_run<Elem, W, BLOCK>(zl, L, st, key, s_begin, i_begin, 0, next);
     for (uint32_t x = tid; x < nres; x += BLOCK) z[x] = zl[x];
 }
 
