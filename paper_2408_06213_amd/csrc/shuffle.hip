@@ -752,7 +752,7 @@ __global__ __launch_bounds__(kLaneItems) void k_lane_batched(const RunArgs *__re
 constexpr uint32_t kPeel = 6144;       // positions per peel while the array is in HBM/L2
 constexpr uint32_t kPeelHashBits = 13; // 8192 hash chains, load factor <= 0.75
 constexpr uint32_t kPeelRes = 4096;    // positions per peel once the array is in LDS
-constexpr uint32_t kPeelResHashBits = 12;
+constexpr uint32_t kPeelResHashBits = 13;
 constexpr uint32_t kPeelTierMax = 1u << 20;
 constexpr int kPeelThreads = 1024;
 // One dynamic LDS buffer per workgroup (one workgroup per CU): the peel
@@ -873,17 +873,16 @@ __device__ __forceinline__ void peel_run(ZP z, const PeelLds<PEEL, HB> &L, const
         if (tid == 0)
             peel_bounds<PEEL>(st, s_end, i_end, next[round & 1][0], next[round & 1][1]);
         write_back();
-        for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += BLOCK) {
+        // one batch per thread (the two batches of a word pair compute its
+        // block twice: more threads roll and push at once)
+        for (uint32_t s = s_begin + tid; s < s_end; s += BLOCK) {
             uint64_t w[2];
-            first_pair(src_words, m, key, w[0], w[1]);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const uint32_t s = 2 * m + h;
-                if (s < s_begin || s >= s_end) continue;
+            first_pair(src_words, s / 2, key, w[0], w[1]);
+            {
                 uint32_t i, k, f;
                 uint64_t u;
                 batch_at(s, st.seg, st.nseg, i, k, u, f);
-                uint64_t r = batch_state(src_words, f, i, k, u, w[h], st.S, s, key);
+                uint64_t r = batch_state(src_words, f, i, k, u, (s & 1u) ? w[1] : w[0], st.S, s, key);
                 for (uint32_t l = 0; l < k; ++l) {
                     const uint32_t q = next_die(src_words, f, i - l, r);
                     const uint32_t e = i - 1 - l - i_end;
