@@ -1464,11 +1464,18 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *keys, 
     }
 }
 
-// Radix sort, pass on the RB-bit digit at bit sh: the block sorts its tile
-// by the digit in LDS (stable splits on 2 bits at a time, the last on 1
-// when RB is odd), then writes each digit's run to its place: the scanned
-// count of that digit over all earlier digits and blocks, plus the rank
-// inside the tile's run.
+// Radix sort, pass on the RB-bit digit at bit sh: the block ranks its tile
+// by the digit in LDS, stably, then writes each digit's run to its place:
+// the scanned count of that digit over all earlier digits and blocks, plus
+// the rank inside the tile's run.
+// Ranking: wavefront w holds the tile's items w*512 + u*64 + lane (u < 8),
+// a contiguous eighth, so tile order is (w, u, lane). For each u in turn the
+// lanes holding the same digit are found with one ballot per digit bit; an
+// item's rank among its wavefront's items of that digit is the wavefront's
+// running count of the digit (a 16-bit LDS counter per wavefront and digit)
+// plus the same-digit lanes below it, and the lowest of them advances the
+// counter. The counters then become per-digit prefixes over the wavefronts,
+// and a block scan gives every digit's start in the tile.
 // IOTA: the pass's input values are their own indices (the first pass, whose
 // value for the key at index x is x), generated rather than read.
 template <uint32_t RB, bool IOTA>
@@ -1478,69 +1485,79 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
                                                              uint32_t sh, const uint32_t *hist,
                                                              uint32_t nblk)
 {
-    constexpr uint32_t NB = 1u << RB;
-    // tile index i lives at i + i/8: a thread's consecutive items then fall
-    // in distinct banks
+    constexpr uint32_t NB = 1u << RB, NW = kSortThreads / 64;
+    constexpr uint32_t DPT = (NB + kSortThreads - 1) / kSortThreads; // digits per thread
+    constexpr uint32_t WI = 64 * kSortItems;                         // items per wavefront
+    static_assert(kSortTile <= 0xFFFFu, "16-bit digit counters");
+    // tile index i lives at i + i/8 (sort_pad)
     __shared__ uint32_t sk[kSortTile + kSortTile / 8], sv[kSortTile + kSortTile / 8];
-    __shared__ uint32_t first[NB], dst[NB];
-    __shared__ uint64_t wsum[kSortThreads / 64];
-    const uint32_t tid = threadIdx.x, tile = xcd_tile(blockIdx.x, nblk);
+    __shared__ uint16_t wcnt[NW][NB];
+    __shared__ uint32_t dstart[NB], dst[NB];
+    __shared__ uint64_t wsum[NW];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t tile = xcd_tile(blockIdx.x, nblk);
     const uint64_t base = (uint64_t)tile * kSortTile;
     const uint32_t valid = (uint32_t)min<uint64_t>(kSortTile, n - base);
+    for (uint32_t d = lane; d < NB; d += 64) wcnt[w][d] = 0; // own row, used only by this wave
+    for (uint32_t d = tid; d < NB; d += kSortThreads) dst[d] = hist[(uint64_t)d * nblk + tile];
+    uint32_t k[kSortItems], v[kSortItems], r[kSortItems];
 #pragma unroll
     for (uint32_t u = 0; u < kSortItems; ++u) { // coalesced; padding sorts last
-        const uint32_t i = u * kSortThreads + tid;
-        sk[sort_pad(i)] = (i < valid) ? kin[base + i] : kSortNone;
-        sv[sort_pad(i)] = IOTA ? (uint32_t)(base + i) : ((i < valid) ? vin[base + i] : 0u);
+        const uint32_t i = w * WI + u * 64 + lane;
+        k[u] = (i < valid) ? kin[base + i] : kSortNone;
+        v[u] = IOTA ? (uint32_t)(base + i) : ((i < valid) ? vin[base + i] : 0u);
     }
-    for (uint32_t d = tid; d < NB; d += kSortThreads) dst[d] = hist[(uint64_t)d * nblk + tile];
-    __syncthreads();
-    uint32_t k[kSortItems], v[kSortItems];
-#pragma unroll
-    for (uint32_t u = 0; u < kSortItems; ++u) { // thread tid: consecutive tile items
-        k[u] = sk[sort_pad(tid * kSortItems + u)];
-        v[u] = sv[sort_pad(tid * kSortItems + u)];
-    }
-    __syncthreads();
-#pragma unroll
-    for (uint32_t r = 0; r < (RB + 1) / 2; ++r) {
-        const uint32_t b = sh + 2 * r;
-        const uint32_t mask = (2 * r + 1 < RB) ? 3u : 1u;
-        // per thread: running count of each split value in 16-bit fields
-        uint64_t run = 0;
-        uint32_t before[kSortItems];
-#pragma unroll
-        for (uint32_t u = 0; u < kSortItems; ++u) {
-            const uint32_t d = (k[u] >> b) & mask;
-            before[u] = (uint32_t)(run >> (16 * d)) & 0xFFFFu;
-            run += 1ull << (16 * d);
-        }
-        uint64_t total;
-        const uint64_t excl = sort_block_scan(run, wsum, total);
-        const uint32_t t0 = (uint32_t)total & 0xFFFFu, t1 = (uint32_t)(total >> 16) & 0xFFFFu,
-                       t2 = (uint32_t)(total >> 32) & 0xFFFFu;
-        const uint32_t start[4] = {0, t0, t0 + t1, t0 + t1 + t2};
-#pragma unroll
-        for (uint32_t u = 0; u < kSortItems; ++u) {
-            const uint32_t d = (k[u] >> b) & mask;
-            const uint32_t pos = start[d] + ((uint32_t)(excl >> (16 * d)) & 0xFFFFu) + before[u];
-            sk[sort_pad(pos)] = k[u];
-            sv[sort_pad(pos)] = v[u];
-        }
-        __syncthreads();
-#pragma unroll
-        for (uint32_t u = 0; u < kSortItems; ++u) {
-            k[u] = sk[sort_pad(tid * kSortItems + u)];
-            v[u] = sv[sort_pad(tid * kSortItems + u)];
-        }
-        __syncthreads();
-    }
-    // the tile is now in LDS sorted by digit; first index of each digit's run
+    const uint64_t below_mask = (1ull << lane) - 1ull;
 #pragma unroll
     for (uint32_t u = 0; u < kSortItems; ++u) {
-        const uint32_t i = tid * kSortItems + u;
         const uint32_t d = sort_digit<RB>(k[u], sh);
-        if (i == 0 || sort_digit<RB>(sk[sort_pad(i - 1)], sh) != d) first[d] = i;
+        uint64_t same = ~0ull;
+#pragma unroll
+        for (uint32_t bit = 0; bit < RB; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const uint64_t bal = __ballot(on);
+            same &= on ? bal : ~bal;
+        }
+        const uint32_t below = (uint32_t)__builtin_popcountll(same & below_mask);
+        const uint32_t run = wcnt[w][d];
+        r[u] = run + below;
+        if (below == 0) wcnt[w][d] = (uint16_t)(run + (uint32_t)__builtin_popcountll(same));
+    }
+    __syncthreads();
+    // per digit: the wavefronts' counts become exclusive prefixes over the
+    // wavefronts; the digit's count in the tile
+    uint32_t tot[DPT];
+    uint64_t mine = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < DPT; ++j) {
+        const uint32_t d = tid * DPT + j;
+        uint32_t acc = 0;
+        if (d < NB) {
+#pragma unroll
+            for (uint32_t x = 0; x < NW; ++x) {
+                const uint32_t c = wcnt[x][d];
+                wcnt[x][d] = (uint16_t)acc;
+                acc += c;
+            }
+        }
+        tot[j] = acc;
+        mine += acc;
+    }
+    uint64_t all;
+    uint32_t start = (uint32_t)sort_block_scan(mine, wsum, all); // ends with a barrier
+#pragma unroll
+    for (uint32_t j = 0; j < DPT; ++j) {
+        const uint32_t d = tid * DPT + j;
+        if (d < NB) dstart[d] = start;
+        start += tot[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t u = 0; u < kSortItems; ++u) {
+        const uint32_t d = sort_digit<RB>(k[u], sh);
+        const uint32_t pos = dstart[d] + wcnt[w][d] + r[u];
+        sk[sort_pad(pos)] = k[u];
+        sv[sort_pad(pos)] = v[u];
     }
     __syncthreads();
 #pragma unroll
@@ -1548,7 +1565,7 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t *kin
         const uint32_t i = u * kSortThreads + tid;
         if (i < valid) {
             const uint32_t key = sk[sort_pad(i)], d = sort_digit<RB>(key, sh);
-            const uint32_t o = dst[d] + (i - first[d]);
+            const uint32_t o = dst[d] + (i - dstart[d]);
             kout[o] = key;
             vout[o] = sv[sort_pad(i)];
         }
