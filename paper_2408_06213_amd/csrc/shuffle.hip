@@ -1437,30 +1437,50 @@ __device__ __forceinline__ uint32_t sort_digit(uint32_t key, uint32_t sh)
 }
 
 // Radix sort, pass on the RB-bit digit at bit sh: digit counts of every
-// block's tile (one LDS histogram per wavefront, summed at the end).
+// tile. A block counts kHistTiles consecutive tiles, one after the other,
+// in one LDS histogram (atomic adds), with the keys of every tile loaded up
+// front so that they are in flight together; blocks take their tile groups
+// XCD by XCD, as the scatter blocks take their tiles.
+constexpr uint32_t kHistTiles = 4;
+__host__ __device__ inline uint32_t hist_blocks(uint32_t nblk)
+{
+    return (nblk + kHistTiles - 1) / kHistTiles;
+}
+
 template <uint32_t RB>
 __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t *keys, uint64_t n,
                                                           uint32_t sh, uint32_t *hist,
                                                           uint32_t nblk)
 {
-    constexpr uint32_t NB = 1u << RB, NW = kSortThreads / 64;
-    __shared__ uint32_t cnt[NW][NB];
-    for (uint32_t d = threadIdx.x; d < NW * NB; d += kSortThreads) (&cnt[0][0])[d] = 0;
-    __syncthreads();
-    uint32_t *mine = cnt[threadIdx.x >> 6];
-    const uint32_t tile = xcd_tile(blockIdx.x, nblk);
-    const uint64_t base = (uint64_t)tile * kSortTile;
+    constexpr uint32_t NB = 1u << RB;
+    __shared__ uint32_t cnt[NB];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t t0 = xcd_tile(blockIdx.x, hist_blocks(nblk)) * kHistTiles;
+    for (uint32_t d = tid; d < NB; d += kSortThreads) cnt[d] = 0;
+    uint32_t k[kHistTiles][kSortItems];
 #pragma unroll
-    for (uint32_t u = 0; u < kSortItems; ++u) {
-        const uint64_t i = base + u * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&mine[sort_digit<RB>(keys[i], sh)], 1u);
+    for (uint32_t t = 0; t < kHistTiles; ++t) {
+        const uint64_t base = (uint64_t)(t0 + t) * kSortTile;
+#pragma unroll
+        for (uint32_t u = 0; u < kSortItems; ++u) {
+            const uint64_t i = base + u * kSortThreads + tid;
+            k[t][u] = (t0 + t < nblk && i < n) ? keys[i] : 0u;
+        }
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < NB; d += kSortThreads) {
-        uint32_t c = 0;
 #pragma unroll
-        for (uint32_t w = 0; w < NW; ++w) c += cnt[w][d];
-        hist[(uint64_t)d * nblk + tile] = c;
+    for (uint32_t t = 0; t < kHistTiles; ++t) {
+        if (t0 + t >= nblk) break; // the same for the whole block
+        const uint64_t base = (uint64_t)(t0 + t) * kSortTile;
+#pragma unroll
+        for (uint32_t u = 0; u < kSortItems; ++u)
+            if (base + u * kSortThreads + tid < n) atomicAdd(&cnt[sort_digit<RB>(k[t][u], sh)], 1u);
+        __syncthreads();
+        for (uint32_t d = tid; d < NB; d += kSortThreads) {
+            hist[(uint64_t)d * nblk + t0 + t] = cnt[d];
+            cnt[d] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -1710,7 +1730,7 @@ template <uint32_t RB>
 void sort_pass(const GArrays &g, int cur, uint64_t npos, uint32_t sh, uint32_t nblk,
                hipStream_t stream)
 {
-    k_rs_hist<RB><<<nblk, kSortThreads, 0, stream>>>(g.key[cur], npos, sh, g.hist, nblk);
+    k_rs_hist<RB><<<hist_blocks(nblk), kSortThreads, 0, stream>>>(g.key[cur], npos, sh, g.hist, nblk);
     scan_exclusive(g.hist, g.tiles, ((uint64_t)1 << RB) * nblk, stream);
     if (sh == 0)
         k_rs_scatter<RB, true><<<nblk, kSortThreads, 0, stream>>>(
