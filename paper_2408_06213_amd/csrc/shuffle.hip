@@ -1667,6 +1667,21 @@ __global__ __launch_bounds__(256) void k_gp_copy(GProblem P, GArrays g, Elem *da
     }
 }
 
+// The copy pass of one in-place shuffle whose array starts 16-byte aligned
+// (as the placement buffer does): 16-byte vectors, then the tail.
+template <typename Elem>
+__global__ __launch_bounds__(256) void k_gp_copy_vec(Elem *data, const Elem *tmp, uint64_t n)
+{
+    constexpr uint32_t V = 16 / sizeof(Elem);
+    const uint64_t nv = n / V, stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(tmp);
+    global_t<u32x4> *dst = reinterpret_cast<global_t<u32x4> *>(as_global(data));
+    for (uint64_t x = t; x < nv; x += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + x), dst + x);
+    for (uint64_t x = nv * V + t; x < n; x += stride) as_global(data)[x] = tmp[x];
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_gp_scan_tiles(const uint32_t *a,
                                                                  uint32_t *tiles, uint64_t len)
 {
@@ -1740,6 +1755,22 @@ void sort_pass(const GArrays &g, int cur, uint64_t npos, uint32_t sh, uint32_t n
             g.key[cur], g.val[cur], g.key[cur ^ 1], g.val[cur ^ 1], npos, sh, g.hist, nblk);
 }
 
+// The copy pass: by 16-byte vectors for one in-place shuffle whose array is
+// aligned like the placement buffer, else element by element.
+template <typename Elem>
+void launch_copy(const GProblem &P, const GArrays &g, void *data, hipStream_t stream)
+{
+    Elem *z = static_cast<Elem *>(data) + P.one.data_off;
+    if (!P.items && !P.dyn && !P.one.out && (reinterpret_cast<uintptr_t>(z) & 15) == 0 &&
+        (reinterpret_cast<uintptr_t>(g.tmp) & 15) == 0) {
+        const uint64_t nv = P.npos / (16 / sizeof(Elem)) + 1;
+        k_gp_copy_vec<Elem><<<grid_for(nv, 256), 256, 0, stream>>>(z, static_cast<const Elem *>(g.tmp),
+                                                                   P.npos);
+        return;
+    }
+    k_gp_copy<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, static_cast<Elem *>(data));
+}
+
 template <typename Elem, bool W>
 hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratch,
                       hipStream_t stream)
@@ -1754,8 +1785,7 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
         k_g_walk<uint32_t><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g);
         k_g_place<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(
             P, g, static_cast<const Elem *>(data));
-        k_gp_copy<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,
-                                                                   static_cast<Elem *>(data));
+        launch_copy<Elem>(P, g, data, stream);
         return hipGetLastError();
     }
     k_gp_init<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, P.npos);
@@ -1784,7 +1814,7 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
     }
     k_g_place<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g,
                                                                static_cast<const Elem *>(data));
-    k_gp_copy<Elem><<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, static_cast<Elem *>(data));
+    launch_copy<Elem>(P, g, data, stream);
     return hipGetLastError();
 }
 
