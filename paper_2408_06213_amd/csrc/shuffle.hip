@@ -1208,8 +1208,17 @@ __device__ __forceinline__ uint32_t item_of_pos(const GProblem &P, uint64_t x)
 __global__ __launch_bounds__(256) void k_gp_init(GProblem P, GArrays g, uint64_t npos)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0 && P.claim.counter) (void)take_claim(P.claim);
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < npos;
-         x += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    if (!P.items) { // one item at position 0: 16-byte vectors (last[] is 256-byte aligned)
+        const u32x4 none = {kNone32, kNone32, kNone32, kNone32};
+        u32x4 *last4 = reinterpret_cast<u32x4 *>(g.last);
+        for (uint64_t x = t; x < npos / 4; x += stride) __builtin_nontemporal_store(none, last4 + x);
+        for (uint64_t x = npos / 4 * 4 + t; x < npos; x += stride) g.last[x] = kNone32;
+        for (uint64_t x = t; x < P.one.n - P.one.steps; x += stride) g.key[0][x] = kSortNone;
+        return;
+    }
+    for (uint64_t x = t; x < npos; x += stride) {
         g.last[x] = kNone32;
         const GItem &it = item_at(P, item_of_pos(P, x));
         if (x - it.pos_base < it.n - it.steps) g.key[0][x] = kSortNone;
