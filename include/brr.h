@@ -332,7 +332,8 @@ brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t c
 void brr_plan_destroy(brr_plan *plan);
 
 /* How many times the plan has captured its launch graph: 0 before its first
- * run with use_graph = 1, then 1 (the capture is never repeated). */
+ * run with use_graph = 1 (and always 0 for a plan launched as a single
+ * kernel, see brr_mapping), then 1 (the capture is never repeated). */
 uint32_t brr_plan_captures(const brr_plan *plan);
 
 /* Plan knobs for the size-class mapping; brr_plan_create uses defaults that
@@ -346,8 +347,11 @@ uint32_t brr_plan_captures(const brr_plan *plan);
  * classes up to wg_threads (256, 512 or 1024) threads; larger ones one per
  * workgroup in peels of whole batches (up to 2^20 elements), else
  * device-wide with device scratch. use_graph: 1 = capture the launch sequence once
- * and replay it as a hip graph. Every mapping gives the same output; an
- * out-of-range knob, or a call after the first run, is BRR_EINVAL. */
+ * and replay it as a hip graph (a plan whose arrays all fall in one class
+ * other than the device-wide one is a single kernel, which it launches
+ * directly either way: one kernel launch costs less than a graph launch).
+ * Every mapping gives the same output; an out-of-range knob, or a call
+ * after the first run, is BRR_EINVAL. */
 typedef struct {
     uint32_t lane_max;
     uint32_t wave_max;

