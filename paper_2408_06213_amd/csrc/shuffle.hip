@@ -873,31 +873,44 @@ __device__ __forceinline__ void peel_run(ZP z, const PeelLds<PEEL, HB> &L, const
         if (tid == 0)
             peel_bounds<PEEL>(st, s_end, i_end, next[round & 1][0], next[round & 1][1]);
         write_back();
-        // one batch per thread (the two batches of a word pair compute its
-        // block twice: more threads roll and push at once)
-        for (uint32_t s = s_begin + tid; s < s_end; s += BLOCK) {
-            uint64_t w[2];
-            first_pair(src_words, s / 2, key, w[0], w[1]);
-            {
-                uint32_t i, k, f;
-                uint64_t u;
-                batch_at(s, st.seg, st.nseg, i, k, u, f);
-                uint64_t r = batch_state(src_words, f, i, k, u, (s & 1u) ? w[1] : w[0], st.S, s, key);
-                for (uint32_t l = 0; l < k; ++l) {
-                    const uint32_t q = next_die(src_words, f, i - l, r);
-                    const uint32_t e = i - 1 - l - i_end;
-                    L.qof[e] = q;
-                    if (q == i - 1 - l) continue; // stays
-                    // push e on the chain of q: compare-and-swap on its head
-                    uint32_t *head = L.table + peel_hash<HB>(q);
-                    uint32_t cur = *head, seen;
-                    do {
-                        seen = cur;
-                        cur = atomicCAS(head, seen, tag | e);
-                    } while (cur != seen);
-                    L.nxt[e] = (seen & 0xFFFF0000u) == tag ? (uint16_t)seen : kNone16;
-                    if (q >= i_end) atomicMax(&L.root[q - i_end], tag | (0xFFFFu - e));
-                }
+        auto roll = [&](uint32_t s, uint64_t w) {
+            uint32_t i, k, f;
+            uint64_t u;
+            batch_at(s, st.seg, st.nseg, i, k, u, f);
+            uint64_t r = batch_state(src_words, f, i, k, u, w, st.S, s, key);
+            for (uint32_t l = 0; l < k; ++l) {
+                const uint32_t q = next_die(src_words, f, i - l, r);
+                const uint32_t e = i - 1 - l - i_end;
+                L.qof[e] = q;
+                if (q == i - 1 - l) continue; // stays
+                // push e on the chain of q: compare-and-swap on its head
+                uint32_t *head = L.table + peel_hash<HB>(q);
+                uint32_t cur = *head, seen;
+                do {
+                    seen = cur;
+                    cur = atomicCAS(head, seen, tag | e);
+                } while (cur != seen);
+                L.nxt[e] = (seen & 0xFFFF0000u) == tag ? (uint16_t)seen : kNone16;
+                if (q >= i_end) atomicMax(&L.root[q - i_end], tag | (0xFFFFu - e));
+            }
+        };
+        if (W && src_words == BRR_WORDS_CHACHA20) {
+            // a ChaCha20 block costs as much for one word as for two: a
+            // thread takes both batches of a word pair
+            for (uint32_t m = s_begin / 2 + tid; 2 * m < s_end; m += BLOCK) {
+                uint64_t w[2];
+                first_pair(src_words, m, key, w[0], w[1]);
+                if (2 * m >= s_begin) roll(2 * m, w[0]);
+                if (2 * m + 1 < s_end) roll(2 * m + 1, w[1]);
+            }
+        } else {
+            // one batch per thread (the two batches of a word pair compute
+            // its cheap Philox block twice: more threads roll and push at
+            // once)
+            for (uint32_t s = s_begin + tid; s < s_end; s += BLOCK) {
+                uint64_t w[2];
+                first_pair(src_words, s / 2, key, w[0], w[1]);
+                roll(s, (s & 1u) ? w[1] : w[0]);
             }
         }
         __syncthreads();
