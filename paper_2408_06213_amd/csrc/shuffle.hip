@@ -1081,7 +1081,7 @@ __global__ __launch_bounds__(BLOCK) void k_peel_batched(const RunArgs *__restric
 constexpr uint32_t kSortThreads = 512;
 constexpr uint32_t kSortItems = 8;
 constexpr uint32_t kSortTile = kSortThreads * kSortItems; // pairs per sort block
-static_assert(kSortThreads % 64 == 0 && kSortTile < 65536, "16-bit split counters");
+static_assert(kSortThreads % 64 == 0 && kSortTile < 65536, "16-bit digit counters");
 // A pass sorts on a digit of 8..kSortDigitMax bits: as few passes as the
 // key width allows, each digit as narrow as that many passes allow (wider
 // digits split a tile into shorter runs, whose writes coalesce worse).
