@@ -260,10 +260,11 @@ brr_status brr_dice_div(const uint32_t *d_bounds, uint32_t *d_out, uint64_t coun
  * words 12-13 and the 64-bit nonce inst in words 14-15. Dice, acceptance,
  * attempt addressing (attempt a of group s reads word a*S + s), arguments
  * and errors as brr_dice. Groups rejected on their first word are rerolled
- * by a second kernel from a queue in device scratch of 8 bytes per queued
- * group, at most max(S/8, 2^16) of them, taken from the stream-ordered
- * allocator on `stream`; groups beyond it, or all of them if the scratch
- * cannot be had, are rerolled in place (the same dice, more slowly). */
+ * by a second kernel of persistent wavefronts from per-tile records in
+ * device scratch (68 bytes per tile of 512 groups, up to 32 rejected groups
+ * a tile, the stream's scratch buffer; see brr_release_scratch); a tile
+ * with more, or every tile if the scratch cannot be had, rerolls in place
+ * (the same dice, more slowly). */
 brr_status brr_dice_chacha(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
                            uint64_t seed, uint64_t inst, void *stream);
 
@@ -287,9 +288,8 @@ brr_status brr_dice32(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count,
  * Fisher-Yates shuffle produces: batch at size i rolls bounds i, i-1, ...,
  * i-k+1 and swaps z[i-1] with z[a_1] first. n <= 1 is a no-op;
  * n < 2^32. n above 16,384 takes device scratch of about 33 bytes plus
- * elem_bytes per element from the stream-ordered allocator on `stream`
- * (hipMallocAsync), freed on the same stream when the call's kernels end;
- * BRR_ENOMEM if it cannot be had. */
+ * elem_bytes per element (brr_scratch_bytes) from the stream's scratch
+ * buffer (see brr_release_scratch); BRR_ENOMEM if it cannot be had. */
 brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_schedule *sched,
                        uint64_t seed, uint64_t inst, void *stream);
 
@@ -468,7 +468,7 @@ brr_status brr_plan_autotune_learned(brr_plan *plan, brr_mlp *model, uint32_t to
  * elements the work and the device scratch are O(m), whatever n: only the
  * m steps are rolled and resolved, and only the at most 2m positions they
  * touch are read (brr_scratch_bytes gives the scratch; it comes from the
- * stream-ordered allocator on `stream`). */
+ * stream's scratch buffer, see brr_release_scratch). */
 brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_bytes, void *d_out,
                       const brr_schedule *sched, uint64_t seed, uint64_t inst, void *stream);
 
@@ -478,6 +478,19 @@ brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_
  * element for a shuffle and 28 bytes per sampled element for a sample.
  * Returns 0 for invalid sizes (elem_bytes not 4 or 8, m > n, n >= 2^32). */
 uint64_t brr_scratch_bytes(uint64_t n, uint64_t m, uint32_t elem_bytes);
+
+/* Scratch of brr_shuffle, brr_sample, brr_dice_chacha and the server's
+ * large requests: the library keeps one device buffer per (device, stream),
+ * allocated with hipMalloc the first time a call on that stream needs
+ * scratch and replaced by a larger one (after the stream's earlier work has
+ * ended) when a later call needs more; calls on one stream share it in
+ * stream order, so those calls stay asynchronous. A server frees its
+ * streams' buffers when it is destroyed; the others are held until this
+ * call, which waits for each device that holds one to finish its work and
+ * frees them all (later calls allocate again). Not to be called while calls
+ * that use the buffers are being made from other threads. BRR_EHIP if a
+ * wait or a free fails. */
+brr_status brr_release_scratch(void);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of shuffle and sample requests              */
@@ -496,7 +509,10 @@ uint64_t brr_scratch_bytes(uint64_t n, uint64_t m, uint32_t elem_bytes);
  * run concurrently and may finish in any order, also within a session: a
  * buffer must not be used by two requests in flight at once. A request that
  * needs more scratch than the whole budget still runs, alone. Shuffles
- * follow brr_shuffle, samples brr_sample, with the server's schedule. */
+ * follow brr_shuffle, samples brr_sample, with the server's schedule; a
+ * large request uses the scratch buffer of its stream (brr_release_scratch),
+ * so the device memory held is up to nstreams times the largest request's
+ * scratch, whatever the budget admits at once. */
 typedef struct brr_server brr_server;
 
 typedef struct {

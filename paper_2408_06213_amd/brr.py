@@ -22,6 +22,7 @@ BRR_MAX_K = 20
 EXPORTS = (
     "brr_schedule_paper", "brr_schedule_batches", "brr_schedule_check",
     "brr_schedule_check_upto", "brr_shuffle_noalloc", "brr_scratch_bytes", "brr_plan_captures",
+    "brr_release_scratch",
     "brr_dice",
     "brr_dice_const", "brr_shuffle", "brr_plan_create", "brr_plan_destroy",
     "brr_plan_get_mapping", "brr_plan_set_mapping", "brr_shuffle_batched", "brr_sample",
@@ -142,6 +143,7 @@ def _load():
         "brr_shuffle": (st, [p, u64, u32, sched_p, u64, u64, p]),
         "brr_shuffle_noalloc": (st, [p, u64, u32, sched_p, u64, u64, p]),
         "brr_scratch_bytes": (u64, [u64, u64, u32]),
+        "brr_release_scratch": (st, []),
         "brr_plan_create": (st, [ctypes.POINTER(p), p, u64, u32, sched_p]),
         "brr_plan_destroy": (None, [p]),
         "brr_plan_captures": (u32, [p]),
@@ -317,6 +319,10 @@ def brr_shuffle_noalloc(data, n: int, elem_bytes: int, sched=None, seed: int = 0
 
 def brr_scratch_bytes(n: int, m: int, elem_bytes: int) -> int:
     return int(lib.brr_scratch_bytes(n, m, elem_bytes))
+
+
+def brr_release_scratch() -> int:
+    return lib.brr_release_scratch()
 
 
 def brr_sample(data, n: int, m: int, elem_bytes: int, out, sched=None, seed: int = 0,

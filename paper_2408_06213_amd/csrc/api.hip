@@ -224,9 +224,110 @@ brr_status check_upto(const brr_schedule &sc, uint64_t max_n)
 
 DevSched to_dev(const brr_schedule &sc) { return dev_schedule(sc); }
 
+// Scratch of single calls (brr_shuffle, brr_sample, brr_dice_chacha, the
+// server's large requests): one buffer per (device, stream), grown to the
+// largest need seen on that stream and kept for the calls after it. Stream
+// order keeps the calls on one stream from overlapping; the buffer's lock
+// keeps two host threads from enqueueing on it while it is replaced. The
+// stream-ordered allocator would do the same job per call, but on this
+// stack its allocation or release waits for the device, which made every
+// such call block the host until its kernels had run.
+struct StreamScratch {
+    int dev = -1;
+    hipStream_t stream = nullptr;
+    void *ptr = nullptr;
+    uint64_t bytes = 0;
+    std::mutex mu;
+};
+std::mutex g_scratch_mu;
+std::vector<StreamScratch *> g_scratch; // entries live as long as the process
+
 } // namespace
 
 brr_status brr::ensure_device() { return device_ready(nullptr); }
+
+brr_status brr::stream_scratch(hipStream_t s, uint64_t bytes, std::unique_lock<std::mutex> &hold,
+                               void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return BRR_EDEVICE;
+    StreamScratch *e = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        for (StreamScratch *x : g_scratch)
+            if (x->dev == dev && x->stream == s) e = x;
+        if (!e) {
+            e = new (std::nothrow) StreamScratch;
+            if (!e) return BRR_ENOMEM;
+            e->dev = dev;
+            e->stream = s;
+            g_scratch.push_back(e);
+        }
+    }
+    hold = std::unique_lock<std::mutex>(e->mu);
+    if (e->bytes < bytes) {
+        if (e->ptr) { // earlier calls on the stream may still read the old buffer
+            if (hipStreamSynchronize(s) != hipSuccess) return BRR_EHIP;
+            (void)hipFree(e->ptr);
+            e->ptr = nullptr;
+            e->bytes = 0;
+        }
+        if (hipMalloc(&e->ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            e->ptr = nullptr;
+            return BRR_ENOMEM;
+        }
+        e->bytes = bytes;
+    }
+    *out = e->ptr;
+    return BRR_OK;
+}
+
+brr_status brr::drop_stream_scratch(hipStream_t s)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return BRR_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    brr_status st = BRR_OK;
+    for (StreamScratch *e : g_scratch) {
+        if (e->dev != dev || e->stream != s) continue;
+        std::lock_guard<std::mutex> hold(e->mu);
+        if (e->ptr && hipFree(e->ptr) != hipSuccess) st = BRR_EHIP;
+        e->ptr = nullptr;
+        e->bytes = 0;
+    }
+    return st;
+}
+
+brr_status brr_release_scratch(void)
+{
+    // Streams may have been destroyed since their buffers were made, so the
+    // wait is for each device as a whole, never for a stream handle.
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    brr_status st = BRR_OK;
+    std::vector<int> synced;
+    for (StreamScratch *e : g_scratch) {
+        std::lock_guard<std::mutex> hold(e->mu);
+        if (!e->ptr) continue;
+        if (std::find(synced.begin(), synced.end(), e->dev) == synced.end()) {
+            if (hipSetDevice(e->dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+                st = BRR_EHIP;
+                continue;
+            }
+            synced.push_back(e->dev);
+        } else if (hipSetDevice(e->dev) != hipSuccess) {
+            st = BRR_EHIP;
+            continue;
+        }
+        if (hipFree(e->ptr) != hipSuccess) st = BRR_EHIP;
+        e->ptr = nullptr;
+        e->bytes = 0;
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+    return st;
+}
 
 // ---------------------------------------------------------------------------
 // Plans
@@ -701,10 +802,15 @@ brr_status brr_dice_chacha(const uint32_t *d_bounds, uint32_t *d_out, uint64_t c
     if (count == 0) return BRR_OK;
     if (!d_bounds || !d_out || misaligned(d_bounds, 4) || misaligned(d_out, 4)) return BRR_EINVAL;
     uint32_t *status = nullptr;
-    const brr_status st = device_ready(&status);
+    brr_status st = device_ready(&status);
     if (st != BRR_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::unique_lock<std::mutex> hold;
+    void *rec = nullptr;
+    if (stream_scratch(s, chacha_record_bytes(count, k), hold, &rec) != BRR_OK)
+        rec = nullptr; // no record: every group rerolls in place
     return hip_status(launch_dice_chacha(d_bounds, d_out, count, k, make_key(seed, inst), status,
-                                         static_cast<hipStream_t>(stream)));
+                                         rec, s));
 }
 
 brr_status brr_dice32(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
@@ -784,8 +890,13 @@ brr_status brr_shuffle(void *d_data, uint64_t n, uint32_t elem_bytes, const brr_
     if (st != BRR_OK) return st;
     st = device_ready(nullptr);
     if (st != BRR_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::unique_lock<std::mutex> hold;
+    void *scr = nullptr;
+    const uint64_t bytes = one_scratch_bytes(n, elem_bytes);
+    if (bytes && (st = stream_scratch(s, bytes, hold, &scr)) != BRR_OK) return st;
     return hip_status(launch_one(d_data, (uint32_t)n, (uint32_t)(n - 1), 0, elem_bytes, nullptr,
-                                 to_dev(sc), seed, inst, DevClaim{}, static_cast<hipStream_t>(stream)));
+                                 to_dev(sc), seed, inst, DevClaim{}, s, scr));
 }
 
 brr_status brr_shuffle_noalloc(void *d_data, uint64_t n, uint32_t elem_bytes,
@@ -835,8 +946,12 @@ brr_status brr_sample(const void *d_data, uint64_t n, uint64_t m, uint32_t elem_
     if (n == 1) // one element, no step: the sample is the element itself
         return hip_status(hipMemcpyAsync(d_out, d_data, elem_bytes, hipMemcpyDeviceToDevice, s));
     void *data = const_cast<void *>(d_data); // only read when an output buffer is given
+    std::unique_lock<std::mutex> hold;
+    void *scr = nullptr;
+    const uint64_t bytes = one_scratch_bytes(n, elem_bytes, m);
+    if (bytes && (st = stream_scratch(s, bytes, hold, &scr)) != BRR_OK) return st;
     return hip_status(launch_one(data, (uint32_t)n, (uint32_t)steps, (uint32_t)(n - m), elem_bytes,
-                                 d_out, to_dev(sc), seed, inst, DevClaim{}, s));
+                                 d_out, to_dev(sc), seed, inst, DevClaim{}, s, scr));
 }
 
 brr_status brr_plan_create(brr_plan **out, const uint64_t *h_offsets, uint64_t count,

@@ -360,7 +360,7 @@ __global__ __launch_bounds__(256) void dice_chacha_rerolls(const uint32_t *__res
 
 template <int K>
 hipError_t launch_dice_chacha_k(const uint32_t *bounds, uint32_t *out, uint64_t count,
-                                StreamKey key, uint32_t *status, hipStream_t stream)
+                                StreamKey key, uint32_t *status, void *mem, hipStream_t stream)
 {
     const uint64_t S = (count + K - 1) / K;
     const uint64_t full = count / K;
@@ -368,14 +368,8 @@ hipError_t launch_dice_chacha_k(const uint32_t *bounds, uint32_t *out, uint64_t 
     const uint64_t blocks = (waves + 3) / 4;           // 4 wavefronts per block
     if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
     // the record: a count and kTileSlots offsets per tile (68 bytes per 512
-    // groups); without the memory for it, every tile rerolls in place
-    RerollRecord rec{nullptr, nullptr, waves};
-    void *mem = nullptr;
-    if (hipMallocAsync(&mem, waves * (4 + 2 * kTileSlots), stream) != hipSuccess) {
-        (void)hipGetLastError();
-        mem = nullptr;
-        rec.tiles = 0;
-    }
+    // groups); without memory for it, every tile rerolls in place
+    RerollRecord rec{nullptr, nullptr, mem ? waves : 0};
     if (mem) {
         rec.count = static_cast<uint32_t *>(mem);
         rec.slot = reinterpret_cast<uint16_t *>(rec.count + waves);
@@ -394,27 +388,30 @@ hipError_t launch_dice_chacha_k(const uint32_t *bounds, uint32_t *out, uint64_t 
         const uint64_t per = (waves + rwaves - 1) / rwaves;
         dice_chacha_rerolls<K><<<(uint32_t)((rwaves + 3) / 4), 256, 0, stream>>>(
             bounds, out, count, S, full, key, rec, per);
-        hipError_t e = hipGetLastError();
-        const hipError_t f = hipFreeAsync(mem, stream);
-        return e != hipSuccess ? e : f;
     }
     return hipGetLastError();
 }
 
 } // namespace
 
+uint64_t chacha_record_bytes(uint64_t count, uint32_t k)
+{
+    const uint64_t S = (count + k - 1) / k;
+    return (S + 64 * 8 - 1) / (64 * 8) * (4 + 2 * kTileSlots);
+}
+
 hipError_t launch_dice_chacha(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
-                              StreamKey key, uint32_t *status, hipStream_t stream)
+                              StreamKey key, uint32_t *status, void *rec, hipStream_t stream)
 {
     switch (k) {
-    case 1: return launch_dice_chacha_k<1>(bounds, out, count, key, status, stream);
-    case 2: return launch_dice_chacha_k<2>(bounds, out, count, key, status, stream);
-    case 3: return launch_dice_chacha_k<3>(bounds, out, count, key, status, stream);
-    case 4: return launch_dice_chacha_k<4>(bounds, out, count, key, status, stream);
-    case 5: return launch_dice_chacha_k<5>(bounds, out, count, key, status, stream);
-    case 6: return launch_dice_chacha_k<6>(bounds, out, count, key, status, stream);
-    case 7: return launch_dice_chacha_k<7>(bounds, out, count, key, status, stream);
-    case 8: return launch_dice_chacha_k<8>(bounds, out, count, key, status, stream);
+    case 1: return launch_dice_chacha_k<1>(bounds, out, count, key, status, rec, stream);
+    case 2: return launch_dice_chacha_k<2>(bounds, out, count, key, status, rec, stream);
+    case 3: return launch_dice_chacha_k<3>(bounds, out, count, key, status, rec, stream);
+    case 4: return launch_dice_chacha_k<4>(bounds, out, count, key, status, rec, stream);
+    case 5: return launch_dice_chacha_k<5>(bounds, out, count, key, status, rec, stream);
+    case 6: return launch_dice_chacha_k<6>(bounds, out, count, key, status, rec, stream);
+    case 7: return launch_dice_chacha_k<7>(bounds, out, count, key, status, rec, stream);
+    case 8: return launch_dice_chacha_k<8>(bounds, out, count, key, status, rec, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "brr.h"
 #include "device.hpp"
 
@@ -12,6 +14,17 @@ namespace brr {
 // Checks once per device that the current device is a gfx950 and sets up
 // the library's per-device state.
 brr_status ensure_device();
+
+// Device scratch of single calls, one buffer per (device, stream): at least
+// `bytes`, valid while `hold` (the buffer's lock, taken here) is held, which
+// the caller keeps until its kernels are enqueued. Grown (after the
+// stream's earlier work ends) when a call needs more; kept for later calls
+// on the stream, whose stream order keeps them from overlapping.
+brr_status stream_scratch(hipStream_t s, uint64_t bytes, std::unique_lock<std::mutex> &hold,
+                          void **out);
+// Frees the current device's scratch buffer of stream s, whose work must
+// have ended (a stream's owner calls it before destroying the stream).
+brr_status drop_stream_scratch(hipStream_t s);
 
 // A validated schedule in the form the kernels read (thresholds clamped to
 // 32 bits: every shuffle here has n < 2^32).
@@ -132,8 +145,11 @@ hipError_t launch_dice_const(const BoundTuple &tb, uint32_t *out, uint64_t count
 hipError_t launch_dice_div(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
                            StreamKey key, uint32_t *status, hipStream_t stream);
 // The dice stream with ChaCha20 words (dice_chacha.hip).
+// rec: device memory of chacha_record_bytes(count, k) bytes for the
+// records of rejected groups, or nullptr (every group rerolls in place).
+uint64_t chacha_record_bytes(uint64_t count, uint32_t k);
 hipError_t launch_dice_chacha(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
-                              StreamKey key, uint32_t *status, hipStream_t stream);
+                              StreamKey key, uint32_t *status, void *rec, hipStream_t stream);
 // The dice stream at word width 32 (dice32.hip).
 hipError_t launch_dice32(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,
                          StreamKey key, uint32_t *status, hipStream_t stream);

@@ -226,14 +226,22 @@ void launch_tick(brr_server *sv, const std::vector<uint64_t> &ids)
         hipStream_t st = sv->streams[q.stream];
         const DevClaim claim{nullptr, sv->d_slots + q.slot, 0};
         const uint64_t n = q.r.n;
+        // the stream's scratch buffer (requests on one stream run in turn)
+        std::unique_lock<std::mutex> hold;
+        void *scr = nullptr;
+        const brr_status ss = stream_scratch(st, q.footprint, hold, &scr);
+        if (ss != BRR_OK) {
+            q.status = ss;
+            continue;
+        }
         hipError_t f = hipStreamWaitEvent(st, sv->claimed, 0);
         if (f == hipSuccess && q.r.kind == BRR_REQ_SHUFFLE)
             f = launch_one(q.r.d_data, (uint32_t)n, (uint32_t)(n - 1), 0, q.r.elem_bytes, nullptr,
-                           sv->ds, sv->cfg.seed, 0, claim, st);
+                           sv->ds, sv->cfg.seed, 0, claim, st, scr);
         else if (f == hipSuccess)
             f = launch_one(q.r.d_data, (uint32_t)n, (uint32_t)std::min<uint64_t>(q.r.m, n - 1),
                            (uint32_t)(n - q.r.m), q.r.elem_bytes, q.r.d_out, sv->ds,
-                           sv->cfg.seed, 0, claim, st);
+                           sv->cfg.seed, 0, claim, st, scr);
         if (f != hipSuccess) {
             fail(q, f);
             continue;
@@ -503,8 +511,12 @@ void brr_server_destroy(brr_server *sv)
         sv->cv.notify_all();
     }
     if (sv->worker.joinable()) sv->worker.join();
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(sv->device);
     for (hipStream_t s : sv->streams) {
         (void)hipStreamSynchronize(s);
+        (void)drop_stream_scratch(s); // the stream's scratch buffer goes with it
         (void)hipStreamDestroy(s);
     }
     if (sv->control) {
@@ -515,6 +527,7 @@ void brr_server_destroy(brr_server *sv)
     for (hipEvent_t ev : sv->slot_events) (void)hipEventDestroy(ev);
     if (sv->d_counters) (void)hipFree(sv->d_counters);
     if (sv->d_slots) (void)hipFree(sv->d_slots);
+    if (prev >= 0) (void)hipSetDevice(prev);
     delete sv;
 }
 

@@ -354,6 +354,60 @@ def test_batched_tier_boundaries(gpu, orc, dtype, wave_max):
         assert np.array_equal(got, want)
 
 
+def test_single_calls_stay_asynchronous(gpu, orc):
+    """Shuffles and samples that take scratch (above 16,384 elements), and a
+    ChaCha20 dice stream, enqueued behind a long-running kernel return while
+    that kernel still runs (their scratch is the stream's buffer, not a
+    per-call allocation); the buffers then grow for a larger call, are
+    released, and are taken again; every result equals the oracle's."""
+    import time
+
+    import torch
+
+    s6g, s6o = both_schedules(gpu, orc, 6)
+    sizes = [100003, (1 << 21) + 5, 40000]
+    arrays = [np.arange(n, dtype=np.uint32) * 3 + 1 for n in sizes]
+    devs = [to_dev(a) for a in arrays]
+    n_s, m_s = 3000000, 300000
+    src = np.arange(n_s, dtype=np.uint64) * 7
+    d_src, d_out = to_dev(src), to_dev(np.zeros(m_s, np.uint64))
+    bounds = workloads.dice_bounds(1 << 20, seed=3)
+    d_b, d_o = to_dev(bounds), to_dev(np.zeros(1 << 20, np.uint32))
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    say("single calls behind a long kernel")
+    torch.cuda._sleep(400_000_000)  # on the order of 0.2 s
+    busy = torch.cuda.Event()
+    busy.record(s)
+    t0 = time.perf_counter()
+    for i, (d, n) in enumerate(zip(devs, sizes)):
+        gpu.check(gpu.brr_shuffle(d, n, 4, s6g, 5, i), "brr_shuffle")
+    gpu.check(gpu.brr_sample(d_src, n_s, m_s, 8, d_out, s6g, 6, 0), "brr_sample")
+    gpu.check(gpu.brr_dice_chacha(d_b, d_o, 1 << 20, 4, 7, 0), "brr_dice_chacha")
+    host_s = time.perf_counter() - t0
+    still_running = not busy.query()
+    torch.cuda.synchronize()
+    print("host seconds:", host_s, "sleep still running:", still_running)
+    assert still_running, host_s
+    assert gpu.brr_sync_status() == 0
+    for i, (a, n) in enumerate(zip(arrays, sizes)):
+        want = a.copy()
+        assert orc.shuffle(want, s6o, 5, i) == 0
+        assert np.array_equal(to_host(devs[i]), want), n
+    err, want = orc.sample(src, m_s, s6o, 6, 0)
+    assert err == 0 and np.array_equal(to_host(d_out), want)
+    err, want = orc.dice_stream(orc.STREAM_CHACHA20, bounds, 4, 7, 0)
+    assert err == 0 and np.array_equal(to_host(d_o), want)
+    say("released scratch, then taken again")
+    assert gpu.brr_release_scratch() == 0
+    d = to_dev(arrays[0])
+    gpu.check(gpu.brr_shuffle(d, sizes[0], 4, s6g, 5, 0), "brr_shuffle")
+    assert gpu.brr_sync_status() == 0
+    want = arrays[0].copy()
+    assert orc.shuffle(want, s6o, 5, 0) == 0
+    assert np.array_equal(to_host(d), want)
+
+
 @pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
 @pytest.mark.parametrize("which", ["k6", "k1", "chacha20"])
 def test_peel_resident_boundaries(gpu, orc, dtype, which):
