@@ -118,14 +118,31 @@ uint32_t session_of(brr_server *sv, uint64_t session, bool *ok)
     return sidx;
 }
 
-// Launches one tick of admitted requests (lock held); sets each request's
-// status and completion event. Requests that fail are finished by the
-// caller.
-void launch_tick(brr_server *sv, const std::vector<uint64_t> &ids)
+// One admitted request as the tick's launches see it: copied out of the
+// request table, so that the launches run without the server's lock.
+struct TickReq {
+    uint64_t id;
+    brr_request r;
+    uint64_t footprint;
+    int slot;
+    uint32_t stream;
+    hipEvent_t ev = nullptr;
+    brr_status status = BRR_OK;
+};
+
+// Launches one tick of admitted requests; sets each request's status and
+// completion event. Called with the server's lock held; the lock is
+// released while the tick's kernels are launched (clients submit and wait
+// meanwhile) and held again on return. Requests that fail are finished by
+// the caller.
+void launch_tick(brr_server *sv, const std::vector<uint64_t> &ids,
+                 std::unique_lock<std::mutex> &lock)
 {
     ClaimBatch cb;
     std::memset(&cb, 0, sizeof cb);
-    std::vector<uint64_t> fused, big, trivial;
+    std::vector<TickReq> t;
+    t.reserve(ids.size());
+    std::vector<size_t> fused, big, trivial;
     for (uint64_t id : ids) {
         Req &q = sv->reqs[id];
         bool ok = true;
@@ -141,15 +158,17 @@ void launch_tick(brr_server *sv, const std::vector<uint64_t> &ids)
         cb.session[cb.count] = q.r.session;
         ++cb.count;
         q.stream = sidx % (uint32_t)sv->streams.size();
+        t.push_back(TickReq{id, q.r, q.footprint, q.slot, q.stream});
         const uint64_t n = q.r.n;
         const bool work = q.r.kind == BRR_REQ_SHUFFLE ? n > 1 : (n > 1 && q.r.m > 0);
         if (!work)
-            trivial.push_back(id);
+            trivial.push_back(t.size() - 1);
         else if (n <= lds_tier_max_n())
-            fused.push_back(id);
+            fused.push_back(t.size() - 1);
         else
-            big.push_back(id);
+            big.push_back(t.size() - 1);
     }
+    lock.unlock();
     hipStream_t ctl = sv->control;
     hipError_t e = hipSuccess;
     if (cb.count) {
@@ -157,7 +176,7 @@ void launch_tick(brr_server *sv, const std::vector<uint64_t> &ids)
         e = hipGetLastError();
         if (e == hipSuccess) e = hipEventRecord(sv->claimed, ctl);
     }
-    auto fail = [&](Req &q, hipError_t err) {
+    auto fail = [&](TickReq &q, hipError_t err) {
         q.status = err == hipErrorOutOfMemory ? BRR_ENOMEM : BRR_EHIP;
     };
     // small requests: one launch per (class, element width), up to
@@ -175,8 +194,8 @@ void launch_tick(brr_server *sv, const std::vector<uint64_t> &ids)
                     rb.count = 0;
                     max_n = 0;
                 };
-                for (uint64_t id : fused) {
-                    const Req &q = sv->reqs[id];
+                for (size_t i : fused) {
+                    const TickReq &q = t[i];
                     if (q.r.elem_bytes != eb || lds_request_class((uint32_t)q.r.n) != c) continue;
                     const uint32_t n = (uint32_t)q.r.n;
                     const bool sample = q.r.kind == BRR_REQ_SAMPLE;
@@ -190,35 +209,25 @@ void launch_tick(brr_server *sv, const std::vector<uint64_t> &ids)
                 flush();
             }
     }
-    for (uint64_t id : trivial) {
-        Req &q = sv->reqs[id];
+    for (size_t i : trivial) {
+        const TickReq &q = t[i];
         if (e == hipSuccess && q.r.kind == BRR_REQ_SAMPLE && q.r.n == 1 && q.r.m == 1)
             e = hipMemcpyAsync(q.r.d_out, q.r.d_data, q.r.elem_bytes, hipMemcpyDeviceToDevice, ctl);
     }
-    for (uint64_t id : fused) {
-        Req &q = sv->reqs[id];
-        if (e != hipSuccess) fail(q, e);
-    }
-    for (uint64_t id : trivial) {
-        Req &q = sv->reqs[id];
-        if (e != hipSuccess) fail(q, e);
-    }
     // the tick's small and trivial requests complete with the control stream
-    for (uint64_t id : fused) {
-        Req &q = sv->reqs[id];
-        if (q.status != BRR_OK) continue;
-        q.ev = sv->slot_events[q.slot];
-        if (hipEventRecord(q.ev, ctl) != hipSuccess) q.status = BRR_EHIP;
-    }
-    for (uint64_t id : trivial) {
-        Req &q = sv->reqs[id];
-        if (q.status != BRR_OK) continue;
-        q.ev = sv->slot_events[q.slot];
-        if (hipEventRecord(q.ev, ctl) != hipSuccess) q.status = BRR_EHIP;
-    }
+    for (const std::vector<size_t> *group : {&fused, &trivial})
+        for (size_t i : *group) {
+            TickReq &q = t[i];
+            if (e != hipSuccess) {
+                fail(q, e);
+                continue;
+            }
+            q.ev = sv->slot_events[q.slot];
+            if (hipEventRecord(q.ev, ctl) != hipSuccess) q.status = BRR_EHIP;
+        }
     // large requests: each on its session's stream, behind the claims
-    for (uint64_t id : big) {
-        Req &q = sv->reqs[id];
+    for (size_t i : big) {
+        TickReq &q = t[i];
         if (e != hipSuccess) {
             fail(q, e);
             continue;
@@ -248,6 +257,12 @@ void launch_tick(brr_server *sv, const std::vector<uint64_t> &ids)
         }
         q.ev = sv->slot_events[q.slot];
         if (hipEventRecord(q.ev, st) != hipSuccess) q.status = BRR_EHIP;
+    }
+    lock.lock();
+    for (const TickReq &q : t) {
+        Req &r = sv->reqs[q.id];
+        r.status = q.status;
+        r.ev = q.ev;
     }
 }
 
@@ -308,7 +323,7 @@ void worker_loop(brr_server *sv)
             tick.push_back(id);
         }
         if (!tick.empty()) {
-            launch_tick(sv, tick);
+            launch_tick(sv, tick, lock);
             for (uint64_t id : tick) {
                 Req &q = sv->reqs[id];
                 if (q.status != BRR_OK) finish(sv, q, id);
