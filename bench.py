@@ -125,7 +125,7 @@ def host_cpu():
 
 
 def serving(brr, workloads, up, rates=(1000, 2000, 4000, 8000, 16000, 32000, 64000), count=400,
-            clients=64):
+            clients=64, max_inflight=128, nstreams=32):
     """Poisson arrivals at each rate: requests (shuffle or sample, n
     log-uniform in [2^4, 2^22], u64 payload, m <= n/10) from `clients`
     independent clients (request i belongs to session i mod clients; a
@@ -143,7 +143,7 @@ def serving(brr, workloads, up, rates=(1000, 2000, 4000, 8000, 16000, 32000, 640
             o = up(np.zeros(r["m"], np.uint64)) if r["kind"] == "sample" else None
             bufs.append((d, o))
         torch_sync()
-        srv = brr.Server(hbm_budget=8 << 30, max_inflight=64, nstreams=8, seed=11)
+        srv = brr.Server(hbm_budget=8 << 30, max_inflight=max_inflight, nstreams=nstreams, seed=11)
         t0 = time.perf_counter()
         for i, (r, (d, o)) in enumerate(zip(reqs, bufs)):
             while time.perf_counter() - t0 < r["t"]:
