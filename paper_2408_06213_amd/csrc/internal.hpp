@@ -248,7 +248,9 @@ constexpr uint64_t kMaxGtierPositions = 0xFFFFFFFFull;
 // shuffle) or the sparse sample path (O(m) work and scratch), with
 // one_scratch_bytes(n, eb, m) bytes of scratch (m = 0 for a shuffle): the
 // caller's (scratch != nullptr; nothing is allocated) or taken from the
-// stream-ordered allocator and freed on the stream.
+// stream-ordered allocator and freed on the stream (whose allocation or
+// release waits for the device here: the library's own callers pass the
+// stream's scratch buffer, see stream_scratch).
 uint64_t one_scratch_bytes(uint64_t n, uint32_t eb, uint64_t m = 0);
 hipError_t launch_one(void *data, uint32_t n, uint32_t steps, uint32_t out_lo, uint32_t eb,
                       void *out, const DevSched &ds, uint64_t seed, uint64_t inst,
