@@ -132,27 +132,18 @@ struct BoundProduct {
         zero = (b == 0);
     }
 
+    // Branch-free (lanes of a wavefront all take the same steps).
     __host__ __device__ __forceinline__ void mul(uint32_t b)
     {
         zero |= (b == 0);
-        if (e64) { // 2^64 * b: stays 2^64 for b == 1, exceeds it for b > 1
-            over |= (b > 1);
-            return;
-        }
-        if ((p >> 32) == 0) {
-            p = (uint64_t)(uint32_t)p * b; // < 2^64, exact
-            return;
-        }
+        over |= e64 && b > 1; // 2^64 * b exceeds 2^64 for b > 1 (p is 0 and stays 0)
         const uint64_t lo = (uint64_t)(uint32_t)p * b;
-        const uint64_t hi = (uint64_t)(uint32_t)(p >> 32) * b + (lo >> 32);
-        const uint64_t top = hi >> 32; // bits 64.. of the product
+        const uint64_t hi = (uint64_t)(uint32_t)(p >> 32) * b + (lo >> 32); // < 2^64
+        const uint32_t top = (uint32_t)(hi >> 32); // bits 64.. of the product
         p = (hi << 32) | (uint32_t)lo;
-        if (top != 0) {
-            if (top == 1 && p == 0)
-                e64 = true;
-            else
-                over = true;
-        }
+        const bool exact = top == 1 && p == 0;
+        e64 |= exact;
+        over |= top != 0 && !exact;
     }
 };
 

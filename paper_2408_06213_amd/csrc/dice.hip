@@ -11,6 +11,8 @@
 // m, so lanes L and L^1 each compute one block per pair of their groups and
 // swap the half the other one needs (a DPP lane swap). Rerolls read word
 // a*S + g on attempt a.
+#include <algorithm>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -20,6 +22,7 @@ namespace {
 
 constexpr uint64_t kMaxAttempts = 1024;
 constexpr int kGroupsPerLane = 4;
+constexpr uint32_t kUndecided = 64;
 
 // Value of lane L^1 (swap within lane pairs, quad_perm [1,0,3,2]).
 __device__ __forceinline__ uint64_t swap_lane_pair(uint64_t v)
@@ -111,6 +114,27 @@ __device__ __forceinline__ void check_group(const uint32_t *b, int kk, uint64_t 
     }
 }
 
+// The group's product when its threshold decides (r below it), else 0:
+// accepted at once (r >= P > t, or P = 2^64), or a bad group, flagged in
+// err.
+template <int K>
+__device__ __forceinline__ uint64_t undecided_product(const uint32_t *b, uint64_t r, uint32_t &err)
+{
+    BoundProduct P;
+    P.init(b[0]);
+#pragma unroll
+    for (int i = 1; i < K; ++i) P.mul(b[i]);
+    if (P.zero) {
+        err |= kDevZeroBound;
+        return 0;
+    }
+    if (P.over) {
+        err |= kDevOverflow;
+        return 0;
+    }
+    return (P.e64 || r >= P.p) ? 0 : P.p; // P >= 1 here
+}
+
 // Rolls group g again from attempt 1 on until accepted.
 template <int K>
 __device__ __forceinline__ void reroll_group(const uint32_t *b, int kk, uint32_t *a, uint64_t t,
@@ -135,7 +159,13 @@ __global__ __launch_bounds__(256) void dice_kernel(const uint32_t *__restrict__ 
                                                    uint64_t S, uint64_t full, StreamKey key,
                                                    uint32_t *status)
 {
-    const uint32_t lane = threadIdx.x & 63;
+    // Groups whose threshold decides (r < P: one in 16 at k = 4 with 16-bit
+    // bounds) are set aside (up to kUndecided per wave) and decided after
+    // the checks, one per lane in one pass, instead of in the check of
+    // every j, where nearly every j has such a lane and the whole wave runs
+    // the threshold's steps.
+    __shared__ uint64_t und_p[4][kUndecided], und_r[4][kUndecided];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t g0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * G);
     if (g0 >= S) return; // the whole wavefront leaves together
     uint64_t r[G];
@@ -143,18 +173,49 @@ __global__ __launch_bounds__(256) void dice_kernel(const uint32_t *__restrict__ 
     uint32_t b[G][K], a[G][K];
     uint32_t err = 0;
     if (g0 + 64 * G <= full) { // every group of the tile has K dice
+        const uint64_t lt_mask = (1ull << lane) - 1;
 #pragma unroll
         for (int j = 0; j < G; ++j) load_group<K, VEC>(bounds + K * (g0 + 64 * j + lane), b[j]);
 #pragma unroll
         for (int j = 0; j < G; ++j)
 #pragma unroll
             for (int i = 0; i < K; ++i) a[j][i] = mul_roll(b[j][i], r[j]);
+        uint32_t at[G], nu = 0; // slot of each set-aside group (kUndecided: none)
 #pragma unroll
         for (int j = 0; j < G; ++j) {
-            bool need;
-            uint64_t t;
-            check_group<K>(b[j], K, r[j], need, t, err);
-            if (need) reroll_group<K>(b[j], K, a[j], t, S, g0 + 64 * j + lane, key);
+            const uint64_t ps = undecided_product<K>(b[j], r[j], err);
+            const uint64_t um = __ballot(ps != 0);
+            const uint32_t slot = nu + (uint32_t)__builtin_popcountll(um & lt_mask);
+            nu += (uint32_t)__builtin_popcountll(um);
+            at[j] = kUndecided;
+            if (ps != 0) {
+                if (slot < kUndecided) {
+                    und_p[w][slot] = ps;
+                    und_r[w][slot] = r[j];
+                    at[j] = slot;
+                } else {
+                    const uint64_t t = pow2_64_mod(ps);
+                    if (r[j] < t) reroll_group<K>(b[j], K, a[j], t, S, g0 + 64 * j + lane, key);
+                }
+            }
+        }
+        if (nu != 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // the threshold of each set-aside group, or 0 once its word is accepted
+            if (lane < std::min(nu, kUndecided)) {
+                const uint64_t t = pow2_64_mod(und_p[w][lane]);
+                und_p[w][lane] = und_r[w][lane] < t ? t : 0;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const uint64_t t = at[j] < kUndecided ? und_p[w][at[j]] : 0;
+                if (t != 0) reroll_group<K>(b[j], K, a[j], t, S, g0 + 64 * j + lane, key);
+            }
         }
 #pragma unroll
         for (int j = 0; j < G; ++j) store_group<K, VEC>(out + K * (g0 + 64 * j + lane), a[j]);

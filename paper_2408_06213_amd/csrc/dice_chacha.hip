@@ -26,9 +26,14 @@
 // in device memory, and a second kernel of persistent waves works through
 // them with every lane busy: each wave owns a run of tiles, a lane takes
 // the next recorded group as soon as its current one is accepted, and keeps
-// rerolling a group until it is. A tile with more rejected groups rerolls
-// them in place, one block per lane and pass for the lane's lowest rejected
-// group (as does every tile when the memory cannot be had).
+// rerolling a group until it is; when the run is drained, idle lanes try
+// the remaining groups' next attempts side by side. A tile with more
+// rejected groups rerolls them in place, one block per lane and pass for
+// the lane's lowest rejected group (as does every tile when the memory
+// cannot be had). Pooling the rerolls of a block's four tiles in LDS inside
+// the first kernel instead was slower: a pool of about 64 groups per block
+// still pays its tail passes, 16 times as many tails as the persistent
+// waves have.
 #include <algorithm>
 
 #include "chacha.hpp"
@@ -166,6 +171,29 @@ __device__ __forceinline__ uint64_t group_threshold(const uint32_t *b, int kk, u
     return pow2_64_mod(P.p);
 }
 
+// The group's product when its threshold decides (the leftover rr is below
+// it), else 0: accepted at once (r >= P > t, or P = 2^64), or a bad group,
+// flagged in err (its dice are stored as they are).
+template <int K>
+__device__ __forceinline__ uint64_t undecided_product(const uint32_t *b, int kk, uint64_t rr,
+                                                      uint32_t &err)
+{
+    BoundProduct P;
+    P.init(b[0]);
+#pragma unroll
+    for (int i = 1; i < K; ++i)
+        if (i < kk) P.mul(b[i]);
+    if (P.zero) {
+        err |= kDevZeroBound;
+        return 0;
+    }
+    if (P.over) {
+        err |= kDevOverflow;
+        return 0;
+    }
+    return (P.e64 || rr >= P.p) ? 0 : P.p; // P >= 1 here
+}
+
 // Dice count of group g (K, the short last group's count, or 0 past it).
 template <int K>
 __device__ __forceinline__ int group_dice(uint64_t g, uint64_t full, uint64_t S, uint64_t count)
@@ -209,12 +237,49 @@ __device__ __forceinline__ void store_dice(uint32_t *__restrict__ out, uint64_t 
 // the start of the stream). tiles = 0: no record, every tile rerolls in
 // place.
 constexpr uint32_t kTileSlots = 32;
+constexpr uint32_t kUndecided = 64;
 constexpr uint64_t kNoGroup = ~0ull;
+// The offsets follow the counts, from the next multiple of 16 bytes.
+__host__ __device__ constexpr uint64_t slot_offset(uint64_t tiles)
+{
+    return (4 * tiles + 15) & ~15ull;
+}
 struct RerollRecord {
     uint32_t *count;
     uint16_t *slot;
     uint64_t tiles;
 };
+
+// Attempt `attempt` of group g (word attempt * S + g): its dice into a;
+// true if accepted, or at the attempt cap, which only bounds the loop
+// against corrupted inputs (each attempt is rejected with probability
+// t / 2^64 < 1/2).
+template <int K>
+__device__ __forceinline__ bool try_attempt(const uint32_t *b, int kk, uint64_t g,
+                                            uint64_t attempt, uint64_t S, const StreamKey &key,
+                                            uint32_t *a)
+{
+    const uint64_t rr = chain<K>(b, kk, a, chacha_word_at(attempt * S + g, key));
+    uint32_t e = 0; // bad groups were flagged by their first attempt
+    return rr >= group_threshold<K>(b, kk, rr, e) || attempt >= kMaxAttemptsChaCha;
+}
+
+template <int K>
+__device__ __forceinline__ void load_group_bounds(const uint32_t *__restrict__ bounds, uint64_t g,
+                                                  int kk, uint32_t *b)
+{
+#pragma unroll
+    for (int i = 0; i < K; ++i) b[i] = (i < kk) ? bounds[(uint64_t)K * g + i] : 1u;
+}
+
+template <int K>
+__device__ __forceinline__ void store_group_dice(uint32_t *__restrict__ out, uint64_t g, int kk,
+                                                 const uint32_t *a)
+{
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < kk) out[(uint64_t)K * g + i] = a[i];
+}
 
 template <int K, bool VEC>
 __global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__restrict__ bounds,
@@ -224,26 +289,62 @@ __global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__rest
                                                           uint32_t *status, RerollRecord rec)
 {
     constexpr int G = 8; // groups per lane
-    const uint32_t lane = threadIdx.x & 63;
+    // Groups whose threshold decides (rr < P: one in 16 at k = 4 with
+    // 16-bit bounds) are not decided in the loop, where nearly every j
+    // would have a lane on that path and the whole wave would run it:
+    // their product and leftover are set aside (up to kUndecided per wave)
+    // and decided after the loop, one group per lane, in one pass.
+    __shared__ uint64_t und_p[4][kUndecided], und_r[4][kUndecided];
+    __shared__ uint16_t und_at[4][kUndecided]; // 64 j + lane
+    __shared__ uint32_t rejected[4][64];      // bit j: group 64 j + lane rejected
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt_mask = (1ull << lane) - 1;
     const uint64_t g0 = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * G);
     if (g0 >= S) return; // the whole wavefront leaves together
     const bool whole = g0 + 64 * G <= full; // every group of the tile has K dice
+    rejected[w][lane] = 0;
     uint64_t r[G];
     tile_words_chacha(g0, lane, key, r);
-    uint32_t err = 0, pending = 0;
+    uint32_t err = 0, pending = 0, nu = 0; // nu: set aside (uniform)
 #pragma unroll
     for (int j = 0; j < G; ++j) {
         const uint64_t g = g0 + 64 * j + lane;
         const int kk = group_dice<K>(g, full, S, count);
-        if (kk == 0) continue;
-        uint32_t b[K], a[K];
-        load_bounds<K, VEC>(bounds, g, kk, whole, b);
-        const uint64_t rr = chain<K>(b, kk, a, r[j]);
-        if (rr < group_threshold<K>(b, kk, rr, err))
-            pending |= 1u << j;
-        else
-            store_dice<K, VEC>(out, g, kk, whole, a);
+        uint64_t ps = 0, rr = 0;
+        uint32_t a[K];
+        if (kk > 0) {
+            uint32_t b[K];
+            load_bounds<K, VEC>(bounds, g, kk, whole, b);
+            rr = chain<K>(b, kk, a, r[j]);
+            ps = undecided_product<K>(b, kk, rr, err);
+        }
+        const uint64_t um = __ballot(ps != 0);
+        const uint32_t at = nu + (uint32_t)__builtin_popcountll(um & lt_mask);
+        nu += (uint32_t)__builtin_popcountll(um);
+        bool keep = kk > 0;
+        if (ps != 0) {
+            if (at < kUndecided) { // its dice are stored, and rewritten if it rerolls
+                und_p[w][at] = ps;
+                und_r[w][at] = rr;
+                und_at[w][at] = (uint16_t)(64 * j + lane);
+            } else if (rr < pow2_64_mod(ps)) {
+                pending |= 1u << j;
+                keep = false;
+            }
+        }
+        if (keep) store_dice<K, VEC>(out, g, kk, whole, a);
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < std::min(nu, kUndecided) && und_r[w][lane] < pow2_64_mod(und_p[w][lane])) {
+        const uint32_t at = und_at[w][lane];
+        atomicOr(&rejected[w][at & 63], 1u << (at >> 6));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    pending |= rejected[w][lane];
     // record the rejected groups for the reroll kernel, if they fit
     if (rec.tiles) {
         const uint64_t t = g0 / (64 * 8);
@@ -258,10 +359,8 @@ __global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__rest
         }
         if (lane == 0) rec.count[t] = total <= kTileSlots ? total : 0;
     }
-    // rerolls in place (more than kTileSlots rejected), compacted: a lane works on its
-    // lowest pending group; each attempt is rejected with probability
-    // t / 2^64 < 1/2 and the cap only bounds the loop against corrupted
-    // inputs
+    // rerolls in place (more than kTileSlots rejected), compacted: a lane
+    // works on its lowest pending group
     uint64_t attempt = 1;
     while (__any(pending != 0)) {
         if (pending) {
@@ -269,14 +368,9 @@ __global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__rest
             const uint64_t g = g0 + 64 * (uint64_t)m + lane;
             const int kk = group_dice<K>(g, full, S, count);
             uint32_t b[K], a[K];
-#pragma unroll
-            for (int i = 0; i < K; ++i) b[i] = (i < kk) ? bounds[(uint64_t)K * g + i] : 1u;
-            const uint64_t rr = chain<K>(b, kk, a, chacha_word_at(attempt * S + g, key));
-            uint32_t e = 0;
-            if (rr >= group_threshold<K>(b, kk, rr, e) || attempt >= kMaxAttemptsChaCha) {
-#pragma unroll
-                for (int i = 0; i < K; ++i)
-                    if (i < kk) out[(uint64_t)K * g + i] = a[i];
+            load_group_bounds<K>(bounds, g, kk, b);
+            if (try_attempt<K>(b, kk, g, attempt, S, key, a)) {
+                store_group_dice<K>(out, g, kk, a);
                 pending &= pending - 1;
                 attempt = 1;
             } else {
@@ -288,10 +382,19 @@ __global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__rest
 }
 
 // Works through the recorded rejected groups: wave w owns the tiles
-// [w * per, (w + 1) * per). A lane holding a group tries its next attempt;
-// idle lanes take the next recorded groups in tile order. A group is
-// rerolled until accepted (or at the attempt cap), so its attempts run in
-// order and its first accepted word is the one that counts.
+// [w * per, (w + 1) * per), taken in chunks of up to 64 tiles (one count
+// per lane). A chunk's records are first gathered into a list in the
+// wave's LDS (the tile's counts scanned across the wave give each tile its
+// place in the list), so taking a group is one LDS read and the only
+// global reads left in the loop are the groups' bounds. A lane holding a
+// group tries its next attempt; idle lanes take the next listed groups. A
+// group is rerolled until accepted (or at the attempt cap), and its first
+// accepted word is the one that counts. Once the wave's list is drained and
+// at most half its lanes hold a group, the idle lanes try those groups'
+// next attempts side by side (spread passes), so that a group rejected
+// again and again does not keep the wave running one pass per attempt with
+// its other lanes idle.
+constexpr uint32_t kRerollChunk = 64;
 template <int K>
 __global__ __launch_bounds__(256) void dice_chacha_rerolls(const uint32_t *__restrict__ bounds,
                                                            uint32_t *__restrict__ out,
@@ -299,61 +402,117 @@ __global__ __launch_bounds__(256) void dice_chacha_rerolls(const uint32_t *__res
                                                            uint64_t full, StreamKey key,
                                                            RerollRecord rec, uint64_t per)
 {
+    // entry (tile in chunk << 9) | group offset in the tile
+    __shared__ uint16_t lists[4][kRerollChunk * kTileSlots];
+    __shared__ uint8_t holders[4][64]; // lanes of the active groups, in order (spread passes)
+    uint16_t *list = lists[threadIdx.x >> 6];
+    uint8_t *holder = holders[threadIdx.x >> 6];
     const uint32_t lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (1ull << lane) - 1;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const uint64_t t_begin = std::min<uint64_t>(wave * per, rec.tiles);
     const uint64_t t_end = std::min<uint64_t>(t_begin + per, rec.tiles);
-    // the first tile at or after `from` with recorded groups (t_end if
-    // none): 64 counts per step, most tiles having none
-    auto next_tile = [&](uint64_t from) -> uint64_t {
-        for (uint64_t base = from; base < t_end; base += 64) {
-            const uint64_t tt = base + lane;
-            const uint64_t nz = __ballot(tt < t_end && rec.count[tt] != 0);
-            if (nz) return base + (uint64_t)__builtin_ctzll(nz);
-        }
-        return t_end;
-    };
-    uint64_t t = next_tile(t_begin);                          // next tile to take from
-    uint32_t used = 0, avail = t < t_end ? rec.count[t] : 0; // of tile t
-    uint64_t g = kNoGroup, attempt = 1;
+    uint64_t t0 = t_begin, chunk = t_begin; // next chunk, chunk in the list
+    uint32_t n = 0, next = 0;               // listed, taken (uniform)
+    uint64_t g = kNoGroup;
+    uint32_t attempt = 1, b[K];
     while (true) {
-        // idle lanes take groups, from up to four tiles per round
-        for (int rounds = 0; rounds < 4 && t < t_end; ++rounds) {
-            const uint64_t idle = __ballot(g == kNoGroup);
-            if (!idle) break;
-            const uint32_t take = std::min<uint32_t>((uint32_t)__builtin_popcountll(idle),
-                                                     avail - used);
-            const uint32_t rank = (uint32_t)__builtin_popcountll(idle & ((1ull << lane) - 1));
-            if (g == kNoGroup && rank < take) {
-                g = t * (64 * 8) + rec.slot[t * kTileSlots + used + rank];
-                attempt = 1;
+        if (next == n && t0 < t_end) {
+            const uint32_t nt = (uint32_t)std::min<uint64_t>(kRerollChunk, t_end - t0);
+            const uint32_t c = lane < nt ? rec.count[t0 + lane] : 0;
+            const uint32_t incl = wave_inclusive_scan(c);
+            // 16 bytes (eight offsets) per lane and pass, four per tile
+            for (uint32_t e0 = 0; e0 < 4 * nt; e0 += 64) {
+                const uint32_t e = e0 + lane, tile = e >> 2, base = (e & 3) * 8;
+                const uint32_t tc = (uint32_t)__shfl((int)c, (int)(tile & 63), 64);
+                const uint32_t tx = (uint32_t)__shfl((int)incl, (int)(tile & 63), 64) - tc;
+                if (tile < nt && base < tc) {
+                    const u32x4 v = *reinterpret_cast<const u32x4 *>(
+                        rec.slot + (t0 + tile) * kTileSlots + base);
+                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (base + j < tc)
+                            list[tx + base + j] =
+                                (uint16_t)((tile << 9) | ((w[j >> 1] >> (16 * (j & 1))) & 0xFFFF));
+                }
             }
-            used += take;
-            if (used == avail) {
-                t = next_tile(t + 1);
-                used = 0;
-                avail = t < t_end ? rec.count[t] : 0;
-            }
+            n = (uint32_t)__shfl((int)incl, 63, 64);
+            next = 0;
+            chunk = t0;
+            t0 += nt;
+            // the list's writes land before any lane of the wave reads it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        if (!__any(g != kNoGroup)) {
-            if (t >= t_end) break;
+        // idle lanes take the next listed groups
+        const uint64_t idle = __ballot(g == kNoGroup);
+        const uint32_t take = std::min<uint32_t>((uint32_t)__builtin_popcountll(idle), n - next);
+        const uint32_t rank = (uint32_t)__builtin_popcountll(idle & lt_mask);
+        if (g == kNoGroup && rank < take) {
+            const uint32_t e = list[next + rank];
+            g = (chunk + (e >> 9)) * (64 * 8) + (e & 511);
+            attempt = 1;
+            load_group_bounds<K>(bounds, g, group_dice<K>(g, full, S, count), b);
+        }
+        next += take;
+        const bool drained = t0 >= t_end && next == n;
+        const uint64_t act = __ballot(g != kNoGroup);
+        if (!act) {
+            if (drained) break;
             continue;
         }
-        if (g != kNoGroup) {
-            const int kk = group_dice<K>(g, full, S, count);
-            uint32_t b[K], a[K];
-#pragma unroll
-            for (int i = 0; i < K; ++i) b[i] = (i < kk) ? bounds[(uint64_t)K * g + i] : 1u;
-            const uint64_t rr = chain<K>(b, kk, a, chacha_word_at(attempt * S + g, key));
-            uint32_t e = 0;
-            if (rr >= group_threshold<K>(b, kk, rr, e) || attempt >= kMaxAttemptsChaCha) {
-#pragma unroll
-                for (int i = 0; i < K; ++i)
-                    if (i < kk) out[(uint64_t)K * g + i] = a[i];
-                g = kNoGroup;
-            } else {
-                ++attempt;
+        const uint32_t c = (uint32_t)__builtin_popcountll(act);
+        if (!drained || 2 * c > 64) {
+            if (g != kNoGroup) {
+                const int kk = group_dice<K>(g, full, S, count);
+                uint32_t a[K];
+                if (try_attempt<K>(b, kk, g, attempt, S, key, a)) {
+                    store_group_dice<K>(out, g, kk, a);
+                    g = kNoGroup;
+                } else {
+                    ++attempt;
+                }
             }
+            continue;
+        }
+        // Spread pass (the list drained, at most half the lanes busy): the
+        // q-th active group, in lane order, gets the m = 64 / c lanes
+        // [q m, q m + m) for its attempts attempt .. attempt + m - 1; the
+        // lowest accepted of them is the one a lane trying them in order
+        // would have taken.
+        const uint32_t m = 64 / c;
+        if (g != kNoGroup) holder[__builtin_popcountll(act & lt_mask)] = (uint8_t)lane;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t q = lane / m;
+        const bool mine = q < c;
+        const int src = holder[mine ? q : 0];
+        const uint64_t gs = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(g >> 32), src, 64) << 32) |
+                            (uint32_t)__shfl((int)(uint32_t)g, src, 64);
+        const uint32_t as = (uint32_t)__shfl((int)attempt, src, 64) + lane % m;
+        uint32_t bs[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) bs[i] = (uint32_t)__shfl((int)b[i], src, 64);
+        bool acc = false;
+        int kk = 0;
+        uint32_t a[K];
+        if (mine) {
+            kk = group_dice<K>(gs, full, S, count);
+            acc = try_attempt<K>(bs, kk, gs, as, S, key, a);
+        }
+        const uint64_t seg = mine ? (~0ull >> (64 - m)) << (q * m) : 0ull;
+        const uint64_t hits = __ballot(acc) & seg;
+        g = kNoGroup;
+        if (hits) {
+            if (lane == (uint32_t)__builtin_ctzll(hits)) store_group_dice<K>(out, gs, kk, a);
+        } else if (mine && lane == q * m) { // none accepted: on from attempt as + m
+            g = gs;
+            attempt = as + m;
+#pragma unroll
+            for (int i = 0; i < K; ++i) b[i] = bs[i];
         }
     }
 }
@@ -368,11 +527,12 @@ hipError_t launch_dice_chacha_k(const uint32_t *bounds, uint32_t *out, uint64_t 
     const uint64_t blocks = (waves + 3) / 4;           // 4 wavefronts per block
     if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
     // the record: a count and kTileSlots offsets per tile (68 bytes per 512
-    // groups); without memory for it, every tile rerolls in place
+    // groups, the offsets 16-byte aligned); without memory for it, every
+    // tile rerolls in place
     RerollRecord rec{nullptr, nullptr, mem ? waves : 0};
     if (mem) {
         rec.count = static_cast<uint32_t *>(mem);
-        rec.slot = reinterpret_cast<uint16_t *>(rec.count + waves);
+        rec.slot = reinterpret_cast<uint16_t *>(static_cast<char *>(mem) + slot_offset(waves));
     }
     const bool vec = ((((uintptr_t)bounds) | ((uintptr_t)out)) & 15) == 0;
     if (vec)
@@ -397,7 +557,8 @@ hipError_t launch_dice_chacha_k(const uint32_t *bounds, uint32_t *out, uint64_t 
 uint64_t chacha_record_bytes(uint64_t count, uint32_t k)
 {
     const uint64_t S = (count + k - 1) / k;
-    return (S + 64 * 8 - 1) / (64 * 8) * (4 + 2 * kTileSlots);
+    const uint64_t tiles = (S + 64 * 8 - 1) / (64 * 8);
+    return slot_offset(tiles) + tiles * 2 * kTileSlots;
 }
 
 hipError_t launch_dice_chacha(const uint32_t *bounds, uint32_t *out, uint64_t count, uint32_t k,

@@ -372,6 +372,31 @@ def test_full_size_stream_whole(gpu, orc, full_bounds, entry, k, seed):
         raise AssertionError(f"{entry} k={k}: {bad.size} of {FULL} rolls differ, first at {bad[0]}")
 
 
+@pytest.mark.slow
+def test_dice_chacha_long_stream(gpu, orc):
+    """ChaCha20 dice, k = 2, on 2^29 + 4101 * 1024 + 77 bounds uniform below
+    2^31 (about 3% of the groups reroll, as in the 16-bit stream at k = 4):
+    270535207 groups in 132098 blocks of 2048, the last one short, and
+    reroll words past index 2^29."""
+    import torch
+
+    count = (1 << 29) + 4101 * 1024 + 77
+    bounds = workloads.dice_bounds(count, seed=9, high=1 << 31)
+    say("dice_chacha long stream", count)
+    b = to_dev(bounds)
+    out = torch.empty(count, dtype=torch.uint32, device="cuda")
+    gpu.check(gpu.brr_dice_chacha(b, out, count, 2, 12, 3), "brr_dice_chacha")
+    assert gpu.brr_sync_status() == 0
+    del b
+    got = to_host(out)
+    del out
+    err, want = orc.dice_stream(orc.STREAM_CHACHA20, bounds, 2, 12, 3)
+    assert err == 0
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError(f"{bad.size} of {count} rolls differ, first at {bad[0]}")
+
+
 def test_copy_probe_copies(gpu):
     """The roofline's copy probe moves the bytes it claims: dst equals src
     after it, with a ragged last tile (1 MiB + 48 bytes)."""
