@@ -139,26 +139,27 @@ __device__ __forceinline__ void store_group(uint32_t *__restrict__ p, const uint
 }
 
 // The chain on word r for one group: dice into a, returns the leftover.
+// A short group's bounds are padded with 1 past its dice: a bound of 1
+// rolls a 0 and leaves the leftover and the product as they are, so the
+// chain and the product run over all K without a branch per die.
 template <int K>
-__device__ __forceinline__ uint64_t chain(const uint32_t *b, int kk, uint32_t *a, uint64_t r)
+__device__ __forceinline__ uint64_t chain(const uint32_t *b, uint32_t *a, uint64_t r)
 {
 #pragma unroll
-    for (int i = 0; i < K; ++i)
-        if (i < kk) a[i] = mul_roll(b[i], r);
+    for (int i = 0; i < K; ++i) a[i] = mul_roll(b[i], r);
     return r;
 }
 
 // Lemire's threshold of the group's product, or 0 when the leftover rr
 // already accepts (r >= P > t, or P = 2^64); flags bad groups in err.
 template <int K>
-__device__ __forceinline__ uint64_t group_threshold(const uint32_t *b, int kk, uint64_t rr,
+__device__ __forceinline__ uint64_t group_threshold(const uint32_t *b, uint64_t rr,
                                                     uint32_t &err)
 {
     BoundProduct P;
     P.init(b[0]);
 #pragma unroll
-    for (int i = 1; i < K; ++i)
-        if (i < kk) P.mul(b[i]);
+    for (int i = 1; i < K; ++i) P.mul(b[i]);
     if (P.zero) {
         err |= kDevZeroBound;
         return 0;
@@ -175,14 +176,13 @@ __device__ __forceinline__ uint64_t group_threshold(const uint32_t *b, int kk, u
 // it), else 0: accepted at once (r >= P > t, or P = 2^64), or a bad group,
 // flagged in err (its dice are stored as they are).
 template <int K>
-__device__ __forceinline__ uint64_t undecided_product(const uint32_t *b, int kk, uint64_t rr,
+__device__ __forceinline__ uint64_t undecided_product(const uint32_t *b, uint64_t rr,
                                                       uint32_t &err)
 {
     BoundProduct P;
     P.init(b[0]);
 #pragma unroll
-    for (int i = 1; i < K; ++i)
-        if (i < kk) P.mul(b[i]);
+    for (int i = 1; i < K; ++i) P.mul(b[i]);
     if (P.zero) {
         err |= kDevZeroBound;
         return 0;
@@ -255,13 +255,13 @@ struct RerollRecord {
 // against corrupted inputs (each attempt is rejected with probability
 // t / 2^64 < 1/2).
 template <int K>
-__device__ __forceinline__ bool try_attempt(const uint32_t *b, int kk, uint64_t g,
+__device__ __forceinline__ bool try_attempt(const uint32_t *b, uint64_t g,
                                             uint64_t attempt, uint64_t S, const StreamKey &key,
                                             uint32_t *a)
 {
-    const uint64_t rr = chain<K>(b, kk, a, chacha_word_at(attempt * S + g, key));
+    const uint64_t rr = chain<K>(b, a, chacha_word_at(attempt * S + g, key));
     uint32_t e = 0; // bad groups were flagged by their first attempt
-    return rr >= group_threshold<K>(b, kk, rr, e) || attempt >= kMaxAttemptsChaCha;
+    return rr >= group_threshold<K>(b, rr, e) || attempt >= kMaxAttemptsChaCha;
 }
 
 template <int K>
@@ -309,14 +309,14 @@ __global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__rest
 #pragma unroll
     for (int j = 0; j < G; ++j) {
         const uint64_t g = g0 + 64 * j + lane;
-        const int kk = group_dice<K>(g, full, S, count);
+        const int kk = whole ? K : group_dice<K>(g, full, S, count);
         uint64_t ps = 0, rr = 0;
         uint32_t a[K];
         if (kk > 0) {
             uint32_t b[K];
             load_bounds<K, VEC>(bounds, g, kk, whole, b);
-            rr = chain<K>(b, kk, a, r[j]);
-            ps = undecided_product<K>(b, kk, rr, err);
+            rr = chain<K>(b, a, r[j]);
+            ps = undecided_product<K>(b, rr, err);
         }
         const uint64_t um = __ballot(ps != 0);
         const uint32_t at = nu + (uint32_t)__builtin_popcountll(um & lt_mask);
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(256) void dice_chacha_kernel(const uint32_t *__rest
             const int kk = group_dice<K>(g, full, S, count);
             uint32_t b[K], a[K];
             load_group_bounds<K>(bounds, g, kk, b);
-            if (try_attempt<K>(b, kk, g, attempt, S, key, a)) {
+            if (try_attempt<K>(b, g, attempt, S, key, a)) {
                 store_group_dice<K>(out, g, kk, a);
                 pending &= pending - 1;
                 attempt = 1;
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(256) void dice_chacha_rerolls(const uint32_t *__res
             if (g != kNoGroup) {
                 const int kk = group_dice<K>(g, full, S, count);
                 uint32_t a[K];
-                if (try_attempt<K>(b, kk, g, attempt, S, key, a)) {
+                if (try_attempt<K>(b, g, attempt, S, key, a)) {
                     store_group_dice<K>(out, g, kk, a);
                     g = kNoGroup;
                 } else {
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(256) void dice_chacha_rerolls(const uint32_t *__res
         uint32_t a[K];
         if (mine) {
             kk = group_dice<K>(gs, full, S, count);
-            acc = try_attempt<K>(bs, kk, gs, as, S, key, a);
+            acc = try_attempt<K>(bs, gs, as, S, key, a);
         }
         const uint64_t seg = mine ? (~0ull >> (64 - m)) << (q * m) : 0ull;
         const uint64_t hits = __ballot(acc) & seg;
