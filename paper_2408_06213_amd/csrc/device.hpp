@@ -147,6 +147,25 @@ struct BoundProduct {
     }
 };
 
+// The product of a group's K bounds; the first two in one step (two u32
+// factors never exceed 2^64).
+template <int K>
+__host__ __device__ __forceinline__ BoundProduct bound_product(const uint32_t *b)
+{
+    BoundProduct P;
+    if constexpr (K == 1) {
+        P.init(b[0]);
+    } else {
+        P.p = (uint64_t)b[0] * b[1];
+        P.e64 = false;
+        P.over = false;
+        P.zero = (b[0] == 0) || (b[1] == 0);
+#pragma unroll
+        for (int i = 2; i < K; ++i) P.mul(b[i]);
+    }
+    return P;
+}
+
 // Acceptance of a rolled group with exact product P (Lemire's criterion on
 // the leftover, Theorem 1): returns the threshold t to compare r against.
 // Only called when r < P, so t is computed on the rare slow path.

@@ -120,10 +120,7 @@ __device__ __forceinline__ void check_group(const uint32_t *b, int kk, uint64_t 
 template <int K>
 __device__ __forceinline__ uint64_t undecided_product(const uint32_t *b, uint64_t r, uint32_t &err)
 {
-    BoundProduct P;
-    P.init(b[0]);
-#pragma unroll
-    for (int i = 1; i < K; ++i) P.mul(b[i]);
+    const BoundProduct P = bound_product<K>(b);
     if (P.zero) {
         err |= kDevZeroBound;
         return 0;

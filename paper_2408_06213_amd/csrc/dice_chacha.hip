@@ -156,10 +156,7 @@ template <int K>
 __device__ __forceinline__ uint64_t group_threshold(const uint32_t *b, uint64_t rr,
                                                     uint32_t &err)
 {
-    BoundProduct P;
-    P.init(b[0]);
-#pragma unroll
-    for (int i = 1; i < K; ++i) P.mul(b[i]);
+    const BoundProduct P = bound_product<K>(b);
     if (P.zero) {
         err |= kDevZeroBound;
         return 0;
@@ -179,10 +176,7 @@ template <int K>
 __device__ __forceinline__ uint64_t undecided_product(const uint32_t *b, uint64_t rr,
                                                       uint32_t &err)
 {
-    BoundProduct P;
-    P.init(b[0]);
-#pragma unroll
-    for (int i = 1; i < K; ++i) P.mul(b[i]);
+    const BoundProduct P = bound_product<K>(b);
     if (P.zero) {
         err |= kDevZeroBound;
         return 0;
