@@ -261,8 +261,9 @@ brr_status brr_dice_div(const uint32_t *d_bounds, uint32_t *d_out, uint64_t coun
  * attempt addressing (attempt a of group s reads word a*S + s), arguments
  * and errors as brr_dice. Groups rejected on their first word are rerolled
  * by a second kernel of persistent wavefronts from per-tile records in
- * device scratch (68 bytes per tile of 512 groups, up to 32 rejected groups
- * a tile, the stream's scratch buffer; see brr_release_scratch); a tile
+ * device scratch (68 bytes per tile of 512 groups, plus up to 12 to align
+ * the offsets to 16 bytes; up to 32 rejected groups a tile; the stream's
+ * scratch buffer, see brr_release_scratch); a tile
  * with more, or every tile if the scratch cannot be had, rerolls in place
  * (the same dice, more slowly). */
 brr_status brr_dice_chacha(const uint32_t *d_bounds, uint32_t *d_out, uint64_t count, uint32_t k,
