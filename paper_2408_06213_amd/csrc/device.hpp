@@ -147,8 +147,12 @@ struct BoundProduct {
     }
 };
 
-// The product of a group's K bounds; the first two in one step (two u32
-// factors never exceed 2^64).
+// The product of a group's K bounds. The usual case (no zero bound, product
+// below 2^64) takes plain multiplies, the first two bounds in one step (two
+// u32 factors never exceed 2^64), and only notes whether any step carried
+// past 64 bits; a zero bound or a carry sends the group through the exact
+// steps of BoundProduct, which tell a product of exactly 2^64 from a larger
+// one.
 template <int K>
 __host__ __device__ __forceinline__ BoundProduct bound_product(const uint32_t *b)
 {
@@ -156,12 +160,24 @@ __host__ __device__ __forceinline__ BoundProduct bound_product(const uint32_t *b
     if constexpr (K == 1) {
         P.init(b[0]);
     } else {
-        P.p = (uint64_t)b[0] * b[1];
-        P.e64 = false;
-        P.over = false;
-        P.zero = (b[0] == 0) || (b[1] == 0);
+        uint64_t p = (uint64_t)b[0] * b[1];
+        uint32_t carry = 0, low = b[0] < b[1] ? b[0] : b[1];
 #pragma unroll
-        for (int i = 2; i < K; ++i) P.mul(b[i]);
+        for (int i = 2; i < K; ++i) {
+            const uint64_t lo = (uint64_t)(uint32_t)p * b[i];
+            const uint64_t hi = (uint64_t)(uint32_t)(p >> 32) * b[i] + (lo >> 32);
+            carry |= (uint32_t)(hi >> 32);
+            p = (hi << 32) | (uint32_t)lo;
+            low = low < b[i] ? low : b[i];
+        }
+        if (carry == 0 && low != 0) {
+            P.p = p;
+            P.e64 = P.over = P.zero = false;
+        } else {
+            P.init(b[0]);
+#pragma unroll
+            for (int i = 1; i < K; ++i) P.mul(b[i]);
+        }
     }
     return P;
 }
