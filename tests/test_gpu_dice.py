@@ -372,6 +372,24 @@ def test_full_size_stream_whole(gpu, orc, full_bounds, entry, k, seed):
         raise AssertionError(f"{entry} k={k}: {bad.size} of {FULL} rolls differ, first at {bad[0]}")
 
 
+def test_dice_chacha_rare_heavy_groups(gpu, orc):
+    """ChaCha20 dice, k = 2: small bounds (no rerolls) except one group in
+    997 with product 2^63 + 2^31 - 1, rejected about half the time, so the
+    reroll waves hold one or two groups each and try many attempts of a
+    group side by side (a group's first accepted attempt must win)."""
+    rng = np.random.default_rng(41)
+    groups = (1 << 20) + 333
+    bounds = rng.integers(1, 1 << 10, size=2 * groups, dtype=np.uint64).astype(np.uint32)
+    heavy = np.arange(5, groups, 997)
+    bounds[2 * heavy] = 2**31 + 1
+    bounds[2 * heavy + 1] = 2**32 - 1
+    say("dice_chacha rare heavy groups", groups)
+    st, got = run_dice_chacha(gpu, bounds, 2, seed=17, inst=2)
+    err, want = orc.dice_chacha(bounds, 2, 17, 2)
+    assert st == 0 and err == 0
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.slow
 def test_dice_chacha_long_stream(gpu, orc):
     """ChaCha20 dice, k = 2, on 2^29 + 4101 * 1024 + 77 bounds uniform below
